@@ -1,0 +1,350 @@
+"""Plain FP64 CPU oracle of the field-window estimator.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library calls this module: it is
+imported by the tests, by the smoke check and by the CPU-baseline leg of the
+benchmark, and by nothing else.  It shares no code with the HIP path.
+
+Everything here is written for obviousness, not speed: float64 throughout,
+full complex spectra (no Hermitian shortcut), explicit loops over l, m and
+bins.  Library primitives used as single steps: scipy.fft (a DFT), numpy's
+bincount (a histogram), scipy.special (spherical Bessel, Legendre, spherical
+harmonics) and numpy's Gauss-Legendre nodes.
+
+Conventions (the paper's notation; section / equation named per function):
+  grid node l = (lx, ly, lz), l_a in {0..N-1}, sits at position l*h, h = L/N;
+  array index [lx, ly, lz], lz fastest;
+  forward DFT  f^(n) = sum_l f_l exp(-2 pi i n.l/N)  (unnormalised),
+  inverse      f_l   = N^-3 sum_n f^(n) exp(+2 pi i n.l/N);
+  signed mode index n~_a in (-N/2, N/2], k = 2 pi n~ / L.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import scipy.fft as sfft
+from scipy.special import eval_legendre, spherical_jn, sph_harm_y
+
+_WORKERS = max(1, os.cpu_count() or 1)
+_GL_POINTS = 64
+
+
+# ----------------------------------------------------------------------------
+# Assignment (Sec. 3.1, Eq. phi_projection): eps_l = sum_i w_i phi(x_i/h - l)
+# ----------------------------------------------------------------------------
+
+def bspline3(t):
+    """Centred cubic B-spline: the scaling function phi used for projection.
+
+    B3(t) = (4 - 6 t^2 + 3|t|^3)/6 for |t| < 1, (2-|t|)^3/6 for 1 <= |t| < 2,
+    0 otherwise.  (Sec. 3.1: compactly supported MRA scaling function.)
+    """
+    a = np.abs(np.asarray(t, dtype=np.float64))
+    out = np.zeros_like(a)
+    m1 = a < 1.0
+    out[m1] = (4.0 - 6.0 * a[m1] ** 2 + 3.0 * a[m1] ** 3) / 6.0
+    m2 = (a >= 1.0) & (a < 2.0)
+    out[m2] = (2.0 - a[m2]) ** 3 / 6.0
+    return out
+
+
+def assign(pos, weight, box_L, n):
+    """Project a weighted catalogue onto the N^3 grid of B3 coefficients.
+
+    Sec. 3.1, Eq. phi_projection: eps_l = sum_i w_i prod_a B3(x_{i,a}/h - l_a),
+    node index taken mod N (periodic box).  ``weight`` None means unit weights
+    (Eq. dendis with w_i = 1; Eq. weighted_field for marks).
+    Returns (eps [N,N,N] float64, sum of weights).
+    """
+    pos = np.asarray(pos, dtype=np.float32)
+    h = float(box_L) / n
+    u = pos.astype(np.float64) / h
+    npts = u.shape[0]
+    w = np.ones(npts) if weight is None else np.asarray(weight, dtype=np.float64)
+    i0 = np.floor(u).astype(np.int64)
+    eps = np.zeros(n ** 3)
+    for ox in (-1, 0, 1, 2):
+        cx = i0[:, 0] + ox
+        wx = bspline3(u[:, 0] - cx)
+        cx = np.mod(cx, n)
+        for oy in (-1, 0, 1, 2):
+            cy = i0[:, 1] + oy
+            wy = bspline3(u[:, 1] - cy)
+            cy = np.mod(cy, n)
+            for oz in (-1, 0, 1, 2):
+                cz = i0[:, 2] + oz
+                wz = bspline3(u[:, 2] - cz)
+                cz = np.mod(cz, n)
+                flat = (cx * n + cy) * n + cz
+                eps += np.bincount(flat, weights=w * wx * wy * wz, minlength=n ** 3)
+    return eps.reshape(n, n, n), float(w.sum())
+
+
+def contrast(eps, sum_w):
+    """delta_l = eps_l / eps_bar - 1 with eps_bar = sum_w / N^3 (Sec. 2 notation;
+    Sec. 4.2 field_mean_density; uniform analytic random, Sec. 4.3.1)."""
+    n3 = eps.size
+    return eps / (sum_w / n3) - 1.0
+
+
+def dft3(field):
+    """Full complex forward DFT of a real field; the k=0 mode is set to zero."""
+    fh = sfft.fftn(np.asarray(field, dtype=np.complex128), workers=_WORKERS)
+    fh[0, 0, 0] = 0.0
+    return fh
+
+
+def idft3(spec):
+    """Inverse DFT including the N^-3 factor (complex result)."""
+    return sfft.ifftn(spec, workers=_WORKERS)
+
+
+# ----------------------------------------------------------------------------
+# Mode geometry and the basis kernel (Sec. 3.3.1 Eq. shift-scaling_coeff-kspace;
+# Sec. 4.2 discrete kernel K_W = W^ Phi^)
+# ----------------------------------------------------------------------------
+
+def signed_index(n, nyquist_sign=+1):
+    """Signed mode index per axis; the Nyquist index N/2 (even N) maps to
+    +N/2 or -N/2 according to ``nyquist_sign``."""
+    i = np.arange(n)
+    s = np.where(i <= n // 2, i, i - n).astype(np.float64)
+    if n % 2 == 0 and nyquist_sign < 0:
+        s[n // 2] = -n / 2
+    return s
+
+
+def phi_hat_1d(n):
+    """Per-axis Fourier transform of the B3 autocorrelation at the grid modes:
+    |B3^|^2 = sinc^8(pi n~/N), alias images dropped (Eq.
+    shift-scaling_coeff-kspace keeps only the principal mode)."""
+    s = signed_index(n)
+    return np.sinc(s / n) ** 8          # np.sinc(x) = sin(pi x)/(pi x)
+
+
+def phi_hat(n):
+    p = phi_hat_1d(n)
+    return p[:, None, None] * p[None, :, None] * p[None, None, :]
+
+
+def mode_vectors(n, box_L, signs=(1, 1, 1)):
+    """k-vector components (broadcastable [N,1,1], [1,N,1], [1,1,N])."""
+    f = 2.0 * np.pi / box_L
+    kx = f * signed_index(n, signs[0])[:, None, None]
+    ky = f * signed_index(n, signs[1])[None, :, None]
+    kz = f * signed_index(n, signs[2])[None, None, :]
+    return kx, ky, kz
+
+
+def mode_q(n):
+    """Integer |n~|^2 for every mode (Nyquist sign irrelevant)."""
+    s = signed_index(n).astype(np.int64)
+    return s[:, None, None] ** 2 + s[None, :, None] ** 2 + s[None, None, :] ** 2
+
+
+# ----------------------------------------------------------------------------
+# Window functions (Sec. 2.2.1 Eqs. Wshell, Wshell_k; Table A1 (a)-(c);
+# Sec. 3.3.3 multipole windows)
+# ----------------------------------------------------------------------------
+
+def w_sphere(x):
+    """Spherical top-hat 3(sin x - x cos x)/x^3 (Table A1 (b)); Taylor series
+    1 - x^2/10 + x^4/280 - x^6/15120 below x = 0.05."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    small = np.abs(x) < 0.05
+    xs = x[small]
+    x2 = xs * xs
+    out[small] = 1.0 - x2 / 10.0 + x2 * x2 / 280.0 - x2 * x2 * x2 / 15120.0
+    xl = x[~small]
+    out[~small] = 3.0 * (np.sin(xl) - xl * np.cos(xl)) / xl ** 3
+    return out
+
+
+def w_shell(k, r_lo, r_hi):
+    """Volume-normalised thick shell: difference of two spheres (Eq. Wshell_k)."""
+    return (r_hi ** 3 * w_sphere(k * r_hi) - r_lo ** 3 * w_sphere(k * r_lo)) / (r_hi ** 3 - r_lo ** 3)
+
+
+def w_gauss(k, R):
+    """Gaussian low-pass exp(-k^2 R^2 / 2) (Table A1 (c))."""
+    return np.exp(-0.5 * (k * R) ** 2)
+
+
+def jbar(ell, k, r_lo, r_hi):
+    """Finite-bin radial factor: the r^2-weighted bin average of j_l(k r)
+    (Sec. 3.3.3: replace j_l(kr) by its average over the radial window),
+    by 64-point Gauss-Legendre quadrature on [r_lo, r_hi]."""
+    k = np.asarray(k, dtype=np.float64)
+    x, wq = np.polynomial.legendre.leggauss(_GL_POINTS)
+    r = 0.5 * (r_hi - r_lo) * x + 0.5 * (r_hi + r_lo)
+    wr = 0.5 * (r_hi - r_lo) * wq * r * r
+    vol = (r_hi ** 3 - r_lo ** 3) / 3.0
+    flat = k.reshape(-1)
+    out = np.zeros(flat.shape)
+    for rj, wj in zip(r, wr):
+        out += wj * spherical_jn(ell, flat * rj)
+    return (out / vol).reshape(k.shape)
+
+
+def ylm_real(ell, m, kx, ky, kz):
+    """Real orthonormal spherical harmonic of the direction of k.
+
+    m > 0: sqrt2 (-1)^m Re Y_l^m; m < 0: sqrt2 (-1)^m Im Y_l^|m|; m = 0: Y_l^0.
+    At k = 0 the value is 1/sqrt(4 pi) for l = 0 and 0 otherwise.
+    """
+    kx, ky, kz = np.broadcast_arrays(kx, ky, kz)
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    zero = kk == 0.0
+    safe = np.where(zero, 1.0, kk)
+    theta = np.arccos(np.clip(kz / safe, -1.0, 1.0))
+    phi = np.arctan2(ky, kx)
+    y = sph_harm_y(ell, abs(m), theta, phi)
+    if m > 0:
+        out = np.sqrt(2.0) * (-1) ** m * y.real
+    elif m < 0:
+        out = np.sqrt(2.0) * (-1) ** m * y.imag
+    else:
+        out = y.real.copy()
+    out = np.where(zero, (1.0 / np.sqrt(4.0 * np.pi)) if ell == 0 else 0.0, out)
+    return out
+
+
+def _radial_by_q(n, box_L, fn):
+    """Evaluate a radial function of |k| once per distinct |n~|^2 and spread it
+    over the grid (same value at every mode of equal |k|)."""
+    q = mode_q(n)
+    uq, inv = np.unique(q.reshape(-1), return_inverse=True)
+    kq = 2.0 * np.pi / box_L * np.sqrt(uq.astype(np.float64))
+    return fn(kq)[inv].reshape(q.shape)
+
+
+def nyquist_average(n, box_L, fn):
+    """Average a k-space kernel over the two signed representatives of every
+    Nyquist index (even N): K(n) = mean over s in {+,-}^3 of fn(k_s).  Off the
+    Nyquist planes all eight evaluations coincide, so K equals fn there."""
+    if n % 2:
+        return fn(*mode_vectors(n, box_L))
+    acc = 0.0
+    for sx in (1, -1):
+        for sy in (1, -1):
+            for sz in (1, -1):
+                acc = acc + fn(*mode_vectors(n, box_L, (sx, sy, sz)))
+    return acc / 8.0
+
+
+# ----------------------------------------------------------------------------
+# Two-point statistics by Parseval (Sec. 3.3.1 Eqs. pair-counting-kspace,
+# xi-deltaDD-over-RR; Sec. 3.3.3 Legendre multipoles DD_l)
+# ----------------------------------------------------------------------------
+
+def xi_multipoles(delta_hat, box_L, edges, ells=(0,), los_axis=2):
+    """xi_l[b] = N^-6 sum_n |delta^_n|^2 Phi^(n) (2l+1) i^l jbar_l(k;b) L_l(mu_k).
+
+    Full spectrum, every mode.  l = 0 uses the thick-shell window (identical
+    to jbar_0).  Only even l carry a real value; odd l are rejected.
+    Returns float64 [len(ells), n_bins].
+    """
+    n = delta_hat.shape[0]
+    nc = float(n) ** 3
+    edges = np.asarray(edges, dtype=np.float64)
+    p = (np.abs(delta_hat) ** 2) * phi_hat(n)
+    kx, ky, kz = mode_vectors(n, box_L)
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    klos = (kx, ky, kz)[los_axis]
+    mu = np.where(kk > 0, klos / np.where(kk > 0, kk, 1.0), 0.0)
+    out = np.zeros((len(ells), len(edges) - 1))
+    for il, ell in enumerate(ells):
+        if ell % 2:
+            raise ValueError("odd multipoles of the auto-correlation vanish; use even l")
+        leg = eval_legendre(ell, mu) if ell > 0 else 1.0
+        pref = (2 * ell + 1) * (-1) ** (ell // 2)
+        pl = p * leg
+        for b in range(len(edges) - 1):
+            lo, hi = edges[b], edges[b + 1]
+            if ell == 0:
+                rad = _radial_by_q(n, box_L, lambda kq: w_shell(kq, lo, hi))
+            else:
+                rad = _radial_by_q(n, box_L, lambda kq: jbar(ell, kq, lo, hi))
+            out[il, b] = pref * np.sum(pl * rad) / nc ** 2
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Counts-in-cells moments (Sec. 3.1 filtered field n_W; Sec. 2.2.2 Eq. varw)
+# ----------------------------------------------------------------------------
+
+def filtered_field(delta_hat, box_L, kernel_of_k):
+    """delta_W = Re iDFT[delta^ Phi^ W^(|k|)] for a radial window."""
+    n = delta_hat.shape[0]
+    rad = _radial_by_q(n, box_L, kernel_of_k)
+    return idft3(delta_hat * phi_hat(n) * rad).real
+
+
+def cic_moments(delta_hat, box_L, windows):
+    """<delta_W^p> for p = 2, 3, 4 (mean over all grid nodes) per window.
+
+    ``windows``: list of ("sphere"|"gauss", R).  Returns float64 [n_win, 3].
+    """
+    out = np.zeros((len(windows), 3))
+    for i, (kind, R) in enumerate(windows):
+        if kind == "sphere":
+            fn = lambda kq, R=R: w_sphere(kq * R)
+        elif kind == "gauss":
+            fn = lambda kq, R=R: w_gauss(kq, R)
+        else:
+            raise ValueError(kind)
+        dw = filtered_field(delta_hat, box_L, fn)
+        out[i] = [np.mean(dw ** 2), np.mean(dw ** 3), np.mean(dw ** 4)]
+    return out
+
+
+# ----------------------------------------------------------------------------
+# 3PCF multipoles (Sec. 3.3.3 Eqs. multipole-window, iFFT-multipoleSFC,
+# 2-fold-translation; Sec. 3.4 particle_nfold with a naked primary vertex)
+# ----------------------------------------------------------------------------
+
+def sh_window(n, box_L, ell, m):
+    """Nyquist-averaged real spherical harmonic Y^R_lm(k^) on the grid."""
+    return nyquist_average(n, box_L, lambda kx, ky, kz: ylm_real(ell, m, kx, ky, kz))
+
+
+def multipole_field(delta_hat, box_L, ell, m, r_lo, r_hi, ylm=None):
+    """a_lmb(x) = iDFT[delta^ Phi^ 4 pi i^l jbar_l(k;b) Y^R_lm(k^)] (real).
+
+    Returns (real part, max |imag part|).
+    """
+    n = delta_hat.shape[0]
+    if ylm is None:
+        ylm = sh_window(n, box_L, ell, m)
+    rad = _radial_by_q(n, box_L, lambda kq: jbar(ell, kq, r_lo, r_hi))
+    kern = 4.0 * np.pi * (1j ** ell) * rad * ylm * phi_hat(n)
+    f = idft3(delta_hat * kern)
+    return f.real, float(np.max(np.abs(f.imag)))
+
+
+def zeta_multipoles(delta, delta_hat, box_L, edges, ells, bins=None):
+    """zeta_l[b1,b2] = (4 pi N^3)^-1 sum_m sum_x delta(x) a_lmb1(x) a_lmb2(x).
+
+    Explicit loops over l in ``ells``, m = -l..l and the bins in ``bins``
+    (default all).  Returns float64 [len(ells), len(bins), len(bins)].
+    """
+    n = delta_hat.shape[0]
+    nc = float(n) ** 3
+    edges = np.asarray(edges, dtype=np.float64)
+    if bins is None:
+        bins = list(range(len(edges) - 1))
+    out = np.zeros((len(ells), len(bins), len(bins)))
+    for il, ell in enumerate(ells):
+        for m in range(-ell, ell + 1):
+            ylm = sh_window(n, box_L, ell, m)
+            fields = []
+            for b in bins:
+                a, _ = multipole_field(delta_hat, box_L, ell, m, edges[b], edges[b + 1], ylm)
+                fields.append(a)
+            for i in range(len(bins)):
+                da = delta * fields[i]
+                for j in range(len(bins)):
+                    out[il, i, j] += np.sum(da * fields[j])
+        out[il] /= 4.0 * np.pi * nc
+    return out
