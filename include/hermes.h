@@ -1,0 +1,196 @@
+/*
+ * hermes.h -- C ABI of the MI355X (gfx950) field-window estimator library.
+ *
+ * The library computes, on one GPU, the hot path of the in-situ field-window
+ * estimator of clustering statistics:
+ *   catalogue -> B3 scaling-function coefficients (hermes_assign)
+ *   -> density contrast and its 3-D real FFT        (hermes_fft)
+ *   -> 2PCF and its Legendre multipoles by Parseval  (hermes_xi)
+ *   -> window-filtered fields, counts-in-cells moments (hermes_filter_bins)
+ *   -> 3PCF multipoles zeta_l(r1, r2)                 (hermes_zeta_l)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grid: N^3 nodes, N a power of two in [8, 1024]; node l = (lx, ly, lz)
+ *    sits at position l*h, h = L/N, in a periodic box of side L.  Real
+ *    fields are row-major [N][N][N] with lz fastest.
+ *  - Half spectrum: complex [N][N][N/2+1] (interleaved re, im), index
+ *    (kx, ky, kz) with kz in [0, N/2]; forward DFT unnormalised,
+ *    f^(n) = sum_l f_l exp(-2 pi i n.l / N).  Signed mode n~ in (-N/2, N/2],
+ *    k = 2 pi n~ / L.
+ *  - dtype: HERMES_F32 (float fields, complex64 spectra) or HERMES_F64
+ *    (double fields, complex128 spectra).  Positions and weights are always
+ *    float32.  Grid-wide reductions are always accumulated in float64.
+ *  - Every device buffer is owned by the caller, including workspace, whose
+ *    size hermes_workspace_size() reports.  The library owns only the opaque
+ *    context (twiddle, basis-kernel and quadrature tables).  No entry point
+ *    allocates device memory.
+ *  - All calls are asynchronous on the given stream; outputs (device
+ *    pointers, including the double-precision statistics) are valid after the
+ *    stream has been synchronised.  Host arrays passed in (bin edges, window
+ *    lists, multipole lists) are read before the call returns.
+ *  - Errors: every entry point returns a hermes_status; on anything but
+ *    HERMES_OK, hermes_last_error() returns a thread-local message and no
+ *    kernel has been launched.  HERMES_ERR_HIP reports a HIP runtime error
+ *    raised by a launch.
+ */
+#ifndef HERMES_H
+#define HERMES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hermes_status {
+    HERMES_OK = 0,
+    HERMES_ERR_ARG = 1,         /* bad pointer, size, bin edges, multipole, ... */
+    HERMES_ERR_OOM = 2,         /* workspace smaller than hermes_workspace_size() */
+    HERMES_ERR_HIP = 3,         /* HIP runtime error */
+    HERMES_ERR_UNSUPPORTED = 4  /* valid request outside what this build supports */
+} hermes_status;
+
+typedef enum hermes_dtype { HERMES_F32 = 0, HERMES_F64 = 1 } hermes_dtype;
+
+/* Precision of the 3PCF contraction (the FFTs always run in float32). */
+typedef enum hermes_precision {
+    HERMES_PREC_FP32 = 0,   /* float32 vector FMA contraction */
+    HERMES_PREC_BF16X3 = 1, /* bf16 hi+lo split, three MFMA products, fp32 accumulate */
+    HERMES_PREC_FP16X3 = 2  /* fp16 hi+lo split, three MFMA products, fp32 accumulate */
+} hermes_precision;
+
+/* Window kinds (Table A1 (a)-(c) and the multipole windows of Sec. 3.3.3). */
+typedef enum hermes_window_type {
+    HERMES_WIN_SHELL = 0,    /* volume-normalised thick shell [r_lo, r_hi] (Eq. Wshell_k) */
+    HERMES_WIN_SPHERE = 1,   /* spherical top-hat of radius r_hi (Table A1 (b)) */
+    HERMES_WIN_GAUSS = 2,    /* Gaussian exp(-k^2 r_hi^2 / 2) (Table A1 (c)) */
+    HERMES_WIN_SH_SHELL = 3  /* 4 pi i^l jbar_l(k; r_lo, r_hi) Y^R_lm(k^) (Eq. multipole-window) */
+} hermes_window_type;
+
+/* One window.  r_lo is ignored for SPHERE and GAUSS; ell and m (real
+ * spherical-harmonic index, -ell..ell) are used by SH_SHELL only. */
+typedef struct hermes_window {
+    int32_t type;
+    int32_t ell;
+    int32_t m;
+    int32_t reserved;   /* must be 0 */
+    double r_lo;
+    double r_hi;
+} hermes_window;
+
+/* Operation ids for hermes_workspace_size(). */
+typedef enum hermes_op {
+    HERMES_OP_ASSIGN = 0,
+    HERMES_OP_FFT = 1,
+    HERMES_OP_XI = 2,
+    HERMES_OP_FILTER = 3,
+    HERMES_OP_ZETA = 4
+} hermes_op;
+
+typedef struct hermes_ctx_s* hermes_ctx;
+
+#define HERMES_MAX_BINS 64   /* bins per hermes_xi / hermes_zeta_l call */
+#define HERMES_MAX_ELLS 8    /* multipoles per hermes_xi call */
+#define HERMES_MAX_LMAX 16   /* highest 3PCF multipole */
+
+/* Create a context on HIP device `device`; fills *out.  Allocates the
+ * context's constant tables (about 0.2 MB) on that device. */
+hermes_status hermes_create(hermes_ctx* out, int device);
+
+/* Release a context (NULL is ignored).  Not to be called while work that
+ * uses it is still in flight. */
+void hermes_destroy(hermes_ctx ctx);
+
+/* Thread-local text of the last error raised on this thread ("" if none). */
+const char* hermes_last_error(void);
+
+/* Device workspace, in bytes, that `op` needs for an N^3 grid.  n_batch is
+ * the number of windows (FILTER) or radial bins (ZETA); n_ells the number of
+ * multipoles (XI).  Zero for ASSIGN and FFT, which need none. */
+hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtype,
+                                    int n_batch, int n_ells, size_t* bytes);
+
+/* MRA projection of a weighted catalogue (Sec. 3.1, Eq. phi_projection):
+ *   eps_l = sum_i w_i prod_a B3(x_{i,a}/h - l_a),  l_a taken mod N,
+ * with the centred cubic B-spline B3 as scaling function (64 nodes per
+ * point).  Position fractions are formed in float64.
+ *   pos    device float32 [n_pts][3], any real values (wrapped into the box)
+ *   weight device float32 [n_pts], or NULL for unit weights (Eq. dendis;
+ *          marks or physical values as in Eq. weighted_field)
+ *   eps    device [N^3] of dtype; overwritten
+ *   sum_w  device double[1]; overwritten with sum_i w_i (float64)
+ * n_pts may be 0 (eps is zeroed, sum_w = 0).  ERR_ARG for NULL buffers,
+ * n_pts < 0, box_L <= 0 or N not a power of two in [8, 1024]. */
+hermes_status hermes_assign(hermes_ctx ctx, const float* pos, const float* weight,
+                            int64_t n_pts, double box_L, int n_grid, int dtype,
+                            void* eps, double* sum_w, hipStream_t stream);
+
+/* Density contrast and forward transform (Sec. 4.2; analytic uniform random
+ * of Sec. 4.3.1):  delta_l = eps_l / eps_bar - 1, eps_bar = sum_w / N^3,
+ * then delta^ = r2c DFT of delta with delta^(0) := 0.
+ *   eps     device [N^3] of dtype (read only)
+ *   sum_w   device double[1] from hermes_assign
+ *   delta_k device complex [N][N][N/2+1] of dtype; overwritten
+ *   delta   device [N^3] of dtype receiving delta_l, or NULL
+ * ERR_ARG if sum_w holds zero is NOT detected (the result is then inf/nan). */
+hermes_status hermes_fft(hermes_ctx ctx, const void* eps, const double* sum_w,
+                         int n_grid, int dtype, void* delta_k, void* delta,
+                         hipStream_t stream);
+
+/* 2PCF and its Legendre multipoles by Parseval (Sec. 3.3.1 Eq.
+ * pair-counting-kspace; Sec. 3.3.3 DD_l with the bin-averaged radial factor):
+ *   xi_l[b] = N^-6 sum_n |delta^_n|^2 Phi^(n) (2l+1) i^l jbar_l(k_n; b) L_l(mu_n),
+ * Phi^(n) = prod_a sinc^8(pi n~_a / N) (B3 autocorrelation), mu = k_los/|k|,
+ * jbar_0 = volume-normalised thick shell (Eq. Wshell_k).  Raw estimator:
+ * no shot-noise subtraction.
+ *   delta_k  device half spectrum from hermes_fft
+ *   edges    host double [n_bins+1], strictly increasing, edges[0] >= 0
+ *   ells     host int [n_ells], even values in [0, HERMES_MAX_LMAX]
+ *   los_axis 0, 1 or 2 (plane-parallel line of sight)
+ *   xi       device double [n_ells][n_bins]; overwritten
+ *   work     device workspace of >= hermes_workspace_size(XI) bytes */
+hermes_status hermes_xi(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype,
+                        double box_L, const double* edges, int n_bins,
+                        const int* ells, int n_ells, int los_axis, double* xi,
+                        void* work, size_t work_bytes, hipStream_t stream);
+
+/* Window-filtered fields (Sec. 4.2: eps_W = iFT[FT(eps) W^ Phi^]) and their
+ * counts-in-cells moments (Sec. 3.1 filtered field, Sec. 2.2.2 Eq. varw):
+ *   out_w(l) = N^-3 sum_n delta^_n Phi^(n) W^_w(k_n) exp(2 pi i n.l/N)   (real)
+ *   moments[w] = ( <out_w^2>, <out_w^3>, <out_w^4> ), mean over all nodes.
+ * Windows of kind SH_SHELL use the Nyquist-averaged real spherical harmonic.
+ *   win      host array of n_win windows
+ *   out      device [n_win][N^3] of dtype, or NULL to skip storing fields
+ *   moments  device double [n_win][3], or NULL
+ *   work     device workspace of >= hermes_workspace_size(FILTER, n_win) */
+hermes_status hermes_filter_bins(hermes_ctx ctx, const void* delta_k, int n_grid,
+                                 int dtype, double box_L, const hermes_window* win,
+                                 int n_win, void* out, double* moments, void* work,
+                                 size_t work_bytes, hipStream_t stream);
+
+/* 3PCF multipoles with a naked primary vertex (Sec. 3.3.3 Eqs.
+ * multipole-window, iFFT-multipoleSFC, 2-fold-translation; Sec. 3.4):
+ *   a_lmb(x) = iDFT[delta^ Phi^ 4 pi i^l jbar_l(k; b) Y^R_lm(k^)](x)  (real),
+ *   zeta_l[b1][b2] = (4 pi N^3)^-1 sum_{m=-l..l} sum_x delta(x) a_lmb1(x) a_lmb2(x),
+ * i.e. the Legendre coefficients of the rotation-averaged triple product.
+ * Float32 FFTs; the contraction per `precision`; float64 across tiles.
+ *   delta    device float [N^3]: the contrast written by hermes_fft
+ *   delta_k  device complex64 half spectrum from hermes_fft
+ *   edges    host double [n_bins+1], strictly increasing, edges[0] >= 0
+ *   l_max    0..HERMES_MAX_LMAX
+ *   zeta     device double [l_max+1][n_bins][n_bins]; overwritten
+ *   work     device workspace of >= hermes_workspace_size(ZETA, n_bins) */
+hermes_status hermes_zeta_l(hermes_ctx ctx, const float* delta, const void* delta_k,
+                            int n_grid, double box_L, const double* edges, int n_bins,
+                            int l_max, int precision, double* zeta, void* work,
+                            size_t work_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HERMES_H */

@@ -1,0 +1,278 @@
+// C ABI entry points: argument validation, context tables, dispatch.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace hermes {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+hermes_status fail(hermes_status st, const std::string& msg) {
+    set_error(msg);
+    return st;
+}
+
+hermes_status check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(HERMES_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return HERMES_OK;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_n.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+static hermes_status build_tables(hermes_ctx c) {
+    std::vector<float2> tw32(kTwTable);
+    std::vector<double2> tw64(kTwTable);
+    for (int L = 1; L <= kTwTable / 2; L *= 2) {
+        for (int m = 0; m < L; ++m) {
+            const double a = -2.0 * M_PI * double(m) / double(L);
+            tw64[L + m] = double2{std::cos(a), std::sin(a)};
+            tw32[L + m] = float2{float(std::cos(a)), float(std::sin(a))};
+        }
+    }
+    std::vector<double> phi(2 * kMaxN, 0.0);
+    for (int n = 1; n <= kMaxN; n *= 2) {
+        for (int i = 0; i < n; ++i) {
+            const int s = i <= n / 2 ? i : i - n;
+            const double a = M_PI * double(s) / double(n);
+            const double sn = s == 0 ? 1.0 : std::sin(a) / a;
+            phi[n + i] = std::pow(sn, 8);
+        }
+    }
+    std::vector<double> gx, gw;
+    gauss_legendre(16, gx, gw);
+    std::vector<double> gl(32);
+    for (int i = 0; i < 16; ++i) {
+        gl[i] = gx[i];
+        gl[16 + i] = gw[i];
+    }
+    auto up = [](void** dst, const void* src, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return e;
+        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    hipError_t e;
+    if ((e = up((void**)&c->t.tw32, tw32.data(), tw32.size() * sizeof(float2))) != hipSuccess ||
+        (e = up((void**)&c->t.tw64, tw64.data(), tw64.size() * sizeof(double2))) != hipSuccess ||
+        (e = up((void**)&c->t.phi1d, phi.data(), phi.size() * sizeof(double))) != hipSuccess ||
+        (e = up((void**)&c->t.gl, gl.data(), gl.size() * sizeof(double))) != hipSuccess)
+        return fail(HERMES_ERR_HIP, std::string("hermes_create: ") + hipGetErrorString(e));
+    return HERMES_OK;
+}
+
+static hermes_status get_edges(const double* edges, int n_bins, Edges& out, const char* who) {
+    if (!edges) return fail(HERMES_ERR_ARG, std::string(who) + ": edges is NULL");
+    if (n_bins < 1 || n_bins > HERMES_MAX_BINS)
+        return fail(HERMES_ERR_ARG, std::string(who) + ": n_bins must be in [1, 64]");
+    if (!(edges[0] >= 0.0)) return fail(HERMES_ERR_ARG, std::string(who) + ": edges[0] must be >= 0");
+    for (int i = 0; i < n_bins; ++i)
+        if (!(edges[i + 1] > edges[i]))
+            return fail(HERMES_ERR_ARG, std::string(who) + ": edges must be strictly increasing");
+    for (int i = 0; i <= n_bins; ++i) out.e[i] = edges[i];
+    out.n_bins = n_bins;
+    return HERMES_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace hermes
+
+using namespace hermes;
+
+extern "C" {
+
+const char* hermes_last_error(void) { return g_last_error.c_str(); }
+
+hermes_status hermes_create(hermes_ctx* out, int device) {
+    if (!out) return fail(HERMES_ERR_ARG, "hermes_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(HERMES_ERR_ARG, "hermes_create: no such HIP device");
+    DeviceGuard g(device);
+    hermes_ctx c = new hermes_ctx_s();
+    c->device = device;
+    const hermes_status st = build_tables(c);
+    if (st != HERMES_OK) {
+        hermes_destroy(c);
+        return st;
+    }
+    *out = c;
+    return HERMES_OK;
+}
+
+void hermes_destroy(hermes_ctx ctx) {
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    (void)hipFree(ctx->t.tw32);
+    (void)hipFree(ctx->t.tw64);
+    (void)hipFree(ctx->t.phi1d);
+    (void)hipFree(ctx->t.gl);
+    delete ctx;
+}
+
+hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtype, int n_batch,
+                                    int n_ells, size_t* bytes) {
+    if (!ctx || !bytes) return fail(HERMES_ERR_ARG, "hermes_workspace_size: NULL argument");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_workspace_size: N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_workspace_size: bad dtype");
+    switch (op) {
+        case HERMES_OP_ASSIGN:
+        case HERMES_OP_FFT:
+            *bytes = 0;
+            return HERMES_OK;
+        case HERMES_OP_XI:
+            if (n_ells < 1 || n_ells > HERMES_MAX_ELLS || n_batch < 1 || n_batch > HERMES_MAX_BINS)
+                return fail(HERMES_ERR_ARG, "hermes_workspace_size: XI needs 1..8 multipoles and 1..64 bins");
+            *bytes = xi_workspace(n_grid, n_ells, n_batch);
+            return HERMES_OK;
+        case HERMES_OP_FILTER:
+            if (n_batch < 1) return fail(HERMES_ERR_ARG, "hermes_workspace_size: FILTER needs n_batch >= 1");
+            *bytes = filter_workspace(n_grid, dtype, n_batch);
+            return HERMES_OK;
+        case HERMES_OP_ZETA:
+            if (dtype != HERMES_F32) return fail(HERMES_ERR_UNSUPPORTED, "hermes_workspace_size: ZETA runs in float32");
+            if (n_batch < 1 || n_batch > HERMES_MAX_BINS)
+                return fail(HERMES_ERR_ARG, "hermes_workspace_size: ZETA needs 1..64 bins");
+            *bytes = zeta_workspace(n_grid, n_batch);
+            return HERMES_OK;
+        default:
+            return fail(HERMES_ERR_ARG, "hermes_workspace_size: unknown op");
+    }
+}
+
+hermes_status hermes_assign(hermes_ctx ctx, const float* pos, const float* weight, int64_t n_pts,
+                            double box_L, int n_grid, int dtype, void* eps, double* sum_w,
+                            hipStream_t stream) {
+    if (!ctx || !eps || !sum_w || (n_pts > 0 && !pos))
+        return fail(HERMES_ERR_ARG, "hermes_assign: NULL argument");
+    if (n_pts < 0) return fail(HERMES_ERR_ARG, "hermes_assign: n_pts < 0");
+    if (!(box_L > 0.0)) return fail(HERMES_ERR_ARG, "hermes_assign: box_L must be > 0");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_assign: N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_assign: bad dtype");
+    DeviceGuard g(ctx->device);
+    return assign_impl(ctx, pos, weight, n_pts, box_L, n_grid, dtype, eps, sum_w, stream);
+}
+
+hermes_status hermes_fft(hermes_ctx ctx, const void* eps, const double* sum_w, int n_grid, int dtype,
+                         void* delta_k, void* delta, hipStream_t stream) {
+    if (!ctx || !eps || !sum_w || !delta_k) return fail(HERMES_ERR_ARG, "hermes_fft: NULL argument");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_fft: N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_fft: bad dtype");
+    DeviceGuard g(ctx->device);
+    return fft_impl(ctx, eps, sum_w, n_grid, dtype, delta_k, delta, stream);
+}
+
+hermes_status hermes_xi(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype, double box_L,
+                        const double* edges, int n_bins, const int* ells, int n_ells, int los_axis,
+                        double* xi, void* work, size_t work_bytes, hipStream_t stream) {
+    if (!ctx || !delta_k || !xi || !ells || !work) return fail(HERMES_ERR_ARG, "hermes_xi: NULL argument");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_xi: N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_xi: bad dtype");
+    if (!(box_L > 0.0)) return fail(HERMES_ERR_ARG, "hermes_xi: box_L must be > 0");
+    if (los_axis < 0 || los_axis > 2) return fail(HERMES_ERR_ARG, "hermes_xi: los_axis must be 0, 1 or 2");
+    if (n_ells < 1 || n_ells > HERMES_MAX_ELLS) return fail(HERMES_ERR_ARG, "hermes_xi: n_ells must be in [1, 8]");
+    for (int i = 0; i < n_ells; ++i)
+        if (ells[i] < 0 || ells[i] > HERMES_MAX_LMAX || (ells[i] & 1))
+            return fail(HERMES_ERR_ARG, "hermes_xi: multipoles must be even and in [0, 16]");
+    Edges e;
+    hermes_status st = get_edges(edges, n_bins, e, "hermes_xi");
+    if (st != HERMES_OK) return st;
+    if (work_bytes < xi_workspace(n_grid, n_ells, n_bins))
+        return fail(HERMES_ERR_OOM, "hermes_xi: workspace too small");
+    DeviceGuard g(ctx->device);
+    return xi_impl(ctx, delta_k, n_grid, dtype, box_L, e, ells, n_ells, los_axis, xi, work, work_bytes, stream);
+}
+
+hermes_status hermes_filter_bins(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype,
+                                 double box_L, const hermes_window* win, int n_win, void* out,
+                                 double* moments, void* work, size_t work_bytes, hipStream_t stream) {
+    if (!ctx || !delta_k || !win || !work) return fail(HERMES_ERR_ARG, "hermes_filter_bins: NULL argument");
+    if (!out && !moments) return fail(HERMES_ERR_ARG, "hermes_filter_bins: out and moments both NULL");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_filter_bins: N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_filter_bins: bad dtype");
+    if (!(box_L > 0.0)) return fail(HERMES_ERR_ARG, "hermes_filter_bins: box_L must be > 0");
+    if (n_win < 1) return fail(HERMES_ERR_ARG, "hermes_filter_bins: n_win must be >= 1");
+    for (int i = 0; i < n_win; ++i) {
+        const hermes_window& w = win[i];
+        if (w.reserved != 0) return fail(HERMES_ERR_ARG, "hermes_filter_bins: reserved field must be 0");
+        switch (w.type) {
+            case HERMES_WIN_SPHERE:
+            case HERMES_WIN_GAUSS:
+                if (!(w.r_hi > 0.0)) return fail(HERMES_ERR_ARG, "hermes_filter_bins: radius must be > 0");
+                break;
+            case HERMES_WIN_SHELL:
+                if (!(w.r_lo >= 0.0 && w.r_hi > w.r_lo))
+                    return fail(HERMES_ERR_ARG, "hermes_filter_bins: shell needs 0 <= r_lo < r_hi");
+                break;
+            case HERMES_WIN_SH_SHELL:
+                if (!(w.r_lo >= 0.0 && w.r_hi > w.r_lo))
+                    return fail(HERMES_ERR_ARG, "hermes_filter_bins: shell needs 0 <= r_lo < r_hi");
+                if (w.ell < 0 || w.ell > HERMES_MAX_LMAX || w.m < -w.ell || w.m > w.ell)
+                    return fail(HERMES_ERR_ARG, "hermes_filter_bins: need 0 <= ell <= 16 and |m| <= ell");
+                break;
+            default:
+                return fail(HERMES_ERR_ARG, "hermes_filter_bins: unknown window type");
+        }
+    }
+    if (work_bytes < filter_workspace(n_grid, dtype, n_win))
+        return fail(HERMES_ERR_OOM, "hermes_filter_bins: workspace too small");
+    DeviceGuard g(ctx->device);
+    return filter_impl(ctx, delta_k, n_grid, dtype, box_L, win, n_win, out, moments, work, work_bytes, stream);
+}
+
+hermes_status hermes_zeta_l(hermes_ctx ctx, const float* delta, const void* delta_k, int n_grid,
+                            double box_L, const double* edges, int n_bins, int l_max, int precision,
+                            double* zeta, void* work, size_t work_bytes, hipStream_t stream) {
+    if (!ctx || !delta || !delta_k || !zeta || !work) return fail(HERMES_ERR_ARG, "hermes_zeta_l: NULL argument");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_zeta_l: N must be a power of two in [8, 1024]");
+    if (!(box_L > 0.0)) return fail(HERMES_ERR_ARG, "hermes_zeta_l: box_L must be > 0");
+    if (l_max < 0 || l_max > HERMES_MAX_LMAX) return fail(HERMES_ERR_ARG, "hermes_zeta_l: l_max must be in [0, 16]");
+    if (precision != HERMES_PREC_FP32 && precision != HERMES_PREC_BF16X3 && precision != HERMES_PREC_FP16X3)
+        return fail(HERMES_ERR_ARG, "hermes_zeta_l: unknown precision");
+    Edges e;
+    hermes_status st = get_edges(edges, n_bins, e, "hermes_zeta_l");
+    if (st != HERMES_OK) return st;
+    if (work_bytes < zeta_workspace(n_grid, n_bins)) return fail(HERMES_ERR_OOM, "hermes_zeta_l: workspace too small");
+    DeviceGuard g(ctx->device);
+    return zeta_impl(ctx, delta, delta_k, n_grid, box_L, e, l_max, precision, zeta, work, work_bytes, stream);
+}
+
+}  // extern "C"

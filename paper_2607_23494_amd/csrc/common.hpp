@@ -1,0 +1,80 @@
+// Internal declarations shared by the HIP translation units of libhermes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "hermes.h"
+
+namespace hermes {
+
+constexpr int kThreads = 256;      // threads per workgroup for every kernel
+constexpr int kMaxN = 1024;        // largest grid per axis
+constexpr int kTwTable = 2 * 2048; // twiddle entries: table for length L at [L, 2L)
+constexpr int kGL = 64;            // Gauss-Legendre nodes for bin-averaged j_l
+
+// Per-device constant tables owned by a context.
+struct Tables {
+    float2* tw32 = nullptr;     // exp(-2 pi i m / L) at tw[L + m], L = 1..2048 (powers of 2)
+    double2* tw64 = nullptr;
+    double* phi1d = nullptr;    // sinc^8(pi n~/N) at phi1d[N + i], i in [0, N)
+    double* gl = nullptr;       // kGL nodes then kGL weights on [-1, 1]
+};
+
+}  // namespace hermes
+
+struct hermes_ctx_s {
+    int device = 0;
+    hermes::Tables t;
+};
+
+namespace hermes {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+hermes_status fail(hermes_status st, const std::string& msg);
+hermes_status check_launch(const char* what);
+
+inline bool valid_n(int n) { return n >= 8 && n <= kMaxN && (n & (n - 1)) == 0; }
+
+// ---------------------------------------------------------------- types
+template <typename T> struct cplx_of;
+template <> struct cplx_of<float> { using type = float2; };
+template <> struct cplx_of<double> { using type = double2; };
+
+template <typename T> struct tw_of;
+
+// Bin edges passed by value to kernels.
+struct Edges {
+    double e[HERMES_MAX_BINS + 1];
+    int n_bins;
+};
+
+// Workspace layout helpers (bytes, 256-aligned).
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+inline int64_t qmax_of(int n) { return 3LL * (n / 2) * (n / 2); }
+
+// ---------------------------------------------------------------- entry points
+// (implemented per translation unit, dispatched by dtype / N)
+hermes_status assign_impl(hermes_ctx ctx, const float* pos, const float* weight, int64_t n_pts,
+                          double box_L, int n, int dtype, void* eps, double* sum_w,
+                          hipStream_t stream);
+hermes_status fft_impl(hermes_ctx ctx, const void* eps, const double* sum_w, int n, int dtype,
+                       void* delta_k, void* delta, hipStream_t stream);
+hermes_status xi_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype, double box_L,
+                      const Edges& edges, const int* ells, int n_ells, int los_axis, double* xi,
+                      void* work, size_t work_bytes, hipStream_t stream);
+size_t xi_workspace(int n, int n_ells, int n_bins);
+hermes_status filter_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype, double box_L,
+                          const hermes_window* win, int n_win, void* out, double* moments,
+                          void* work, size_t work_bytes, hipStream_t stream);
+size_t filter_workspace(int n, int dtype, int n_win);
+hermes_status zeta_impl(hermes_ctx ctx, const float* delta, const void* delta_k, int n,
+                        double box_L, const Edges& edges, int l_max, int precision, double* zeta,
+                        void* work, size_t work_bytes, hipStream_t stream);
+size_t zeta_workspace(int n, int n_bins);
+
+}  // namespace hermes

@@ -1,0 +1,147 @@
+// Workgroup-level Stockham FFT on lines held in LDS.
+//
+// A workgroup of kThreads threads transforms `nlines` lines of length L
+// (power of two) stored line-major in LDS with a pitch of LP complex
+// elements.  Each radix-R stage (R = 8, then 4 or 2 for the remainder) reads
+// every butterfly's R inputs into registers, synchronises, then writes the
+// outputs in self-sorting (Stockham) order, so the result is in natural
+// order in place and no second buffer is needed.  Twiddles come from a table
+// tw[L + m] = exp(-2 pi i m / L) built in float64 on the host; the inverse
+// transform conjugates them (unnormalised, e^{+2 pi i}).
+#pragma once
+
+#include "common.hpp"
+
+namespace hermes {
+
+template <typename C> __device__ __forceinline__ C c_add(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C c_sub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C c_mul(C a, C b) {
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C> __device__ __forceinline__ C c_conj(C a) { return C{a.x, -a.y}; }
+template <typename C, typename T> __device__ __forceinline__ C c_scale(C a, T s) { return C{a.x * s, a.y * s}; }
+
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename C> __device__ __forceinline__ C c_rot(C a) {
+    return INV ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+
+template <typename C> struct real_of;
+template <> struct real_of<float2> { using type = float; };
+template <> struct real_of<double2> { using type = double; };
+
+template <bool INV, typename C>
+__device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
+    const C s02 = c_add(a0, a2), d02 = c_sub(a0, a2);
+    const C s13 = c_add(a1, a3), d13 = c_rot<INV>(c_sub(a1, a3));
+    a0 = c_add(s02, s13);
+    a2 = c_sub(s02, s13);
+    a1 = c_add(d02, d13);
+    a3 = c_sub(d02, d13);
+}
+
+template <bool INV, int R, typename C>
+__device__ __forceinline__ void butterfly(C* v) {
+    using T = typename real_of<C>::type;
+    if constexpr (R == 2) {
+        const C t = v[0];
+        v[0] = c_add(t, v[1]);
+        v[1] = c_sub(t, v[1]);
+    } else if constexpr (R == 4) {
+        dft4<INV>(v[0], v[1], v[2], v[3]);
+    } else {
+        static_assert(R == 8, "radix");
+        const T h = T(0.70710678118654752440084436210484903928);
+        C a0 = c_add(v[0], v[4]), a1 = c_add(v[1], v[5]);
+        C a2 = c_add(v[2], v[6]), a3 = c_add(v[3], v[7]);
+        C b0 = c_sub(v[0], v[4]);
+        C d1 = c_sub(v[1], v[5]);
+        C d2 = c_sub(v[2], v[6]);
+        C d3 = c_sub(v[3], v[7]);
+        C b1, b3;
+        if (!INV) {   // times e^{-i pi/4}, e^{-3 i pi/4}
+            b1 = C{(d1.x + d1.y) * h, (d1.y - d1.x) * h};
+            b3 = C{(d3.y - d3.x) * h, -(d3.x + d3.y) * h};
+        } else {      // times e^{+i pi/4}, e^{+3 i pi/4}
+            b1 = C{(d1.x - d1.y) * h, (d1.x + d1.y) * h};
+            b3 = C{-(d3.x + d3.y) * h, (d3.x - d3.y) * h};
+        }
+        C b2 = c_rot<INV>(d2);
+        dft4<INV>(a0, a1, a2, a3);
+        dft4<INV>(b0, b1, b2, b3);
+        v[0] = a0; v[2] = a1; v[4] = a2; v[6] = a3;
+        v[1] = b0; v[3] = b1; v[5] = b2; v[7] = b3;
+    }
+}
+
+template <int REM> struct radix_for {
+    static constexpr int value = (REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : 2);
+};
+
+// One Stockham stage with current sub-transform length NS.
+template <typename C, int L, int LP, int MAXLINES, int NS, bool INV>
+__device__ __forceinline__ void fft_stage(C* s, const C* __restrict__ tw, int nlines) {
+    constexpr int R = radix_for<L / NS>::value;
+    constexpr int PER = L / R;
+    constexpr int MAXB = MAXLINES * PER;
+    constexpr int BPT = (MAXB + kThreads - 1) / kThreads;
+    constexpr int TWS = L / (NS * R);
+    const int total = nlines * PER;
+    C v[BPT][R];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = threadIdx.x + i * kThreads;
+        if (b < total) {
+            const int line = b / PER, j = b - line * PER;
+            const C* src = s + line * LP + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = src[r * PER];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = threadIdx.x + i * kThreads;
+        if (b < total) {
+            const int line = b / PER, j = b - line * PER;
+            const int k = j & (NS - 1);
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = tw[L + r * k * TWS];
+                    if (INV) w.y = -w.y;
+                    v[i][r] = c_mul(v[i][r], w);
+                }
+            }
+            butterfly<INV, R>(v[i]);
+            C* dst = s + line * LP + (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r * NS] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename C, int L, int LP, int MAXLINES, int NS, bool INV>
+__device__ __forceinline__ void fft_stages(C* s, const C* __restrict__ tw, int nlines) {
+    if constexpr (NS < L) {
+        constexpr int R = radix_for<L / NS>::value;
+        fft_stage<C, L, LP, MAXLINES, NS, INV>(s, tw, nlines);
+        fft_stages<C, L, LP, MAXLINES, NS * R, INV>(s, tw, nlines);
+    }
+}
+
+// In-place FFT of nlines (<= MAXLINES) lines.  Begins with a barrier so the
+// caller's LDS writes are visible; ends with one so results are readable.
+template <typename C, int L, int LP, int MAXLINES, bool INV>
+__device__ __forceinline__ void lds_fft(C* s, const C* __restrict__ tw, int nlines) {
+    __syncthreads();
+    fft_stages<C, L, LP, MAXLINES, 1, INV>(s, tw, nlines);
+}
+
+// ---------------------------------------------------------------- mode helpers
+// signed mode index of array index i on an axis of length N (Nyquist -> +N/2)
+template <int N> __device__ __forceinline__ int signed_mode(int i) { return i <= N / 2 ? i : i - N; }
+
+}  // namespace hermes

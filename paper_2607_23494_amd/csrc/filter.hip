@@ -1,0 +1,567 @@
+// Batched window filtering and the 3PCF multipole contraction.
+//
+// For a batch of nb windows that share one angular factor A(k^) (1 for the
+// isotropic windows, 4 pi i^l Y^R_lm(k^) for the multipole windows of
+// Sec. 3.3.3 Eq. multipole-window), each filtered field is
+//   f_b = iDFT[ delta^ Phi^ A R_b(|k|) ]      (Sec. 4.2, K_W = W^ Phi^)
+// and the three inverse passes are:
+//   X  (k_win_x):  read delta^ once per tile, form delta^ Phi^ A / N^3 in
+//                  registers, then for every window multiply by the radial
+//                  factor R_b(q) (exact table over q = |n~|^2), inverse FFT
+//                  along x in LDS and write the batch spectrum b;
+//   Y  (k_c2c_strided): inverse FFT along y of all nb spectra in place;
+//   Z  (k_c2r_z):  c2r along z for all nb windows of a row group at once and
+//                  a fused epilogue: either the counts-in-cells moments (and
+//                  optionally the stored fields), or the contraction
+//                  sum_x delta(x) f_b1(x) f_b2(x) of the 3PCF (Sec. 3.4,
+//                  Eq. particle_nfold with a naked primary vertex).
+// Grid-wide sums are accumulated in float32 over a row group (<= 1024 cells)
+// and in float64 across groups and workgroups.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "fft_kernels.hpp"
+#include "kernels.hpp"
+#include "special.hpp"
+
+namespace hermes {
+
+constexpr int kMaxBatch = 32;        // windows per batch (registers of the epilogues)
+constexpr int kFilterChunk = 8;      // windows per workspace batch in hermes_filter_bins
+constexpr int kZGroups = 1024;       // persistent workgroups of the z pass
+
+struct WinSet {
+    int type[kMaxBatch];
+    int ell[kMaxBatch];
+    int out[kMaxBatch];              // destination index of each window
+    double lo[kMaxBatch];
+    double hi[kMaxBatch];
+    int n;
+};
+
+template <int N> struct zrows {
+    static constexpr int M = N / 2;
+    static constexpr int R = M >= 256 ? 1 : 256 / M;   // rows per group
+    static constexpr int LP = M + 1;
+};
+
+template <typename T, int N>
+constexpr size_t z_lds_bytes(int nb) {
+    using C = typename cplx_of<T>::type;
+    constexpr int R = zrows<N>::R, LP = zrows<N>::LP;
+    const size_t lines = size_t(nb) * R * LP * sizeof(C) + size_t(R) * N * sizeof(T);
+    const size_t red = size_t(kThreads) * 16 * sizeof(double);
+    return lines > red ? lines : red;
+}
+
+// Largest batch whose z-pass tile fits the LDS budget.
+template <typename T, int N>
+constexpr int z_max_batch() {
+    int nb = kMaxBatch;
+    while (nb > 1 && z_lds_bytes<T, N>(nb) > size_t(kLdsBudget)) --nb;
+    return nb;
+}
+
+inline int z_max_batch_rt(int n, bool dbl) {
+#define HERMES_ZMB(NN) \
+    case NN:           \
+        return dbl ? z_max_batch<double, NN>() : z_max_batch<float, NN>();
+    switch (n) {
+        HERMES_ZMB(8)
+        HERMES_ZMB(16)
+        HERMES_ZMB(32)
+        HERMES_ZMB(64)
+        HERMES_ZMB(128)
+        HERMES_ZMB(256)
+        HERMES_ZMB(512)
+        HERMES_ZMB(1024)
+    }
+#undef HERMES_ZMB
+    return 1;
+}
+
+inline size_t spec_bytes(int n, bool dbl) {
+    return size_t(n) * n * (n / 2 + 1) * (dbl ? 16 : 8);
+}
+
+// ---------------------------------------------------------------- radial table
+// tab[q * nb + b] = R_b(k_q), k_q = kfac sqrt(q), evaluated in float64.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_radial(T* __restrict__ tab, int64_t nq, WinSet ws, double kfac,
+                                                     const double* __restrict__ gl) {
+    const int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (q >= nq) return;
+    const double k = kfac * sqrt(double(q));
+    for (int b = 0; b < ws.n; ++b) {
+        double v;
+        switch (ws.type[b]) {
+            case HERMES_WIN_SHELL: v = w_shell(k, ws.lo[b], ws.hi[b]); break;
+            case HERMES_WIN_SPHERE: v = w_sphere(k * ws.hi[b]); break;
+            case HERMES_WIN_GAUSS: v = exp(-0.5 * (k * ws.hi[b]) * (k * ws.hi[b])); break;
+            default: v = jbar(ws.ell[b], k, ws.lo[b], ws.hi[b], gl); break;
+        }
+        tab[q * ws.n + b] = T(v);
+    }
+}
+
+// ---------------------------------------------------------------- pass X
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_win_x(const typename cplx_of<T>::type* __restrict__ dk,
+                                                    typename cplx_of<T>::type* __restrict__ out,
+                                                    int64_t bin_stride, int nb, const T* __restrict__ rtab,
+                                                    int sh, int ell, int m, double sre, double sim,
+                                                    const double* __restrict__ phi1d,
+                                                    const typename cplx_of<T>::type* __restrict__ tw) {
+    using C = typename cplx_of<T>::type;
+    constexpr int M = N / 2, P = M + 1;
+    constexpr int LP = strided_cfg<T, N>::LP, TC = strided_cfg<T, N>::TC;
+    constexpr int EL = TC * N;
+    constexpr int EPT = (EL + kThreads - 1) / kThreads;
+    constexpr int64_t PLANE = int64_t(N) * P;
+    __shared__ C s[TC * LP];
+    const int c0 = blockIdx.x * TC;
+    const int nc = min(TC, int(PLANE) - c0);
+    C base[EPT];
+    int qv[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        const int col = e % TC, kx = e / TC;
+        base[i] = C{T(0), T(0)};
+        qv[i] = 0;
+        if (e < EL && col < nc) {
+            const int c = c0 + col;
+            const int ky = c / P, kz = c - ky * P;
+            const C v = dk[int64_t(kx) * PLANE + c];
+            const int sx = signed_mode<N>(kx), sy = signed_mode<N>(ky);
+            qv[i] = sx * sx + sy * sy + kz * kz;
+            double f = phi1d[N + kx] * phi1d[N + ky] * phi1d[N + kz];
+            if (sh) f *= ylm_mode(ell, m, sx, sy, kz, kx == M, ky == M, kz == M);
+            const double re = double(v.x) * sre - double(v.y) * sim;
+            const double im = double(v.x) * sim + double(v.y) * sre;
+            base[i] = C{T(re * f), T(im * f)};
+        }
+    }
+    for (int b = 0; b < nb; ++b) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            const int col = e % TC, kx = e / TC;
+            if (e < EL && col < nc) {
+                const T r = rtab[int64_t(qv[i]) * nb + b];
+                s[col * LP + kx] = C{base[i].x * r, base[i].y * r};
+            }
+        }
+        lds_fft<C, N, LP, TC, true>(s, tw, nc);
+        C* ob = out + b * bin_stride + c0;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            const int col = e % TC, kx = e / TC;
+            if (e < EL && col < nc) ob[int64_t(kx) * PLANE + col] = s[col * LP + kx];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- pass Z
+enum { EPI_MOMENTS = 0, EPI_CONTRACT = 1 };
+
+// c2r along z of nb windows x R rows, then the epilogue.  Dynamic LDS:
+// lines [nb][R][LP] complex, then the delta rows [R][N] (contraction).
+template <typename T, int N, int EPI>
+__global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::type* __restrict__ spec,
+                                                    int64_t bin_stride, int nb, const T* __restrict__ delta,
+                                                    T* __restrict__ out, WinSet map,
+                                                    double* __restrict__ part,
+                                                    const typename cplx_of<T>::type* __restrict__ tw) {
+    using C = typename cplx_of<T>::type;
+    constexpr int M = N / 2, P = M + 1;
+    constexpr int R = zrows<N>::R, LP = zrows<N>::LP;
+    constexpr int CELLS = R * N;
+    constexpr int GROUPS = N * N / R;
+    constexpr int MAXLINES = z_max_batch<T, N>() * R;
+    extern __shared__ double lds_raw[];
+    C* s = reinterpret_cast<C*>(lds_raw);
+    T* sf = reinterpret_cast<T*>(lds_raw);
+    T* sd = reinterpret_cast<T*>(s + nb * R * LP);
+    const int nlines = nb * R;
+
+    // epilogue thread roles
+    // contraction: 4x4 bin tiles (I <= J), CG cell groups
+    const int nt4 = (nb + 3) / 4;
+    const int ntp = nt4 * (nt4 + 1) / 2;
+    const int cg_n = kThreads / ntp;
+    const int tp = threadIdx.x % ntp, cg = threadIdx.x / ntp;
+    int ti = 0, tj = 0;
+    {
+        int idx = tp;
+        for (int I = 0; I < nt4; ++I) {
+            if (idx < nt4 - I) {
+                ti = I;
+                tj = I + idx;
+                break;
+            }
+            idx -= nt4 - I;
+        }
+    }
+    // moments: one window per thread, SUBS cell groups
+    const int subs = kThreads / nb;
+    const int mb = threadIdx.x % nb, msub = threadIdx.x / nb;
+
+    double acc64[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc64[i] = 0.0;
+
+    for (int g = blockIdx.x; g < GROUPS; g += gridDim.x) {
+        const int64_t row0 = int64_t(g) * R;
+        // load the half-spectrum rows of every window
+        for (int e = threadIdx.x; e < nlines * P; e += kThreads) {
+            const int line = e / P, k = e - line * P;
+            const int b = line / R, r = line - b * R;
+            s[line * LP + k] = spec[b * bin_stride + (row0 + r) * P + k];
+        }
+        if (EPI == EPI_CONTRACT)
+            for (int e = threadIdx.x; e < CELLS; e += kThreads) sd[e] = delta[row0 * N + e];
+        __syncthreads();
+        // c2r packing, in place by (k, M-k) pairs:
+        //   Z[k] = (X[k] + X*[M-k]) + i e^{+2 pi i k/N} (X[k] - X*[M-k])
+        for (int e = threadIdx.x; e < nlines * (M / 2 + 1); e += kThreads) {
+            const int line = e / (M / 2 + 1), k = e - line * (M / 2 + 1);
+            C* L = s + line * LP;
+            const C xk = L[k], xm = L[M - k];
+            {
+                const C sum{xk.x + xm.x, xk.y - xm.y};
+                const C dif{xk.x - xm.x, xk.y + xm.y};
+                const C w = c_conj(tw[N + k]);
+                const C t = c_mul(w, dif);
+                L[k] = C{sum.x - t.y, sum.y + t.x};
+            }
+            if (k > 0 && k < M - k) {
+                const C sum{xm.x + xk.x, xm.y - xk.y};
+                const C dif{xm.x - xk.x, xm.y + xk.y};
+                const C w = c_conj(tw[N + M - k]);
+                const C t = c_mul(w, dif);
+                L[M - k] = C{sum.x - t.y, sum.y + t.x};
+            }
+        }
+        lds_fft<C, M, LP, MAXLINES, true>(s, tw, nlines);
+        // real value of window b, row r, z: sf[2 * (b * R + r) * LP + z]
+        if (EPI == EPI_CONTRACT) {
+            if (cg < cg_n) {
+                float acc[4][4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[a][c] = 0.f;
+                for (int cell = cg; cell < CELLS; cell += cg_n) {
+                    const int r = cell / N, z = cell - r * N;
+                    const float d = float(sd[cell]);
+                    float xa[4], xb[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int b1 = 4 * ti + a, b2 = 4 * tj + a;
+                        xa[a] = b1 < nb ? float(sf[2 * (b1 * R + r) * LP + z]) * d : 0.f;
+                        xb[a] = b2 < nb ? float(sf[2 * (b2 * R + r) * LP + z]) : 0.f;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(xa[a], xb[c], acc[a][c]);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc64[a * 4 + c] += double(acc[a][c]);
+            }
+        } else {
+            if (out) {
+                for (int e = threadIdx.x; e < nb * CELLS; e += kThreads) {
+                    const int b = e / CELLS, rem = e - b * CELLS;
+                    const int r = rem / N, z = rem - r * N;
+                    out[int64_t(map.out[b]) * N * N * N + (row0 + r) * N + z] = sf[2 * (b * R + r) * LP + z];
+                }
+            }
+            if (part && msub < subs) {
+                T s2 = 0, s3 = 0, s4 = 0;
+                for (int cell = msub; cell < CELLS; cell += subs) {
+                    const int r = cell / N, z = cell - r * N;
+                    const T v = sf[2 * (mb * R + r) * LP + z];
+                    const T v2 = v * v;
+                    s2 += v2;
+                    s3 += v2 * v;
+                    s4 += v2 * v2;
+                }
+                acc64[0] += double(s2);
+                acc64[1] += double(s3);
+                acc64[2] += double(s4);
+            }
+        }
+        __syncthreads();
+    }
+
+    // workgroup reduction of the float64 partial sums
+    double* red = lds_raw;
+    if (EPI == EPI_CONTRACT) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) red[threadIdx.x * 16 + i] = acc64[i];
+        __syncthreads();
+        if (threadIdx.x < ntp) {
+            double sum[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) sum[i] = 0.0;
+            for (int c = 0; c < cg_n; ++c)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) sum[i] += red[(c * ntp + threadIdx.x) * 16 + i];
+            double* dst = part + int64_t(blockIdx.x) * nb * nb;
+            for (int a = 0; a < 4; ++a)
+                for (int c = 0; c < 4; ++c) {
+                    const int b1 = 4 * ti + a, b2 = 4 * tj + c;
+                    if (b1 < nb && b2 < nb) {
+                        dst[b1 * nb + b2] = sum[a * 4 + c];
+                        dst[b2 * nb + b1] = sum[a * 4 + c];
+                    }
+                }
+        }
+    } else if (part) {
+        for (int i = 0; i < 3; ++i) red[threadIdx.x * 3 + i] = acc64[i];
+        __syncthreads();
+        if (threadIdx.x < nb) {
+            double sum[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < subs; ++c)
+                for (int i = 0; i < 3; ++i) sum[i] += red[(c * nb + threadIdx.x) * 3 + i];
+            double* dst = part + (int64_t(blockIdx.x) * nb + threadIdx.x) * 3;
+            for (int i = 0; i < 3; ++i) dst[i] = sum[i];
+        }
+    }
+}
+
+// dst[i] (+)= scale * sum_g part[g * n + i]
+__global__ void k_reduce_part(const double* __restrict__ part, int ngroups, int n, double scale,
+                              double* __restrict__ dst, int accumulate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int g = 0; g < ngroups; ++g) s += part[int64_t(g) * n + i];
+    dst[i] = (accumulate ? dst[i] : 0.0) + scale * s;
+}
+
+// moments[map.out[b]][p] = scale * sum_g part[g][b][p]
+__global__ void k_reduce_moments(const double* __restrict__ part, int ngroups, WinSet map, double scale,
+                                 double* __restrict__ moments) {
+    const int i = threadIdx.x;
+    if (i >= map.n * 3) return;
+    double s = 0.0;
+    for (int g = 0; g < ngroups; ++g) s += part[int64_t(g) * map.n * 3 + i];
+    moments[map.out[i / 3] * 3 + i % 3] = scale * s;
+}
+
+template <typename KernelT>
+inline void allow_lds(KernelT kernel, size_t bytes) {
+    if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+// One batch: pass X, Y, Z over nb windows sharing the angular factor.
+template <typename T, int N, int EPI>
+static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, double box_L, const WinSet& ws, int sh,
+                      int ell, int m, bool build_table, void* spec_ws, T* rtab, double* part, T* out,
+                      hipStream_t stream) {
+    using C = typename cplx_of<T>::type;
+    constexpr int P = N / 2 + 1;
+    constexpr int TC = strided_cfg<T, N>::TC;
+    const C* tw = tw_ptr<T>(ctx->t);
+    const int nb = ws.n;
+    const int64_t nq = qmax_of(N) + 1;
+    const int64_t plane = int64_t(N) * P;
+    const int64_t bin_stride = int64_t(N) * plane;
+    if (build_table)
+        hipLaunchKernelGGL((k_radial<T>), dim3((nq + kThreads - 1) / kThreads), dim3(kThreads), 0, stream, rtab, nq,
+                           ws, 2.0 * M_PI / box_L, ctx->t.gl);
+    // scale: angular constant times 1/N^3 (inverse DFT normalisation)
+    const double inv = 1.0 / (double(N) * N * N);
+    double sre = inv, sim = 0.0;
+    if (sh) {
+        const double f = 4.0 * M_PI * inv;
+        switch (ell & 3) {
+            case 0: sre = f; break;
+            case 1: sre = 0.0; sim = f; break;
+            case 2: sre = -f; break;
+            default: sre = 0.0; sim = -f; break;
+        }
+    }
+    C* sp = static_cast<C*>(spec_ws);
+    hipLaunchKernelGGL((k_win_x<T, N>), dim3((plane + TC - 1) / TC), dim3(kThreads), 0, stream,
+                       static_cast<const C*>(delta_k), sp, bin_stride, nb, rtab, sh, ell, m, sre, sim,
+                       ctx->t.phi1d, tw);
+    launch_c2c_strided<T, N, true>(sp, nb * N, plane, P, P, false, tw, stream);
+    const size_t lds = z_lds_bytes<T, N>(nb);
+    allow_lds(k_c2r_z<T, N, EPI>, lds);
+    constexpr int GROUPS = N * N / zrows<N>::R;
+    const int grid = GROUPS < kZGroups ? GROUPS : kZGroups;
+    hipLaunchKernelGGL((k_c2r_z<T, N, EPI>), dim3(grid), dim3(kThreads), lds, stream, sp, bin_stride, nb, delta,
+                       out, ws, part, tw);
+}
+
+template <int N>
+constexpr int z_grid() {
+    return (N * N / zrows<N>::R) < kZGroups ? (N * N / zrows<N>::R) : kZGroups;
+}
+
+inline int z_grid_rt(int n) {
+    const int groups = n * n / (n / 2 >= 256 ? 1 : 256 / (n / 2));
+    return groups < kZGroups ? groups : kZGroups;
+}
+
+// ---------------------------------------------------------------- filter_bins
+size_t filter_workspace(int n, int dtype, int n_win) {
+    const bool dbl = dtype == HERMES_F64;
+    const int chunk = std::min({n_win, kFilterChunk, z_max_batch_rt(n, dbl)});
+    const size_t nq = size_t(qmax_of(n) + 1);
+    return align256(spec_bytes(n, dbl) * chunk) + align256(nq * chunk * (dbl ? 8 : 4)) +
+           align256(size_t(z_grid_rt(n)) * chunk * 3 * sizeof(double));
+}
+
+template <typename T, int N>
+static hermes_status filter_n(hermes_ctx ctx, const void* delta_k, double box_L, const hermes_window* win, int n_win,
+                              void* out, double* moments, void* work, hipStream_t stream) {
+    const bool dbl = sizeof(T) == 8;
+    const int chunk = std::min({n_win, kFilterChunk, z_max_batch<T, N>()});
+    const size_t nq = size_t(qmax_of(N) + 1);
+    char* w = static_cast<char*>(work);
+    void* spec = w;
+    T* rtab = reinterpret_cast<T*>(w + align256(spec_bytes(N, dbl) * chunk));
+    double* part = reinterpret_cast<double*>(w + align256(spec_bytes(N, dbl) * chunk) + align256(nq * chunk * sizeof(T)));
+    // group windows by angular factor: isotropic ones together, SH ones by (l, m)
+    struct Key {
+        int sh, ell, m;
+    };
+    std::vector<int> order(n_win);
+    for (int i = 0; i < n_win; ++i) order[i] = i;
+    auto key = [&](int i) {
+        const hermes_window& x = win[i];
+        return x.type == HERMES_WIN_SH_SHELL ? Key{1, x.ell, x.m} : Key{0, 0, 0};
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const Key ka = key(a), kb = key(b);
+        if (ka.sh != kb.sh) return ka.sh < kb.sh;
+        if (ka.ell != kb.ell) return ka.ell < kb.ell;
+        return ka.m < kb.m;
+    });
+    const double inv_nc = 1.0 / (double(N) * N * N);
+    const int grid = z_grid<N>();
+    size_t i = 0;
+    while (i < order.size()) {
+        const Key k0 = key(order[i]);
+        WinSet ws{};
+        ws.n = 0;
+        while (i < order.size() && ws.n < chunk) {
+            const Key k = key(order[i]);
+            if (k.sh != k0.sh || k.ell != k0.ell || k.m != k0.m) break;
+            const hermes_window& x = win[order[i]];
+            ws.type[ws.n] = x.type;
+            ws.ell[ws.n] = x.ell;
+            ws.lo[ws.n] = x.r_lo;
+            ws.hi[ws.n] = x.r_hi;
+            ws.out[ws.n] = order[i];
+            ++ws.n;
+            ++i;
+        }
+        run_batch<T, N, EPI_MOMENTS>(ctx, delta_k, nullptr, box_L, ws, k0.sh, k0.ell, k0.m, true, spec, rtab,
+                                     moments ? part : nullptr, static_cast<T*>(out), stream);
+        if (moments)
+            hipLaunchKernelGGL(k_reduce_moments, dim3(1), dim3(kThreads), 0, stream, part, grid, ws, inv_nc, moments);
+    }
+    return check_launch("hermes_filter_bins");
+}
+
+hermes_status filter_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype, double box_L,
+                          const hermes_window* win, int n_win, void* out, double* moments, void* work, size_t,
+                          hipStream_t stream) {
+#define HERMES_FILTER_CASE(NN)                                                                                   \
+    case NN:                                                                                                     \
+        return dtype == HERMES_F32                                                                               \
+                   ? filter_n<float, NN>(ctx, delta_k, box_L, win, n_win, out, moments, work, stream)          \
+                   : filter_n<double, NN>(ctx, delta_k, box_L, win, n_win, out, moments, work, stream);
+    switch (n) {
+        HERMES_FILTER_CASE(8)
+        HERMES_FILTER_CASE(16)
+        HERMES_FILTER_CASE(32)
+        HERMES_FILTER_CASE(64)
+        HERMES_FILTER_CASE(128)
+        HERMES_FILTER_CASE(256)
+        HERMES_FILTER_CASE(512)
+        HERMES_FILTER_CASE(1024)
+        default:
+            return fail(HERMES_ERR_ARG, "hermes_filter_bins: unsupported N");
+    }
+#undef HERMES_FILTER_CASE
+}
+
+// ---------------------------------------------------------------- zeta_l
+size_t zeta_workspace(int n, int n_bins) {
+    const size_t nq = size_t(qmax_of(n) + 1);
+    return align256(spec_bytes(n, false) * n_bins) + align256(nq * n_bins * sizeof(float)) +
+           align256(size_t(z_grid_rt(n)) * n_bins * n_bins * sizeof(double));
+}
+
+template <int N>
+static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delta_k, double box_L,
+                            const Edges& edges, int l_max, int precision, double* zeta, void* work,
+                            hipStream_t stream) {
+    const int nb = edges.n_bins;
+    if (nb > z_max_batch<float, N>())
+        return fail(HERMES_ERR_UNSUPPORTED, "hermes_zeta_l: too many radial bins for this grid size");
+    if (precision != HERMES_PREC_FP32)
+        return fail(HERMES_ERR_UNSUPPORTED, "hermes_zeta_l: mixed-precision contraction not available");
+    const size_t nq = size_t(qmax_of(N) + 1);
+    char* w = static_cast<char*>(work);
+    void* spec = w;
+    float* rtab = reinterpret_cast<float*>(w + align256(spec_bytes(N, false) * nb));
+    double* part = reinterpret_cast<double*>(w + align256(spec_bytes(N, false) * nb) + align256(nq * nb * sizeof(float)));
+    const int grid = z_grid<N>();
+    const double scale = 1.0 / (4.0 * M_PI * double(N) * N * N);
+    launch_fill<double>(zeta, int64_t(l_max + 1) * nb * nb, 0.0, stream);
+    for (int ell = 0; ell <= l_max; ++ell) {
+        WinSet ws{};
+        ws.n = nb;
+        for (int b = 0; b < nb; ++b) {
+            ws.type[b] = HERMES_WIN_SH_SHELL;
+            ws.ell[b] = ell;
+            ws.lo[b] = edges.e[b];
+            ws.hi[b] = edges.e[b + 1];
+            ws.out[b] = b;
+        }
+        for (int m = -ell; m <= ell; ++m) {
+            run_batch<float, N, EPI_CONTRACT>(ctx, delta_k, delta, box_L, ws, 1, ell, m, m == -ell, spec, rtab,
+                                              part, nullptr, stream);
+            hipLaunchKernelGGL(k_reduce_part, dim3((nb * nb + 127) / 128), dim3(128), 0, stream, part, grid, nb * nb,
+                               scale, zeta + int64_t(ell) * nb * nb, 1);
+        }
+    }
+    return check_launch("hermes_zeta_l");
+}
+
+hermes_status zeta_impl(hermes_ctx ctx, const float* delta, const void* delta_k, int n, double box_L,
+                        const Edges& edges, int l_max, int precision, double* zeta, void* work, size_t,
+                        hipStream_t stream) {
+#define HERMES_ZETA_CASE(NN) \
+    case NN:                 \
+        return zeta_n<NN>(ctx, delta, delta_k, box_L, edges, l_max, precision, zeta, work, stream);
+    switch (n) {
+        HERMES_ZETA_CASE(8)
+        HERMES_ZETA_CASE(16)
+        HERMES_ZETA_CASE(32)
+        HERMES_ZETA_CASE(64)
+        HERMES_ZETA_CASE(128)
+        HERMES_ZETA_CASE(256)
+        HERMES_ZETA_CASE(512)
+        HERMES_ZETA_CASE(1024)
+        default:
+            return fail(HERMES_ERR_ARG, "hermes_zeta_l: unsupported N");
+    }
+#undef HERMES_ZETA_CASE
+}
+
+}  // namespace hermes

@@ -1,0 +1,141 @@
+// 2PCF and its Legendre multipoles by Parseval (Sec. 3.3.1 Eq.
+// pair-counting-kspace; Sec. 3.3.3 DD_l).
+//
+// The radial window depends on a mode only through the integer
+// q = |n~|^2, so the sum over modes is regrouped exactly as
+//   xi_l[b] = N^-6 (2l+1) (-1)^{l/2} sum_q R_lb(q) H_l(q),
+//   H_l(q)  = sum_{|n~|^2 = q} |delta^_n|^2 Phi^(n) L_l(mu_n).
+// Pass 1 reads the half spectrum once and scatters H with float64 atomics
+// (one atomic per four sign-related modes); pass 2 evaluates R_lb(q) in
+// float64 (thick shell in closed form for l = 0, bin-averaged j_l by
+// quadrature for l > 0) and reduces.
+#include "common.hpp"
+#include "fft_core.hpp"
+#include "kernels.hpp"
+#include "special.hpp"
+
+namespace hermes {
+
+struct EllSet {
+    int l[HERMES_MAX_ELLS];
+    int n;
+};
+
+constexpr int kXiSplit = 64;   // q-range chunks per (l, bin) in pass 2
+
+size_t xi_workspace(int n, int n_ells, int n_bins) {
+    const size_t nq = size_t(qmax_of(n) + 1);
+    return align256(nq * n_ells * sizeof(double)) + align256(size_t(n_ells) * n_bins * kXiSplit * sizeof(double));
+}
+
+// One thread per representative (|kx|, |ky|, kz), kx, ky in [0, N/2]; the
+// modes (+-kx, +-ky, kz) share q and |mu| and are summed before the atomic.
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_xi_hist(const typename cplx_of<T>::type* __restrict__ dk,
+                                                      EllSet ells, int los, const double* __restrict__ phi1d,
+                                                      double* __restrict__ H, int64_t nq) {
+    constexpr int M = N / 2, P = M + 1;
+    const int64_t total = int64_t(P) * P * P;
+    const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (t >= total) return;
+    const int kz = int(t % P);
+    const int iy = int((t / P) % P);
+    const int ix = int(t / (int64_t(P) * P));
+    const int xs[2] = {ix, (N - ix) & (N - 1)};
+    const int ys[2] = {iy, (N - iy) & (N - 1)};
+    const int nx = (ix == 0 || ix == M) ? 1 : 2;
+    const int ny = (iy == 0 || iy == M) ? 1 : 2;
+    double p = 0.0;
+    for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < ny; ++b) {
+            const auto v = dk[(int64_t(xs[a]) * N + ys[b]) * P + kz];
+            p += double(v.x) * v.x + double(v.y) * v.y;
+        }
+    const int64_t q = int64_t(ix) * ix + int64_t(iy) * iy + int64_t(kz) * kz;
+    if (q == 0) return;
+    const double herm = (kz == 0 || kz == M) ? 1.0 : 2.0;
+    p *= herm * phi1d[N + ix] * phi1d[N + iy] * phi1d[N + kz];
+    const int comp = los == 0 ? ix : (los == 1 ? iy : kz);
+    const double mu = double(comp) / sqrt(double(q));
+    for (int i = 0; i < ells.n; ++i) unsafeAtomicAdd(H + int64_t(i) * nq + q, p * legendre(ells.l[i], mu));
+}
+
+__global__ __launch_bounds__(kThreads) void k_xi_sum(const double* __restrict__ H, int64_t nq, EllSet ells,
+                                                     Edges edges, double kfac, const double* __restrict__ gl,
+                                                     double* __restrict__ part) {
+    __shared__ double red[kThreads];
+    const int b = blockIdx.x, il = blockIdx.y, sp = blockIdx.z;
+    const int ell = ells.l[il];
+    const double lo = edges.e[b], hi = edges.e[b + 1];
+    const int64_t chunk = (nq + kXiSplit - 1) / kXiSplit;
+    const int64_t q0 = sp * chunk, q1 = min(nq, q0 + chunk);
+    double acc = 0.0;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += kThreads) {
+        const double h = H[int64_t(il) * nq + q];
+        if (h == 0.0) continue;
+        const double k = kfac * sqrt(double(q));
+        acc += h * (ell == 0 ? w_shell(k, lo, hi) : jbar(ell, k, lo, hi, gl));
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) part[(int64_t(il) * gridDim.x + b) * kXiSplit + sp] = s;
+}
+
+__global__ void k_xi_final(const double* __restrict__ part, EllSet ells, int n_bins, double inv_nc2,
+                           double* __restrict__ xi) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ells.n * n_bins) return;
+    const int il = i / n_bins;
+    const int ell = ells.l[il];
+    double s = 0.0;
+    for (int sp = 0; sp < kXiSplit; ++sp) s += part[int64_t(i) * kXiSplit + sp];
+    const double pref = (2 * ell + 1) * (((ell / 2) & 1) ? -1.0 : 1.0);
+    xi[i] = pref * s * inv_nc2;
+}
+
+template <typename T, int N>
+static hermes_status xi_n(hermes_ctx ctx, const void* delta_k, double box_L, const Edges& edges, const EllSet& ells,
+                          int los, double* xi, void* work, hipStream_t stream) {
+    using C = typename cplx_of<T>::type;
+    constexpr int P = N / 2 + 1;
+    const int64_t nq = qmax_of(N) + 1;
+    double* H = static_cast<double*>(work);
+    double* part = reinterpret_cast<double*>(static_cast<char*>(work) + align256(nq * ells.n * sizeof(double)));
+    launch_fill<double>(H, nq * ells.n, 0.0, stream);
+    const int64_t reps = int64_t(P) * P * P;
+    hipLaunchKernelGGL((k_xi_hist<T, N>), dim3((reps + kThreads - 1) / kThreads), dim3(kThreads), 0, stream,
+                       static_cast<const C*>(delta_k), ells, los, ctx->t.phi1d, H, nq);
+    hipLaunchKernelGGL(k_xi_sum, dim3(edges.n_bins, ells.n, kXiSplit), dim3(kThreads), 0, stream, H, nq, ells,
+                       edges, 2.0 * M_PI / box_L, ctx->t.gl, part);
+    const int n_out = ells.n * edges.n_bins;
+    const double nc = double(N) * N * N;
+    hipLaunchKernelGGL(k_xi_final, dim3((n_out + 127) / 128), dim3(128), 0, stream, part, ells, edges.n_bins,
+                       1.0 / (nc * nc), xi);
+    return check_launch("hermes_xi");
+}
+
+hermes_status xi_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype, double box_L, const Edges& edges,
+                      const int* ell_list, int n_ells, int los_axis, double* xi, void* work, size_t,
+                      hipStream_t stream) {
+    EllSet ells{};
+    ells.n = n_ells;
+    for (int i = 0; i < n_ells; ++i) ells.l[i] = ell_list[i];
+#define HERMES_XI_CASE(NN)                                                                                 \
+    case NN:                                                                                               \
+        return dtype == HERMES_F32 ? xi_n<float, NN>(ctx, delta_k, box_L, edges, ells, los_axis, xi, work, stream) \
+                                   : xi_n<double, NN>(ctx, delta_k, box_L, edges, ells, los_axis, xi, work, stream);
+    switch (n) {
+        HERMES_XI_CASE(8)
+        HERMES_XI_CASE(16)
+        HERMES_XI_CASE(32)
+        HERMES_XI_CASE(64)
+        HERMES_XI_CASE(128)
+        HERMES_XI_CASE(256)
+        HERMES_XI_CASE(512)
+        HERMES_XI_CASE(1024)
+        default:
+            return fail(HERMES_ERR_ARG, "hermes_xi: unsupported N");
+    }
+#undef HERMES_XI_CASE
+}
+
+}  // namespace hermes

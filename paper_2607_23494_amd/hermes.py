@@ -1,0 +1,236 @@
+"""Python binding of libhermes: argument marshalling over the C ABI only.
+
+Every computation runs in the library's HIP kernels.  PyTorch supplies device
+memory (tensors) and the current HIP stream.  Importing this module loads
+libhermes.so and raises ImportError if it has not been built; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Iterable, Sequence
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhermes.so")
+
+F32, F64 = 0, 1
+PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
+WIN = {"shell": 0, "sphere": 1, "gauss": 2, "sh_shell": 3}
+OP_ASSIGN, OP_FFT, OP_XI, OP_FILTER, OP_ZETA = range(5)
+MAX_BINS = 64
+
+
+class HermesError(RuntimeError):
+    """A libhermes entry point returned an error status."""
+
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libhermes status {status}: {msg}")
+        self.status = status
+
+
+class _Window(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("ell", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("r_lo", ctypes.c_double), ("r_hi", ctypes.c_double)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2607_23494_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sz = ctypes.c_size_t
+    lib.hermes_create.argtypes = [ctypes.POINTER(vp), i32]
+    lib.hermes_destroy.argtypes = [vp]
+    lib.hermes_destroy.restype = None
+    lib.hermes_last_error.restype = ctypes.c_char_p
+    lib.hermes_workspace_size.argtypes = [vp, i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
+    lib.hermes_assign.argtypes = [vp, vp, vp, i64, f64, i32, i32, vp, vp, vp]
+    lib.hermes_fft.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
+    lib.hermes_xi.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, sz, vp]
+    lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
+    lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
+    for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi",
+                 "hermes_filter_bins", "hermes_zeta_l"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+_ctx_lock = threading.Lock()
+_ctx: dict[int, ctypes.c_void_p] = {}
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise HermesError(status, _lib.hermes_last_error().decode())
+
+
+def context(device: int) -> ctypes.c_void_p:
+    """The library context of a device (created once per process)."""
+    with _ctx_lock:
+        c = _ctx.get(device)
+        if c is None:
+            c = ctypes.c_void_p()
+            _check(_lib.hermes_create(ctypes.byref(c), device))
+            _ctx[device] = c
+        return c
+
+
+def _dev(t: torch.Tensor) -> int:
+    if not t.is_cuda:
+        raise ValueError("libhermes works on device tensors only")
+    return t.device.index if t.device.index is not None else torch.cuda.current_device()
+
+
+def _stream(device: int, stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(dtype: torch.dtype) -> int:
+    if dtype in (torch.float32, torch.complex64):
+        return F32
+    if dtype in (torch.float64, torch.complex128):
+        return F64
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def _edges_arr(edges) -> np.ndarray:
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+    if e.ndim != 1 or e.size < 2:
+        raise ValueError("edges must be a 1-D array of at least two values")
+    return e
+
+
+def workspace_size(op: int, n_grid: int, dtype=torch.float32, n_batch: int = 1, n_ells: int = 1,
+                   device: int = 0) -> int:
+    b = ctypes.c_size_t()
+    _check(_lib.hermes_workspace_size(context(device), op, n_grid, _dtype_code(dtype), n_batch, n_ells,
+                                      ctypes.byref(b)))
+    return int(b.value)
+
+
+def _workspace(nbytes: int, device: int, work: torch.Tensor | None) -> torch.Tensor:
+    if work is not None:
+        if work.numel() * work.element_size() < nbytes:
+            raise ValueError("workspace tensor too small")
+        return work
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=f"cuda:{device}")
+
+
+# ----------------------------------------------------------------------------
+# entry points
+# ----------------------------------------------------------------------------
+
+def assign(pos: torch.Tensor, weight: torch.Tensor | None, box_L: float, n_grid: int,
+           dtype=torch.float32, eps: torch.Tensor | None = None, sum_w: torch.Tensor | None = None,
+           stream=None):
+    """B3 projection of a catalogue: returns (eps [N,N,N], sum_w [1] float64)."""
+    dev = _dev(pos)
+    if pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3 or not pos.is_contiguous():
+        raise ValueError("pos must be a contiguous float32 [n, 3] device tensor")
+    if weight is not None and (weight.dtype != torch.float32 or weight.numel() != pos.shape[0]
+                               or not weight.is_contiguous() or _dev(weight) != dev):
+        raise ValueError("weight must be a contiguous float32 [n] tensor on the same device")
+    if eps is None:
+        eps = torch.empty((n_grid, n_grid, n_grid), dtype=dtype, device=pos.device)
+    if sum_w is None:
+        sum_w = torch.empty(1, dtype=torch.float64, device=pos.device)
+    _check(_lib.hermes_assign(context(dev), _ptr(pos), _ptr(weight), pos.shape[0], float(box_L), n_grid,
+                              _dtype_code(eps.dtype), _ptr(eps), _ptr(sum_w), _stream(dev, stream)))
+    return eps, sum_w
+
+
+def fft(eps: torch.Tensor, sum_w: torch.Tensor, want_delta: bool = True, delta_k: torch.Tensor | None = None,
+        delta: torch.Tensor | None = None, stream=None):
+    """Contrast and forward r2c FFT: returns (delta_k [N,N,N/2+1] complex, delta or None)."""
+    dev = _dev(eps)
+    n = eps.shape[0]
+    cdt = torch.complex64 if eps.dtype == torch.float32 else torch.complex128
+    if delta_k is None:
+        delta_k = torch.empty((n, n, n // 2 + 1), dtype=cdt, device=eps.device)
+    if want_delta and delta is None:
+        delta = torch.empty_like(eps)
+    _check(_lib.hermes_fft(context(dev), _ptr(eps), _ptr(sum_w), n, _dtype_code(eps.dtype), _ptr(delta_k),
+                           _ptr(delta) if want_delta else None, _stream(dev, stream)))
+    return delta_k, (delta if want_delta else None)
+
+
+def xi(delta_k: torch.Tensor, box_L: float, edges, ells: Sequence[int] = (0,), los_axis: int = 2,
+       out: torch.Tensor | None = None, work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """2PCF multipoles by Parseval: device float64 [len(ells), n_bins]."""
+    dev = _dev(delta_k)
+    n = delta_k.shape[0]
+    e = _edges_arr(edges)
+    el = np.ascontiguousarray(np.asarray(list(ells), dtype=np.int32))
+    nb = e.size - 1
+    dt = _dtype_code(delta_k.dtype)
+    wbytes = workspace_size(OP_XI, n, delta_k.dtype, nb, el.size, dev)
+    w = _workspace(wbytes, dev, work)
+    if out is None:
+        out = torch.empty((el.size, nb), dtype=torch.float64, device=delta_k.device)
+    _check(_lib.hermes_xi(context(dev), _ptr(delta_k), n, dt, float(box_L), e.ctypes.data_as(ctypes.c_void_p), nb,
+                          el.ctypes.data_as(ctypes.c_void_p), el.size, los_axis, _ptr(out), _ptr(w), wbytes,
+                          _stream(dev, stream)))
+    return out
+
+
+def make_windows(specs: Iterable) -> ctypes.Array:
+    """specs: tuples (kind, r_lo, r_hi[, ell, m]) with kind in WIN."""
+    specs = list(specs)
+    arr = (_Window * len(specs))()
+    for i, s in enumerate(specs):
+        kind, lo, hi = s[0], s[1], s[2]
+        ell, m = (s[3], s[4]) if len(s) > 3 else (0, 0)
+        arr[i] = _Window(WIN[kind], int(ell), int(m), 0, float(lo), float(hi))
+    return arr
+
+
+def filter_bins(delta_k: torch.Tensor, box_L: float, windows, store_fields: bool = False,
+                moments: bool = True, out: torch.Tensor | None = None, work: torch.Tensor | None = None,
+                stream=None):
+    """Window-filtered fields and counts-in-cells moments.
+
+    Returns (fields [n_win,N,N,N] or None, moments [n_win,3] float64 or None).
+    """
+    dev = _dev(delta_k)
+    n = delta_k.shape[0]
+    win = make_windows(windows)
+    nw = len(win)
+    rdt = torch.float32 if delta_k.dtype == torch.complex64 else torch.float64
+    wbytes = workspace_size(OP_FILTER, n, rdt, nw, 1, dev)
+    w = _workspace(wbytes, dev, work)
+    if store_fields and out is None:
+        out = torch.empty((nw, n, n, n), dtype=rdt, device=delta_k.device)
+    mom = torch.empty((nw, 3), dtype=torch.float64, device=delta_k.device) if moments else None
+    _check(_lib.hermes_filter_bins(context(dev), _ptr(delta_k), n, _dtype_code(rdt), float(box_L), win, nw,
+                                   _ptr(out) if store_fields else None, _ptr(mom), _ptr(w), wbytes,
+                                   _stream(dev, stream)))
+    return (out if store_fields else None), mom
+
+
+def zeta_l(delta: torch.Tensor, delta_k: torch.Tensor, box_L: float, edges, l_max: int,
+           precision: str = "fp32", out: torch.Tensor | None = None, work: torch.Tensor | None = None,
+           stream=None) -> torch.Tensor:
+    """3PCF multipoles: device float64 [l_max+1, n_bins, n_bins]."""
+    dev = _dev(delta)
+    n = delta.shape[0]
+    e = _edges_arr(edges)
+    nb = e.size - 1
+    wbytes = workspace_size(OP_ZETA, n, torch.float32, nb, 1, dev)
+    w = _workspace(wbytes, dev, work)
+    if out is None:
+        out = torch.empty((l_max + 1, nb, nb), dtype=torch.float64, device=delta.device)
+    _check(_lib.hermes_zeta_l(context(dev), _ptr(delta), _ptr(delta_k), n, float(box_L),
+                              e.ctypes.data_as(ctypes.c_void_p), nb, l_max, PREC[precision], _ptr(out), _ptr(w),
+                              wbytes, _stream(dev, stream)))
+    return out
