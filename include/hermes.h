@@ -30,9 +30,10 @@
  *    stream has been synchronised.  Host arrays passed in (bin edges, window
  *    lists, multipole lists) are read before the call returns.
  *  - Errors: every entry point returns a hermes_status; on anything but
- *    HERMES_OK, hermes_last_error() returns a thread-local message and no
- *    kernel has been launched.  HERMES_ERR_HIP reports a HIP runtime error
- *    raised by a launch.
+ *    HERMES_OK, hermes_last_error() returns a thread-local message.  Argument
+ *    errors (ERR_ARG, ERR_OOM, ERR_UNSUPPORTED) are detected before any
+ *    kernel is launched; HERMES_ERR_HIP reports a HIP runtime error raised by
+ *    a launch.
  */
 #ifndef HERMES_H
 #define HERMES_H
@@ -188,6 +189,17 @@ hermes_status hermes_zeta_l(hermes_ctx ctx, const float* delta, const void* delt
                             int n_grid, double box_L, const double* edges, int n_bins,
                             int l_max, int precision, double* zeta, void* work,
                             size_t work_bytes, hipStream_t stream);
+
+/* Per-kernel timing for measurement.  While enabled, every kernel launch of
+ * this context is bracketed with HIP events recorded on its launch stream;
+ * hermes_profile_read synchronises the outstanding events and returns, for
+ * the index-th kernel class (alphabetical; ERR_ARG past the last one), its
+ * name, launch count and summed duration in milliseconds.  Reset clears the
+ * totals.  Timing adds two event records per launch. */
+hermes_status hermes_profile_enable(hermes_ctx ctx, int enable);
+hermes_status hermes_profile_reset(hermes_ctx ctx);
+hermes_status hermes_profile_read(hermes_ctx ctx, int index, char* name, size_t name_len,
+                                  int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

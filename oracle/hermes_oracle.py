@@ -63,20 +63,16 @@ def assign(pos, weight, box_L, n):
     w = np.ones(npts) if weight is None else np.asarray(weight, dtype=np.float64)
     i0 = np.floor(u).astype(np.int64)
     eps = np.zeros(n ** 3)
-    for ox in (-1, 0, 1, 2):
-        cx = i0[:, 0] + ox
-        wx = bspline3(u[:, 0] - cx)
-        cx = np.mod(cx, n)
-        for oy in (-1, 0, 1, 2):
-            cy = i0[:, 1] + oy
-            wy = bspline3(u[:, 1] - cy)
-            cy = np.mod(cy, n)
-            for oz in (-1, 0, 1, 2):
-                cz = i0[:, 2] + oz
-                wz = bspline3(u[:, 2] - cz)
-                cz = np.mod(cz, n)
-                flat = (cx * n + cy) * n + cz
-                eps += np.bincount(flat, weights=w * wx * wy * wz, minlength=n ** 3)
+    # per axis: node index (mod N) and B3 weight of the four nodes i0-1..i0+2
+    cells = [[np.mod(i0[:, a] + o, n) for o in (-1, 0, 1, 2)] for a in range(3)]
+    taps = [[bspline3(u[:, a] - (i0[:, a] + o)) for o in (-1, 0, 1, 2)] for a in range(3)]
+    for ox in range(4):
+        # the 16 (oy, oz) taps of one ox in a single histogram call
+        flat = np.concatenate([(cells[0][ox] * n + cells[1][oy]) * n + cells[2][oz]
+                               for oy in range(4) for oz in range(4)])
+        vals = np.concatenate([w * taps[0][ox] * taps[1][oy] * taps[2][oz]
+                               for oy in range(4) for oz in range(4)])
+        eps += np.bincount(flat, weights=vals, minlength=n ** 3)
     return eps.reshape(n, n, n), float(w.sum())
 
 
@@ -211,26 +207,35 @@ def ylm_real(ell, m, kx, ky, kz):
 
 
 def _radial_by_q(n, box_L, fn):
-    """Evaluate a radial function of |k| once per distinct |n~|^2 and spread it
-    over the grid (same value at every mode of equal |k|)."""
+    """Evaluate a radial function of |k| once per integer q = |n~|^2 in
+    [0, max q] and spread it over the grid (same value at every mode of
+    equal |k|)."""
     q = mode_q(n)
-    uq, inv = np.unique(q.reshape(-1), return_inverse=True)
-    kq = 2.0 * np.pi / box_L * np.sqrt(uq.astype(np.float64))
-    return fn(kq)[inv].reshape(q.shape)
+    kq = 2.0 * np.pi / box_L * np.sqrt(np.arange(int(q.max()) + 1, dtype=np.float64))
+    return fn(kq)[q]
 
 
 def nyquist_average(n, box_L, fn):
     """Average a k-space kernel over the two signed representatives of every
-    Nyquist index (even N): K(n) = mean over s in {+,-}^3 of fn(k_s).  Off the
-    Nyquist planes all eight evaluations coincide, so K equals fn there."""
+    Nyquist index (even N): K(n) = mean over s in {+,-}^3 of fn(k_s), where
+    only components at the Nyquist index change sign.  Off the Nyquist planes
+    all eight evaluations coincide, so K equals fn there and only the modes
+    on a Nyquist plane are re-evaluated."""
+    kx, ky, kz = mode_vectors(n, box_L)
+    out = np.array(np.broadcast_to(fn(kx, ky, kz), (n, n, n)), dtype=np.float64)
     if n % 2:
-        return fn(*mode_vectors(n, box_L))
-    acc = 0.0
+        return out
+    h = n // 2
+    ix, iy, iz = np.nonzero((np.arange(n)[:, None, None] == h) | (np.arange(n)[None, :, None] == h)
+                            | (np.arange(n)[None, None, :] == h))
+    f = 2.0 * np.pi / box_L
+    acc = np.zeros(ix.size)
     for sx in (1, -1):
         for sy in (1, -1):
             for sz in (1, -1):
-                acc = acc + fn(*mode_vectors(n, box_L, (sx, sy, sz)))
-    return acc / 8.0
+                acc += fn(f * signed_index(n, sx)[ix], f * signed_index(n, sy)[iy], f * signed_index(n, sz)[iz])
+    out[ix, iy, iz] = acc / 8.0
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -1,6 +1,8 @@
 // C ABI entry points: argument validation, context tables, dispatch.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <iterator>
 #include <string>
 #include <vector>
 
@@ -21,6 +23,37 @@ hermes_status check_launch(const char* what) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(HERMES_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
     return HERMES_OK;
+}
+
+LaunchScope::LaunchScope(hermes_ctx c, hipStream_t s, const char* name) : c_(c), s_(s), name_(name) {
+    if (!c_ || !c_->prof.on) return;
+    std::lock_guard<std::mutex> lk(c_->prof.mu);
+    auto take = [&]() {
+        hipEvent_t e = nullptr;
+        if (!c_->prof.pool.empty()) {
+            e = c_->prof.pool.back();
+            c_->prof.pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    };
+    a_ = take();
+    b_ = take();
+    if (a_ && b_) {
+        (void)hipEventRecord(a_, s_);
+    } else {
+        if (a_) c_->prof.pool.push_back(a_);
+        if (b_) c_->prof.pool.push_back(b_);
+        a_ = b_ = nullptr;
+    }
+}
+
+LaunchScope::~LaunchScope() {
+    if (!a_) return;
+    (void)hipEventRecord(b_, s_);
+    std::lock_guard<std::mutex> lk(c_->prof.mu);
+    c_->prof.pending.push_back({name_, a_, b_});
 }
 
 // Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_n.
@@ -141,11 +174,69 @@ hermes_status hermes_create(hermes_ctx* out, int device) {
 void hermes_destroy(hermes_ctx ctx) {
     if (!ctx) return;
     DeviceGuard g(ctx->device);
+    {
+        std::lock_guard<std::mutex> lk(ctx->prof.mu);
+        for (auto& p : ctx->prof.pending) {
+            (void)hipEventSynchronize(p.b);
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
+        ctx->prof.pending.clear();
+        ctx->prof.pool.clear();
+    }
     (void)hipFree(ctx->t.tw32);
     (void)hipFree(ctx->t.tw64);
     (void)hipFree(ctx->t.phi1d);
     (void)hipFree(ctx->t.gl);
     delete ctx;
+}
+
+hermes_status hermes_profile_enable(hermes_ctx ctx, int enable) {
+    if (!ctx) return fail(HERMES_ERR_ARG, "hermes_profile_enable: NULL context");
+    std::lock_guard<std::mutex> lk(ctx->prof.mu);
+    ctx->prof.on = enable != 0;
+    return HERMES_OK;
+}
+
+static void drain(hermes_ctx ctx) {
+    for (auto& p : ctx->prof.pending) {
+        float ms = 0.f;
+        (void)hipEventSynchronize(p.b);
+        if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) ms = 0.f;
+        auto& acc = ctx->prof.acc[p.name];
+        acc.first += 1;
+        acc.second += ms;
+        ctx->prof.pool.push_back(p.a);
+        ctx->prof.pool.push_back(p.b);
+    }
+    ctx->prof.pending.clear();
+}
+
+hermes_status hermes_profile_reset(hermes_ctx ctx) {
+    if (!ctx) return fail(HERMES_ERR_ARG, "hermes_profile_reset: NULL context");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->prof.mu);
+    drain(ctx);
+    ctx->prof.acc.clear();
+    return HERMES_OK;
+}
+
+hermes_status hermes_profile_read(hermes_ctx ctx, int index, char* name, size_t name_len, int64_t* launches,
+                                  double* total_ms) {
+    if (!ctx || !name || name_len == 0 || !launches || !total_ms)
+        return fail(HERMES_ERR_ARG, "hermes_profile_read: NULL argument");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->prof.mu);
+    drain(ctx);
+    if (index < 0 || index >= int(ctx->prof.acc.size()))
+        return fail(HERMES_ERR_ARG, "hermes_profile_read: index past the last record");
+    auto it = ctx->prof.acc.begin();
+    std::advance(it, index);
+    std::snprintf(name, name_len, "%s", it->first.c_str());
+    *launches = it->second.first;
+    *total_ms = it->second.second;
+    return HERMES_OK;
 }
 
 hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtype, int n_batch,

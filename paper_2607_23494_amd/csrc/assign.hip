@@ -63,12 +63,19 @@ __global__ __launch_bounds__(kThreads) void k_assign(const float* __restrict__ p
 }
 
 template <typename T, int N>
-static hermes_status assign_n(const float* pos, const float* weight, int64_t n_pts, double box_L,
+static hermes_status assign_n(hermes_ctx ctx, const float* pos, const float* weight, int64_t n_pts, double box_L,
                               void* eps, double* sum_w, hipStream_t stream) {
     const int64_t cells = int64_t(N) * N * N;
-    launch_fill<T>(static_cast<T*>(eps), cells, T(0), stream);
-    launch_fill<double>(sum_w, 1, 0.0, stream);
+    {
+        LaunchScope ls(ctx, stream, "fill");
+        launch_fill<T>(static_cast<T*>(eps), cells, T(0), stream);
+    }
+    {
+        LaunchScope ls(ctx, stream, "fill");
+        launch_fill<double>(sum_w, 1, 0.0, stream);
+    }
     if (n_pts > 0) {
+        LaunchScope ls(ctx, stream, "assign");
         const int64_t want = (n_pts + kThreads - 1) / kThreads;
         const int blocks = int(want < 8192 ? want : 8192);
         hipLaunchKernelGGL((k_assign<T, N>), dim3(blocks), dim3(kThreads), 0, stream, pos, weight, n_pts,
@@ -77,12 +84,12 @@ static hermes_status assign_n(const float* pos, const float* weight, int64_t n_p
     return check_launch("hermes_assign");
 }
 
-hermes_status assign_impl(hermes_ctx, const float* pos, const float* weight, int64_t n_pts, double box_L,
+hermes_status assign_impl(hermes_ctx ctx, const float* pos, const float* weight, int64_t n_pts, double box_L,
                           int n, int dtype, void* eps, double* sum_w, hipStream_t stream) {
 #define HERMES_ASSIGN_CASE(NN)                                                                  \
     case NN:                                                                                    \
-        return dtype == HERMES_F32 ? assign_n<float, NN>(pos, weight, n_pts, box_L, eps, sum_w, stream) \
-                                   : assign_n<double, NN>(pos, weight, n_pts, box_L, eps, sum_w, stream);
+        return dtype == HERMES_F32 ? assign_n<float, NN>(ctx, pos, weight, n_pts, box_L, eps, sum_w, stream) \
+                                   : assign_n<double, NN>(ctx, pos, weight, n_pts, box_L, eps, sum_w, stream);
     switch (n) {
         HERMES_ASSIGN_CASE(8)
         HERMES_ASSIGN_CASE(16)

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "hermes.h"
 
@@ -23,11 +26,26 @@ struct Tables {
     double* gl = nullptr;       // kGL nodes then kGL weights on [-1, 1]
 };
 
+// Optional per-kernel timing: launches are bracketed with HIP events on the
+// launch stream; durations are collected when the records are read.
+struct Profiler {
+    bool on = false;
+    std::mutex mu;
+    struct Pending {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    std::map<std::string, std::pair<int64_t, double>> acc;   // name -> (launches, total ms)
+};
+
 }  // namespace hermes
 
 struct hermes_ctx_s {
     int device = 0;
     hermes::Tables t;
+    hermes::Profiler prof;
 };
 
 namespace hermes {
@@ -36,6 +54,21 @@ namespace hermes {
 void set_error(const std::string& msg);
 hermes_status fail(hermes_status st, const std::string& msg);
 hermes_status check_launch(const char* what);
+
+// Brackets one kernel launch with timing events when profiling is on.
+class LaunchScope {
+public:
+    LaunchScope(hermes_ctx c, hipStream_t s, const char* name);
+    ~LaunchScope();
+    LaunchScope(const LaunchScope&) = delete;
+    LaunchScope& operator=(const LaunchScope&) = delete;
+
+private:
+    hermes_ctx c_;
+    hipStream_t s_;
+    const char* name_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
 
 inline bool valid_n(int n) { return n >= 8 && n <= kMaxN && (n & (n - 1)) == 0; }
 

@@ -15,12 +15,19 @@ static hermes_status fft_n(hermes_ctx ctx, const void* eps, const double* sum_w,
     const C* tw = tw_ptr<T>(ctx->t);
     C* dk = static_cast<C*>(delta_k);
     const int rows = N * N;
-    hipLaunchKernelGGL((k_fwd_z<T, N>), dim3((rows + LINES - 1) / LINES), dim3(kThreads), 0, stream,
-                       static_cast<const T*>(eps), sum_w, static_cast<T*>(delta), dk, tw);
-    // y: N planes (one per x), P columns, stride P
-    launch_c2c_strided<T, N, false>(dk, N, int64_t(N) * P, P, P, false, tw, stream);
-    // x: one plane of N*P columns, stride N*P
-    launch_c2c_strided<T, N, false>(dk, 1, 0, N * P, int64_t(N) * P, true, tw, stream);
+    {
+        LaunchScope ls(ctx, stream, "fwd_z");
+        hipLaunchKernelGGL((k_fwd_z<T, N>), dim3((rows + LINES - 1) / LINES), dim3(kThreads), 0, stream,
+                           static_cast<const T*>(eps), sum_w, static_cast<T*>(delta), dk, tw);
+    }
+    {   // y: N planes (one per x), P columns, stride P
+        LaunchScope ls(ctx, stream, "fwd_y");
+        launch_c2c_cols<T, N, false, false>(dk, N, int64_t(N) * P, P, P, false, tw, stream);
+    }
+    {   // x: one plane of N*P columns, stride N*P
+        LaunchScope ls(ctx, stream, "fwd_x");
+        launch_c2c_cols<T, N, false, true>(dk, 1, 0, N * P, int64_t(N) * P, true, tw, stream);
+    }
     return check_launch("hermes_fft");
 }
 

@@ -140,6 +140,65 @@ __device__ __forceinline__ void lds_fft(C* s, const C* __restrict__ tw, int nlin
     fft_stages<C, L, LP, MAXLINES, 1, INV>(s, tw, nlines);
 }
 
+// ---------------------------------------------------------------- interleaved layout
+// TC lines (a tile of adjacent columns) stored element-major: element idx of
+// line c at s[idx * TC + c].  Consecutive threads take consecutive lines, so
+// every LDS access of a wavefront covers whole contiguous rows of the tile and
+// no padding is needed against bank conflicts.  All TC lines are transformed.
+template <typename C, int L, int TC, int NS, bool INV, int NT>
+__device__ __forceinline__ void fft_stage_il(C* s, const C* __restrict__ tw) {
+    constexpr int R = radix_for<L / NS>::value;
+    constexpr int PER = L / R;
+    constexpr int TOT = TC * PER;
+    static_assert(TOT % NT == 0, "tile must split evenly over the workgroup");
+    constexpr int BPT = TOT / NT;
+    constexpr int TWS = L / (NS * R);
+    C v[BPT][R];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = threadIdx.x + i * NT;
+        const int line = b % TC, j = b / TC;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[i][r] = s[(j + r * PER) * TC + line];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = threadIdx.x + i * NT;
+        const int line = b % TC, j = b / TC;
+        const int k = j & (NS - 1);
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                C w = tw[L + r * k * TWS];
+                if (INV) w.y = -w.y;
+                v[i][r] = c_mul(v[i][r], w);
+            }
+        }
+        butterfly<INV, R>(v[i]);
+        const int o = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[(o + r * NS) * TC + line] = v[i][r];
+    }
+    __syncthreads();
+}
+
+template <typename C, int L, int TC, int NS, bool INV, int NT>
+__device__ __forceinline__ void fft_stages_il(C* s, const C* __restrict__ tw) {
+    if constexpr (NS < L) {
+        constexpr int R = radix_for<L / NS>::value;
+        fft_stage_il<C, L, TC, NS, INV, NT>(s, tw);
+        fft_stages_il<C, L, TC, NS * R, INV, NT>(s, tw);
+    }
+}
+
+// NT = threads of the workgroup
+template <typename C, int L, int TC, bool INV, int NT>
+__device__ __forceinline__ void lds_fft_il(C* s, const C* __restrict__ tw) {
+    __syncthreads();
+    fft_stages_il<C, L, TC, 1, INV, NT>(s, tw);
+}
+
 // ---------------------------------------------------------------- mode helpers
 // signed mode index of array index i on an axis of length N (Nyquist -> +N/2)
 template <int N> __device__ __forceinline__ int signed_mode(int i) { return i <= N / 2 ? i : i - N; }

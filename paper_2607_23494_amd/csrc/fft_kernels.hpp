@@ -2,30 +2,91 @@
 //
 // Forward: (1) r2c along z with the contrast delta = eps/eps_bar - 1 fused
 // into the load, (2) c2c along y, (3) c2c along x.  Each pass reads and
-// writes HBM once.  The strided passes stage a tile of TC adjacent columns
-// (contiguous in memory) times the full line length in LDS, so that every
-// global access is a run of TC consecutive complex values.
+// writes HBM once.  The strided (column) passes stage a tile of TC adjacent
+// columns times the full line length in LDS in the interleaved layout, with
+// all of a thread's global loads issued before the first is consumed and
+// 16-byte accesses where the layout is 16-byte aligned.
 #pragma once
 
 #include "fft_core.hpp"
 
 namespace hermes {
 
-constexpr int kLdsBudget = 65536;   // bytes of LDS per workgroup used by the pass kernels
-
 template <typename T> struct fft_cfg;
-template <> struct fft_cfg<float> { static constexpr int elems = 8192; };   // complex per 64 KB
+template <> struct fft_cfg<float> { static constexpr int elems = 8192; };   // complex per 64 KB tile
 template <> struct fft_cfg<double> { static constexpr int elems = 4096; };
 
-// columns per tile of a strided pass: TC * (N + 1) complex fit the budget
-template <typename T, int N> struct strided_cfg {
-    static constexpr int LP = N + 1;
-    static constexpr int TC = fft_cfg<T>::elems / LP;
+constexpr int kColThreads = 512;   // threads of the column-pass workgroups
+
+// Column tile geometry: TC columns x N positions, 16-byte vectors of VEC
+// complex, LPR lanes per tile row, RPP rows per load round, NLD rounds.
+template <typename T, int N> struct col_cfg {
+    using C = typename cplx_of<T>::type;
+    static constexpr int TC = fft_cfg<T>::elems / N;
+    static constexpr int VEC = 16 / int(sizeof(C));
+    static constexpr int LPR = TC / VEC;
+    static constexpr int RPP = kColThreads / LPR;
+    static constexpr int NLD = N / RPP;
+    static_assert(LPR <= kColThreads && N % RPP == 0, "column tile");
 };
+
+// Row pitch (complex elements) of the internal padded half spectra: N/2+1
+// rounded up to 16, so every row starts on a 128-byte boundary.
+template <int N> constexpr int pitch_of() { return ((N / 2 + 1) + 15) / 16 * 16; }
+inline int pitch_rt(int n) { return ((n / 2 + 1) + 15) / 16 * 16; }
 
 template <typename T> inline const typename cplx_of<T>::type* tw_ptr(const Tables& t);
 template <> inline const float2* tw_ptr<float>(const Tables& t) { return t.tw32; }
 template <> inline const double2* tw_ptr<double>(const Tables& t) { return t.tw64; }
+
+// 16-byte vector of complex values
+template <typename C> struct vec_of;
+template <> struct vec_of<float2> { using type = float4; };
+template <> struct vec_of<double2> { using type = double2; };
+
+template <typename C, int VEC>
+__device__ __forceinline__ void vec_split(const typename vec_of<C>::type& v, C* out) {
+    if constexpr (VEC == 2) {
+        out[0] = C{v.x, v.y};
+        out[1] = C{v.z, v.w};
+    } else {
+        out[0] = v;
+    }
+}
+
+template <typename C, int VEC>
+__device__ __forceinline__ typename vec_of<C>::type vec_join(const C* in) {
+    if constexpr (VEC == 2) {
+        return typename vec_of<C>::type{in[0].x, in[0].y, in[1].x, in[1].y};
+    } else {
+        return in[0];
+    }
+}
+
+// Load VEC consecutive complex values at src (columns lc.. of a tile with nc
+// valid columns); 16-byte access when allowed and fully valid.
+template <typename C, int VEC, bool VECLD>
+__device__ __forceinline__ void load_cols(const C* src, int lc, int nc, C* out) {
+    using V = typename vec_of<C>::type;
+    if (VECLD && lc + VEC <= nc) {
+        vec_split<C, VEC>(*reinterpret_cast<const V*>(src), out);
+    } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) out[v] = lc + v < nc ? src[v] : C{0, 0};
+    }
+}
+
+template <typename C, int VEC, bool VECLD>
+__device__ __forceinline__ void store_cols(C* dst, int lc, int nc, const C* in) {
+    using V = typename vec_of<C>::type;
+    if (VECLD && lc + VEC <= nc) {
+        *reinterpret_cast<V*>(dst) = vec_join<C, VEC>(in);
+    } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+            if (lc + v < nc) dst[v] = in[v];
+    }
+}
 
 // ---------------------------------------------------------------- forward z (r2c)
 // rows of N reals -> rows of N/2+1 complex.  Real pairs are packed into a
@@ -39,20 +100,26 @@ __global__ __launch_bounds__(kThreads) void k_fwd_z(const T* __restrict__ eps, c
     constexpr int M = N / 2, P = M + 1, LP = M;
     constexpr int LINES = fft_cfg<T>::elems / M;
     constexpr int ROWS = N * N;
+    constexpr int EPT = LINES * M / kThreads;
     __shared__ C s[LINES * LP];
     const int row0 = blockIdx.x * LINES;
     const int nl = min(LINES, ROWS - row0);
     const double inv_mean = double(N) * double(N) * double(N) / sum_w[0];
-    // load + contrast
-    for (int e = threadIdx.x; e < nl * M; e += kThreads) {
-        const int64_t g = int64_t(row0) * N + 2 * e;      // rows are contiguous
-        const T a = T(double(eps[g]) * inv_mean - 1.0);
-        const T b = T(double(eps[g + 1]) * inv_mean - 1.0);
-        if (delta_out) {
-            delta_out[g] = a;
-            delta_out[g + 1] = b;
+    const C* src = reinterpret_cast<const C*>(eps) + int64_t(row0) * M;   // real pairs
+    C pre[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        pre[i] = e < nl * M ? src[e] : C{0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        if (e < nl * M) {
+            const C d{T(double(pre[i].x) * inv_mean - 1.0), T(double(pre[i].y) * inv_mean - 1.0)};
+            if (delta_out) reinterpret_cast<C*>(delta_out)[int64_t(row0) * M + e] = d;
+            s[e] = d;   // line e / M, element e % M, LP == M
         }
-        s[e] = C{a, b};   // line e / M, element e % M, LP == M
     }
     lds_fft<C, M, LP, LINES, false>(s, tw, nl);
     // separate the packed transforms: X[k] = (Z[k] + Z*[M-k])/2 - i/2 W^k (Z[k] - Z*[M-k])
@@ -67,44 +134,48 @@ __global__ __launch_bounds__(kThreads) void k_fwd_z(const T* __restrict__ eps, c
     }
 }
 
-// ---------------------------------------------------------------- strided c2c
+// ---------------------------------------------------------------- column c2c
 // In-place FFT along an axis of length N with element stride `stride`, for
 // `ncols` contiguous columns in each of gridDim.y planes.  zero_dc clears
-// element 0 of plane 0 after the transform.
-template <typename T, int N, bool INV>
-__global__ __launch_bounds__(kThreads) void k_c2c_strided(typename cplx_of<T>::type* __restrict__ data,
-                                                          int64_t plane_stride, int ncols, int64_t stride,
-                                                          int zero_dc,
-                                                          const typename cplx_of<T>::type* __restrict__ tw) {
+// element 0 of plane 0 after the transform.  VECLD requires 16-byte aligned
+// rows (stride, plane_stride and the base pointer multiples of VEC).
+template <typename T, int N, bool INV, bool VECLD>
+__global__ __launch_bounds__(kColThreads) void k_c2c_cols(typename cplx_of<T>::type* __restrict__ data,
+                                                       int64_t plane_stride, int ncols, int64_t stride,
+                                                       int zero_dc,
+                                                       const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
-    constexpr int LP = strided_cfg<T, N>::LP, TC = strided_cfg<T, N>::TC;
-    constexpr int EL = TC * N;
-    __shared__ C s[TC * LP];
+    using G = col_cfg<T, N>;
+    constexpr int TC = G::TC, VEC = G::VEC, LPR = G::LPR, RPP = G::RPP, NLD = G::NLD;
+    __shared__ C s[N * TC];
     const int c0 = blockIdx.x * TC;
     const int nc = min(TC, ncols - c0);
     C* base = data + int64_t(blockIdx.y) * plane_stride + c0;
-    for (int e = threadIdx.x; e < EL; e += kThreads) {
-        const int col = e % TC, pos = e / TC;
-        if (col < nc) s[col * LP + pos] = base[int64_t(pos) * stride + col];
-    }
-    lds_fft<C, N, LP, TC, INV>(s, tw, nc);
-    for (int e = threadIdx.x; e < EL; e += kThreads) {
-        const int col = e % TC, pos = e / TC;
-        if (col < nc) {
-            C v = s[col * LP + pos];
-            if (zero_dc && blockIdx.y == 0 && c0 + col == 0 && pos == 0) v = C{T(0), T(0)};
-            base[int64_t(pos) * stride + col] = v;
-        }
+    const int lc = (threadIdx.x % LPR) * VEC, r0 = threadIdx.x / LPR;
+    C buf[NLD][VEC];
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) load_cols<C, VEC, VECLD>(base + int64_t(r0 + i * RPP) * stride + lc, lc, nc, buf[i]);
+#pragma unroll
+    for (int i = 0; i < NLD; ++i)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) s[(r0 + i * RPP) * TC + lc + v] = buf[i][v];
+    lds_fft_il<C, N, TC, INV, kColThreads>(s, tw);
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+        const int p = r0 + i * RPP;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) buf[i][v] = s[p * TC + lc + v];
+        if (zero_dc && blockIdx.y == 0 && c0 + lc == 0 && p == 0) buf[i][0] = C{0, 0};
+        store_cols<C, VEC, VECLD>(base + int64_t(p) * stride + lc, lc, nc, buf[i]);
     }
 }
 
-template <typename T, int N, bool INV>
-inline void launch_c2c_strided(typename cplx_of<T>::type* data, int n_planes, int64_t plane_stride, int ncols,
-                               int64_t stride, bool zero_dc, const typename cplx_of<T>::type* tw,
-                               hipStream_t stream) {
-    constexpr int TC = strided_cfg<T, N>::TC;
+template <typename T, int N, bool INV, bool VECLD>
+inline void launch_c2c_cols(typename cplx_of<T>::type* data, int n_planes, int64_t plane_stride, int ncols,
+                            int64_t stride, bool zero_dc, const typename cplx_of<T>::type* tw, hipStream_t stream) {
+    constexpr int TC = col_cfg<T, N>::TC;
     const int tiles = (ncols + TC - 1) / TC;
-    hipLaunchKernelGGL((k_c2c_strided<T, N, INV>), dim3(tiles, n_planes), dim3(kThreads), 0, stream, data,
+    hipLaunchKernelGGL((k_c2c_cols<T, N, INV, VECLD>), dim3(tiles, n_planes), dim3(kColThreads), 0, stream, data,
                        plane_stride, ncols, stride, zero_dc ? 1 : 0, tw);
 }
 

@@ -9,7 +9,7 @@
 //                  registers, then for every window multiply by the radial
 //                  factor R_b(q) (exact table over q = |n~|^2), inverse FFT
 //                  along x in LDS and write the batch spectrum b;
-//   Y  (k_c2c_strided): inverse FFT along y of all nb spectra in place;
+//   Y  (k_c2c_cols): inverse FFT along y of all nb spectra in place;
 //   Z  (k_c2r_z):  c2r along z for all nb windows of a row group at once and
 //                  a fused epilogue: either the counts-in-cells moments (and
 //                  optionally the stored fields), or the contraction
@@ -47,6 +47,8 @@ template <int N> struct zrows {
     static constexpr int LP = M + 1;
 };
 
+constexpr size_t kZLdsBudget = 81920;   // bytes: two z-pass workgroups per CU
+
 template <typename T, int N>
 constexpr size_t z_lds_bytes(int nb) {
     using C = typename cplx_of<T>::type;
@@ -60,7 +62,7 @@ constexpr size_t z_lds_bytes(int nb) {
 template <typename T, int N>
 constexpr int z_max_batch() {
     int nb = kMaxBatch;
-    while (nb > 1 && z_lds_bytes<T, N>(nb) > size_t(kLdsBudget)) --nb;
+    while (nb > 1 && z_lds_bytes<T, N>(nb) > kZLdsBudget) --nb;
     return nb;
 }
 
@@ -82,12 +84,13 @@ inline int z_max_batch_rt(int n, bool dbl) {
     return 1;
 }
 
+// bytes of one padded half spectrum [N][N][pitch]
 inline size_t spec_bytes(int n, bool dbl) {
-    return size_t(n) * n * (n / 2 + 1) * (dbl ? 16 : 8);
+    return size_t(n) * n * pitch_rt(n) * (dbl ? 16 : 8);
 }
 
 // ---------------------------------------------------------------- radial table
-// tab[q * nb + b] = R_b(k_q), k_q = kfac sqrt(q), evaluated in float64.
+// tab[b * nq + q] = R_b(k_q), k_q = kfac sqrt(q), evaluated in float64.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_radial(T* __restrict__ tab, int64_t nq, WinSet ws, double kfac,
                                                      const double* __restrict__ gl) {
@@ -102,65 +105,96 @@ __global__ __launch_bounds__(kThreads) void k_radial(T* __restrict__ tab, int64_
             case HERMES_WIN_GAUSS: v = exp(-0.5 * (k * ws.hi[b]) * (k * ws.hi[b])); break;
             default: v = jbar(ws.ell[b], k, ws.lo[b], ws.hi[b], gl); break;
         }
-        tab[q * ws.n + b] = T(v);
+        tab[b * nq + q] = T(v);
     }
 }
 
-// ---------------------------------------------------------------- pass X
+// ---------------------------------------------------------------- angular factor
+// B[kx][ky][kz] = delta^ Phi^ A(k^) s / N^3 on the padded layout (zeros in the
+// row padding), with A = 1 or the Nyquist-averaged Y^R_lm evaluated in float64
+// and s the complex constant (1 or 4 pi i^l).  One thread per padded element.
 template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void k_win_x(const typename cplx_of<T>::type* __restrict__ dk,
+__global__ __launch_bounds__(kThreads) void k_angular(const typename cplx_of<T>::type* __restrict__ dk,
+                                                      typename cplx_of<T>::type* __restrict__ B, int sh, int ell,
+                                                      int m, double sre, double sim,
+                                                      const double* __restrict__ phi1d) {
+    using C = typename cplx_of<T>::type;
+    constexpr int M = N / 2, P = M + 1, PP = pitch_of<N>();
+    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (e >= int64_t(N) * N * PP) return;
+    const int kz = int(e % PP);
+    const int64_t row = e / PP;
+    const int ky = int(row % N), kx = int(row / N);
+    C o{T(0), T(0)};
+    if (kz < P) {
+        const C v = dk[row * P + kz];
+        const int sx = signed_mode<N>(kx), sy = signed_mode<N>(ky);
+        double f = phi1d[N + kx] * phi1d[N + ky] * phi1d[N + kz];
+        if (sh) f *= ylm_mode(ell, m, sx, sy, kz, kx == M, ky == M, kz == M);
+        const double re = double(v.x) * sre - double(v.y) * sim;
+        const double im = double(v.x) * sim + double(v.y) * sre;
+        o = C{T(re * f), T(im * f)};
+    }
+    B[e] = o;
+}
+
+// ---------------------------------------------------------------- pass X
+// Tiles of TC consecutive columns of the padded (ky, kz) plane of B: for every
+// window b multiply by the radial factor R_b(q), q = |n~|^2, inverse FFT along
+// x in LDS and write spectrum b.  Rows are 128-byte aligned.
+template <typename T, int N>
+__global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>::type* __restrict__ B,
                                                     typename cplx_of<T>::type* __restrict__ out,
                                                     int64_t bin_stride, int nb, const T* __restrict__ rtab,
-                                                    int sh, int ell, int m, double sre, double sim,
-                                                    const double* __restrict__ phi1d,
-                                                    const typename cplx_of<T>::type* __restrict__ tw) {
+                                                    int nq, const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
-    constexpr int M = N / 2, P = M + 1;
-    constexpr int LP = strided_cfg<T, N>::LP, TC = strided_cfg<T, N>::TC;
-    constexpr int EL = TC * N;
-    constexpr int EPT = (EL + kThreads - 1) / kThreads;
-    constexpr int64_t PLANE = int64_t(N) * P;
-    __shared__ C s[TC * LP];
+    using G = col_cfg<T, N>;
+    constexpr int TC = G::TC, VEC = G::VEC, LPR = G::LPR, RPP = G::RPP, NLD = G::NLD;
+    constexpr int PP = pitch_of<N>();
+    constexpr int64_t PLANE = int64_t(N) * PP;
+    __shared__ C s[N * TC];
     const int c0 = blockIdx.x * TC;
-    const int nc = min(TC, int(PLANE) - c0);
-    C base[EPT];
-    int qv[EPT];
+    const int lc = (threadIdx.x % LPR) * VEC, r0 = threadIdx.x / LPR;
+    const bool in_plane = c0 + lc < PLANE;   // PLANE is a multiple of VEC
+    int qyz[VEC];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * kThreads;
-        const int col = e % TC, kx = e / TC;
-        base[i] = C{T(0), T(0)};
-        qv[i] = 0;
-        if (e < EL && col < nc) {
-            const int c = c0 + col;
-            const int ky = c / P, kz = c - ky * P;
-            const C v = dk[int64_t(kx) * PLANE + c];
-            const int sx = signed_mode<N>(kx), sy = signed_mode<N>(ky);
-            qv[i] = sx * sx + sy * sy + kz * kz;
-            double f = phi1d[N + kx] * phi1d[N + ky] * phi1d[N + kz];
-            if (sh) f *= ylm_mode(ell, m, sx, sy, kz, kx == M, ky == M, kz == M);
-            const double re = double(v.x) * sre - double(v.y) * sim;
-            const double im = double(v.x) * sim + double(v.y) * sre;
-            base[i] = C{T(re * f), T(im * f)};
+    for (int v = 0; v < VEC; ++v) {
+        const int c = c0 + lc + v;
+        const int ky = c / PP, kz = c - (c / PP) * PP;
+        const int sy = signed_mode<N>(ky & (N - 1));
+        qyz[v] = sy * sy + kz * kz;
+    }
+    C raw[NLD][VEC];
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+        if (in_plane) {
+            load_cols<C, VEC, true>(B + (r0 + i * RPP) * PLANE + c0 + lc, 0, VEC, raw[i]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) raw[i][v] = C{T(0), T(0)};
         }
     }
     for (int b = 0; b < nb; ++b) {
+        const T* rb = rtab + int64_t(b) * nq;   // uniform per iteration
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = threadIdx.x + i * kThreads;
-            const int col = e % TC, kx = e / TC;
-            if (e < EL && col < nc) {
-                const T r = rtab[int64_t(qv[i]) * nb + b];
-                s[col * LP + kx] = C{base[i].x * r, base[i].y * r};
+        for (int i = 0; i < NLD; ++i) {
+            const int sx = signed_mode<N>(r0 + i * RPP);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                const int q = in_plane ? sx * sx + qyz[v] : 0;
+                const T r = rb[q];
+                s[(r0 + i * RPP) * TC + lc + v] = C{raw[i][v].x * r, raw[i][v].y * r};
             }
         }
-        lds_fft<C, N, LP, TC, true>(s, tw, nc);
-        C* ob = out + b * bin_stride + c0;
+        lds_fft_il<C, N, TC, true, kColThreads>(s, tw);
+        C* ob = out + b * bin_stride + c0 + lc;
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = threadIdx.x + i * kThreads;
-            const int col = e % TC, kx = e / TC;
-            if (e < EL && col < nc) ob[int64_t(kx) * PLANE + col] = s[col * LP + kx];
+        for (int i = 0; i < NLD; ++i) {
+            const int p = r0 + i * RPP;
+            C o[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) o[v] = s[p * TC + lc + v];
+            if (in_plane) store_cols<C, VEC, true>(ob + p * PLANE, 0, VEC, o);
         }
         __syncthreads();
     }
@@ -169,28 +203,32 @@ __global__ __launch_bounds__(kThreads) void k_win_x(const typename cplx_of<T>::t
 // ---------------------------------------------------------------- pass Z
 enum { EPI_MOMENTS = 0, EPI_CONTRACT = 1 };
 
-// c2r along z of nb windows x R rows, then the epilogue.  Dynamic LDS:
-// lines [nb][R][LP] complex, then the delta rows [R][N] (contraction).
-template <typename T, int N, int EPI>
+// c2r along z of nb windows x R rows per group, then the epilogue.  Persistent
+// workgroups; the next group's rows are fetched into registers while the
+// current group is transformed.  Dynamic LDS: lines [nb][R][LP] complex, then
+// the delta rows [R][N] (contraction).  NBCAP bounds nb (registers).
+template <typename T, int N, int EPI, int NBCAP>
 __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::type* __restrict__ spec,
                                                     int64_t bin_stride, int nb, const T* __restrict__ delta,
                                                     T* __restrict__ out, WinSet map,
                                                     double* __restrict__ part,
                                                     const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
-    constexpr int M = N / 2, P = M + 1;
+    constexpr int M = N / 2, P = M + 1, PP = pitch_of<N>();
     constexpr int R = zrows<N>::R, LP = zrows<N>::LP;
     constexpr int CELLS = R * N;
     constexpr int GROUPS = N * N / R;
-    constexpr int MAXLINES = z_max_batch<T, N>() * R;
+    constexpr int MAXLINES = NBCAP * R;
+    constexpr int MAXE = (MAXLINES * P + kThreads - 1) / kThreads;
+    constexpr int DPT = (CELLS + kThreads - 1) / kThreads;
     extern __shared__ double lds_raw[];
     C* s = reinterpret_cast<C*>(lds_raw);
     T* sf = reinterpret_cast<T*>(lds_raw);
     T* sd = reinterpret_cast<T*>(s + nb * R * LP);
     const int nlines = nb * R;
+    const int ne = nlines * P;
 
-    // epilogue thread roles
-    // contraction: 4x4 bin tiles (I <= J), CG cell groups
+    // contraction roles: 4x4 bin tiles (I <= J) x cell groups
     const int nt4 = (nb + 3) / 4;
     const int ntp = nt4 * (nt4 + 1) / 2;
     const int cg_n = kThreads / ntp;
@@ -207,7 +245,7 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
             idx -= nt4 - I;
         }
     }
-    // moments: one window per thread, SUBS cell groups
+    // moments roles: one window per thread, subs cell groups
     const int subs = kThreads / nb;
     const int mb = threadIdx.x % nb, msub = threadIdx.x / nb;
 
@@ -215,36 +253,65 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc64[i] = 0.0;
 
+    C pre[MAXE];
+    T dpre[DPT];
+    auto fetch = [&](int g) {
+        const int64_t row0 = int64_t(g) * R;
+#pragma unroll
+        for (int i = 0; i < MAXE; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            if (e < ne) {
+                const int line = e / P, k = e - line * P;
+                const int b = line / R, r = line - b * R;
+                pre[i] = spec[b * bin_stride + (row0 + r) * PP + k];
+            }
+        }
+        if (EPI == EPI_CONTRACT) {
+#pragma unroll
+            for (int i = 0; i < DPT; ++i) {
+                const int e = threadIdx.x + i * kThreads;
+                if (e < CELLS) dpre[i] = delta[row0 * N + e];
+            }
+        }
+    };
+
+    if (blockIdx.x < GROUPS) fetch(blockIdx.x);
     for (int g = blockIdx.x; g < GROUPS; g += gridDim.x) {
         const int64_t row0 = int64_t(g) * R;
-        // load the half-spectrum rows of every window
-        for (int e = threadIdx.x; e < nlines * P; e += kThreads) {
-            const int line = e / P, k = e - line * P;
-            const int b = line / R, r = line - b * R;
-            s[line * LP + k] = spec[b * bin_stride + (row0 + r) * P + k];
+#pragma unroll
+        for (int i = 0; i < MAXE; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            if (e < ne) {
+                const int line = e / P, k = e - line * P;
+                s[line * LP + k] = pre[i];
+            }
         }
-        if (EPI == EPI_CONTRACT)
-            for (int e = threadIdx.x; e < CELLS; e += kThreads) sd[e] = delta[row0 * N + e];
+        if (EPI == EPI_CONTRACT) {
+#pragma unroll
+            for (int i = 0; i < DPT; ++i) {
+                const int e = threadIdx.x + i * kThreads;
+                if (e < CELLS) sd[e] = dpre[i];
+            }
+        }
         __syncthreads();
+        if (g + int(gridDim.x) < GROUPS) fetch(g + gridDim.x);
         // c2r packing, in place by (k, M-k) pairs:
         //   Z[k] = (X[k] + X*[M-k]) + i e^{+2 pi i k/N} (X[k] - X*[M-k])
         for (int e = threadIdx.x; e < nlines * (M / 2 + 1); e += kThreads) {
             const int line = e / (M / 2 + 1), k = e - line * (M / 2 + 1);
-            C* L = s + line * LP;
-            const C xk = L[k], xm = L[M - k];
+            C* Lr = s + line * LP;
+            const C xk = Lr[k], xm = Lr[M - k];
             {
                 const C sum{xk.x + xm.x, xk.y - xm.y};
                 const C dif{xk.x - xm.x, xk.y + xm.y};
-                const C w = c_conj(tw[N + k]);
-                const C t = c_mul(w, dif);
-                L[k] = C{sum.x - t.y, sum.y + t.x};
+                const C t = c_mul(c_conj(tw[N + k]), dif);
+                Lr[k] = C{sum.x - t.y, sum.y + t.x};
             }
             if (k > 0 && k < M - k) {
                 const C sum{xm.x + xk.x, xm.y - xk.y};
                 const C dif{xm.x - xk.x, xm.y + xk.y};
-                const C w = c_conj(tw[N + M - k]);
-                const C t = c_mul(w, dif);
-                L[M - k] = C{sum.x - t.y, sum.y + t.x};
+                const C t = c_mul(c_conj(tw[N + M - k]), dif);
+                Lr[M - k] = C{sum.x - t.y, sum.y + t.x};
             }
         }
         lds_fft<C, M, LP, MAXLINES, true>(s, tw, nlines);
@@ -338,47 +405,73 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
     }
 }
 
-// dst[i] (+)= scale * sum_g part[g * n + i]
-__global__ void k_reduce_part(const double* __restrict__ part, int ngroups, int n, double scale,
-                              double* __restrict__ dst, int accumulate) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// dst[i] (+)= scale * sum_g part[g * n + i]; one workgroup per output element.
+__global__ __launch_bounds__(kThreads) void k_reduce_part(const double* __restrict__ part, int ngroups, int n,
+                                                          double scale, double* __restrict__ dst, int accumulate) {
+    __shared__ double red[kThreads];
+    const int i = blockIdx.x;
     double s = 0.0;
-    for (int g = 0; g < ngroups; ++g) s += part[int64_t(g) * n + i];
-    dst[i] = (accumulate ? dst[i] : 0.0) + scale * s;
+    for (int g = threadIdx.x; g < ngroups; g += kThreads) s += part[int64_t(g) * n + i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) dst[i] = (accumulate ? dst[i] : 0.0) + scale * s;
 }
 
-// moments[map.out[b]][p] = scale * sum_g part[g][b][p]
-__global__ void k_reduce_moments(const double* __restrict__ part, int ngroups, WinSet map, double scale,
-                                 double* __restrict__ moments) {
-    const int i = threadIdx.x;
-    if (i >= map.n * 3) return;
+// moments[map.out[b]][p] = scale * sum_g part[g][b][p]; one workgroup per (b, p).
+__global__ __launch_bounds__(kThreads) void k_reduce_moments(const double* __restrict__ part, int ngroups,
+                                                             WinSet map, double scale,
+                                                             double* __restrict__ moments) {
+    __shared__ double red[kThreads];
+    const int i = blockIdx.x;
     double s = 0.0;
-    for (int g = 0; g < ngroups; ++g) s += part[int64_t(g) * map.n * 3 + i];
-    moments[map.out[i / 3] * 3 + i % 3] = scale * s;
+    for (int g = threadIdx.x; g < ngroups; g += kThreads) s += part[int64_t(g) * map.n * 3 + i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) moments[map.out[i / 3] * 3 + i % 3] = scale * s;
 }
 
 template <typename KernelT>
 inline void allow_lds(KernelT kernel, size_t bytes) {
-    if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+template <int N>
+constexpr int z_grid() {
+    return (N * N / zrows<N>::R) < kZGroups ? (N * N / zrows<N>::R) : kZGroups;
+}
+
+inline int z_grid_rt(int n) {
+    const int groups = n * n / (n / 2 >= 256 ? 1 : 256 / (n / 2));
+    return groups < kZGroups ? groups : kZGroups;
+}
+
+template <typename T, int N, int EPI, int NBCAP>
+static void launch_z(const typename cplx_of<T>::type* sp, int64_t bin_stride, int nb, const T* delta, T* out,
+                     const WinSet& ws, double* part, const typename cplx_of<T>::type* tw, hipStream_t stream) {
+    constexpr int CAP = NBCAP < z_max_batch<T, N>() ? NBCAP : z_max_batch<T, N>();
+    const size_t lds = z_lds_bytes<T, N>(nb);
+    allow_lds(k_c2r_z<T, N, EPI, CAP>, lds);
+    hipLaunchKernelGGL((k_c2r_z<T, N, EPI, CAP>), dim3(z_grid<N>()), dim3(kThreads), lds, stream, sp, bin_stride, nb,
+                       delta, out, ws, part, tw);
 }
 
 // One batch: pass X, Y, Z over nb windows sharing the angular factor.
 template <typename T, int N, int EPI>
 static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, double box_L, const WinSet& ws, int sh,
-                      int ell, int m, bool build_table, void* spec_ws, T* rtab, double* part, T* out,
+                      int ell, int m, bool build_table, void* ang_ws, void* spec_ws, T* rtab, double* part, T* out,
                       hipStream_t stream) {
     using C = typename cplx_of<T>::type;
-    constexpr int P = N / 2 + 1;
-    constexpr int TC = strided_cfg<T, N>::TC;
+    constexpr int P = N / 2 + 1, PP = pitch_of<N>();
+    constexpr int TC = col_cfg<T, N>::TC;
     const C* tw = tw_ptr<T>(ctx->t);
     const int nb = ws.n;
     const int64_t nq = qmax_of(N) + 1;
-    const int64_t plane = int64_t(N) * P;
+    const int64_t plane = int64_t(N) * PP;
     const int64_t bin_stride = int64_t(N) * plane;
-    if (build_table)
+    if (build_table) {
+        LaunchScope ls(ctx, stream, "radial_table");
         hipLaunchKernelGGL((k_radial<T>), dim3((nq + kThreads - 1) / kThreads), dim3(kThreads), 0, stream, rtab, nq,
                            ws, 2.0 * M_PI / box_L, ctx->t.gl);
+    }
     // scale: angular constant times 1/N^3 (inverse DFT normalisation)
     const double inv = 1.0 / (double(N) * N * N);
     double sre = inv, sim = 0.0;
@@ -392,26 +485,30 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
         }
     }
     C* sp = static_cast<C*>(spec_ws);
-    hipLaunchKernelGGL((k_win_x<T, N>), dim3((plane + TC - 1) / TC), dim3(kThreads), 0, stream,
-                       static_cast<const C*>(delta_k), sp, bin_stride, nb, rtab, sh, ell, m, sre, sim,
-                       ctx->t.phi1d, tw);
-    launch_c2c_strided<T, N, true>(sp, nb * N, plane, P, P, false, tw, stream);
-    const size_t lds = z_lds_bytes<T, N>(nb);
-    allow_lds(k_c2r_z<T, N, EPI>, lds);
-    constexpr int GROUPS = N * N / zrows<N>::R;
-    const int grid = GROUPS < kZGroups ? GROUPS : kZGroups;
-    hipLaunchKernelGGL((k_c2r_z<T, N, EPI>), dim3(grid), dim3(kThreads), lds, stream, sp, bin_stride, nb, delta,
-                       out, ws, part, tw);
-}
-
-template <int N>
-constexpr int z_grid() {
-    return (N * N / zrows<N>::R) < kZGroups ? (N * N / zrows<N>::R) : kZGroups;
-}
-
-inline int z_grid_rt(int n) {
-    const int groups = n * n / (n / 2 >= 256 ? 1 : 256 / (n / 2));
-    return groups < kZGroups ? groups : kZGroups;
+    C* ang = static_cast<C*>(ang_ws);
+    {
+        LaunchScope ls(ctx, stream, "angular");
+        hipLaunchKernelGGL((k_angular<T, N>), dim3((bin_stride + kThreads - 1) / kThreads), dim3(kThreads), 0, stream,
+                           static_cast<const C*>(delta_k), ang, sh, ell, m, sre, sim, ctx->t.phi1d);
+    }
+    {
+        LaunchScope ls(ctx, stream, "inv_x_window");
+        hipLaunchKernelGGL((k_win_x<T, N>), dim3((plane + TC - 1) / TC), dim3(kColThreads), 0, stream, ang, sp,
+                           bin_stride, nb, rtab, int(nq), tw);
+    }
+    {
+        LaunchScope ls(ctx, stream, "inv_y");
+        launch_c2c_cols<T, N, true, true>(sp, nb * N, plane, P, PP, false, tw, stream);
+    }
+    {
+        LaunchScope ls(ctx, stream, EPI == EPI_CONTRACT ? "inv_z_contract" : "inv_z_moments");
+        if (EPI == EPI_CONTRACT && nb <= 20)
+            launch_z<T, N, EPI, 20>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+        else if (EPI == EPI_CONTRACT)
+            launch_z<T, N, EPI, kMaxBatch>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+        else
+            launch_z<T, N, EPI, kFilterChunk>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+    }
 }
 
 // ---------------------------------------------------------------- filter_bins
@@ -419,7 +516,7 @@ size_t filter_workspace(int n, int dtype, int n_win) {
     const bool dbl = dtype == HERMES_F64;
     const int chunk = std::min({n_win, kFilterChunk, z_max_batch_rt(n, dbl)});
     const size_t nq = size_t(qmax_of(n) + 1);
-    return align256(spec_bytes(n, dbl) * chunk) + align256(nq * chunk * (dbl ? 8 : 4)) +
+    return align256(spec_bytes(n, dbl) * (chunk + 1)) + align256(nq * chunk * (dbl ? 8 : 4)) +
            align256(size_t(z_grid_rt(n)) * chunk * 3 * sizeof(double));
 }
 
@@ -430,9 +527,11 @@ static hermes_status filter_n(hermes_ctx ctx, const void* delta_k, double box_L,
     const int chunk = std::min({n_win, kFilterChunk, z_max_batch<T, N>()});
     const size_t nq = size_t(qmax_of(N) + 1);
     char* w = static_cast<char*>(work);
-    void* spec = w;
-    T* rtab = reinterpret_cast<T*>(w + align256(spec_bytes(N, dbl) * chunk));
-    double* part = reinterpret_cast<double*>(w + align256(spec_bytes(N, dbl) * chunk) + align256(nq * chunk * sizeof(T)));
+    void* ang = w;
+    void* spec = w + spec_bytes(N, dbl);
+    T* rtab = reinterpret_cast<T*>(w + align256(spec_bytes(N, dbl) * (chunk + 1)));
+    double* part = reinterpret_cast<double*>(w + align256(spec_bytes(N, dbl) * (chunk + 1)) +
+                                             align256(nq * chunk * sizeof(T)));
     // group windows by angular factor: isotropic ones together, SH ones by (l, m)
     struct Key {
         int sh, ell, m;
@@ -468,10 +567,13 @@ static hermes_status filter_n(hermes_ctx ctx, const void* delta_k, double box_L,
             ++ws.n;
             ++i;
         }
-        run_batch<T, N, EPI_MOMENTS>(ctx, delta_k, nullptr, box_L, ws, k0.sh, k0.ell, k0.m, true, spec, rtab,
+        run_batch<T, N, EPI_MOMENTS>(ctx, delta_k, nullptr, box_L, ws, k0.sh, k0.ell, k0.m, true, ang, spec, rtab,
                                      moments ? part : nullptr, static_cast<T*>(out), stream);
-        if (moments)
-            hipLaunchKernelGGL(k_reduce_moments, dim3(1), dim3(kThreads), 0, stream, part, grid, ws, inv_nc, moments);
+        if (moments) {
+            LaunchScope ls(ctx, stream, "reduce");
+            hipLaunchKernelGGL(k_reduce_moments, dim3(ws.n * 3), dim3(kThreads), 0, stream, part, grid, ws, inv_nc,
+                               moments);
+        }
     }
     return check_launch("hermes_filter_bins");
 }
@@ -502,7 +604,7 @@ hermes_status filter_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype,
 // ---------------------------------------------------------------- zeta_l
 size_t zeta_workspace(int n, int n_bins) {
     const size_t nq = size_t(qmax_of(n) + 1);
-    return align256(spec_bytes(n, false) * n_bins) + align256(nq * n_bins * sizeof(float)) +
+    return align256(spec_bytes(n, false) * (n_bins + 1)) + align256(nq * n_bins * sizeof(float)) +
            align256(size_t(z_grid_rt(n)) * n_bins * n_bins * sizeof(double));
 }
 
@@ -517,12 +619,17 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
         return fail(HERMES_ERR_UNSUPPORTED, "hermes_zeta_l: mixed-precision contraction not available");
     const size_t nq = size_t(qmax_of(N) + 1);
     char* w = static_cast<char*>(work);
-    void* spec = w;
-    float* rtab = reinterpret_cast<float*>(w + align256(spec_bytes(N, false) * nb));
-    double* part = reinterpret_cast<double*>(w + align256(spec_bytes(N, false) * nb) + align256(nq * nb * sizeof(float)));
+    void* ang = w;
+    void* spec = w + spec_bytes(N, false);
+    float* rtab = reinterpret_cast<float*>(w + align256(spec_bytes(N, false) * (nb + 1)));
+    double* part = reinterpret_cast<double*>(w + align256(spec_bytes(N, false) * (nb + 1)) +
+                                             align256(nq * nb * sizeof(float)));
     const int grid = z_grid<N>();
     const double scale = 1.0 / (4.0 * M_PI * double(N) * N * N);
-    launch_fill<double>(zeta, int64_t(l_max + 1) * nb * nb, 0.0, stream);
+    {
+        LaunchScope ls(ctx, stream, "fill");
+        launch_fill<double>(zeta, int64_t(l_max + 1) * nb * nb, 0.0, stream);
+    }
     for (int ell = 0; ell <= l_max; ++ell) {
         WinSet ws{};
         ws.n = nb;
@@ -534,10 +641,11 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
             ws.out[b] = b;
         }
         for (int m = -ell; m <= ell; ++m) {
-            run_batch<float, N, EPI_CONTRACT>(ctx, delta_k, delta, box_L, ws, 1, ell, m, m == -ell, spec, rtab,
-                                              part, nullptr, stream);
-            hipLaunchKernelGGL(k_reduce_part, dim3((nb * nb + 127) / 128), dim3(128), 0, stream, part, grid, nb * nb,
-                               scale, zeta + int64_t(ell) * nb * nb, 1);
+            run_batch<float, N, EPI_CONTRACT>(ctx, delta_k, delta, box_L, ws, 1, ell, m, m == -ell, ang, spec,
+                                              rtab, part, nullptr, stream);
+            LaunchScope ls(ctx, stream, "reduce");
+            hipLaunchKernelGGL(k_reduce_part, dim3(nb * nb), dim3(kThreads), 0, stream, part, grid, nb * nb, scale,
+                               zeta + int64_t(ell) * nb * nb, 1);
         }
     }
     return check_launch("hermes_zeta_l");

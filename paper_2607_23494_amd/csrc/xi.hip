@@ -100,16 +100,28 @@ static hermes_status xi_n(hermes_ctx ctx, const void* delta_k, double box_L, con
     const int64_t nq = qmax_of(N) + 1;
     double* H = static_cast<double*>(work);
     double* part = reinterpret_cast<double*>(static_cast<char*>(work) + align256(nq * ells.n * sizeof(double)));
-    launch_fill<double>(H, nq * ells.n, 0.0, stream);
+    {
+        LaunchScope ls(ctx, stream, "fill");
+        launch_fill<double>(H, nq * ells.n, 0.0, stream);
+    }
     const int64_t reps = int64_t(P) * P * P;
-    hipLaunchKernelGGL((k_xi_hist<T, N>), dim3((reps + kThreads - 1) / kThreads), dim3(kThreads), 0, stream,
-                       static_cast<const C*>(delta_k), ells, los, ctx->t.phi1d, H, nq);
-    hipLaunchKernelGGL(k_xi_sum, dim3(edges.n_bins, ells.n, kXiSplit), dim3(kThreads), 0, stream, H, nq, ells,
-                       edges, 2.0 * M_PI / box_L, ctx->t.gl, part);
+    {
+        LaunchScope ls(ctx, stream, "xi_hist");
+        hipLaunchKernelGGL((k_xi_hist<T, N>), dim3((reps + kThreads - 1) / kThreads), dim3(kThreads), 0, stream,
+                           static_cast<const C*>(delta_k), ells, los, ctx->t.phi1d, H, nq);
+    }
+    {
+        LaunchScope ls(ctx, stream, "xi_sum");
+        hipLaunchKernelGGL(k_xi_sum, dim3(edges.n_bins, ells.n, kXiSplit), dim3(kThreads), 0, stream, H, nq, ells,
+                           edges, 2.0 * M_PI / box_L, ctx->t.gl, part);
+    }
     const int n_out = ells.n * edges.n_bins;
     const double nc = double(N) * N * N;
-    hipLaunchKernelGGL(k_xi_final, dim3((n_out + 127) / 128), dim3(128), 0, stream, part, ells, edges.n_bins,
-                       1.0 / (nc * nc), xi);
+    {
+        LaunchScope ls(ctx, stream, "reduce");
+        hipLaunchKernelGGL(k_xi_final, dim3((n_out + 127) / 128), dim3(128), 0, stream, part, ells, edges.n_bins,
+                           1.0 / (nc * nc), xi);
+    }
     return check_launch("hermes_xi");
 }
 

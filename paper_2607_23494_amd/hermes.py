@@ -54,8 +54,12 @@ def _load() -> ctypes.CDLL:
     lib.hermes_xi.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, sz, vp]
     lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
     lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
+    lib.hermes_profile_enable.argtypes = [vp, i32]
+    lib.hermes_profile_reset.argtypes = [vp]
+    lib.hermes_profile_read.argtypes = [vp, i32, ctypes.c_char_p, sz, ctypes.POINTER(i64), ctypes.POINTER(f64)]
     for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi",
-                 "hermes_filter_bins", "hermes_zeta_l"):
+                 "hermes_filter_bins", "hermes_zeta_l", "hermes_profile_enable", "hermes_profile_reset",
+                 "hermes_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -233,4 +237,33 @@ def zeta_l(delta: torch.Tensor, delta_k: torch.Tensor, box_L: float, edges, l_ma
     _check(_lib.hermes_zeta_l(context(dev), _ptr(delta), _ptr(delta_k), n, float(box_L),
                               e.ctypes.data_as(ctypes.c_void_p), nb, l_max, PREC[precision], _ptr(out), _ptr(w),
                               wbytes, _stream(dev, stream)))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# per-kernel timing
+# ----------------------------------------------------------------------------
+
+def profile_enable(on: bool = True, device: int = 0) -> None:
+    """Bracket every library kernel launch with HIP events on its stream."""
+    _check(_lib.hermes_profile_enable(context(device), 1 if on else 0))
+
+
+def profile_reset(device: int = 0) -> None:
+    _check(_lib.hermes_profile_reset(context(device)))
+
+
+def profile_read(device: int = 0) -> dict:
+    """{kernel class: (launches, total milliseconds)} since the last reset."""
+    out = {}
+    buf = ctypes.create_string_buffer(128)
+    i = 0
+    while True:
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        st = _lib.hermes_profile_read(context(device), i, buf, 128, ctypes.byref(n), ctypes.byref(ms))
+        if st != 0:
+            break
+        out[buf.value.decode()] = (int(n.value), float(ms.value))
+        i += 1
     return out
