@@ -122,7 +122,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--compare", action="store_true",
                     help="also time one step with the fp32 contraction for the mixed-vs-fp32 ratio")
     ap.add_argument("--no-cpu-baseline", action="store_true")

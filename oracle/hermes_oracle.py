@@ -206,7 +206,7 @@ def ylm_real(ell, m, kx, ky, kz):
     return out
 
 
-def _radial_by_q(n, box_L, fn):
+def radial_by_q(n, box_L, fn):
     """Evaluate a radial function of |k| once per integer q = |n~|^2 in
     [0, max q] and spread it over the grid (same value at every mode of
     equal |k|)."""
@@ -268,9 +268,9 @@ def xi_multipoles(delta_hat, box_L, edges, ells=(0,), los_axis=2):
         for b in range(len(edges) - 1):
             lo, hi = edges[b], edges[b + 1]
             if ell == 0:
-                rad = _radial_by_q(n, box_L, lambda kq: w_shell(kq, lo, hi))
+                rad = radial_by_q(n, box_L, lambda kq: w_shell(kq, lo, hi))
             else:
-                rad = _radial_by_q(n, box_L, lambda kq: jbar(ell, kq, lo, hi))
+                rad = radial_by_q(n, box_L, lambda kq: jbar(ell, kq, lo, hi))
             out[il, b] = pref * np.sum(pl * rad) / nc ** 2
     return out
 
@@ -282,7 +282,7 @@ def xi_multipoles(delta_hat, box_L, edges, ells=(0,), los_axis=2):
 def filtered_field(delta_hat, box_L, kernel_of_k):
     """delta_W = Re iDFT[delta^ Phi^ W^(|k|)] for a radial window."""
     n = delta_hat.shape[0]
-    rad = _radial_by_q(n, box_L, kernel_of_k)
+    rad = radial_by_q(n, box_L, kernel_of_k)
     return idft3(delta_hat * phi_hat(n) * rad).real
 
 
@@ -322,7 +322,7 @@ def multipole_field(delta_hat, box_L, ell, m, r_lo, r_hi, ylm=None):
     n = delta_hat.shape[0]
     if ylm is None:
         ylm = sh_window(n, box_L, ell, m)
-    rad = _radial_by_q(n, box_L, lambda kq: jbar(ell, kq, r_lo, r_hi))
+    rad = radial_by_q(n, box_L, lambda kq: jbar(ell, kq, r_lo, r_hi))
     kern = 4.0 * np.pi * (1j ** ell) * rad * ylm * phi_hat(n)
     f = idft3(delta_hat * kern)
     return f.real, float(np.max(np.abs(f.imag)))

@@ -203,11 +203,75 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
 // ---------------------------------------------------------------- pass Z
 enum { EPI_MOMENTS = 0, EPI_CONTRACT = 1 };
 
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+// Contraction of one row group on the matrix cores:
+//   C[i][j] += sum_c x_i(c) * (delta(c) x_j(c)),  i, j < 32 (bins >= nb are zero),
+// with a = x and b = delta x split as a = a_hi + a_lo, b = b_hi + b_lo in
+// bf16 (PREC 1) or fp16 (PREC 2) and C accumulated as a_hi b_hi + a_hi b_lo +
+// a_lo b_hi by 32x32x16 MFMAs in float32.  Wave w takes a quarter of the
+// group's cells; lane l supplies bin l % 32 at cells 8 (l / 32) .. +7 of each
+// 16-cell step for both operands.  The float32 tile sum is added to float64
+// accumulators once per group.
+template <typename T, int N, int PREC>
+__device__ __forceinline__ void mfma_contract(const T* sf, const T* sd, int nb, double* acc64) {
+    constexpr int R = zrows<N>::R, LP = zrows<N>::LP;
+    constexpr int CELLS = R * N;
+    constexpr int PER_WAVE = CELLS / (kThreads / 64);
+    static_assert(PER_WAVE % 16 == 0, "16-cell MFMA steps");
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int bin = l % 32, half = l / 32;
+    f32x16_t acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int step = 0; step < PER_WAVE / 16; ++step) {
+        const int c0 = w * PER_WAVE + step * 16 + 8 * half;   // 8 consecutive cells of one row
+        const int r = c0 / N, z = c0 - r * N;
+        float x[8], d[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            x[t] = bin < nb ? float(sf[2 * (bin * R + r) * LP + z + t]) : 0.f;
+            d[t] = float(sd[c0 + t]);
+        }
+        if constexpr (PREC == HERMES_PREC_BF16X3) {
+            bf16x8_t ah, al, bh, bl;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float a = x[t], b = d[t] * x[t];
+                ah[t] = (__bf16)a;
+                al[t] = (__bf16)(a - float(ah[t]));
+                bh[t] = (__bf16)b;
+                bl[t] = (__bf16)(b - float(bh[t]));
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+        } else {
+            f16x8_t ah, al, bh, bl;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float a = x[t], b = d[t] * x[t];
+                ah[t] = (_Float16)a;
+                al[t] = (_Float16)(a - float(ah[t]));
+                bh[t] = (_Float16)b;
+                bl[t] = (_Float16)(b - float(bh[t]));
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc64[r] += double(acc[r]);
+}
+
 // c2r along z of nb windows x R rows per group, then the epilogue.  Persistent
 // workgroups; the next group's rows are fetched into registers while the
 // current group is transformed.  Dynamic LDS: lines [nb][R][LP] complex, then
 // the delta rows [R][N] (contraction).  NBCAP bounds nb (registers).
-template <typename T, int N, int EPI, int NBCAP>
+template <typename T, int N, int EPI, int NBCAP, int PREC>
 __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::type* __restrict__ spec,
                                                     int64_t bin_stride, int nb, const T* __restrict__ delta,
                                                     T* __restrict__ out, WinSet map,
@@ -316,7 +380,9 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
         }
         lds_fft<C, M, LP, MAXLINES, true>(s, tw, nlines);
         // real value of window b, row r, z: sf[2 * (b * R + r) * LP + z]
-        if (EPI == EPI_CONTRACT) {
+        if constexpr (EPI == EPI_CONTRACT && PREC != HERMES_PREC_FP32) {
+            mfma_contract<T, N, PREC>(sf, sd, nb, acc64);
+        } else if constexpr (EPI == EPI_CONTRACT) {
             if (cg < cg_n) {
                 float acc[4][4];
 #pragma unroll
@@ -371,7 +437,23 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
 
     // workgroup reduction of the float64 partial sums
     double* red = lds_raw;
-    if (EPI == EPI_CONTRACT) {
+    if constexpr (EPI == EPI_CONTRACT && PREC != HERMES_PREC_FP32) {
+        // acc64[r] of lane l in wave w holds C[i][j], j = l % 32,
+        // i = 8 (r / 4) + 4 (l / 32) + r % 4 (32x32 MFMA accumulator layout)
+        const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+        for (int st = 0; st < 4; ++st) {
+            if (w == st) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int i = 8 * (r / 4) + 4 * (l / 32) + (r % 4), j = l % 32;
+                    red[i * 32 + j] = (st == 0 ? 0.0 : red[i * 32 + j]) + acc64[r];
+                }
+            }
+            __syncthreads();
+        }
+        double* dst = part + int64_t(blockIdx.x) * nb * nb;
+        for (int e = threadIdx.x; e < nb * nb; e += kThreads) dst[e] = red[(e / nb) * 32 + e % nb];
+    } else if constexpr (EPI == EPI_CONTRACT) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) red[threadIdx.x * 16 + i] = acc64[i];
         __syncthreads();
@@ -444,21 +526,21 @@ inline int z_grid_rt(int n) {
     return groups < kZGroups ? groups : kZGroups;
 }
 
-template <typename T, int N, int EPI, int NBCAP>
+template <typename T, int N, int EPI, int NBCAP, int PREC>
 static void launch_z(const typename cplx_of<T>::type* sp, int64_t bin_stride, int nb, const T* delta, T* out,
                      const WinSet& ws, double* part, const typename cplx_of<T>::type* tw, hipStream_t stream) {
     constexpr int CAP = NBCAP < z_max_batch<T, N>() ? NBCAP : z_max_batch<T, N>();
     const size_t lds = z_lds_bytes<T, N>(nb);
-    allow_lds(k_c2r_z<T, N, EPI, CAP>, lds);
-    hipLaunchKernelGGL((k_c2r_z<T, N, EPI, CAP>), dim3(z_grid<N>()), dim3(kThreads), lds, stream, sp, bin_stride, nb,
-                       delta, out, ws, part, tw);
+    allow_lds(k_c2r_z<T, N, EPI, CAP, PREC>, lds);
+    hipLaunchKernelGGL((k_c2r_z<T, N, EPI, CAP, PREC>), dim3(z_grid<N>()), dim3(kThreads), lds, stream, sp, bin_stride,
+                       nb, delta, out, ws, part, tw);
 }
 
 // One batch: pass X, Y, Z over nb windows sharing the angular factor.
 template <typename T, int N, int EPI>
 static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, double box_L, const WinSet& ws, int sh,
                       int ell, int m, bool build_table, void* ang_ws, void* spec_ws, T* rtab, double* part, T* out,
-                      hipStream_t stream) {
+                      int precision, hipStream_t stream) {
     using C = typename cplx_of<T>::type;
     constexpr int P = N / 2 + 1, PP = pitch_of<N>();
     constexpr int TC = col_cfg<T, N>::TC;
@@ -502,12 +584,22 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
     }
     {
         LaunchScope ls(ctx, stream, EPI == EPI_CONTRACT ? "inv_z_contract" : "inv_z_moments");
-        if (EPI == EPI_CONTRACT && nb <= 20)
-            launch_z<T, N, EPI, 20>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-        else if (EPI == EPI_CONTRACT)
-            launch_z<T, N, EPI, kMaxBatch>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-        else
-            launch_z<T, N, EPI, kFilterChunk>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+        if constexpr (EPI == EPI_CONTRACT) {
+            // register capacity: 20 bins (the common case) or the full batch
+            const bool small = nb <= 20;
+            if (precision == HERMES_PREC_BF16X3) {
+                if (small) launch_z<T, N, EPI, 20, HERMES_PREC_BF16X3>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+                else launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_BF16X3>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+            } else if (precision == HERMES_PREC_FP16X3) {
+                if (small) launch_z<T, N, EPI, 20, HERMES_PREC_FP16X3>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+                else launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_FP16X3>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+            } else {
+                if (small) launch_z<T, N, EPI, 20, HERMES_PREC_FP32>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+                else launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_FP32>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+            }
+        } else {
+            launch_z<T, N, EPI, kFilterChunk, HERMES_PREC_FP32>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+        }
     }
 }
 
@@ -568,7 +660,7 @@ static hermes_status filter_n(hermes_ctx ctx, const void* delta_k, double box_L,
             ++i;
         }
         run_batch<T, N, EPI_MOMENTS>(ctx, delta_k, nullptr, box_L, ws, k0.sh, k0.ell, k0.m, true, ang, spec, rtab,
-                                     moments ? part : nullptr, static_cast<T*>(out), stream);
+                                     moments ? part : nullptr, static_cast<T*>(out), HERMES_PREC_FP32, stream);
         if (moments) {
             LaunchScope ls(ctx, stream, "reduce");
             hipLaunchKernelGGL(k_reduce_moments, dim3(ws.n * 3), dim3(kThreads), 0, stream, part, grid, ws, inv_nc,
@@ -615,8 +707,8 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
     const int nb = edges.n_bins;
     if (nb > z_max_batch<float, N>())
         return fail(HERMES_ERR_UNSUPPORTED, "hermes_zeta_l: too many radial bins for this grid size");
-    if (precision != HERMES_PREC_FP32)
-        return fail(HERMES_ERR_UNSUPPORTED, "hermes_zeta_l: mixed-precision contraction not available");
+    if (precision != HERMES_PREC_FP32 && nb > 32)
+        return fail(HERMES_ERR_UNSUPPORTED, "hermes_zeta_l: the matrix-core contraction takes at most 32 bins");
     const size_t nq = size_t(qmax_of(N) + 1);
     char* w = static_cast<char*>(work);
     void* ang = w;
@@ -642,7 +734,7 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
         }
         for (int m = -ell; m <= ell; ++m) {
             run_batch<float, N, EPI_CONTRACT>(ctx, delta_k, delta, box_L, ws, 1, ell, m, m == -ell, ang, spec,
-                                              rtab, part, nullptr, stream);
+                                              rtab, part, nullptr, precision, stream);
             LaunchScope ls(ctx, stream, "reduce");
             hipLaunchKernelGGL(k_reduce_part, dim3(nb * nb), dim3(kThreads), 0, stream, part, grid, nb * nb, scale,
                                zeta + int64_t(ell) * nb * nb, 1);

@@ -154,18 +154,44 @@ def test_filter_sh_window_field(hermes):
         assert normwise(fields[i], ref) < 1e-10, (ell, m)
 
 
-def test_zeta_small(hermes):
+ZETA_TOL = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16x3": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def small_zeta_case():
     L, n = 120.0, 32
     pos, _ = _cat(40, 40, 2.0, L, 5001)
-    _, _, dk, delta = _gpu_field(hermes, pos, None, L, n, torch.float32)
     _, _, od, odh = _oracle_field(pos, None, L, n)
     edges = np.array([6.0, 10.0, 15.0, 21.0, 28.0])
     lmax = 4
-    got = hermes.zeta_l(delta, dk, L, edges, lmax).cpu().numpy()
     ref = O.zeta_multipoles(od, odh, L, edges, ells=tuple(range(lmax + 1)))
+    return pos, L, n, edges, lmax, ref
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+def test_zeta_small(hermes, small_zeta_case, precision):
+    pos, L, n, edges, lmax, ref = small_zeta_case
+    _, _, dk, delta = _gpu_field(hermes, pos, None, L, n, torch.float32)
+    got = hermes.zeta_l(delta, dk, L, edges, lmax, precision=precision).cpu().numpy()
     for ell in range(lmax + 1):
-        assert normwise(got[ell], ref[ell]) < 1e-5, ell
-    assert np.max(np.abs(got - got.transpose(0, 2, 1))) == 0
+        assert normwise(got[ell], ref[ell]) < ZETA_TOL[precision], (precision, ell)
+    if precision == "fp32":
+        assert np.max(np.abs(got - got.transpose(0, 2, 1))) == 0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_zeta_ragged_bins_and_tiny_grid(hermes, precision):
+    """Odd bin counts (ragged 4x4 tiles and MFMA padding), l_max = 0 and the
+    smallest grid."""
+    for n, L, edges, lmax in [(8, 40.0, [3.0, 7.0, 11.0], 2), (32, 100.0, np.linspace(5, 40, 8), 0),
+                              (16, 64.0, [4.0, 9.0], 3)]:
+        pos, _ = _cat(20, 30, 2.0, L, 5100 + n)
+        _, _, dk, delta = _gpu_field(hermes, pos, None, L, n, torch.float32)
+        _, _, od, odh = _oracle_field(pos, None, L, n)
+        got = hermes.zeta_l(delta, dk, L, edges, lmax, precision=precision).cpu().numpy()
+        ref = O.zeta_multipoles(od, odh, L, np.asarray(edges), ells=tuple(range(lmax + 1)))
+        for ell in range(lmax + 1):
+            assert normwise(got[ell], ref[ell]) < ZETA_TOL[precision], (n, ell)
 
 
 def test_errors_are_reported(hermes):
