@@ -117,6 +117,47 @@ def cpu_baseline(n: int, box_L: float, nb_xi: int, nb_zeta: int, l_max: int) -> 
     }
 
 
+def serving_benchmark(precisions, n_requests: int = 64) -> dict:
+    """The serving workload: requests with Poisson arrivals at 0.7 of the
+    solo service capacity, continuous admission under an HBM budget."""
+    import copy
+
+    import numpy as np
+
+    from paper_2607_23494_amd import serving as S
+
+    t0 = time.perf_counter()
+    base = S.make_workload(n_requests)
+    log(f"serving workload: {n_requests} requests generated in {time.perf_counter() - t0:.1f}s")
+    out = {"workload": f"{n_requests} Neyman-Scott catalogues, 1e5-1e7 points (log-uniform), grids "
+                       "128/256/512, random subsets of {2PCF 40 bins, xi_l l<=4 30 bins, 3PCF l<=6 12 bins}; "
+                       "4 slots, 200 GB budget, Poisson arrivals at 0.7 / mean solo service time"}
+    warm = S.Server(slots=1)
+    for prec in precisions:
+        reqs = copy.copy(base)
+        reqs = [dataclasses_replace(r, precision=prec, arrival=0.0) for r in reqs]
+        warm.run([dataclasses_replace(reqs[0], rid=-1)])
+        solo = S.Server(slots=1).run(reqs)
+        service = np.array([r.finish - r.admit for r in solo if r.status == "ok"])
+        mean = float(service.mean())
+        rate = 0.7 / mean
+        S.poisson_arrivals(reqs, rate, seed=2607_0005)
+        res = S.Server(slots=4, budget_bytes=200 << 30).run(reqs)
+        summ = S.latency_summary(res)
+        summ.update({"mean_solo_service_s": round(mean, 4), "arrival_rate_per_s": round(rate, 3)})
+        for k in ("p50_s", "p99_s", "throughput_req_per_s"):
+            if summ[k] is not None:
+                summ[k] = round(summ[k], 4)
+        out[prec] = summ
+        log(f"serving {prec}: " + json.dumps(summ))
+    return out
+
+
+def dataclasses_replace(obj, **kw):
+    import dataclasses
+    return dataclasses.replace(obj, **kw)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +167,7 @@ def main() -> int:
     ap.add_argument("--compare", action="store_true",
                     help="also time one step with the fp32 contraction for the mixed-vs-fp32 ratio")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU only: the path is built for a single MI355X and has no multi-GPU mode.")
@@ -232,6 +274,11 @@ def main() -> int:
         "roofline": roofline,
     }
     result.update(extra)
+    if not args.no_serving:
+        del pos, w, eps, delta, dk, z_work, xi_work
+        torch.cuda.empty_cache()
+        precs = [args.precision] + (["fp32"] if args.precision != "fp32" else [])
+        result["serving"] = serving_benchmark(precs)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(n, L, nb_xi, nb_z, L_MAX)
     print(json.dumps(result), flush=True)
