@@ -168,6 +168,9 @@ def main() -> int:
                     help="also time one step with the fp32 contraction for the mixed-vs-fp32 ratio")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain elementwise kernel that reads and writes 1 GiB, as the reference "
+                         "for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU only: the path is built for a single MI355X and has no multi-GPU mode.")
@@ -201,6 +204,13 @@ def main() -> int:
                           device="cuda")
     z_work = torch.empty(hermes.workspace_size(hermes.OP_ZETA, n, torch.float32, nb_z, 1), dtype=torch.uint8,
                          device="cuda")
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.neg(a)          # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration: 1 GiB read + 1 GiB write done")
 
     def step(precision):
         hermes.assign(pos, w, L, n, eps=eps, sum_w=sw)
