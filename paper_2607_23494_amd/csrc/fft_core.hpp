@@ -79,8 +79,10 @@ template <int REM> struct radix_for {
     static constexpr int value = (REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : 2);
 };
 
-// One Stockham stage with current sub-transform length NS.
-template <typename C, int L, int LP, int MAXLINES, int NS, bool INV>
+// One Stockham stage with current sub-transform length NS.  The twiddle
+// exp(-2 pi i m / L) is read at tw[TWOFF + m] (the global table keeps length L
+// at offset L; an LDS copy of one table uses offset 0).
+template <typename C, int L, int LP, int MAXLINES, int NS, bool INV, int TWOFF>
 __device__ __forceinline__ void fft_stage(C* s, const C* __restrict__ tw, int nlines) {
     constexpr int R = radix_for<L / NS>::value;
     constexpr int PER = L / R;
@@ -109,7 +111,7 @@ __device__ __forceinline__ void fft_stage(C* s, const C* __restrict__ tw, int nl
             if constexpr (NS > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    C w = tw[L + r * k * TWS];
+                    C w = tw[TWOFF + r * k * TWS];
                     if (INV) w.y = -w.y;
                     v[i][r] = c_mul(v[i][r], w);
                 }
@@ -123,21 +125,21 @@ __device__ __forceinline__ void fft_stage(C* s, const C* __restrict__ tw, int nl
     __syncthreads();
 }
 
-template <typename C, int L, int LP, int MAXLINES, int NS, bool INV>
+template <typename C, int L, int LP, int MAXLINES, int NS, bool INV, int TWOFF>
 __device__ __forceinline__ void fft_stages(C* s, const C* __restrict__ tw, int nlines) {
     if constexpr (NS < L) {
         constexpr int R = radix_for<L / NS>::value;
-        fft_stage<C, L, LP, MAXLINES, NS, INV>(s, tw, nlines);
-        fft_stages<C, L, LP, MAXLINES, NS * R, INV>(s, tw, nlines);
+        fft_stage<C, L, LP, MAXLINES, NS, INV, TWOFF>(s, tw, nlines);
+        fft_stages<C, L, LP, MAXLINES, NS * R, INV, TWOFF>(s, tw, nlines);
     }
 }
 
 // In-place FFT of nlines (<= MAXLINES) lines.  Begins with a barrier so the
 // caller's LDS writes are visible; ends with one so results are readable.
-template <typename C, int L, int LP, int MAXLINES, bool INV>
+template <typename C, int L, int LP, int MAXLINES, bool INV, int TWOFF = L>
 __device__ __forceinline__ void lds_fft(C* s, const C* __restrict__ tw, int nlines) {
     __syncthreads();
-    fft_stages<C, L, LP, MAXLINES, 1, INV>(s, tw, nlines);
+    fft_stages<C, L, LP, MAXLINES, 1, INV, TWOFF>(s, tw, nlines);
 }
 
 // ---------------------------------------------------------------- interleaved layout
@@ -145,7 +147,7 @@ __device__ __forceinline__ void lds_fft(C* s, const C* __restrict__ tw, int nlin
 // line c at s[idx * TC + c].  Consecutive threads take consecutive lines, so
 // every LDS access of a wavefront covers whole contiguous rows of the tile and
 // no padding is needed against bank conflicts.  All TC lines are transformed.
-template <typename C, int L, int TC, int NS, bool INV, int NT>
+template <typename C, int L, int TC, int NS, bool INV, int NT, int TWOFF>
 __device__ __forceinline__ void fft_stage_il(C* s, const C* __restrict__ tw) {
     constexpr int R = radix_for<L / NS>::value;
     constexpr int PER = L / R;
@@ -170,7 +172,7 @@ __device__ __forceinline__ void fft_stage_il(C* s, const C* __restrict__ tw) {
         if constexpr (NS > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                C w = tw[L + r * k * TWS];
+                C w = tw[TWOFF + r * k * TWS];
                 if (INV) w.y = -w.y;
                 v[i][r] = c_mul(v[i][r], w);
             }
@@ -183,20 +185,26 @@ __device__ __forceinline__ void fft_stage_il(C* s, const C* __restrict__ tw) {
     __syncthreads();
 }
 
-template <typename C, int L, int TC, int NS, bool INV, int NT>
+template <typename C, int L, int TC, int NS, bool INV, int NT, int TWOFF>
 __device__ __forceinline__ void fft_stages_il(C* s, const C* __restrict__ tw) {
     if constexpr (NS < L) {
         constexpr int R = radix_for<L / NS>::value;
-        fft_stage_il<C, L, TC, NS, INV, NT>(s, tw);
-        fft_stages_il<C, L, TC, NS * R, INV, NT>(s, tw);
+        fft_stage_il<C, L, TC, NS, INV, NT, TWOFF>(s, tw);
+        fft_stages_il<C, L, TC, NS * R, INV, NT, TWOFF>(s, tw);
     }
 }
 
 // NT = threads of the workgroup
-template <typename C, int L, int TC, bool INV, int NT>
+template <typename C, int L, int TC, bool INV, int NT, int TWOFF = L>
 __device__ __forceinline__ void lds_fft_il(C* s, const C* __restrict__ tw) {
     __syncthreads();
-    fft_stages_il<C, L, TC, 1, INV, NT>(s, tw);
+    fft_stages_il<C, L, TC, 1, INV, NT, TWOFF>(s, tw);
+}
+
+// Copy the twiddle table of length L (tw[L .. 2L)) into LDS (twl[0 .. L)).
+template <typename C, int L, int NT>
+__device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw) {
+    for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[L + i];
 }
 
 // ---------------------------------------------------------------- mode helpers

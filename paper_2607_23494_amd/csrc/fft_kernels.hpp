@@ -148,6 +148,8 @@ __global__ __launch_bounds__(kColThreads) void k_c2c_cols(typename cplx_of<T>::t
     using G = col_cfg<T, N>;
     constexpr int TC = G::TC, VEC = G::VEC, LPR = G::LPR, RPP = G::RPP, NLD = G::NLD;
     __shared__ C s[N * TC];
+    __shared__ C twl[N];
+    stage_twiddles<C, N, kColThreads>(twl, tw);
     const int c0 = blockIdx.x * TC;
     const int nc = min(TC, ncols - c0);
     C* base = data + int64_t(blockIdx.y) * plane_stride + c0;
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(kColThreads) void k_c2c_cols(typename cplx_of<T>::t
     for (int i = 0; i < NLD; ++i)
 #pragma unroll
         for (int v = 0; v < VEC; ++v) s[(r0 + i * RPP) * TC + lc + v] = buf[i][v];
-    lds_fft_il<C, N, TC, INV, kColThreads>(s, tw);
+    lds_fft_il<C, N, TC, INV, kColThreads, 0>(s, twl);
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
         const int p = r0 + i * RPP;

@@ -53,7 +53,7 @@ template <typename T, int N>
 constexpr size_t z_lds_bytes(int nb) {
     using C = typename cplx_of<T>::type;
     constexpr int R = zrows<N>::R, LP = zrows<N>::LP;
-    const size_t lines = size_t(nb) * R * LP * sizeof(C) + size_t(R) * N * sizeof(T);
+    const size_t lines = size_t(nb) * R * LP * sizeof(C) + size_t(R) * N * sizeof(T) + size_t(N + 1) * sizeof(C);
     const size_t red = size_t(kThreads) * 16 * sizeof(double);
     return lines > red ? lines : red;
 }
@@ -153,6 +153,8 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
     constexpr int PP = pitch_of<N>();
     constexpr int64_t PLANE = int64_t(N) * PP;
     __shared__ C s[N * TC];
+    __shared__ C twl[N];
+    stage_twiddles<C, N, kColThreads>(twl, tw);
     const int c0 = blockIdx.x * TC;
     const int lc = (threadIdx.x % LPR) * VEC, r0 = threadIdx.x / LPR;
     const bool in_plane = c0 + lc < PLANE;   // PLANE is a multiple of VEC
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
                 s[(r0 + i * RPP) * TC + lc + v] = C{raw[i][v].x * r, raw[i][v].y * r};
             }
         }
-        lds_fft_il<C, N, TC, true, kColThreads>(s, tw);
+        lds_fft_il<C, N, TC, true, kColThreads, 0>(s, twl);
         C* ob = out + b * bin_stride + c0 + lc;
 #pragma unroll
         for (int i = 0; i < NLD; ++i) {
@@ -269,8 +271,11 @@ __device__ __forceinline__ void mfma_contract(const T* sf, const T* sd, int nb, 
 
 // c2r along z of nb windows x R rows per group, then the epilogue.  Persistent
 // workgroups; the next group's rows are fetched into registers while the
-// current group is transformed.  Dynamic LDS: lines [nb][R][LP] complex, then
-// the delta rows [R][N] (contraction).  NBCAP bounds nb (registers).
+// current group is transformed, and no other global load is issued until they
+// are consumed (twiddles live in LDS), so the fetch overlaps the transform.
+// Dynamic LDS: lines [nb][R][LP] complex, the delta rows [R][N], then the
+// twiddles: exp(-2 pi i m/M) for m < M followed by exp(-2 pi i k/N) for k <= M.
+// NBCAP bounds nb (registers).
 template <typename T, int N, int EPI, int NBCAP, int PREC>
 __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::type* __restrict__ spec,
                                                     int64_t bin_stride, int nb, const T* __restrict__ delta,
@@ -289,8 +294,10 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
     C* s = reinterpret_cast<C*>(lds_raw);
     T* sf = reinterpret_cast<T*>(lds_raw);
     T* sd = reinterpret_cast<T*>(s + nb * R * LP);
+    C* twl = reinterpret_cast<C*>(sd + R * N);
     const int nlines = nb * R;
     const int ne = nlines * P;
+    for (int i = threadIdx.x; i <= N; i += kThreads) twl[i] = i < M ? tw[M + i] : tw[N + (i - M)];
 
     // contraction roles: 4x4 bin tiles (I <= J) x cell groups
     const int nt4 = (nb + 3) / 4;
@@ -368,17 +375,17 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
             {
                 const C sum{xk.x + xm.x, xk.y - xm.y};
                 const C dif{xk.x - xm.x, xk.y + xm.y};
-                const C t = c_mul(c_conj(tw[N + k]), dif);
+                const C t = c_mul(c_conj(twl[M + k]), dif);
                 Lr[k] = C{sum.x - t.y, sum.y + t.x};
             }
             if (k > 0 && k < M - k) {
                 const C sum{xm.x + xk.x, xm.y - xk.y};
                 const C dif{xm.x - xk.x, xm.y + xk.y};
-                const C t = c_mul(c_conj(tw[N + M - k]), dif);
+                const C t = c_mul(c_conj(twl[M + M - k]), dif);
                 Lr[M - k] = C{sum.x - t.y, sum.y + t.x};
             }
         }
-        lds_fft<C, M, LP, MAXLINES, true>(s, tw, nlines);
+        lds_fft<C, M, LP, MAXLINES, true, 0>(s, twl, nlines);
         // real value of window b, row r, z: sf[2 * (b * R + r) * LP + z]
         if constexpr (EPI == EPI_CONTRACT && PREC != HERMES_PREC_FP32) {
             mfma_contract<T, N, PREC>(sf, sd, nb, acc64);
