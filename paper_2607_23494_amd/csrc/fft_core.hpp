@@ -201,6 +201,76 @@ __device__ __forceinline__ void lds_fft_il(C* s, const C* __restrict__ tw) {
     fft_stages_il<C, L, TC, 1, INV, NT, TWOFF>(s, tw);
 }
 
+// ---------------------------------------------------------------- column tiles
+// Register-staged transform of a tile of TC columns of length L (L >= 8) in
+// the interleaved layout, for NT = (TC / VEC) (L / 8) threads.  Thread t owns
+// columns lc .. lc + VEC - 1 (lc = (t % (TC / VEC)) VEC) at positions
+// j + i L/8, i < 8, j = t / (TC / VEC): the inputs of one radix-8 butterfly
+// per column of the first Stockham stage, so values just loaded from global
+// memory go through that stage in registers.  The middle stages run in LDS and
+// the last stage hands every output to st(position, column, value) instead of
+// writing LDS, which halves the LDS traffic of a load / transform / store
+// sequence.  Starts by writing LDS (the caller synchronises after any earlier
+// reads of the tile) and ends with LDS reads still pending (the caller
+// synchronises before writing the tile again).
+template <typename C, int L, int TC, bool INV, int NT, int TWOFF, int NS, typename ST>
+__device__ __forceinline__ void col_stages(C* s, const C* __restrict__ tw, ST& st) {
+    constexpr int R = radix_for<L / NS>::value;
+    if constexpr (NS * R < L) {
+        fft_stage_il<C, L, TC, NS, INV, NT, TWOFF>(s, tw);
+        col_stages<C, L, TC, INV, NT, TWOFF, NS * R>(s, tw, st);
+    } else {
+        // last stage: j < PER = NS, so k = j and the outputs sit at j + r NS
+        constexpr int PER = L / R;
+        constexpr int TOT = TC * PER;
+        static_assert(TOT % NT == 0, "tile must split evenly over the workgroup");
+#pragma unroll
+        for (int i = 0; i < TOT / NT; ++i) {
+            const int b = threadIdx.x + i * NT;
+            const int line = b % TC, j = b / TC;
+            C v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = s[(j + r * PER) * TC + line];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                C w = tw[TWOFF + r * j];
+                if (INV) w.y = -w.y;
+                v[r] = c_mul(v[r], w);
+            }
+            butterfly<INV, R>(v);
+#pragma unroll
+            for (int r = 0; r < R; ++r) st(j + r * NS, line, v[r]);
+        }
+    }
+}
+
+template <typename C, int L, int TC, int VEC, bool INV, int NT, int TWOFF, typename ST>
+__device__ __forceinline__ void col_fft(C* s, const C* __restrict__ tw, C (&x)[8][VEC], int lc, int j, ST& st) {
+    static_assert(L >= 8 && NT == (TC / VEC) * (L / 8), "one radix-8 butterfly per owned column");
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        C y[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) y[i] = x[i][v];
+        butterfly<INV, 8>(y);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i][v] = y[i];
+    }
+    if constexpr (L == 8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) st(r, lc + v, x[r][v]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s[(8 * j + r) * TC + lc + v] = x[r][v];
+        __syncthreads();
+        col_stages<C, L, TC, INV, NT, TWOFF, 8>(s, tw, st);
+    }
+}
+
 // Copy the twiddle table of length L (tw[L .. 2L)) into LDS (twl[0 .. L)).
 template <typename C, int L, int NT>
 __device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw) {

@@ -18,16 +18,17 @@ template <> struct fft_cfg<double> { static constexpr int elems = 4096; };
 
 constexpr int kColThreads = 512;   // threads of the column-pass workgroups
 
-// Column tile geometry: TC columns x N positions, 16-byte vectors of VEC
-// complex, LPR lanes per tile row, RPP rows per load round, NLD rounds.
-template <typename T, int N> struct col_cfg {
+// Column tile geometry: TC columns x N positions for kColThreads threads,
+// each owning VEC adjacent columns (one 8- or 16-byte access) at 8 positions
+// N/8 apart; LPR lanes per tile row, RPP = N/8 rows per load round.
+template <typename T, int N, int VEC_ = 16 / int(sizeof(typename cplx_of<T>::type))> struct col_cfg {
     using C = typename cplx_of<T>::type;
-    static constexpr int TC = fft_cfg<T>::elems / N;
-    static constexpr int VEC = 16 / int(sizeof(C));
+    static constexpr int VEC = VEC_;
+    static constexpr int TC = kColThreads * 8 * VEC / N;
     static constexpr int LPR = TC / VEC;
     static constexpr int RPP = kColThreads / LPR;
     static constexpr int NLD = N / RPP;
-    static_assert(LPR <= kColThreads && N % RPP == 0, "column tile");
+    static_assert(TC >= VEC && NLD == 8 && RPP == N / 8, "column tile");
 };
 
 // Row pitch (complex elements) of the internal padded half spectra: N/2+1
@@ -68,7 +69,9 @@ __device__ __forceinline__ typename vec_of<C>::type vec_join(const C* in) {
 template <typename C, int VEC, bool VECLD>
 __device__ __forceinline__ void load_cols(const C* src, int lc, int nc, C* out) {
     using V = typename vec_of<C>::type;
-    if (VECLD && lc + VEC <= nc) {
+    if constexpr (VEC == 1) {
+        out[0] = lc < nc ? src[0] : C{0, 0};
+    } else if (VECLD && lc + VEC <= nc) {
         vec_split<C, VEC>(*reinterpret_cast<const V*>(src), out);
     } else {
 #pragma unroll
@@ -79,7 +82,9 @@ __device__ __forceinline__ void load_cols(const C* src, int lc, int nc, C* out) 
 template <typename C, int VEC, bool VECLD>
 __device__ __forceinline__ void store_cols(C* dst, int lc, int nc, const C* in) {
     using V = typename vec_of<C>::type;
-    if (VECLD && lc + VEC <= nc) {
+    if constexpr (VEC == 1) {
+        if (lc < nc) dst[0] = in[0];
+    } else if (VECLD && lc + VEC <= nc) {
         *reinterpret_cast<V*>(dst) = vec_join<C, VEC>(in);
     } else {
 #pragma unroll
@@ -157,19 +162,11 @@ __global__ __launch_bounds__(kColThreads) void k_c2c_cols(typename cplx_of<T>::t
     C buf[NLD][VEC];
 #pragma unroll
     for (int i = 0; i < NLD; ++i) load_cols<C, VEC, VECLD>(base + int64_t(r0 + i * RPP) * stride + lc, lc, nc, buf[i]);
-#pragma unroll
-    for (int i = 0; i < NLD; ++i)
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) s[(r0 + i * RPP) * TC + lc + v] = buf[i][v];
-    lds_fft_il<C, N, TC, INV, kColThreads, 0>(s, twl);
-#pragma unroll
-    for (int i = 0; i < NLD; ++i) {
-        const int p = r0 + i * RPP;
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) buf[i][v] = s[p * TC + lc + v];
-        if (zero_dc && blockIdx.y == 0 && c0 + lc == 0 && p == 0) buf[i][0] = C{0, 0};
-        store_cols<C, VEC, VECLD>(base + int64_t(p) * stride + lc, lc, nc, buf[i]);
-    }
+    const bool dc_tile = zero_dc && blockIdx.y == 0 && c0 == 0;
+    auto st = [&](int p, int line, C v) {
+        if (line < nc) base[int64_t(p) * stride + line] = (dc_tile && p == 0 && line == 0) ? C{0, 0} : v;
+    };
+    col_fft<C, N, TC, VEC, INV, kColThreads, 0>(s, twl, buf, lc, r0, st);
 }
 
 template <typename T, int N, bool INV, bool VECLD>

@@ -109,6 +109,38 @@ __global__ __launch_bounds__(kThreads) void k_radial(T* __restrict__ tab, int64_
     }
 }
 
+// ---------------------------------------------------------------- column table
+// The radial factor unrolled along x for every (|ky|, kz) column:
+// U[(row(a, c) nb + b) H + ax] = tab[b nq + a^2 + c^2 + ax^2], H = N/2 + 1,
+// row(a, c) = c (c + 1) / 2 + a for a <= c (the factor is symmetric in |ky|
+// and kz).  The x pass then reads, per column and window, one contiguous run
+// of H values instead of scattering into tab.
+inline int64_t col_rows(int n) { return int64_t(n / 2 + 1) * (n / 2 + 2) / 2; }
+inline size_t col_table_bytes(int n, int nb, size_t elem) { return size_t(col_rows(n)) * nb * (n / 2 + 1) * elem; }
+
+__device__ __forceinline__ int64_t col_row(int a, int c) {
+    if (a > c) { const int t = a; a = c; c = t; }
+    return int64_t(c) * (c + 1) / 2 + a;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_radial_cols(const T* __restrict__ tab, int64_t nq, int nb,
+                                                          T* __restrict__ U) {
+    constexpr int H = N / 2 + 1;
+    const int64_t row = blockIdx.x;
+    // invert row = c (c + 1) / 2 + a, 0 <= a <= c
+    int c = int((sqrt(8.0 * double(row) + 1.0) - 1.0) * 0.5);
+    while (int64_t(c + 1) * (c + 2) / 2 <= row) ++c;
+    while (int64_t(c) * (c + 1) / 2 > row) --c;
+    const int a = int(row - int64_t(c) * (c + 1) / 2);
+    const int64_t q0 = int64_t(a) * a + int64_t(c) * c;
+    T* dst = U + row * nb * H;
+    for (int t = threadIdx.x; t < nb * H; t += kThreads) {
+        const int b = t / H, ax = t - b * H;
+        dst[t] = tab[b * nq + q0 + int64_t(ax) * ax];
+    }
+}
+
 // ---------------------------------------------------------------- angular factor
 // B[kx][ky][kz] = delta^ Phi^ A(k^) s / N^3 on the padded layout (zeros in the
 // row padding), with A = 1 or the Nyquist-averaged Y^R_lm evaluated in float64
@@ -139,65 +171,67 @@ __global__ __launch_bounds__(kThreads) void k_angular(const typename cplx_of<T>:
 }
 
 // ---------------------------------------------------------------- pass X
+// one 16-byte access per thread and tile row: two float or one double complex
+template <typename T> constexpr int win_vec() { return sizeof(T) == 4 ? 2 : 1; }
+
 // Tiles of TC consecutive columns of the padded (ky, kz) plane of B: for every
 // window b multiply by the radial factor R_b(q), q = |n~|^2, inverse FFT along
-// x in LDS and write spectrum b.  Rows are 128-byte aligned.
-template <typename T, int N>
+// x and write spectrum b.  Rows are 128-byte aligned.  The gathers of R_{b+1}
+// are issued before the FFT of window b so their latency overlaps it.
+template <typename T, int N, int VEC>
 __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>::type* __restrict__ B,
                                                     typename cplx_of<T>::type* __restrict__ out,
-                                                    int64_t bin_stride, int nb, const T* __restrict__ rtab,
-                                                    int nq, const typename cplx_of<T>::type* __restrict__ tw) {
+                                                    int64_t bin_stride, int nb, const T* __restrict__ U,
+                                                    const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
-    using G = col_cfg<T, N>;
-    constexpr int TC = G::TC, VEC = G::VEC, LPR = G::LPR, RPP = G::RPP, NLD = G::NLD;
-    constexpr int PP = pitch_of<N>();
+    using G = col_cfg<T, N, VEC>;
+    constexpr int TC = G::TC, LPR = G::LPR, RPP = G::RPP;
+    constexpr int H = N / 2 + 1, PP = pitch_of<N>();
     constexpr int64_t PLANE = int64_t(N) * PP;
     __shared__ C s[N * TC];
     __shared__ C twl[N];
     stage_twiddles<C, N, kColThreads>(twl, tw);
     const int c0 = blockIdx.x * TC;
     const int lc = (threadIdx.x % LPR) * VEC, r0 = threadIdx.x / LPR;
-    const bool in_plane = c0 + lc < PLANE;   // PLANE is a multiple of VEC
-    int qyz[VEC];
+    // columns past N/2 in a row are padding: neither read nor written
+    const T* urow[VEC];
+    bool ok[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         const int c = c0 + lc + v;
         const int ky = c / PP, kz = c - (c / PP) * PP;
-        const int sy = signed_mode<N>(ky & (N - 1));
-        qyz[v] = sy * sy + kz * kz;
+        ok[v] = c < PLANE && kz < H;
+        const int ay = abs(signed_mode<N>(ky & (N - 1)));
+        urow[v] = U + (ok[v] ? col_row(ay, kz) * nb * H : 0);
     }
-    C raw[NLD][VEC];
+    C raw[8][VEC];
 #pragma unroll
-    for (int i = 0; i < NLD; ++i) {
-        if (in_plane) {
-            load_cols<C, VEC, true>(B + (r0 + i * RPP) * PLANE + c0 + lc, 0, VEC, raw[i]);
-        } else {
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) raw[i][v] = C{T(0), T(0)};
+        for (int v = 0; v < VEC; ++v) raw[i][v] = ok[v] ? B[(r0 + i * RPP) * PLANE + c0 + lc + v] : C{T(0), T(0)};
+    T rad[8][VEC];
+    auto gather = [&](int b) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int ax = abs(signed_mode<N>(r0 + i * RPP));
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) rad[i][v] = ok[v] ? urow[v][int64_t(b) * H + ax] : T(0);
         }
-    }
+    };
+    gather(0);
     for (int b = 0; b < nb; ++b) {
-        const T* rb = rtab + int64_t(b) * nq;   // uniform per iteration
+        C x[8][VEC];
 #pragma unroll
-        for (int i = 0; i < NLD; ++i) {
-            const int sx = signed_mode<N>(r0 + i * RPP);
+        for (int i = 0; i < 8; ++i)
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                const int q = in_plane ? sx * sx + qyz[v] : 0;
-                const T r = rb[q];
-                s[(r0 + i * RPP) * TC + lc + v] = C{raw[i][v].x * r, raw[i][v].y * r};
-            }
-        }
-        lds_fft_il<C, N, TC, true, kColThreads, 0>(s, twl);
-        C* ob = out + b * bin_stride + c0 + lc;
-#pragma unroll
-        for (int i = 0; i < NLD; ++i) {
-            const int p = r0 + i * RPP;
-            C o[VEC];
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) o[v] = s[p * TC + lc + v];
-            if (in_plane) store_cols<C, VEC, true>(ob + p * PLANE, 0, VEC, o);
-        }
+            for (int v = 0; v < VEC; ++v) x[i][v] = C{raw[i][v].x * rad[i][v], raw[i][v].y * rad[i][v]};
+        if (b + 1 < nb) gather(b + 1);
+        C* ob = out + b * bin_stride + c0;
+        auto st = [&](int p, int line, C val) {
+            const int c = c0 + line;
+            if (c < PLANE && c % PP < H) ob[int64_t(p) * PLANE + line] = val;
+        };
+        col_fft<C, N, TC, VEC, true, kColThreads, 0>(s, twl, x, lc, r0, st);
         __syncthreads();
     }
 }
@@ -546,11 +580,12 @@ static void launch_z(const typename cplx_of<T>::type* sp, int64_t bin_stride, in
 // One batch: pass X, Y, Z over nb windows sharing the angular factor.
 template <typename T, int N, int EPI>
 static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, double box_L, const WinSet& ws, int sh,
-                      int ell, int m, bool build_table, void* ang_ws, void* spec_ws, T* rtab, double* part, T* out,
+                      int ell, int m, bool build_table, void* ang_ws, void* spec_ws, T* rtab, T* ucol, double* part, T* out,
                       int precision, hipStream_t stream) {
     using C = typename cplx_of<T>::type;
     constexpr int P = N / 2 + 1, PP = pitch_of<N>();
-    constexpr int TC = col_cfg<T, N>::TC;
+    constexpr int XVEC = win_vec<T>();
+    constexpr int TC = col_cfg<T, N, XVEC>::TC;
     const C* tw = tw_ptr<T>(ctx->t);
     const int nb = ws.n;
     const int64_t nq = qmax_of(N) + 1;
@@ -560,6 +595,7 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
         LaunchScope ls(ctx, stream, "radial_table");
         hipLaunchKernelGGL((k_radial<T>), dim3((nq + kThreads - 1) / kThreads), dim3(kThreads), 0, stream, rtab, nq,
                            ws, 2.0 * M_PI / box_L, ctx->t.gl);
+        hipLaunchKernelGGL((k_radial_cols<T, N>), dim3(col_rows(N)), dim3(kThreads), 0, stream, rtab, nq, nb, ucol);
     }
     // scale: angular constant times 1/N^3 (inverse DFT normalisation)
     const double inv = 1.0 / (double(N) * N * N);
@@ -582,8 +618,8 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
     }
     {
         LaunchScope ls(ctx, stream, "inv_x_window");
-        hipLaunchKernelGGL((k_win_x<T, N>), dim3((plane + TC - 1) / TC), dim3(kColThreads), 0, stream, ang, sp,
-                           bin_stride, nb, rtab, int(nq), tw);
+        hipLaunchKernelGGL((k_win_x<T, N, XVEC>), dim3((plane + TC - 1) / TC), dim3(kColThreads), 0, stream, ang, sp,
+                           bin_stride, nb, ucol, tw);
     }
     {
         LaunchScope ls(ctx, stream, "inv_y");
@@ -616,7 +652,7 @@ size_t filter_workspace(int n, int dtype, int n_win) {
     const int chunk = std::min({n_win, kFilterChunk, z_max_batch_rt(n, dbl)});
     const size_t nq = size_t(qmax_of(n) + 1);
     return align256(spec_bytes(n, dbl) * (chunk + 1)) + align256(nq * chunk * (dbl ? 8 : 4)) +
-           align256(size_t(z_grid_rt(n)) * chunk * 3 * sizeof(double));
+           align256(col_table_bytes(n, chunk, dbl ? 8 : 4)) + align256(size_t(z_grid_rt(n)) * chunk * 3 * sizeof(double));
 }
 
 template <typename T, int N>
@@ -628,9 +664,12 @@ static hermes_status filter_n(hermes_ctx ctx, const void* delta_k, double box_L,
     char* w = static_cast<char*>(work);
     void* ang = w;
     void* spec = w + spec_bytes(N, dbl);
-    T* rtab = reinterpret_cast<T*>(w + align256(spec_bytes(N, dbl) * (chunk + 1)));
-    double* part = reinterpret_cast<double*>(w + align256(spec_bytes(N, dbl) * (chunk + 1)) +
-                                             align256(nq * chunk * sizeof(T)));
+    char* tail = w + align256(spec_bytes(N, dbl) * (chunk + 1));
+    T* rtab = reinterpret_cast<T*>(tail);
+    tail += align256(nq * chunk * sizeof(T));
+    T* ucol = reinterpret_cast<T*>(tail);
+    tail += align256(col_table_bytes(N, chunk, sizeof(T)));
+    double* part = reinterpret_cast<double*>(tail);
     // group windows by angular factor: isotropic ones together, SH ones by (l, m)
     struct Key {
         int sh, ell, m;
@@ -667,7 +706,7 @@ static hermes_status filter_n(hermes_ctx ctx, const void* delta_k, double box_L,
             ++i;
         }
         run_batch<T, N, EPI_MOMENTS>(ctx, delta_k, nullptr, box_L, ws, k0.sh, k0.ell, k0.m, true, ang, spec, rtab,
-                                     moments ? part : nullptr, static_cast<T*>(out), HERMES_PREC_FP32, stream);
+                                     ucol, moments ? part : nullptr, static_cast<T*>(out), HERMES_PREC_FP32, stream);
         if (moments) {
             LaunchScope ls(ctx, stream, "reduce");
             hipLaunchKernelGGL(k_reduce_moments, dim3(ws.n * 3), dim3(kThreads), 0, stream, part, grid, ws, inv_nc,
@@ -704,6 +743,7 @@ hermes_status filter_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype,
 size_t zeta_workspace(int n, int n_bins) {
     const size_t nq = size_t(qmax_of(n) + 1);
     return align256(spec_bytes(n, false) * (n_bins + 1)) + align256(nq * n_bins * sizeof(float)) +
+           align256(col_table_bytes(n, n_bins, sizeof(float))) +
            align256(size_t(z_grid_rt(n)) * n_bins * n_bins * sizeof(double));
 }
 
@@ -720,9 +760,12 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
     char* w = static_cast<char*>(work);
     void* ang = w;
     void* spec = w + spec_bytes(N, false);
-    float* rtab = reinterpret_cast<float*>(w + align256(spec_bytes(N, false) * (nb + 1)));
-    double* part = reinterpret_cast<double*>(w + align256(spec_bytes(N, false) * (nb + 1)) +
-                                             align256(nq * nb * sizeof(float)));
+    char* tail = w + align256(spec_bytes(N, false) * (nb + 1));
+    float* rtab = reinterpret_cast<float*>(tail);
+    tail += align256(nq * nb * sizeof(float));
+    float* ucol = reinterpret_cast<float*>(tail);
+    tail += align256(col_table_bytes(N, nb, sizeof(float)));
+    double* part = reinterpret_cast<double*>(tail);
     const int grid = z_grid<N>();
     const double scale = 1.0 / (4.0 * M_PI * double(N) * N * N);
     {
@@ -741,7 +784,7 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
         }
         for (int m = -ell; m <= ell; ++m) {
             run_batch<float, N, EPI_CONTRACT>(ctx, delta_k, delta, box_L, ws, 1, ell, m, m == -ell, ang, spec,
-                                              rtab, part, nullptr, precision, stream);
+                                              rtab, ucol, part, nullptr, precision, stream);
             LaunchScope ls(ctx, stream, "reduce");
             hipLaunchKernelGGL(k_reduce_part, dim3(nb * nb), dim3(kThreads), 0, stream, part, grid, nb * nb, scale,
                                zeta + int64_t(ell) * nb * nb, 1);
