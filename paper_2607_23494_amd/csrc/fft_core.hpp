@@ -271,6 +271,100 @@ __device__ __forceinline__ void col_fft(C* s, const C* __restrict__ tw, C (&x)[8
     }
 }
 
+// ---------------------------------------------------------------- element-major, runtime line count
+// nl lines (at most MAXL) stored element-major with line stride LT >= MAXL:
+// element idx of line c at s[idx * LT + c].  Item b = j nl + c of a stage is
+// taken by thread b % NT, so consecutive threads take consecutive lines and
+// every access of a wavefront is a nearly contiguous run; an odd LT also
+// spreads element-strided accesses (loads of whole lines) over the banks.
+// em_map holds the (j, c) of a thread's first item and the step between its
+// items, so no stage divides by nl.
+struct EmMap {
+    int j0, c0, dj, dc, nl;
+};
+
+template <int NT>
+__device__ __forceinline__ EmMap em_map(int nl) {
+    EmMap m;
+    m.nl = nl;
+    m.j0 = int(threadIdx.x) / nl;
+    m.c0 = int(threadIdx.x) - m.j0 * nl;
+    m.dj = NT / nl;
+    m.dc = NT - m.dj * nl;
+    return m;
+}
+
+__device__ __forceinline__ void em_next(const EmMap& m, int& j, int& c) {
+    c += m.dc;
+    j += m.dj;
+    if (c >= m.nl) {
+        c -= m.nl;
+        ++j;
+    }
+}
+
+// One Stockham stage; tw[m] = exp(-2 pi i m / L) (a table of this length).
+template <typename C, int L, int NS, bool INV, int NT, int MAXL, int LT>
+__device__ __forceinline__ void fft_stage_em(C* s, const C* __restrict__ tw, const EmMap& m) {
+    constexpr int R = radix_for<L / NS>::value;
+    constexpr int PER = L / R;
+    constexpr int TWS = L / (NS * R);
+    constexpr int MAXB = (MAXL * PER + NT - 1) / NT;
+    C v[MAXB][R];
+    int jj[MAXB], cc[MAXB];
+    {
+        int j = m.j0, c = m.c0;
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            jj[i] = j;
+            cc[i] = c;
+            if (j < PER) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i][r] = s[(j + r * PER) * LT + c];
+            }
+            em_next(m, j, c);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int j = jj[i], c = cc[i];
+        if (j < PER) {
+            const int k = j & (NS - 1);
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = tw[r * k * TWS];
+                    if (INV) w.y = -w.y;
+                    v[i][r] = c_mul(v[i][r], w);
+                }
+            }
+            butterfly<INV, R>(v[i]);
+            const int o = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[(o + r * NS) * LT + c] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename C, int L, int NS, bool INV, int NT, int MAXL, int LT>
+__device__ __forceinline__ void fft_stages_em(C* s, const C* __restrict__ tw, const EmMap& m) {
+    if constexpr (NS < L) {
+        constexpr int R = radix_for<L / NS>::value;
+        fft_stage_em<C, L, NS, INV, NT, MAXL, LT>(s, tw, m);
+        fft_stages_em<C, L, NS * R, INV, NT, MAXL, LT>(s, tw, m);
+    }
+}
+
+// In-place FFT of the m.nl lines; begins with a barrier (the caller's writes)
+// and ends with one (results readable).
+template <typename C, int L, bool INV, int NT, int MAXL, int LT>
+__device__ __forceinline__ void lds_fft_em(C* s, const C* __restrict__ tw, const EmMap& m) {
+    __syncthreads();
+    fft_stages_em<C, L, 1, INV, NT, MAXL, LT>(s, tw, m);
+}
+
 // Copy the twiddle table of length L (tw[L .. 2L)) into LDS (twl[0 .. L)).
 template <typename C, int L, int NT>
 __device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw) {

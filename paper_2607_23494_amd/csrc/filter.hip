@@ -44,16 +44,18 @@ struct WinSet {
 template <int N> struct zrows {
     static constexpr int M = N / 2;
     static constexpr int R = M >= 256 ? 1 : 256 / M;   // rows per group
-    static constexpr int LP = M + 1;
 };
+
+// Line stride of the element-major z tile: the line count made odd.
+__host__ __device__ constexpr int z_lt(int nlines) { return nlines | 1; }
 
 constexpr size_t kZLdsBudget = 81920;   // bytes: two z-pass workgroups per CU
 
 template <typename T, int N>
 constexpr size_t z_lds_bytes(int nb) {
     using C = typename cplx_of<T>::type;
-    constexpr int R = zrows<N>::R, LP = zrows<N>::LP;
-    const size_t lines = size_t(nb) * R * LP * sizeof(C) + size_t(R) * N * sizeof(T) + size_t(N + 1) * sizeof(C);
+    constexpr int R = zrows<N>::R, P = N / 2 + 1;
+    const size_t lines = size_t(P) * z_lt(nb * R) * sizeof(C) + size_t(R) * N * sizeof(T) + size_t(N + 1) * sizeof(C);
     const size_t red = size_t(kThreads) * 16 * sizeof(double);
     return lines > red ? lines : red;
 }
@@ -251,9 +253,11 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 // group's cells; lane l supplies bin l % 32 at cells 8 (l / 32) .. +7 of each
 // 16-cell step for both operands.  The float32 tile sum is added to float64
 // accumulators once per group.
-template <typename T, int N, int PREC>
-__device__ __forceinline__ void mfma_contract(const T* sf, const T* sd, int nb, double* acc64) {
-    constexpr int R = zrows<N>::R, LP = zrows<N>::LP;
+template <typename T, int N, int PREC, int LT>
+__device__ __forceinline__ void mfma_contract(const typename cplx_of<T>::type* s, const T* sd, int nb,
+                                              double* acc64) {
+    using C = typename cplx_of<T>::type;
+    constexpr int R = zrows<N>::R;
     constexpr int CELLS = R * N;
     constexpr int PER_WAVE = CELLS / (kThreads / 64);
     static_assert(PER_WAVE % 16 == 0, "16-cell MFMA steps");
@@ -266,11 +270,15 @@ __device__ __forceinline__ void mfma_contract(const T* sf, const T* sd, int nb, 
         const int c0 = w * PER_WAVE + step * 16 + 8 * half;   // 8 consecutive cells of one row
         const int r = c0 / N, z = c0 - r * N;
         float x[8], d[8];
+        const C* src = s + (z >> 1) * LT + bin * R + r;   // complex element z/2 of the line
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            x[t] = bin < nb ? float(sf[2 * (bin * R + r) * LP + z + t]) : 0.f;
-            d[t] = float(sd[c0 + t]);
+        for (int u = 0; u < 4; ++u) {
+            const C v = bin < nb ? src[u * LT] : C{T(0), T(0)};
+            x[2 * u] = float(v.x);
+            x[2 * u + 1] = float(v.y);
         }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) d[t] = float(sd[c0 + t]);
         if constexpr (PREC == HERMES_PREC_BF16X3) {
             bf16x8_t ah, al, bh, bl;
 #pragma unroll
@@ -305,20 +313,24 @@ __device__ __forceinline__ void mfma_contract(const T* sf, const T* sd, int nb, 
 
 // c2r along z of nb windows x R rows per group, then the epilogue.  Persistent
 // workgroups; the next group's rows are fetched into registers while the
-// current group is transformed, and no other global load is issued until they
-// are consumed (twiddles live in LDS), so the fetch overlaps the transform.
-// Dynamic LDS: lines [nb][R][LP] complex, the delta rows [R][N], then the
-// twiddles: exp(-2 pi i m/M) for m < M followed by exp(-2 pi i k/N) for k <= M.
+// current group's epilogue runs (issuing the fetch after the transform keeps
+// those registers free during it), and no other global load is issued until
+// they are consumed (twiddles live in LDS).
+// Dynamic LDS: the nb R lines of N/2 + 1 complex stored element-major with
+// line stride LT = z_lt(NBCAP R) (a compile-time stride keeps every LDS
+// offset of the FFT stages an immediate), the delta rows [R][N], then the twiddles:
+// exp(-2 pi i m/M) for m < M followed by exp(-2 pi i k/N) for k <= M.  Real
+// sample z of line c sits at float index 2 ((z / 2) LT + c) + z % 2.
 // NBCAP bounds nb (registers).
 template <typename T, int N, int EPI, int NBCAP, int PREC>
-__global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::type* __restrict__ spec,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_c2r_z(const typename cplx_of<T>::type* __restrict__ spec,
                                                     int64_t bin_stride, int nb, const T* __restrict__ delta,
                                                     T* __restrict__ out, WinSet map,
                                                     double* __restrict__ part,
                                                     const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
     constexpr int M = N / 2, P = M + 1, PP = pitch_of<N>();
-    constexpr int R = zrows<N>::R, LP = zrows<N>::LP;
+    constexpr int R = zrows<N>::R;
     constexpr int CELLS = R * N;
     constexpr int GROUPS = N * N / R;
     constexpr int MAXLINES = NBCAP * R;
@@ -327,10 +339,13 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
     extern __shared__ double lds_raw[];
     C* s = reinterpret_cast<C*>(lds_raw);
     T* sf = reinterpret_cast<T*>(lds_raw);
-    T* sd = reinterpret_cast<T*>(s + nb * R * LP);
-    C* twl = reinterpret_cast<C*>(sd + R * N);
     const int nlines = nb * R;
+    constexpr int LT = z_lt(MAXLINES);
+    T* sd = reinterpret_cast<T*>(s + P * LT);
+    C* twl = reinterpret_cast<C*>(sd + R * N);
     const int ne = nlines * P;
+    const EmMap em = em_map<kThreads>(nlines);
+    auto at = [&](int line, int z) { return 2 * ((z >> 1) * LT + line) + (z & 1); };
     for (int i = threadIdx.x; i <= N; i += kThreads) twl[i] = i < M ? tw[M + i] : tw[N + (i - M)];
 
     // contraction roles: 4x4 bin tiles (I <= J) x cell groups
@@ -388,7 +403,7 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
             const int e = threadIdx.x + i * kThreads;
             if (e < ne) {
                 const int line = e / P, k = e - line * P;
-                s[line * LP + k] = pre[i];
+                s[k * LT + line] = pre[i];
             }
         }
         if (EPI == EPI_CONTRACT) {
@@ -399,30 +414,34 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
             }
         }
         __syncthreads();
-        if (g + int(gridDim.x) < GROUPS) fetch(g + gridDim.x);
         // c2r packing, in place by (k, M-k) pairs:
         //   Z[k] = (X[k] + X*[M-k]) + i e^{+2 pi i k/N} (X[k] - X*[M-k])
-        for (int e = threadIdx.x; e < nlines * (M / 2 + 1); e += kThreads) {
-            const int line = e / (M / 2 + 1), k = e - line * (M / 2 + 1);
-            C* Lr = s + line * LP;
-            const C xk = Lr[k], xm = Lr[M - k];
-            {
-                const C sum{xk.x + xm.x, xk.y - xm.y};
-                const C dif{xk.x - xm.x, xk.y + xm.y};
-                const C t = c_mul(c_conj(twl[M + k]), dif);
-                Lr[k] = C{sum.x - t.y, sum.y + t.x};
-            }
-            if (k > 0 && k < M - k) {
-                const C sum{xm.x + xk.x, xm.y - xk.y};
-                const C dif{xm.x - xk.x, xm.y + xk.y};
-                const C t = c_mul(c_conj(twl[M + M - k]), dif);
-                Lr[M - k] = C{sum.x - t.y, sum.y + t.x};
+        {
+            int k = em.j0, line = em.c0;
+            while (k <= M / 2) {
+                C* xk_p = s + k * LT + line;
+                C* xm_p = s + (M - k) * LT + line;
+                const C xk = *xk_p, xm = *xm_p;
+                {
+                    const C sum{xk.x + xm.x, xk.y - xm.y};
+                    const C dif{xk.x - xm.x, xk.y + xm.y};
+                    const C t = c_mul(c_conj(twl[M + k]), dif);
+                    *xk_p = C{sum.x - t.y, sum.y + t.x};
+                }
+                if (k > 0 && k < M - k) {
+                    const C sum{xm.x + xk.x, xm.y - xk.y};
+                    const C dif{xm.x - xk.x, xm.y + xk.y};
+                    const C t = c_mul(c_conj(twl[M + M - k]), dif);
+                    *xm_p = C{sum.x - t.y, sum.y + t.x};
+                }
+                em_next(em, k, line);
             }
         }
-        lds_fft<C, M, LP, MAXLINES, true, 0>(s, twl, nlines);
-        // real value of window b, row r, z: sf[2 * (b * R + r) * LP + z]
+        lds_fft_em<C, M, true, kThreads, MAXLINES, LT>(s, twl, em);
+        // the next group's rows load while the epilogue runs
+        if (g + int(gridDim.x) < GROUPS) fetch(g + gridDim.x);
         if constexpr (EPI == EPI_CONTRACT && PREC != HERMES_PREC_FP32) {
-            mfma_contract<T, N, PREC>(sf, sd, nb, acc64);
+            mfma_contract<T, N, PREC, LT>(s, sd, nb, acc64);
         } else if constexpr (EPI == EPI_CONTRACT) {
             if (cg < cg_n) {
                 float acc[4][4];
@@ -437,8 +456,8 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
 #pragma unroll
                     for (int a = 0; a < 4; ++a) {
                         const int b1 = 4 * ti + a, b2 = 4 * tj + a;
-                        xa[a] = b1 < nb ? float(sf[2 * (b1 * R + r) * LP + z]) * d : 0.f;
-                        xb[a] = b2 < nb ? float(sf[2 * (b2 * R + r) * LP + z]) : 0.f;
+                        xa[a] = b1 < nb ? float(sf[at(b1 * R + r, z)]) * d : 0.f;
+                        xb[a] = b2 < nb ? float(sf[at(b2 * R + r, z)]) : 0.f;
                     }
 #pragma unroll
                     for (int a = 0; a < 4; ++a)
@@ -455,14 +474,14 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const typename cplx_of<T>::t
                 for (int e = threadIdx.x; e < nb * CELLS; e += kThreads) {
                     const int b = e / CELLS, rem = e - b * CELLS;
                     const int r = rem / N, z = rem - r * N;
-                    out[int64_t(map.out[b]) * N * N * N + (row0 + r) * N + z] = sf[2 * (b * R + r) * LP + z];
+                    out[int64_t(map.out[b]) * N * N * N + (row0 + r) * N + z] = sf[at(b * R + r, z)];
                 }
             }
             if (part && msub < subs) {
                 T s2 = 0, s3 = 0, s4 = 0;
                 for (int cell = msub; cell < CELLS; cell += subs) {
                     const int r = cell / N, z = cell - r * N;
-                    const T v = sf[2 * (mb * R + r) * LP + z];
+                    const T v = sf[at(mb * R + r, z)];
                     const T v2 = v * v;
                     s2 += v2;
                     s3 += v2 * v;
@@ -571,7 +590,7 @@ template <typename T, int N, int EPI, int NBCAP, int PREC>
 static void launch_z(const typename cplx_of<T>::type* sp, int64_t bin_stride, int nb, const T* delta, T* out,
                      const WinSet& ws, double* part, const typename cplx_of<T>::type* tw, hipStream_t stream) {
     constexpr int CAP = NBCAP < z_max_batch<T, N>() ? NBCAP : z_max_batch<T, N>();
-    const size_t lds = z_lds_bytes<T, N>(nb);
+    const size_t lds = z_lds_bytes<T, N>(CAP);
     allow_lds(k_c2r_z<T, N, EPI, CAP, PREC>, lds);
     hipLaunchKernelGGL((k_c2r_z<T, N, EPI, CAP, PREC>), dim3(z_grid<N>()), dim3(kThreads), lds, stream, sp, bin_stride,
                        nb, delta, out, ws, part, tw);
