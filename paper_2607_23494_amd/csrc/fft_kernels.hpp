@@ -64,6 +64,25 @@ __device__ __forceinline__ typename vec_of<C>::type vec_join(const C* in) {
     }
 }
 
+// Streaming load of one complex value or one 16-byte vector, marked
+// non-temporal: for rows read once and whole (the z pass).  Not for the
+// column passes, whose neighbouring tiles share cache lines.
+typedef float f32x2_nt __attribute__((ext_vector_type(2)));
+typedef float f32x4_nt __attribute__((ext_vector_type(4)));
+typedef double f64x2_nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+    const f32x2_nt v = __builtin_nontemporal_load(reinterpret_cast<const f32x2_nt*>(p));
+    return float2{v.x, v.y};
+}
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+    const f64x2_nt v = __builtin_nontemporal_load(reinterpret_cast<const f64x2_nt*>(p));
+    return double2{v.x, v.y};
+}
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+    const f32x4_nt v = __builtin_nontemporal_load(reinterpret_cast<const f32x4_nt*>(p));
+    return float4{v.x, v.y, v.z, v.w};
+}
+
 // Load VEC consecutive complex values at src (columns lc.. of a tile with nc
 // valid columns); 16-byte access when allowed and fully valid.
 template <typename C, int VEC, bool VECLD>
@@ -144,13 +163,13 @@ __global__ __launch_bounds__(kThreads) void k_fwd_z(const T* __restrict__ eps, c
 // `ncols` contiguous columns in each of gridDim.y planes.  zero_dc clears
 // element 0 of plane 0 after the transform.  VECLD requires 16-byte aligned
 // rows (stride, plane_stride and the base pointer multiples of VEC).
-template <typename T, int N, bool INV, bool VECLD>
+template <typename T, int N, bool INV, bool VECLD, int VEC_>
 __global__ __launch_bounds__(kColThreads) void k_c2c_cols(typename cplx_of<T>::type* __restrict__ data,
                                                        int64_t plane_stride, int ncols, int64_t stride,
                                                        int zero_dc,
                                                        const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
-    using G = col_cfg<T, N>;
+    using G = col_cfg<T, N, VEC_>;
     constexpr int TC = G::TC, VEC = G::VEC, LPR = G::LPR, RPP = G::RPP, NLD = G::NLD;
     __shared__ C s[N * TC];
     __shared__ C twl[N];
@@ -169,12 +188,17 @@ __global__ __launch_bounds__(kColThreads) void k_c2c_cols(typename cplx_of<T>::t
     col_fft<C, N, TC, VEC, INV, kColThreads, 0>(s, twl, buf, lc, r0, st);
 }
 
+// Tiles of 8-byte columns: more, smaller workgroups per CU keep more loads in
+// flight than 16-byte tiles, which these strided column passes need.
+template <typename T> constexpr int c2c_vec() { return 1; }
+
 template <typename T, int N, bool INV, bool VECLD>
 inline void launch_c2c_cols(typename cplx_of<T>::type* data, int n_planes, int64_t plane_stride, int ncols,
                             int64_t stride, bool zero_dc, const typename cplx_of<T>::type* tw, hipStream_t stream) {
-    constexpr int TC = col_cfg<T, N>::TC;
+    constexpr int VEC = c2c_vec<T>();
+    constexpr int TC = col_cfg<T, N, VEC>::TC;
     const int tiles = (ncols + TC - 1) / TC;
-    hipLaunchKernelGGL((k_c2c_cols<T, N, INV, VECLD>), dim3(tiles, n_planes), dim3(kColThreads), 0, stream, data,
+    hipLaunchKernelGGL((k_c2c_cols<T, N, INV, VECLD, VEC>), dim3(tiles, n_planes), dim3(kColThreads), 0, stream, data,
                        plane_stride, ncols, stride, zero_dc ? 1 : 0, tw);
 }
 

@@ -149,8 +149,8 @@ __global__ __launch_bounds__(kThreads) void k_radial_cols(const T* __restrict__ 
 // and s the complex constant (1 or 4 pi i^l).  One thread per padded element.
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_angular(const typename cplx_of<T>::type* __restrict__ dk,
-                                                      typename cplx_of<T>::type* __restrict__ B, int sh, int ell,
-                                                      int m, double sre, double sim,
+                                                      typename cplx_of<T>::type* __restrict__ B, int sh,
+                                                      YlmConst yc, double sre, double sim,
                                                       const double* __restrict__ phi1d) {
     using C = typename cplx_of<T>::type;
     constexpr int M = N / 2, P = M + 1, PP = pitch_of<N>();
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kThreads) void k_angular(const typename cplx_of<T>:
         const C v = dk[row * P + kz];
         const int sx = signed_mode<N>(kx), sy = signed_mode<N>(ky);
         double f = phi1d[N + kx] * phi1d[N + ky] * phi1d[N + kz];
-        if (sh) f *= ylm_mode(ell, m, sx, sy, kz, kx == M, ky == M, kz == M);
+        if (sh) f *= ylm_mode(yc, sx, sy, kz, kx == M, ky == M, kz == M);
         const double re = double(v.x) * sre - double(v.y) * sim;
         const double im = double(v.x) * sim + double(v.y) * sre;
         o = C{T(re * f), T(im * f)};
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             if (e < ne) {
                 const int line = e / P, k = e - line * P;
                 const int b = line / R, r = line - b * R;
-                pre[i] = spec[b * bin_stride + (row0 + r) * PP + k];
+                pre[i] = ld_stream(spec + b * bin_stride + (row0 + r) * PP + k);
             }
         }
         if (EPI == EPI_CONTRACT) {
@@ -394,7 +394,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             }
         }
     };
-
     if (blockIdx.x < GROUPS) fetch(blockIdx.x);
     for (int g = blockIdx.x; g < GROUPS; g += gridDim.x) {
         const int64_t row0 = int64_t(g) * R;
@@ -633,7 +632,7 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
     {
         LaunchScope ls(ctx, stream, "angular");
         hipLaunchKernelGGL((k_angular<T, N>), dim3((bin_stride + kThreads - 1) / kThreads), dim3(kThreads), 0, stream,
-                           static_cast<const C*>(delta_k), ang, sh, ell, m, sre, sim, ctx->t.phi1d);
+                           static_cast<const C*>(delta_k), ang, sh, ylm_const(ell, m), sre, sim, ctx->t.phi1d);
     }
     {
         LaunchScope ls(ctx, stream, "inv_x_window");

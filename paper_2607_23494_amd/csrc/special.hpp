@@ -98,43 +98,67 @@ __device__ __forceinline__ double legendre(int l, double mu) {
 //   m > 0: sqrt2 N_lm P~_l^m(z) Re (x + i y)^m / sin^m theta ...
 // computed through Q_l^m(z) = P_l^m(z) / (1 - z^2)^{m/2} so that
 // sin^m(theta) e^{i m phi} = (x + i y)^m needs no division; P~ carries no
-// Condon-Shortley phase.  m < 0 takes the imaginary part with |m|.
-__device__ __forceinline__ double ylm_real(int l, int m, double x, double y, double z) {
-    const int am = m < 0 ? -m : m;
+// Condon-Shortley phase.  m < 0 takes the imaginary part with |m|.  Every
+// factor that depends on (l, m) only is prepared once on the host (YlmConst):
+// the normalisation sqrt2^{[m != 0]} N_lm (2|m| - 1)!! and the coefficients of
+//   Q_ll = a_ll z Q_{ll-1} - b_ll Q_{ll-2},  a = (2 ll - 1)/(ll - |m|),
+//   b = (ll + |m| - 1)/(ll - |m|),  Q_{|m|} = 1,  Q_{|m|+1} = (2|m| + 1) z,
+// so a mode costs multiplies and adds only.
+struct YlmConst {
+    int l, m, am;
+    double nrm;
+    double a[HERMES_MAX_LMAX + 1], b[HERMES_MAX_LMAX + 1];
+};
+
+inline YlmConst ylm_const(int l, int m) {
+    YlmConst c{};
+    c.l = l;
+    c.m = m;
+    c.am = m < 0 ? -m : m;
     double qmm = 1.0;
-    for (int i = 1; i <= am; ++i) qmm *= (2 * i - 1);
-    double q = qmm;
-    if (l > am) {
-        double q0 = qmm;
-        double q1 = z * (2 * am + 1) * qmm;
-        for (int ll = am + 2; ll <= l; ++ll) {
-            const double q2 = ((2 * ll - 1) * z * q1 - (ll + am - 1) * q0) / (ll - am);
+    for (int i = 1; i <= c.am; ++i) qmm *= (2 * i - 1);
+    double ratio = 1.0;   // (l - |m|)! / (l + |m|)!
+    for (int i = l - c.am + 1; i <= l + c.am; ++i) ratio /= i;
+    c.nrm = sqrt((2 * l + 1) * ratio / (4.0 * 3.14159265358979323846)) * qmm;
+    if (m != 0) c.nrm *= 1.41421356237309504880;
+    for (int ll = c.am + 2; ll <= l; ++ll) {
+        c.a[ll] = double(2 * ll - 1) / (ll - c.am);
+        c.b[ll] = double(ll + c.am - 1) / (ll - c.am);
+    }
+    return c;
+}
+
+__device__ __forceinline__ double ylm_real(const YlmConst& c, double x, double y, double z) {
+    double q = 1.0;
+    if (c.l > c.am) {
+        double q0 = 1.0;
+        double q1 = z * (2 * c.am + 1);
+        for (int ll = c.am + 2; ll <= c.l; ++ll) {
+            const double q2 = c.a[ll] * z * q1 - c.b[ll] * q0;
             q0 = q1;
             q1 = q2;
         }
         q = q1;
     }
-    double ratio = 1.0;   // (l - |m|)! / (l + |m|)!
-    for (int i = l - am + 1; i <= l + am; ++i) ratio /= i;
-    const double nrm = sqrt((2 * l + 1) * ratio / (4.0 * 3.14159265358979323846));
-    if (m == 0) return nrm * q;
+    if (c.m == 0) return c.nrm * q;
     double cr = 1.0, ci = 0.0;
-    for (int i = 0; i < am; ++i) {
+    for (int i = 0; i < c.am; ++i) {
         const double t = cr * x - ci * y;
         ci = cr * y + ci * x;
         cr = t;
     }
-    return 1.41421356237309504880 * nrm * q * (m > 0 ? cr : ci);
+    return c.nrm * q * (c.m > 0 ? cr : ci);
 }
 
 // Y^R_lm at signed mode (sx, sy, sz), averaged over the signed
 // representatives +-N/2 of every Nyquist component (nyq_* true).  At k = 0
 // the value is 1/sqrt(4 pi) for l = 0 and 0 otherwise.
-__device__ __forceinline__ double ylm_mode(int l, int m, int sx, int sy, int sz, bool nyq_x,
-                                           bool nyq_y, bool nyq_z) {
+__device__ __forceinline__ double ylm_mode(const YlmConst& c, int sx, int sy, int sz, bool nyq_x, bool nyq_y,
+                                           bool nyq_z) {
     const double q = double(sx) * sx + double(sy) * sy + double(sz) * sz;
-    if (q == 0.0) return l == 0 ? 0.28209479177387814347 : 0.0;
+    if (q == 0.0) return c.l == 0 ? 0.28209479177387814347 : 0.0;
     const double inv = 1.0 / sqrt(q);
+    if (!(nyq_x || nyq_y || nyq_z)) return ylm_real(c, sx * inv, sy * inv, sz * inv);
     double acc = 0.0;
     int cnt = 0;
     for (int fx = 0; fx <= (nyq_x ? 1 : 0); ++fx)
@@ -143,7 +167,7 @@ __device__ __forceinline__ double ylm_mode(int l, int m, int sx, int sy, int sz,
                 const double x = (fx ? -sx : sx) * inv;
                 const double y = (fy ? -sy : sy) * inv;
                 const double z = (fz ? -sz : sz) * inv;
-                acc += ylm_real(l, m, x, y, z);
+                acc += ylm_real(c, x, y, z);
                 ++cnt;
             }
     return acc / cnt;
