@@ -113,12 +113,23 @@ __global__ __launch_bounds__(kThreads) void k_radial(T* __restrict__ tab, int64_
 
 // ---------------------------------------------------------------- column table
 // The radial factor unrolled along x for every (|ky|, kz) column:
-// U[(row(a, c) nb + b) H + ax] = tab[b nq + a^2 + c^2 + ax^2], H = N/2 + 1,
+// U[(row(a, c) nb + b) HP + ax] = tab[b nq + a^2 + c^2 + ax^2] for ax < H =
+// N/2 + 1 (zeros up to the pitch HP, a multiple of 16 bytes), with
 // row(a, c) = c (c + 1) / 2 + a for a <= c (the factor is symmetric in |ky|
-// and kz).  The x pass then reads, per column and window, one contiguous run
-// of H values instead of scattering into tab.
+// and kz).  The x pass copies the runs of a tile's columns with 16-byte
+// loads instead of scattering into tab.
 inline int64_t col_rows(int n) { return int64_t(n / 2 + 1) * (n / 2 + 2) / 2; }
-inline size_t col_table_bytes(int n, int nb, size_t elem) { return size_t(col_rows(n)) * nb * (n / 2 + 1) * elem; }
+inline int col_pitch_rt(int n, size_t elem) {
+    const int v = int(16 / elem);
+    return (n / 2 + 1 + v - 1) / v * v;
+}
+template <typename T, int N> __host__ __device__ constexpr int col_pitch() {
+    constexpr int v = 16 / int(sizeof(T));
+    return (N / 2 + 1 + v - 1) / v * v;
+}
+inline size_t col_table_bytes(int n, int nb, size_t elem) {
+    return size_t(col_rows(n)) * nb * col_pitch_rt(n, elem) * elem;
+}
 
 __device__ __forceinline__ int64_t col_row(int a, int c) {
     if (a > c) { const int t = a; a = c; c = t; }
@@ -128,7 +139,7 @@ __device__ __forceinline__ int64_t col_row(int a, int c) {
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_radial_cols(const T* __restrict__ tab, int64_t nq, int nb,
                                                           T* __restrict__ U) {
-    constexpr int H = N / 2 + 1;
+    constexpr int H = N / 2 + 1, HP = col_pitch<T, N>();
     const int64_t row = blockIdx.x;
     // invert row = c (c + 1) / 2 + a, 0 <= a <= c
     int c = int((sqrt(8.0 * double(row) + 1.0) - 1.0) * 0.5);
@@ -136,10 +147,10 @@ __global__ __launch_bounds__(kThreads) void k_radial_cols(const T* __restrict__ 
     while (int64_t(c) * (c + 1) / 2 > row) --c;
     const int a = int(row - int64_t(c) * (c + 1) / 2);
     const int64_t q0 = int64_t(a) * a + int64_t(c) * c;
-    T* dst = U + row * nb * H;
-    for (int t = threadIdx.x; t < nb * H; t += kThreads) {
-        const int b = t / H, ax = t - b * H;
-        dst[t] = tab[b * nq + q0 + int64_t(ax) * ax];
+    T* dst = U + row * nb * HP;
+    for (int t = threadIdx.x; t < nb * HP; t += kThreads) {
+        const int b = t / HP, ax = t - b * HP;
+        dst[t] = ax < H ? tab[b * nq + q0 + int64_t(ax) * ax] : T(0);
     }
 }
 
@@ -180,54 +191,86 @@ template <typename T> constexpr int win_vec() { return sizeof(T) == 4 ? 2 : 1; }
 // window b multiply by the radial factor R_b(q), q = |n~|^2, inverse FFT along
 // x and write spectrum b.  Rows are 128-byte aligned.  The gathers of R_{b+1}
 // are issued before the FFT of window b so their latency overlaps it.
+template <typename T> struct vec16;
+template <> struct vec16<float> { using type = float4; };
+template <> struct vec16<double> { using type = double2; };
+
 template <typename T, int N, int VEC>
 __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>::type* __restrict__ B,
                                                     typename cplx_of<T>::type* __restrict__ out,
                                                     int64_t bin_stride, int nb, const T* __restrict__ U,
                                                     const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
+    using V = typename vec16<T>::type;
     using G = col_cfg<T, N, VEC>;
     constexpr int TC = G::TC, LPR = G::LPR, RPP = G::RPP;
-    constexpr int H = N / 2 + 1, PP = pitch_of<N>();
+    constexpr int H = N / 2 + 1, PP = pitch_of<N>(), HP = col_pitch<T, N>();
     constexpr int64_t PLANE = int64_t(N) * PP;
+    constexpr int VE = 16 / int(sizeof(T));           // table values per 16-byte chunk
+    constexpr int CPC = HP / VE;                       // chunks per column run
+    constexpr int NCH = TC * CPC;                      // chunks per tile and window
+    constexpr int CPT = (NCH + kColThreads - 1) / kColThreads;
     __shared__ C s[N * TC];
     __shared__ C twl[N];
+    __shared__ V su[NCH];                              // the tile's table runs, column v at [v CPC, (v+1) CPC)
     stage_twiddles<C, N, kColThreads>(twl, tw);
     const int c0 = blockIdx.x * TC;
     const int lc = (threadIdx.x % LPR) * VEC, r0 = threadIdx.x / LPR;
     // columns past N/2 in a row are padding: neither read nor written
-    const T* urow[VEC];
+    auto col_ok = [&](int c, int64_t& row) {
+        const int ky = c / PP, kz = c - (c / PP) * PP;
+        row = col_row(abs(signed_mode<N>(ky & (N - 1))), kz);
+        return c < PLANE && kz < H;
+    };
     bool ok[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
-        const int c = c0 + lc + v;
-        const int ky = c / PP, kz = c - (c / PP) * PP;
-        ok[v] = c < PLANE && kz < H;
-        const int ay = abs(signed_mode<N>(ky & (N - 1)));
-        urow[v] = U + (ok[v] ? col_row(ay, kz) * nb * H : 0);
+        int64_t row;
+        ok[v] = col_ok(c0 + lc + v, row);
     }
+    // 16-byte chunks of the table runs this thread copies into su
+    const V* csrc[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int i = threadIdx.x + u * kColThreads;
+        const int v = i / CPC;
+        int64_t row = 0;
+        const bool good = i < NCH && col_ok(c0 + v, row);
+        csrc[u] = good ? reinterpret_cast<const V*>(U + row * nb * HP) + (i - v * CPC) : nullptr;
+    }
+    V ureg[CPT];
+    auto uload = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) ureg[u] = csrc[u] ? csrc[u][int64_t(b) * CPC] : V{};
+    };
+    auto ustore = [&]() {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int i = threadIdx.x + u * kColThreads;
+            if (i < NCH) su[i] = ureg[u];
+        }
+    };
+    const T* suf = reinterpret_cast<const T*>(su);
     C raw[8][VEC];
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int v = 0; v < VEC; ++v) raw[i][v] = ok[v] ? B[(r0 + i * RPP) * PLANE + c0 + lc + v] : C{T(0), T(0)};
-    T rad[8][VEC];
-    auto gather = [&](int b) {
+    uload(0);
+    ustore();
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+        C x[8][VEC];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int ax = abs(signed_mode<N>(r0 + i * RPP));
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) rad[i][v] = ok[v] ? urow[v][int64_t(b) * H + ax] : T(0);
+            for (int v = 0; v < VEC; ++v) {
+                const T r = suf[(lc + v) * HP + ax];
+                x[i][v] = C{raw[i][v].x * r, raw[i][v].y * r};
+            }
         }
-    };
-    gather(0);
-    for (int b = 0; b < nb; ++b) {
-        C x[8][VEC];
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) x[i][v] = C{raw[i][v].x * rad[i][v], raw[i][v].y * rad[i][v]};
-        if (b + 1 < nb) gather(b + 1);
+        if (b + 1 < nb) uload(b + 1);   // lands during the transform
         C* ob = out + b * bin_stride + c0;
         auto st = [&](int p, int line, C val) {
             const int c = c0 + line;
@@ -235,6 +278,10 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
         };
         col_fft<C, N, TC, VEC, true, kColThreads, 0>(s, twl, x, lc, r0, st);
         __syncthreads();
+        if (b + 1 < nb) {
+            ustore();
+            __syncthreads();
+        }
     }
 }
 
