@@ -5,6 +5,8 @@ the bins of one statistic (each xi_l, each zeta_l matrix, each moment):
 float32 path <= 1e-5, float64 path <= 1e-10; integer-free, so no bit-exact
 cases apart from the empty catalogue.
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -192,6 +194,29 @@ def test_zeta_ragged_bins_and_tiny_grid(hermes, precision):
         ref = O.zeta_multipoles(od, odh, L, np.asarray(edges), ells=tuple(range(lmax + 1)))
         for ell in range(lmax + 1):
             assert normwise(got[ell], ref[ell]) < ZETA_TOL[precision], (n, ell)
+
+
+@functools.lru_cache(maxsize=None)
+def _wide_case(n_bins):
+    L, n = 160.0, 64
+    pos, _ = _cat(50, 40, 2.5, L, 5200 + n_bins)
+    _, _, od, odh = _oracle_field(pos, None, L, n)
+    edges = np.linspace(4.0, 52.0, n_bins + 1)
+    ref = O.zeta_multipoles(od, odh, L, edges, ells=(0, 1, 2))
+    return pos, L, n, edges, ref
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n_bins", [21, 24])
+def test_zeta_wide_batches(hermes, precision, n_bins):
+    """More than 20 radial bins: the batch-cap-32 kernels of the z pass (odd
+    and even bin counts), on a 64^3 grid (8 rows per z-pass group)."""
+    pos, L, n, edges, ref = _wide_case(n_bins)
+    _, _, dk, delta = _gpu_field(hermes, pos, None, L, n, torch.float32)
+    lmax = 2
+    got = hermes.zeta_l(delta, dk, L, edges, lmax, precision=precision).cpu().numpy()
+    for ell in range(lmax + 1):
+        assert normwise(got[ell], ref[ell]) < ZETA_TOL[precision], (n_bins, ell)
 
 
 def test_errors_are_reported(hermes):
