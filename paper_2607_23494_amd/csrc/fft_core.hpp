@@ -213,12 +213,12 @@ __device__ __forceinline__ void lds_fft_il(C* s, const C* __restrict__ tw) {
 // sequence.  Starts by writing LDS (the caller synchronises after any earlier
 // reads of the tile) and ends with LDS reads still pending (the caller
 // synchronises before writing the tile again).
-template <typename C, int L, int TC, bool INV, int NT, int TWOFF, int NS, typename ST>
-__device__ __forceinline__ void col_stages(C* s, const C* __restrict__ tw, ST& st) {
+template <typename C, int L, int TC, bool INV, int NT, int TWOFF, int NS, typename FIN>
+__device__ __forceinline__ void col_stages(C* s, const C* __restrict__ tw, FIN& fin) {
     constexpr int R = radix_for<L / NS>::value;
     if constexpr (NS * R < L) {
         fft_stage_il<C, L, TC, NS, INV, NT, TWOFF>(s, tw);
-        col_stages<C, L, TC, INV, NT, TWOFF, NS * R>(s, tw, st);
+        col_stages<C, L, TC, INV, NT, TWOFF, NS * R>(s, tw, fin);
     } else {
         // last stage: j < PER = NS, so k = j and the outputs sit at j + r NS
         constexpr int PER = L / R;
@@ -238,15 +238,20 @@ __device__ __forceinline__ void col_stages(C* s, const C* __restrict__ tw, ST& s
                 v[r] = c_mul(v[r], w);
             }
             butterfly<INV, R>(v);
-#pragma unroll
-            for (int r = 0; r < R; ++r) st(j + r * NS, line, v[r]);
+            fin(j, line, v, R, NS);   // v[r] is the output at position j + r NS
         }
     }
 }
 
-template <typename C, int L, int TC, int VEC, bool INV, int NT, int TWOFF, typename ST>
-__device__ __forceinline__ void col_fft(C* s, const C* __restrict__ tw, C (&x)[8][VEC], int lc, int j, ST& st) {
-    static_assert(L >= 8 && NT == (TC / VEC) * (L / 8), "one radix-8 butterfly per owned column");
+// First stage in registers and the middle stages in LDS as described above;
+// the last stage hands each butterfly's outputs to fin(j, line, v, R, NS)
+// (v[r] at position j + r NS of column `line`).  Items of the last stage are
+// dealt so that lane b % 64 of a wavefront holds column b % TC: with TC <= 64
+// the columns of one position j sit in TC consecutive lanes of one wavefront.
+// Requires L > 8.
+template <typename C, int L, int TC, int VEC, bool INV, int NT, int TWOFF, typename FIN>
+__device__ __forceinline__ void col_fft_fin(C* s, const C* __restrict__ tw, C (&x)[8][VEC], int lc, int j, FIN& fin) {
+    static_assert(L > 8 && NT == (TC / VEC) * (L / 8), "one radix-8 butterfly per owned column");
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         C y[8];
@@ -254,20 +259,31 @@ __device__ __forceinline__ void col_fft(C* s, const C* __restrict__ tw, C (&x)[8
         for (int i = 0; i < 8; ++i) y[i] = x[i][v];
         butterfly<INV, 8>(y);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) x[i][v] = y[i];
+        for (int r = 0; r < 8; ++r) s[(8 * j + r) * TC + lc + v] = y[r];
     }
+    __syncthreads();
+    col_stages<C, L, TC, INV, NT, TWOFF, 8>(s, tw, fin);
+}
+
+template <typename C, int L, int TC, int VEC, bool INV, int NT, int TWOFF, typename ST>
+__device__ __forceinline__ void col_fft(C* s, const C* __restrict__ tw, C (&x)[8][VEC], int lc, int j, ST& st) {
+    static_assert(L >= 8 && NT == (TC / VEC) * (L / 8), "one radix-8 butterfly per owned column");
     if constexpr (L == 8) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
+        for (int v = 0; v < VEC; ++v) {
+            C y[8];
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) st(r, lc + v, x[r][v]);
+            for (int i = 0; i < 8; ++i) y[i] = x[i][v];
+            butterfly<INV, 8>(y);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) st(r, lc + v, y[r]);
+        }
     } else {
+        auto fin = [&](int jj, int line, const C* v, int R, int NS) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) s[(8 * j + r) * TC + lc + v] = x[r][v];
-        __syncthreads();
-        col_stages<C, L, TC, INV, NT, TWOFF, 8>(s, tw, st);
+            for (int r = 0; r < R; ++r) st(jj + r * NS, line, v[r]);
+        };
+        col_fft_fin<C, L, TC, VEC, INV, NT, TWOFF>(s, tw, x, lc, j, fin);
     }
 }
 
@@ -363,6 +379,25 @@ template <typename C, int L, bool INV, int NT, int MAXL, int LT>
 __device__ __forceinline__ void lds_fft_em(C* s, const C* __restrict__ tw, const EmMap& m) {
     __syncthreads();
     fft_stages_em<C, L, 1, INV, NT, MAXL, LT>(s, tw, m);
+}
+
+// As col_fft, but every stage after the first one runs in LDS, so the whole
+// transformed tile is left in LDS (element idx of line c at s[idx TC + c])
+// for a caller that combines columns before storing.  Ends with a barrier.
+template <typename C, int L, int TC, int VEC, bool INV, int NT, int TWOFF>
+__device__ __forceinline__ void col_fft_lds(C* s, const C* __restrict__ tw, C (&x)[8][VEC], int lc, int j) {
+    static_assert(L >= 8 && NT == (TC / VEC) * (L / 8), "one radix-8 butterfly per owned column");
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        C y[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) y[i] = x[i][v];
+        butterfly<INV, 8>(y);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) s[(8 * j + r) * TC + lc + v] = y[r];
+    }
+    __syncthreads();
+    fft_stages_il<C, L, TC, 8, INV, NT, TWOFF>(s, tw);
 }
 
 // Copy the twiddle table of length L (tw[L .. 2L)) into LDS (twl[0 .. L)).

@@ -4,17 +4,20 @@
 // isotropic windows, 4 pi i^l Y^R_lm(k^) for the multipole windows of
 // Sec. 3.3.3 Eq. multipole-window), each filtered field is
 //   f_b = iDFT[ delta^ Phi^ A R_b(|k|) ]      (Sec. 4.2, K_W = W^ Phi^)
-// and the three inverse passes are:
-//   X  (k_win_x):  read delta^ once per tile, form delta^ Phi^ A / N^3 in
-//                  registers, then for every window multiply by the radial
-//                  factor R_b(q) (exact table over q = |n~|^2), inverse FFT
-//                  along x in LDS and write the batch spectrum b;
-//   Y  (k_c2c_cols): inverse FFT along y of all nb spectra in place;
-//   Z  (k_c2r_z):  c2r along z for all nb windows of a row group at once and
-//                  a fused epilogue: either the counts-in-cells moments (and
-//                  optionally the stored fields), or the contraction
-//                  sum_x delta(x) f_b1(x) f_b2(x) of the 3PCF (Sec. 3.4,
-//                  Eq. particle_nfold with a naked primary vertex).
+// and, after the angular pass (k_angular: B = delta^ Phi^ A / N^3), the three
+// inverse passes are:
+//   X  (k_win_x):  read a tile of B once, then for every window multiply by
+//                  the radial factor R_b (exact values per |n~|^2, read from a
+//                  per-column table), inverse FFT along x and write the batch
+//                  spectrum b;
+//   Y  (k_inv_y_pack): inverse FFT along y of all nb spectra in place, fused
+//                  with the packing step of the c2r transform along z;
+//   Z  (k_c2r_z):  the length-N/2 complex inverse along z for all nb windows
+//                  of a row group at once and a fused epilogue: either the
+//                  counts-in-cells moments (and optionally the stored
+//                  fields), or the contraction sum_x delta(x) f_b1(x) f_b2(x)
+//                  of the 3PCF (Sec. 3.4, Eq. particle_nfold with a naked
+//                  primary vertex).
 // Grid-wide sums are accumulated in float32 over a row group (<= 1024 cells)
 // and in float64 across groups and workgroups.
 #include <algorithm>
@@ -54,8 +57,8 @@ constexpr size_t kZLdsBudget = 81920;   // bytes: two z-pass workgroups per CU
 template <typename T, int N>
 constexpr size_t z_lds_bytes(int nb) {
     using C = typename cplx_of<T>::type;
-    constexpr int R = zrows<N>::R, P = N / 2 + 1;
-    const size_t lines = size_t(P) * z_lt(nb * R) * sizeof(C) + size_t(R) * N * sizeof(T) + size_t(N + 1) * sizeof(C);
+    constexpr int R = zrows<N>::R, M = N / 2;
+    const size_t lines = size_t(M) * z_lt(nb * R) * sizeof(C) + size_t(R) * N * sizeof(T) + size_t(M) * sizeof(C);
     const size_t red = size_t(kThreads) * 16 * sizeof(double);
     return lines > red ? lines : red;
 }
@@ -110,6 +113,18 @@ __global__ __launch_bounds__(kThreads) void k_radial(T* __restrict__ tab, int64_
         tab[b * nq + q] = T(v);
     }
 }
+
+// ---------------------------------------------------------------- kz order
+// Order of the kz columns in the padded spectra of the inverse passes (after
+// the x pass): the mirror pair (k, M - k), M = N/2, sits at positions 2k and
+// 2k + 1 (k <= M/2), so that the packing step of the c2r transform along z
+// combines neighbouring columns.  Positions 0 .. M hold kz = 0 .. M exactly
+// once (position 1 holds kz = M); position M + 1 would repeat kz = M/2 and the
+// positions above it are row padding.
+template <int N> __host__ __device__ constexpr int kz_of_pos(int pos) { return (pos & 1) ? N / 2 - (pos >> 1) : (pos >> 1); }
+template <int N> __host__ __device__ constexpr bool pos_used(int pos) { return pos <= N / 2; }
+// index k of the packed Z[k] that the y pass stores at position pos, 0 <= pos < N/2
+template <int N> __host__ __device__ constexpr int zk_of_pos(int pos) { return pos == 1 ? N / 4 : kz_of_pos<N>(pos); }
 
 // ---------------------------------------------------------------- column table
 // The radial factor unrolled along x for every (|ky|, kz) column:
@@ -217,16 +232,22 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
     const int c0 = blockIdx.x * TC;
     const int lc = (threadIdx.x % LPR) * VEC, r0 = threadIdx.x / LPR;
     // columns past N/2 in a row are padding: neither read nor written
-    auto col_ok = [&](int c, int64_t& row) {
-        const int ky = c / PP, kz = c - (c / PP) * PP;
+    // output column c of a row is position c % PP, i.e. kz = kz_of_pos(c % PP)
+    auto col_ok = [&](int c, int64_t& row, int& kz) {
+        const int ky = c / PP, pos = c - (c / PP) * PP;
+        kz = kz_of_pos<N>(pos);
         row = col_row(abs(signed_mode<N>(ky & (N - 1))), kz);
-        return c < PLANE && kz < H;
+        return c < PLANE && pos_used<N>(pos);
     };
     bool ok[VEC];
+    int64_t src[VEC];   // element (0, ky, kz) of B in its natural layout
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         int64_t row;
-        ok[v] = col_ok(c0 + lc + v, row);
+        int kz;
+        const int c = c0 + lc + v;
+        ok[v] = col_ok(c, row, kz);
+        src[v] = int64_t(c / PP) * PP + kz;
     }
     // 16-byte chunks of the table runs this thread copies into su
     const V* csrc[CPT];
@@ -235,7 +256,8 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
         const int i = threadIdx.x + u * kColThreads;
         const int v = i / CPC;
         int64_t row = 0;
-        const bool good = i < NCH && col_ok(c0 + v, row);
+        int kz;
+        const bool good = i < NCH && col_ok(c0 + v, row, kz);
         csrc[u] = good ? reinterpret_cast<const V*>(U + row * nb * HP) + (i - v * CPC) : nullptr;
     }
     V ureg[CPT];
@@ -255,7 +277,7 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) raw[i][v] = ok[v] ? B[(r0 + i * RPP) * PLANE + c0 + lc + v] : C{T(0), T(0)};
+        for (int v = 0; v < VEC; ++v) raw[i][v] = ok[v] ? B[(r0 + i * RPP) * PLANE + src[v]] : C{T(0), T(0)};
     uload(0);
     ustore();
     __syncthreads();
@@ -274,13 +296,87 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
         C* ob = out + b * bin_stride + c0;
         auto st = [&](int p, int line, C val) {
             const int c = c0 + line;
-            if (c < PLANE && c % PP < H) ob[int64_t(p) * PLANE + line] = val;
+            if (c < PLANE && pos_used<N>(c % PP)) ob[int64_t(p) * PLANE + line] = val;
         };
         col_fft<C, N, TC, VEC, true, kColThreads, 0>(s, twl, x, lc, r0, st);
         __syncthreads();
         if (b + 1 < nb) {
             ustore();
             __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- pass Y
+// Inverse FFT along y of every (window, x) plane fused with the packing step
+// of the c2r transform along z that follows: with M = N/2, the length-N real
+// inverse of X[0..M] equals the length-M complex inverse of
+//   Z[k] = (X[k] + X*[M-k]) + i e^{+2 pi i k/N} (X[k] - X*[M-k]),  k < M,
+// whose output holds samples 2n and 2n+1 in its real and imaginary parts.
+// Columns k and M - k are neighbours in the pair order (kz_of_pos), so a tile
+// of TC consecutive positions holds whole pairs; the pair is combined right
+// after the transform and Z[kz] overwrites X[kz] at its position, except
+// Z[M/2], which goes to position 1 (kz = M has no Z): the z pass then reads
+// the aligned positions 0 .. M-1, Z[zk_of_pos(pos)].  With TC <= 64 the last Stockham stage leaves the two
+// columns of a pair in neighbouring lanes of one wavefront; wider tiles pair
+// through LDS.  Position M + 1 is loaded as a copy of kz = M/2, the partner of
+// position M.  One 8-byte column per thread and load round.
+template <typename T, int N> struct ypack_cfg {
+    static constexpr int TC = col_cfg<T, N, 1>::TC;   // positions per tile
+    static constexpr int NT = kColThreads;
+    static constexpr int TILES = (N / 2 + 2 + TC - 1) / TC;
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(kColThreads) void k_inv_y_pack(typename cplx_of<T>::type* __restrict__ data,
+                                                         int64_t plane_stride,
+                                                         const typename cplx_of<T>::type* __restrict__ tw) {
+    using C = typename cplx_of<T>::type;
+    constexpr int TC = ypack_cfg<T, N>::TC, NT = kColThreads;
+    constexpr int M = N / 2, PP = pitch_of<N>(), PER = N / 8;
+    static_assert(TC % 2 == 0, "pairs per tile");
+    __shared__ C s[N * TC];
+    __shared__ C twl[N];
+    stage_twiddles<C, N, NT>(twl, tw);
+    C* base = data + int64_t(blockIdx.y) * plane_stride;
+    const int c0 = blockIdx.x * TC;
+    const int c = threadIdx.x % TC, j = threadIdx.x / TC;
+    const int pos = c0 + c;
+    const int lpos = pos == M + 1 ? M : pos;
+    C x[8][1];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i][0] = pos <= M + 1 ? base[int64_t(j + i * PER) * PP + lpos] : C{T(0), T(0)};
+    // Z[kz] from own X[kz] and partner X[M-kz]: (X + X'*) + i e^{+2 pi i kz/N} (X - X'*),
+    // e^{+2 pi i kz/N} = conj(tw[N + kz])
+    auto pack = [&](C own, C oth, C w) {
+        const C sum{own.x + oth.x, own.y - oth.y};
+        const C dif{own.x - oth.x, own.y + oth.y};
+        const C t = c_mul(C{w.x, -w.y}, dif);
+        return C{sum.x - t.y, sum.y + t.x};
+    };
+    if constexpr (TC <= 64 && N > 8) {
+        auto fin = [&](int jj, int line, const C* v, int R, int NS) {
+            const int p = c0 + line;
+            const bool store = pos_used<N>(p) && p != 1;
+            const int sp = p == M ? 1 : p;
+            const C w = twl[kz_of_pos<N>(p) & (N - 1)];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                if (r < R) {
+                    const C oth{__shfl_xor(v[r].x, 1), __shfl_xor(v[r].y, 1)};
+                    const C z = pack(v[r], oth, w);
+                    if (store) base[int64_t(jj + r * NS) * PP + sp] = z;
+                }
+            }
+        };
+        col_fft_fin<C, N, TC, 1, true, NT, 0>(s, twl, x, c, j, fin);
+    } else {
+        col_fft_lds<C, N, TC, 1, true, NT, 0>(s, twl, x, c, j);
+        for (int e = threadIdx.x; e < N * TC; e += NT) {
+            const int y = e / TC, q = e - (e / TC) * TC;
+            const int p = c0 + q;
+            if (!pos_used<N>(p) || p == 1) continue;
+            base[int64_t(y) * PP + (p == M ? 1 : p)] = pack(s[y * TC + q], s[y * TC + (q ^ 1)], twl[kz_of_pos<N>(p)]);
         }
     }
 }
@@ -358,16 +454,18 @@ __device__ __forceinline__ void mfma_contract(const typename cplx_of<T>::type* s
     for (int r = 0; r < 16; ++r) acc64[r] += double(acc[r]);
 }
 
-// c2r along z of nb windows x R rows per group, then the epilogue.  Persistent
+// Inverse along z of nb windows x R rows per group (the input rows hold the
+// packed Z[0..M-1], M = N/2, in the pair order, written by the y pass), then
+// the epilogue.  Persistent
 // workgroups; the next group's rows are fetched into registers while the
 // current group's epilogue runs (issuing the fetch after the transform keeps
 // those registers free during it), and no other global load is issued until
 // they are consumed (twiddles live in LDS).
-// Dynamic LDS: the nb R lines of N/2 + 1 complex stored element-major with
-// line stride LT = z_lt(NBCAP R) (a compile-time stride keeps every LDS
-// offset of the FFT stages an immediate), the delta rows [R][N], then the twiddles:
-// exp(-2 pi i m/M) for m < M followed by exp(-2 pi i k/N) for k <= M.  Real
-// sample z of line c sits at float index 2 ((z / 2) LT + c) + z % 2.
+// Dynamic LDS: the nb R lines of M complex stored element-major with line
+// stride LT = z_lt(NBCAP R) (a compile-time stride keeps every LDS offset of
+// the FFT stages an immediate), the delta rows [R][N], then the twiddles
+// exp(-2 pi i m/M), m < M.  Real sample z of line c sits at float index
+// 2 ((z / 2) LT + c) + z % 2.
 // NBCAP bounds nb (registers).
 template <typename T, int N, int EPI, int NBCAP, int PREC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_c2r_z(const typename cplx_of<T>::type* __restrict__ spec,
@@ -376,24 +474,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                                                     double* __restrict__ part,
                                                     const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
-    constexpr int M = N / 2, P = M + 1, PP = pitch_of<N>();
+    constexpr int M = N / 2, PP = pitch_of<N>();
     constexpr int R = zrows<N>::R;
     constexpr int CELLS = R * N;
     constexpr int GROUPS = N * N / R;
     constexpr int MAXLINES = NBCAP * R;
-    constexpr int MAXE = (MAXLINES * P + kThreads - 1) / kThreads;
+    constexpr int MAXE = (MAXLINES * M + kThreads - 1) / kThreads;
     constexpr int DPT = (CELLS + kThreads - 1) / kThreads;
     extern __shared__ double lds_raw[];
     C* s = reinterpret_cast<C*>(lds_raw);
     T* sf = reinterpret_cast<T*>(lds_raw);
     const int nlines = nb * R;
     constexpr int LT = z_lt(MAXLINES);
-    T* sd = reinterpret_cast<T*>(s + P * LT);
+    T* sd = reinterpret_cast<T*>(s + M * LT);
     C* twl = reinterpret_cast<C*>(sd + R * N);
-    const int ne = nlines * P;
+    const int ne = nlines * M;   // positions 0 .. M-1 of every line
     const EmMap em = em_map<kThreads>(nlines);
     auto at = [&](int line, int z) { return 2 * ((z >> 1) * LT + line) + (z & 1); };
-    for (int i = threadIdx.x; i <= N; i += kThreads) twl[i] = i < M ? tw[M + i] : tw[N + (i - M)];
+    for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw[M + i];
 
     // contraction roles: 4x4 bin tiles (I <= J) x cell groups
     const int nt4 = (nb + 3) / 4;
@@ -428,9 +526,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int i = 0; i < MAXE; ++i) {
             const int e = threadIdx.x + i * kThreads;
             if (e < ne) {
-                const int line = e / P, k = e - line * P;
+                const int line = e / M, pos = e - line * M;
                 const int b = line / R, r = line - b * R;
-                pre[i] = ld_stream(spec + b * bin_stride + (row0 + r) * PP + k);
+                pre[i] = ld_stream(spec + b * bin_stride + (row0 + r) * PP + pos);
             }
         }
         if (EPI == EPI_CONTRACT) {
@@ -448,8 +546,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int i = 0; i < MAXE; ++i) {
             const int e = threadIdx.x + i * kThreads;
             if (e < ne) {
-                const int line = e / P, k = e - line * P;
-                s[k * LT + line] = pre[i];
+                const int line = e / M, pos = e - line * M;
+                s[zk_of_pos<N>(pos) * LT + line] = pre[i];
             }
         }
         if (EPI == EPI_CONTRACT) {
@@ -460,29 +558,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             }
         }
         __syncthreads();
-        // c2r packing, in place by (k, M-k) pairs:
-        //   Z[k] = (X[k] + X*[M-k]) + i e^{+2 pi i k/N} (X[k] - X*[M-k])
-        {
-            int k = em.j0, line = em.c0;
-            while (k <= M / 2) {
-                C* xk_p = s + k * LT + line;
-                C* xm_p = s + (M - k) * LT + line;
-                const C xk = *xk_p, xm = *xm_p;
-                {
-                    const C sum{xk.x + xm.x, xk.y - xm.y};
-                    const C dif{xk.x - xm.x, xk.y + xm.y};
-                    const C t = c_mul(c_conj(twl[M + k]), dif);
-                    *xk_p = C{sum.x - t.y, sum.y + t.x};
-                }
-                if (k > 0 && k < M - k) {
-                    const C sum{xm.x + xk.x, xm.y - xk.y};
-                    const C dif{xm.x - xk.x, xm.y + xk.y};
-                    const C t = c_mul(c_conj(twl[M + M - k]), dif);
-                    *xm_p = C{sum.x - t.y, sum.y + t.x};
-                }
-                em_next(em, k, line);
-            }
-        }
         lds_fft_em<C, M, true, kThreads, MAXLINES, LT>(s, twl, em);
         // the next group's rows load while the epilogue runs
         if (g + int(gridDim.x) < GROUPS) fetch(g + gridDim.x);
@@ -688,7 +763,8 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
     }
     {
         LaunchScope ls(ctx, stream, "inv_y");
-        launch_c2c_cols<T, N, true, true>(sp, nb * N, plane, P, PP, false, tw, stream);
+        using YC = ypack_cfg<T, N>;
+        hipLaunchKernelGGL((k_inv_y_pack<T, N>), dim3(YC::TILES, nb * N), dim3(YC::NT), 0, stream, sp, plane, tw);
     }
     {
         LaunchScope ls(ctx, stream, EPI == EPI_CONTRACT ? "inv_z_contract" : "inv_z_moments");
