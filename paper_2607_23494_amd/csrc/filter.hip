@@ -4,12 +4,11 @@
 // isotropic windows, 4 pi i^l Y^R_lm(k^) for the multipole windows of
 // Sec. 3.3.3 Eq. multipole-window), each filtered field is
 //   f_b = iDFT[ delta^ Phi^ A R_b(|k|) ]      (Sec. 4.2, K_W = W^ Phi^)
-// and, after the angular pass (k_angular: B = delta^ Phi^ A / N^3), the three
-// inverse passes are:
-//   X  (k_win_x):  read a tile of B once, then for every window multiply by
-//                  the radial factor R_b (exact values per |n~|^2, read from a
-//                  per-column table), inverse FFT along x and write the batch
-//                  spectrum b;
+// and the three inverse passes are:
+//   X  (k_win_x):  form B = delta^ Phi^ A s / N^3 for a tile once (float64),
+//                  then for every window multiply by the radial factor R_b
+//                  (exact values per |n~|^2, read from a per-column table),
+//                  inverse FFT along x and write the batch spectrum b;
 //   Y  (k_inv_y_pack): inverse FFT along y of all nb spectra in place, fused
 //                  with the packing step of the c2r transform along z;
 //   Z  (k_c2r_z):  the length-N/2 complex inverse along z for all nb windows
@@ -169,35 +168,6 @@ __global__ __launch_bounds__(kThreads) void k_radial_cols(const T* __restrict__ 
     }
 }
 
-// ---------------------------------------------------------------- angular factor
-// B[kx][ky][kz] = delta^ Phi^ A(k^) s / N^3 on the padded layout (zeros in the
-// row padding), with A = 1 or the Nyquist-averaged Y^R_lm evaluated in float64
-// and s the complex constant (1 or 4 pi i^l).  One thread per padded element.
-template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void k_angular(const typename cplx_of<T>::type* __restrict__ dk,
-                                                      typename cplx_of<T>::type* __restrict__ B, int sh,
-                                                      YlmConst yc, double sre, double sim,
-                                                      const double* __restrict__ phi1d) {
-    using C = typename cplx_of<T>::type;
-    constexpr int M = N / 2, P = M + 1, PP = pitch_of<N>();
-    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (e >= int64_t(N) * N * PP) return;
-    const int kz = int(e % PP);
-    const int64_t row = e / PP;
-    const int ky = int(row % N), kx = int(row / N);
-    C o{T(0), T(0)};
-    if (kz < P) {
-        const C v = dk[row * P + kz];
-        const int sx = signed_mode<N>(kx), sy = signed_mode<N>(ky);
-        double f = phi1d[N + kx] * phi1d[N + ky] * phi1d[N + kz];
-        if (sh) f *= ylm_mode(yc, sx, sy, kz, kx == M, ky == M, kz == M);
-        const double re = double(v.x) * sre - double(v.y) * sim;
-        const double im = double(v.x) * sim + double(v.y) * sre;
-        o = C{T(re * f), T(im * f)};
-    }
-    B[e] = o;
-}
-
 // ---------------------------------------------------------------- pass X
 // one 16-byte access per thread and tile row: two float or one double complex
 template <typename T> constexpr int win_vec() { return sizeof(T) == 4 ? 2 : 1; }
@@ -211,7 +181,9 @@ template <> struct vec16<float> { using type = float4; };
 template <> struct vec16<double> { using type = double2; };
 
 template <typename T, int N, int VEC>
-__global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>::type* __restrict__ B,
+__global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>::type* __restrict__ dk,
+                                                    int sh, YlmConst yc, double sre, double sim,
+                                                    const double* __restrict__ phi1d,
                                                     typename cplx_of<T>::type* __restrict__ out,
                                                     int64_t bin_stride, int nb, const T* __restrict__ U,
                                                     const typename cplx_of<T>::type* __restrict__ tw) {
@@ -240,14 +212,13 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
         return c < PLANE && pos_used<N>(pos);
     };
     bool ok[VEC];
-    int64_t src[VEC];   // element (0, ky, kz) of B in its natural layout
+    int kyv[VEC], kzv[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         int64_t row;
-        int kz;
         const int c = c0 + lc + v;
-        ok[v] = col_ok(c, row, kz);
-        src[v] = int64_t(c / PP) * PP + kz;
+        ok[v] = col_ok(c, row, kzv[v]);
+        kyv[v] = (c / PP) & (N - 1);
     }
     // 16-byte chunks of the table runs this thread copies into su
     const V* csrc[CPT];
@@ -273,11 +244,28 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
         }
     };
     const T* suf = reinterpret_cast<const T*>(su);
+    // raw = delta^ Phi^ A s / N^3 of the tile (A = 1 or the Nyquist-averaged
+    // Y^R_lm, s the complex constant), in float64 and rounded once
     C raw[8][VEC];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 8; ++i) {
+        const int kx = r0 + i * RPP;
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) raw[i][v] = ok[v] ? B[(r0 + i * RPP) * PLANE + src[v]] : C{T(0), T(0)};
+        for (int v = 0; v < VEC; ++v) {
+            raw[i][v] = C{T(0), T(0)};
+            if (ok[v]) {
+                const int ky = kyv[v], kz = kzv[v];
+                const C d = dk[(int64_t(kx) * N + ky) * (N / 2 + 1) + kz];
+                double f = phi1d[N + kx] * phi1d[N + ky] * phi1d[N + kz];
+                if (sh)
+                    f *= ylm_mode(yc, signed_mode<N>(kx), signed_mode<N>(ky), kz, kx == N / 2, ky == N / 2,
+                                  kz == N / 2);
+                const double re = double(d.x) * sre - double(d.y) * sim;
+                const double im = double(d.x) * sim + double(d.y) * sre;
+                raw[i][v] = C{T(re * f), T(im * f)};
+            }
+        }
+    }
     uload(0);
     ustore();
     __syncthreads();
@@ -720,7 +708,7 @@ static void launch_z(const typename cplx_of<T>::type* sp, int64_t bin_stride, in
 // One batch: pass X, Y, Z over nb windows sharing the angular factor.
 template <typename T, int N, int EPI>
 static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, double box_L, const WinSet& ws, int sh,
-                      int ell, int m, bool build_table, void* ang_ws, void* spec_ws, T* rtab, T* ucol, double* part, T* out,
+                      int ell, int m, bool build_table, void* spec_ws, T* rtab, T* ucol, double* part, T* out,
                       int precision, hipStream_t stream) {
     using C = typename cplx_of<T>::type;
     constexpr int P = N / 2 + 1, PP = pitch_of<N>();
@@ -750,15 +738,10 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
         }
     }
     C* sp = static_cast<C*>(spec_ws);
-    C* ang = static_cast<C*>(ang_ws);
-    {
-        LaunchScope ls(ctx, stream, "angular");
-        hipLaunchKernelGGL((k_angular<T, N>), dim3((bin_stride + kThreads - 1) / kThreads), dim3(kThreads), 0, stream,
-                           static_cast<const C*>(delta_k), ang, sh, ylm_const(ell, m), sre, sim, ctx->t.phi1d);
-    }
     {
         LaunchScope ls(ctx, stream, "inv_x_window");
-        hipLaunchKernelGGL((k_win_x<T, N, XVEC>), dim3((plane + TC - 1) / TC), dim3(kColThreads), 0, stream, ang, sp,
+        hipLaunchKernelGGL((k_win_x<T, N, XVEC>), dim3((plane + TC - 1) / TC), dim3(kColThreads), 0, stream,
+                           static_cast<const C*>(delta_k), sh, ylm_const(ell, m), sre, sim, ctx->t.phi1d, sp,
                            bin_stride, nb, ucol, tw);
     }
     {
@@ -792,7 +775,7 @@ size_t filter_workspace(int n, int dtype, int n_win) {
     const bool dbl = dtype == HERMES_F64;
     const int chunk = std::min({n_win, kFilterChunk, z_max_batch_rt(n, dbl)});
     const size_t nq = size_t(qmax_of(n) + 1);
-    return align256(spec_bytes(n, dbl) * (chunk + 1)) + align256(nq * chunk * (dbl ? 8 : 4)) +
+    return align256(spec_bytes(n, dbl) * chunk) + align256(nq * chunk * (dbl ? 8 : 4)) +
            align256(col_table_bytes(n, chunk, dbl ? 8 : 4)) + align256(size_t(z_grid_rt(n)) * chunk * 3 * sizeof(double));
 }
 
@@ -803,9 +786,8 @@ static hermes_status filter_n(hermes_ctx ctx, const void* delta_k, double box_L,
     const int chunk = std::min({n_win, kFilterChunk, z_max_batch<T, N>()});
     const size_t nq = size_t(qmax_of(N) + 1);
     char* w = static_cast<char*>(work);
-    void* ang = w;
-    void* spec = w + spec_bytes(N, dbl);
-    char* tail = w + align256(spec_bytes(N, dbl) * (chunk + 1));
+    void* spec = w;
+    char* tail = w + align256(spec_bytes(N, dbl) * chunk);
     T* rtab = reinterpret_cast<T*>(tail);
     tail += align256(nq * chunk * sizeof(T));
     T* ucol = reinterpret_cast<T*>(tail);
@@ -846,7 +828,7 @@ static hermes_status filter_n(hermes_ctx ctx, const void* delta_k, double box_L,
             ++ws.n;
             ++i;
         }
-        run_batch<T, N, EPI_MOMENTS>(ctx, delta_k, nullptr, box_L, ws, k0.sh, k0.ell, k0.m, true, ang, spec, rtab,
+        run_batch<T, N, EPI_MOMENTS>(ctx, delta_k, nullptr, box_L, ws, k0.sh, k0.ell, k0.m, true, spec, rtab,
                                      ucol, moments ? part : nullptr, static_cast<T*>(out), HERMES_PREC_FP32, stream);
         if (moments) {
             LaunchScope ls(ctx, stream, "reduce");
@@ -883,7 +865,7 @@ hermes_status filter_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype,
 // ---------------------------------------------------------------- zeta_l
 size_t zeta_workspace(int n, int n_bins) {
     const size_t nq = size_t(qmax_of(n) + 1);
-    return align256(spec_bytes(n, false) * (n_bins + 1)) + align256(nq * n_bins * sizeof(float)) +
+    return align256(spec_bytes(n, false) * n_bins) + align256(nq * n_bins * sizeof(float)) +
            align256(col_table_bytes(n, n_bins, sizeof(float))) +
            align256(size_t(z_grid_rt(n)) * n_bins * n_bins * sizeof(double));
 }
@@ -899,9 +881,8 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
         return fail(HERMES_ERR_UNSUPPORTED, "hermes_zeta_l: the matrix-core contraction takes at most 32 bins");
     const size_t nq = size_t(qmax_of(N) + 1);
     char* w = static_cast<char*>(work);
-    void* ang = w;
-    void* spec = w + spec_bytes(N, false);
-    char* tail = w + align256(spec_bytes(N, false) * (nb + 1));
+    void* spec = w;
+    char* tail = w + align256(spec_bytes(N, false) * nb);
     float* rtab = reinterpret_cast<float*>(tail);
     tail += align256(nq * nb * sizeof(float));
     float* ucol = reinterpret_cast<float*>(tail);
@@ -924,7 +905,7 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
             ws.out[b] = b;
         }
         for (int m = -ell; m <= ell; ++m) {
-            run_batch<float, N, EPI_CONTRACT>(ctx, delta_k, delta, box_L, ws, 1, ell, m, m == -ell, ang, spec,
+            run_batch<float, N, EPI_CONTRACT>(ctx, delta_k, delta, box_L, ws, 1, ell, m, m == -ell, spec,
                                               rtab, ucol, part, nullptr, precision, stream);
             LaunchScope ls(ctx, stream, "reduce");
             hipLaunchKernelGGL(k_reduce_part, dim3(nb * nb), dim3(kThreads), 0, stream, part, grid, nb * nb, scale,
