@@ -249,6 +249,14 @@ def main() -> int:
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_bytes": abytes, "launches": launches}
+    # the same figures for every pass that has an algorithmic byte count
+    passes = {}
+    for _, k in sorted(cands, reverse=True):
+        nl, tms = prof[k]
+        a_s = tms / nl / 1e3
+        ab = algorithmic_bytes(k, n, nb_z)
+        passes[k] = {"avg_launch_ms": round(a_s * 1e3, 4), "launches": nl, "algorithmic_bytes": ab,
+                     "achieved_GBps": round(ab / a_s / 1e9, 1), "frac": round(ab / a_s / 1e9 / HBM_PEAK_GBS, 4)}
 
     extra = {}
     if args.compare:
@@ -282,6 +290,7 @@ def main() -> int:
         "cells_bins_per_s": round(cells_bins / s_per_step, 1),
         "stage_ms": stages,
         "roofline": roofline,
+        "passes": passes,
     }
     result.update(extra)
     if not args.no_serving:

@@ -147,17 +147,24 @@ hermes_status hermes_fft(hermes_ctx ctx, const void* eps, const double* sum_w,
  *   xi_l[b] = N^-6 sum_n |delta^_n|^2 Phi^(n) (2l+1) i^l jbar_l(k_n; b) L_l(mu_n),
  * Phi^(n) = prod_a sinc^8(pi n~_a / N) (B3 autocorrelation), mu = k_los/|k|,
  * jbar_0 = volume-normalised thick shell (Eq. Wshell_k).  Raw estimator:
- * no shot-noise subtraction.
+ * no shot-noise subtraction (the self-pair term of Sec. 2.2 Eq. CFpow is left
+ * to the caller, who can take it from `shot`).
  *   delta_k  device half spectrum from hermes_fft
  *   edges    host double [n_bins+1], strictly increasing, edges[0] >= 0
  *   ells     host int [n_ells], even values in [0, HERMES_MAX_LMAX]
  *   los_axis 0, 1 or 2 (plane-parallel line of sight)
  *   xi       device double [n_ells][n_bins]; overwritten
+ *   shot     device double [n_ells][n_bins] or NULL: the shot-noise factor
+ *            S_lb = sum_D K_lb(D) B7(D1) B7(D2) B7(D3) over lags |D_a| <= 3,
+ *            K_lb(D) the real-space window kernel above and B7 the degree-7
+ *            centred B-spline (the B3 autocorrelation at integer lags); for
+ *            iid points of weights w_i, E xi_lb = (sum w^2 / W^2)
+ *            (N^3 S_lb - K_lb(n = 0)), K_0b(0) = 1, K_lb(0) = 0 for l > 0
  *   work     device workspace of >= hermes_workspace_size(XI) bytes */
 hermes_status hermes_xi(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype,
                         double box_L, const double* edges, int n_bins,
                         const int* ells, int n_ells, int los_axis, double* xi,
-                        void* work, size_t work_bytes, hipStream_t stream);
+                        double* shot, void* work, size_t work_bytes, hipStream_t stream);
 
 /* Window-filtered fields (Sec. 4.2: eps_W = iFT[FT(eps) W^ Phi^]) and their
  * counts-in-cells moments (Sec. 3.1 filtered field, Sec. 2.2.2 Eq. varw):

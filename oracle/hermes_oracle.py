@@ -275,6 +275,49 @@ def xi_multipoles(delta_hat, box_L, edges, ells=(0,), los_axis=2):
     return out
 
 
+# B3 autocorrelation at integer lags: the centred B-spline of degree 7.
+B7_LAGS = {0: 2416.0 / 5040.0, 1: 1191.0 / 5040.0, 2: 120.0 / 5040.0, 3: 1.0 / 5040.0}
+
+
+def shot_factor(n, box_L, edges, ells=(0,), los_axis=2):
+    """Shot-noise factor of the Parseval 2PCF estimator (reading of the
+    self-pair term of Sec. 2.2 Eq. CFpow for the field estimator):
+        S_lb = sum_D K_lb(D) B7(D_1) B7(D_2) B7(D_3),  |D_a| <= 3,
+    with K_lb(D) = N^-3 sum_n K_lb(n) e^{+2 pi i n.D/N} the real-space window
+    kernel of xi_multipoles, K_lb(n) = (2l+1) (-1)^{l/2} R_lb(|k|) L_l(mu) Phi^(n)
+    (every mode, n = 0 included), and B7 the B3 autocorrelation at integer
+    lags.  For iid points E xi_lb = (sum w^2 / W^2) (N^3 S_lb - K_lb(0)).
+    Returns float64 [len(ells), n_bins].
+    """
+    edges = np.asarray(edges, dtype=np.float64)
+    kx, ky, kz = mode_vectors(n, box_L)
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    klos = (kx, ky, kz)[los_axis]
+    mu = np.where(kk > 0, klos / np.where(kk > 0, kk, 1.0), 0.0)
+    ph = phi_hat(n)
+    lags = range(-3, 4)
+    out = np.zeros((len(ells), len(edges) - 1))
+    for il, ell in enumerate(ells):
+        if ell % 2:
+            raise ValueError("odd multipoles of the auto-correlation vanish; use even l")
+        leg = eval_legendre(ell, mu) if ell > 0 else 1.0
+        pref = (2 * ell + 1) * (-1) ** (ell // 2)
+        for b in range(len(edges) - 1):
+            lo, hi = edges[b], edges[b + 1]
+            if ell == 0:
+                rad = radial_by_q(n, box_L, lambda kq: w_shell(kq, lo, hi))
+            else:
+                rad = radial_by_q(n, box_L, lambda kq: jbar(ell, kq, lo, hi))
+            kd = idft3(pref * rad * leg * ph).real
+            s = 0.0
+            for dx in lags:
+                for dy in lags:
+                    for dz in lags:
+                        s += kd[dx % n, dy % n, dz % n] * B7_LAGS[abs(dx)] * B7_LAGS[abs(dy)] * B7_LAGS[abs(dz)]
+            out[il, b] = s
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Counts-in-cells moments (Sec. 3.1 filtered field n_W; Sec. 2.2.2 Eq. varw)
 # ----------------------------------------------------------------------------

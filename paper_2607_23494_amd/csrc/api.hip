@@ -99,6 +99,19 @@ static hermes_status build_tables(hermes_ctx c) {
             phi[n + i] = std::pow(sn, 8);
         }
     }
+    // DFT of the B3 autocorrelation at integer lags, the centred B-spline of
+    // degree 7: B7(0) = 2416/5040, B7(+-1) = 1191/5040, B7(+-2) = 120/5040,
+    // B7(+-3) = 1/5040 (the self-pair kernel of the shot-noise factor)
+    std::vector<double> b7(2 * kMaxN, 0.0);
+    {
+        const double c[4] = {2416.0 / 5040.0, 1191.0 / 5040.0, 120.0 / 5040.0, 1.0 / 5040.0};
+        for (int n = 1; n <= kMaxN; n *= 2)
+            for (int i = 0; i < n; ++i) {
+                double v = c[0];
+                for (int d = 1; d <= 3; ++d) v += 2.0 * c[d] * std::cos(2.0 * M_PI * double(d) * double(i) / double(n));
+                b7[n + i] = v;
+            }
+    }
     std::vector<double> gx, gw;
     gauss_legendre(16, gx, gw);
     std::vector<double> gl(32);
@@ -115,6 +128,7 @@ static hermes_status build_tables(hermes_ctx c) {
     if ((e = up((void**)&c->t.tw32, tw32.data(), tw32.size() * sizeof(float2))) != hipSuccess ||
         (e = up((void**)&c->t.tw64, tw64.data(), tw64.size() * sizeof(double2))) != hipSuccess ||
         (e = up((void**)&c->t.phi1d, phi.data(), phi.size() * sizeof(double))) != hipSuccess ||
+        (e = up((void**)&c->t.b7dft, b7.data(), b7.size() * sizeof(double))) != hipSuccess ||
         (e = up((void**)&c->t.gl, gl.data(), gl.size() * sizeof(double))) != hipSuccess)
         return fail(HERMES_ERR_HIP, std::string("hermes_create: ") + hipGetErrorString(e));
     return HERMES_OK;
@@ -188,6 +202,7 @@ void hermes_destroy(hermes_ctx ctx) {
     (void)hipFree(ctx->t.tw32);
     (void)hipFree(ctx->t.tw64);
     (void)hipFree(ctx->t.phi1d);
+    (void)hipFree(ctx->t.b7dft);
     (void)hipFree(ctx->t.gl);
     delete ctx;
 }
@@ -293,7 +308,7 @@ hermes_status hermes_fft(hermes_ctx ctx, const void* eps, const double* sum_w, i
 
 hermes_status hermes_xi(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype, double box_L,
                         const double* edges, int n_bins, const int* ells, int n_ells, int los_axis,
-                        double* xi, void* work, size_t work_bytes, hipStream_t stream) {
+                        double* xi, double* shot, void* work, size_t work_bytes, hipStream_t stream) {
     if (!ctx || !delta_k || !xi || !ells || !work) return fail(HERMES_ERR_ARG, "hermes_xi: NULL argument");
     if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_xi: N must be a power of two in [8, 1024]");
     if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_xi: bad dtype");
@@ -309,7 +324,8 @@ hermes_status hermes_xi(hermes_ctx ctx, const void* delta_k, int n_grid, int dty
     if (work_bytes < xi_workspace(n_grid, n_ells, n_bins))
         return fail(HERMES_ERR_OOM, "hermes_xi: workspace too small");
     DeviceGuard g(ctx->device);
-    return xi_impl(ctx, delta_k, n_grid, dtype, box_L, e, ells, n_ells, los_axis, xi, work, work_bytes, stream);
+    return xi_impl(ctx, delta_k, n_grid, dtype, box_L, e, ells, n_ells, los_axis, xi, shot, work, work_bytes,
+                   stream);
 }
 
 hermes_status hermes_filter_bins(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype,

@@ -23,6 +23,7 @@ struct Tables {
     float2* tw32 = nullptr;     // exp(-2 pi i m / L) at tw[L + m], L = 1..2048 (powers of 2)
     double2* tw64 = nullptr;
     double* phi1d = nullptr;    // sinc^8(pi n~/N) at phi1d[N + i], i in [0, N)
+    double* b7dft = nullptr;    // sum_{|d|<=3} B7(d) cos(2 pi d i / N) at b7dft[N + i]
     double* gl = nullptr;       // kGL nodes then kGL weights on [-1, 1]
 };
 
@@ -99,7 +100,7 @@ hermes_status fft_impl(hermes_ctx ctx, const void* eps, const double* sum_w, int
                        void* delta_k, void* delta, hipStream_t stream);
 hermes_status xi_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype, double box_L,
                       const Edges& edges, const int* ells, int n_ells, int los_axis, double* xi,
-                      void* work, size_t work_bytes, hipStream_t stream);
+                      double* shot, void* work, size_t work_bytes, hipStream_t stream);
 size_t xi_workspace(int n, int n_ells, int n_bins);
 hermes_status filter_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype, double box_L,
                           const hermes_window* win, int n_win, void* out, double* moments,

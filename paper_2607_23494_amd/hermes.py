@@ -51,7 +51,7 @@ def _load() -> ctypes.CDLL:
     lib.hermes_workspace_size.argtypes = [vp, i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
     lib.hermes_assign.argtypes = [vp, vp, vp, i64, f64, i32, i32, vp, vp, vp]
     lib.hermes_fft.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
-    lib.hermes_xi.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, sz, vp]
+    lib.hermes_xi.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, vp, sz, vp]
     lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
     lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
     lib.hermes_profile_enable.argtypes = [vp, i32]
@@ -170,8 +170,10 @@ def fft(eps: torch.Tensor, sum_w: torch.Tensor, want_delta: bool = True, delta_k
 
 
 def xi(delta_k: torch.Tensor, box_L: float, edges, ells: Sequence[int] = (0,), los_axis: int = 2,
-       out: torch.Tensor | None = None, work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """2PCF multipoles by Parseval: device float64 [len(ells), n_bins]."""
+       out: torch.Tensor | None = None, work: torch.Tensor | None = None, stream=None, shot: bool = False):
+    """2PCF multipoles by Parseval: device float64 [len(ells), n_bins]; with
+    shot=True also the shot-noise factors S_lb of the same shape, as a tuple
+    (xi, shot)."""
     dev = _dev(delta_k)
     n = delta_k.shape[0]
     e = _edges_arr(edges)
@@ -182,10 +184,11 @@ def xi(delta_k: torch.Tensor, box_L: float, edges, ells: Sequence[int] = (0,), l
     w = _workspace(wbytes, dev, work)
     if out is None:
         out = torch.empty((el.size, nb), dtype=torch.float64, device=delta_k.device)
+    sh = torch.empty((el.size, nb), dtype=torch.float64, device=delta_k.device) if shot else None
     _check(_lib.hermes_xi(context(dev), _ptr(delta_k), n, dt, float(box_L), e.ctypes.data_as(ctypes.c_void_p), nb,
-                          el.ctypes.data_as(ctypes.c_void_p), el.size, los_axis, _ptr(out), _ptr(w), wbytes,
-                          _stream(dev, stream)))
-    return out
+                          el.ctypes.data_as(ctypes.c_void_p), el.size, los_axis, _ptr(out),
+                          _ptr(sh) if shot else None, _ptr(w), wbytes, _stream(dev, stream)))
+    return (out, sh) if shot else out
 
 
 def make_windows(specs: Iterable) -> ctypes.Array:

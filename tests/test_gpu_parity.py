@@ -104,6 +104,11 @@ def test_xi_multipoles(hermes, dtype):
     gx = hermes.xi(dk, L, edges, ells=(2,), los_axis=0).cpu().numpy()
     rx = O.xi_multipoles(odh, L, edges, ells=(2,), los_axis=0)
     assert normwise(gx[0], rx[0]) < TOL[dtype] * 10
+    # shot-noise factors: float64 on the device whatever the field precision
+    _, shot = hermes.xi(dk, L, edges, ells=ells, los_axis=2, shot=True)
+    sref = O.shot_factor(n, L, edges, ells=ells, los_axis=2)
+    for i in range(3):
+        assert normwise(shot.cpu().numpy()[i], sref[i]) < 1e-10, ells[i]
 
 
 def test_xi_fp64_workload_small(hermes):

@@ -307,21 +307,52 @@ def _kernel_realspace_sum(n, box_L, lo, hi):
 
 
 def test_poisson_expectation():
-    """For iid uniform points E[xi_b] = (sum w^2 / W^2) (N^3 S_b - 1): the
-    estimator measures zero clustering up to the self-pair term."""
+    """For iid uniform points E[xi_lb] = (sum w^2 / W^2) (N^3 S_lb - K_lb(0)):
+    the estimator measures zero clustering up to the self-pair term, for the
+    monopole (K_0b(0) = 1) and the quadrupole (K_2b(0) = 0)."""
     n, L, npts = 16, 100.0, 3000
     edges = [6.0, 12.0, 20.0, 30.0]
     samples = []
     for s in range(16):
         pos = synth.uniform_points(npts, L, seed=synth.SEED_BASE + 100 + s)
         eps, sw = O.assign(pos, None, L, n)
-        samples.append(O.xi_multipoles(O.dft3(O.contrast(eps, sw)), L, edges)[0])
+        samples.append(O.xi_multipoles(O.dft3(O.contrast(eps, sw)), L, edges, ells=(0, 2)))
     samples = np.array(samples)
     mean = samples.mean(axis=0)
     sem = samples.std(axis=0, ddof=1) / 4.0
+    S = O.shot_factor(n, L, edges, ells=(0, 2))
     for b in range(3):
-        expect = (n ** 3 * _kernel_realspace_sum(n, L, edges[b], edges[b + 1]) - 1.0) / npts
-        assert abs(mean[b] - expect) < 4 * sem[b] + 1e-12
+        # the shell kernel built here directly agrees with the oracle's factor
+        assert abs(S[0, b] - _kernel_realspace_sum(n, L, edges[b], edges[b + 1])) < 1e-14
+        for il, k0 in ((0, 1.0), (1, 0.0)):
+            expect = (n ** 3 * S[il, b] - k0) / npts
+            assert abs(mean[il, b] - expect) < 4 * sem[il, b] + 1e-12, (il, b)
+
+
+def test_shot_factor_kspace_identity():
+    """S_lb also equals N^-3 sum_n K_lb(n) B~(n) with B~ the DFT of the
+    7-point B7 stencil (a different route through the same definition), and
+    B~ is the alias sum of Phi^ over the images n + jN (Poisson summation)."""
+    n, L = 16, 80.0
+    edges = [5.0, 11.0, 18.0]
+    S = O.shot_factor(n, L, edges, ells=(0, 2, 4))
+    idx = np.arange(n)
+    g = sum(O.B7_LAGS[abs(d)] * np.cos(2 * np.pi * d * idx / n) for d in range(-3, 4))
+    s_idx = np.where(idx <= n // 2, idx, idx - n)
+    alias = sum(np.sinc(s_idx / n + j) ** 8 for j in range(-60, 61))
+    assert np.max(np.abs(g - alias)) < 1e-12
+    bt = g[:, None, None] * g[None, :, None] * g[None, None, :]
+    kx, ky, kz = O.mode_vectors(n, L)
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    mu = np.where(kk > 0, kz / np.where(kk > 0, kk, 1.0), 0.0)
+    for il, ell in enumerate((0, 2, 4)):
+        for b in range(2):
+            if ell == 0:
+                rad = O.radial_by_q(n, L, lambda kq: O.w_shell(kq, edges[b], edges[b + 1]))
+            else:
+                rad = O.radial_by_q(n, L, lambda kq: O.jbar(ell, kq, edges[b], edges[b + 1]))
+            kn = (2 * ell + 1) * (-1) ** (ell // 2) * rad * eval_legendre(ell, mu) * O.phi_hat(n)
+            assert abs(S[il, b] - np.sum(kn * bt) / n ** 3) < 1e-13 * max(1.0, abs(S[il, b]))
 
 
 # --------------------------------------------------------------------------
