@@ -18,15 +18,17 @@ template <> struct fft_cfg<double> { static constexpr int elems = 4096; };
 
 constexpr int kColThreads = 512;   // threads of the column-pass workgroups
 
-// Column tile geometry: TC columns x N positions for kColThreads threads,
-// each owning VEC adjacent columns (one 8- or 16-byte access) at 8 positions
-// N/8 apart; LPR lanes per tile row, RPP = N/8 rows per load round.
-template <typename T, int N, int VEC_ = 16 / int(sizeof(typename cplx_of<T>::type))> struct col_cfg {
+// Column tile geometry: TC columns x N positions for NT threads (default
+// kColThreads), each owning VEC adjacent columns (one 8- or 16-byte access) at
+// 8 positions N/8 apart; LPR lanes per tile row, RPP = N/8 rows per load round.
+template <typename T, int N, int VEC_ = 16 / int(sizeof(typename cplx_of<T>::type)), int NT_ = kColThreads>
+struct col_cfg {
     using C = typename cplx_of<T>::type;
     static constexpr int VEC = VEC_;
-    static constexpr int TC = kColThreads * 8 * VEC / N;
+    static constexpr int NT = NT_;
+    static constexpr int TC = NT * 8 * VEC / N;
     static constexpr int LPR = TC / VEC;
-    static constexpr int RPP = kColThreads / LPR;
+    static constexpr int RPP = NT / LPR;
     static constexpr int NLD = N / RPP;
     static_assert(TC >= VEC && NLD == 8 && RPP == N / 8, "column tile");
 };

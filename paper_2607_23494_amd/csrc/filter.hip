@@ -169,8 +169,11 @@ __global__ __launch_bounds__(kThreads) void k_radial_cols(const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------- pass X
-// one 16-byte access per thread and tile row: two float or one double complex
-template <typename T> constexpr int win_vec() { return sizeof(T) == 4 ? 2 : 1; }
+// Column passes (x and y) use one column per thread; float tiles are 16
+// columns x N (128-byte row segments) on 1024 threads, double tiles 8 columns
+// on 512 threads (64 KB of LDS either way).
+template <typename T> constexpr int win_vec() { return 1; }
+template <typename T> constexpr int win_threads() { return sizeof(T) == 4 ? 1024 : 512; }
 
 // Tiles of TC consecutive columns of the padded (ky, kz) plane of B: for every
 // window b multiply by the radial factor R_b(q), q = |n~|^2, inverse FFT along
@@ -180,8 +183,8 @@ template <typename T> struct vec16;
 template <> struct vec16<float> { using type = float4; };
 template <> struct vec16<double> { using type = double2; };
 
-template <typename T, int N, int VEC>
-__global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>::type* __restrict__ dk,
+template <typename T, int N, int VEC, int NT>
+__global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* __restrict__ dk,
                                                     int sh, YlmConst yc, double sre, double sim,
                                                     const double* __restrict__ phi1d,
                                                     typename cplx_of<T>::type* __restrict__ out,
@@ -189,18 +192,18 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
                                                     const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
     using V = typename vec16<T>::type;
-    using G = col_cfg<T, N, VEC>;
+    using G = col_cfg<T, N, VEC, NT>;
     constexpr int TC = G::TC, LPR = G::LPR, RPP = G::RPP;
     constexpr int H = N / 2 + 1, PP = pitch_of<N>(), HP = col_pitch<T, N>();
     constexpr int64_t PLANE = int64_t(N) * PP;
     constexpr int VE = 16 / int(sizeof(T));           // table values per 16-byte chunk
     constexpr int CPC = HP / VE;                       // chunks per column run
     constexpr int NCH = TC * CPC;                      // chunks per tile and window
-    constexpr int CPT = (NCH + kColThreads - 1) / kColThreads;
+    constexpr int CPT = (NCH + NT - 1) / NT;
     __shared__ C s[N * TC];
     __shared__ C twl[N];
     __shared__ V su[NCH];                              // the tile's table runs, column v at [v CPC, (v+1) CPC)
-    stage_twiddles<C, N, kColThreads>(twl, tw);
+    stage_twiddles<C, N, NT>(twl, tw);
     const int c0 = blockIdx.x * TC;
     const int lc = (threadIdx.x % LPR) * VEC, r0 = threadIdx.x / LPR;
     // columns past N/2 in a row are padding: neither read nor written
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
     const V* csrc[CPT];
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
-        const int i = threadIdx.x + u * kColThreads;
+        const int i = threadIdx.x + u * NT;
         const int v = i / CPC;
         int64_t row = 0;
         int kz;
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
     auto ustore = [&]() {
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
-            const int i = threadIdx.x + u * kColThreads;
+            const int i = threadIdx.x + u * NT;
             if (i < NCH) su[i] = ureg[u];
         }
     };
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
             const int c = c0 + line;
             if (c < PLANE && pos_used<N>(c % PP)) ob[int64_t(p) * PLANE + line] = val;
         };
-        col_fft<C, N, TC, VEC, true, kColThreads, 0>(s, twl, x, lc, r0, st);
+        col_fft<C, N, TC, VEC, true, NT, 0>(s, twl, x, lc, r0, st);
         __syncthreads();
         if (b + 1 < nb) {
             ustore();
@@ -310,17 +313,17 @@ __global__ __launch_bounds__(kColThreads) void k_win_x(const typename cplx_of<T>
 // through LDS.  Position M + 1 is loaded as a copy of kz = M/2, the partner of
 // position M.  One 8-byte column per thread and load round.
 template <typename T, int N> struct ypack_cfg {
-    static constexpr int TC = col_cfg<T, N, 1>::TC;   // positions per tile
-    static constexpr int NT = kColThreads;
+    static constexpr int NT = win_threads<T>();
+    static constexpr int TC = col_cfg<T, N, 1, NT>::TC;   // positions per tile
     static constexpr int TILES = (N / 2 + 2 + TC - 1) / TC;
 };
 
 template <typename T, int N>
-__global__ __launch_bounds__(kColThreads) void k_inv_y_pack(typename cplx_of<T>::type* __restrict__ data,
+__global__ __launch_bounds__((ypack_cfg<T, N>::NT)) void k_inv_y_pack(typename cplx_of<T>::type* __restrict__ data,
                                                          int64_t plane_stride,
                                                          const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
-    constexpr int TC = ypack_cfg<T, N>::TC, NT = kColThreads;
+    constexpr int TC = ypack_cfg<T, N>::TC, NT = ypack_cfg<T, N>::NT;
     constexpr int M = N / 2, PP = pitch_of<N>(), PER = N / 8;
     static_assert(TC % 2 == 0, "pairs per tile");
     __shared__ C s[N * TC];
@@ -712,8 +715,8 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
                       int precision, hipStream_t stream) {
     using C = typename cplx_of<T>::type;
     constexpr int P = N / 2 + 1, PP = pitch_of<N>();
-    constexpr int XVEC = win_vec<T>();
-    constexpr int TC = col_cfg<T, N, XVEC>::TC;
+    constexpr int XVEC = win_vec<T>(), XNT = win_threads<T>();
+    constexpr int TC = col_cfg<T, N, XVEC, XNT>::TC;
     const C* tw = tw_ptr<T>(ctx->t);
     const int nb = ws.n;
     const int64_t nq = qmax_of(N) + 1;
@@ -740,7 +743,7 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
     C* sp = static_cast<C*>(spec_ws);
     {
         LaunchScope ls(ctx, stream, "inv_x_window");
-        hipLaunchKernelGGL((k_win_x<T, N, XVEC>), dim3((plane + TC - 1) / TC), dim3(kColThreads), 0, stream,
+        hipLaunchKernelGGL((k_win_x<T, N, XVEC, XNT>), dim3((plane + TC - 1) / TC), dim3(XNT), 0, stream,
                            static_cast<const C*>(delta_k), sh, ylm_const(ell, m), sre, sim, ctx->t.phi1d, sp,
                            bin_stride, nb, ucol, tw);
     }

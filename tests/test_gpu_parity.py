@@ -104,11 +104,16 @@ def test_xi_multipoles(hermes, dtype):
     gx = hermes.xi(dk, L, edges, ells=(2,), los_axis=0).cpu().numpy()
     rx = O.xi_multipoles(odh, L, edges, ells=(2,), los_axis=0)
     assert normwise(gx[0], rx[0]) < TOL[dtype] * 10
-    # shot-noise factors: float64 on the device whatever the field precision
+    # shot-noise factors, float64 on the device whatever the field precision;
+    # the self-pair kernel shares the grid's cubic symmetry, so S_2b vanishes
+    # up to rounding and every multipole is compared on the monopole's scale
     _, shot = hermes.xi(dk, L, edges, ells=ells, los_axis=2, shot=True)
+    shot = shot.cpu().numpy()
     sref = O.shot_factor(n, L, edges, ells=ells, los_axis=2)
+    scale = np.max(np.abs(sref[0]))
     for i in range(3):
-        assert normwise(shot.cpu().numpy()[i], sref[i]) < 1e-10, ells[i]
+        assert np.max(np.abs(shot[i] - sref[i])) < 1e-10 * scale, ells[i]
+    assert np.max(np.abs(sref[1])) < 1e-12 * scale
 
 
 def test_xi_fp64_workload_small(hermes):
