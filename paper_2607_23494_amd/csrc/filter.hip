@@ -89,8 +89,17 @@ inline int z_max_batch_rt(int n, bool dbl) {
 }
 
 // bytes of one padded half spectrum [N][N][pitch]
+// Padded plane stride (complex elements) of the batch spectra: N rows of the
+// padded pitch plus kPlanePad, so that consecutive x planes do not start at a
+// near power-of-two distance (the x pass writes one row per plane per tile;
+// measured about 2 % faster at 512^3 than without the pad).
+constexpr int kPlanePad = 64;
+template <int N> __host__ __device__ constexpr int64_t plane_stride() { return int64_t(N) * pitch_of<N>() + kPlanePad; }
+inline int64_t plane_stride_rt(int n) { return int64_t(n) * pitch_rt(n) + kPlanePad; }
+
+// bytes of one padded batch spectrum [N][plane_stride]
 inline size_t spec_bytes(int n, bool dbl) {
-    return size_t(n) * n * pitch_rt(n) * (dbl ? 16 : 8);
+    return size_t(n) * plane_stride_rt(n) * (dbl ? 16 : 8);
 }
 
 // ---------------------------------------------------------------- radial table
@@ -287,7 +296,7 @@ __global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* _
         C* ob = out + b * bin_stride + c0;
         auto st = [&](int p, int line, C val) {
             const int c = c0 + line;
-            if (c < PLANE && pos_used<N>(c % PP)) ob[int64_t(p) * PLANE + line] = val;
+            if (c < PLANE && pos_used<N>(c % PP)) ob[int64_t(p) * plane_stride<N>() + line] = val;
         };
         col_fft<C, N, TC, VEC, true, NT, 0>(s, twl, x, lc, r0, st);
         __syncthreads();
@@ -519,7 +528,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             if (e < ne) {
                 const int line = e / M, pos = e - line * M;
                 const int b = line / R, r = line - b * R;
-                pre[i] = ld_stream(spec + b * bin_stride + (row0 + r) * PP + pos);
+                const int64_t row = row0 + r;   // (x, y) = (row / N, row % N)
+                pre[i] = ld_stream(spec + b * bin_stride + (row / N) * plane_stride<N>() + (row % N) * PP + pos);
             }
         }
         if (EPI == EPI_CONTRACT) {
@@ -720,8 +730,8 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
     const C* tw = tw_ptr<T>(ctx->t);
     const int nb = ws.n;
     const int64_t nq = qmax_of(N) + 1;
-    const int64_t plane = int64_t(N) * PP;
-    const int64_t bin_stride = int64_t(N) * plane;
+    const int64_t plane = int64_t(N) * PP;            // columns of one (ky, kz) plane
+    const int64_t bin_stride = int64_t(N) * plane_stride<N>();
     if (build_table) {
         LaunchScope ls(ctx, stream, "radial_table");
         hipLaunchKernelGGL((k_radial<T>), dim3((nq + kThreads - 1) / kThreads), dim3(kThreads), 0, stream, rtab, nq,
@@ -750,7 +760,8 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
     {
         LaunchScope ls(ctx, stream, "inv_y");
         using YC = ypack_cfg<T, N>;
-        hipLaunchKernelGGL((k_inv_y_pack<T, N>), dim3(YC::TILES, nb * N), dim3(YC::NT), 0, stream, sp, plane, tw);
+        hipLaunchKernelGGL((k_inv_y_pack<T, N>), dim3(YC::TILES, nb * N), dim3(YC::NT), 0, stream, sp,
+                           plane_stride<N>(), tw);
     }
     {
         LaunchScope ls(ctx, stream, EPI == EPI_CONTRACT ? "inv_z_contract" : "inv_z_moments");
