@@ -60,8 +60,9 @@ typedef enum hermes_dtype { HERMES_F32 = 0, HERMES_F64 = 1 } hermes_dtype;
 /* Precision of the 3PCF contraction (the FFTs always run in float32). */
 typedef enum hermes_precision {
     HERMES_PREC_FP32 = 0,   /* float32 vector FMA contraction */
-    HERMES_PREC_BF16X3 = 1, /* bf16 hi+lo split, three MFMA products, fp32 accumulate */
-    HERMES_PREC_FP16X3 = 2  /* fp16 hi+lo split, three MFMA products, fp32 accumulate */
+    HERMES_PREC_BF16X3 = 1, /* y = sqrt|delta| f split hi+lo in bf16; hi.hi and lo.hi MFMA products
+                               (the hi.lo one by symmetry), fp32 accumulate */
+    HERMES_PREC_FP16X3 = 2  /* the same split in fp16 */
 } hermes_precision;
 
 /* Window kinds (Table A1 (a)-(c) and the multipole windows of Sec. 3.3.3). */

@@ -287,26 +287,29 @@ __device__ __forceinline__ void col_fft(C* s, const C* __restrict__ tw, C (&x)[8
     }
 }
 
-// ---------------------------------------------------------------- element-major, runtime line count
-// nl lines (at most MAXL) stored element-major with line stride LT >= MAXL:
-// element idx of line c at s[idx * LT + c].  Item b = j nl + c of a stage is
-// taken by thread b % NT, so consecutive threads take consecutive lines and
-// every access of a wavefront is a nearly contiguous run; an odd LT also
-// spreads element-strided accesses (loads of whole lines) over the banks.
-// em_map holds the (j, c) of a thread's first item and the step between its
+// ---------------------------------------------------------------- element-major, one wavefront
+// nl lines (at most MAXL) owned by one wavefront, stored element-major with
+// line stride LT >= nl: element idx of line c at s[idx * LT + c] (s points at
+// the wavefront's first line).  Item b = j nl + c of a stage is taken by lane
+// b % 64, so consecutive lanes take consecutive lines and every access of the
+// wavefront is a nearly contiguous run; an odd LT also spreads
+// element-strided accesses (loads of whole lines) over the banks.  Only the
+// wavefront touches its lines, so a stage synchronises the wavefront, not the
+// workgroup: LDS executes one wavefront's instructions in order, and the
+// fences keep the compiler from moving accesses across the exchange.
+// em_map holds the (j, c) of a lane's first item and the step between its
 // items, so no stage divides by nl.
 struct EmMap {
     int j0, c0, dj, dc, nl;
 };
 
-template <int NT>
-__device__ __forceinline__ EmMap em_map(int nl) {
+__device__ __forceinline__ EmMap em_map(int nl, int lane) {
     EmMap m;
     m.nl = nl;
-    m.j0 = int(threadIdx.x) / nl;
-    m.c0 = int(threadIdx.x) - m.j0 * nl;
-    m.dj = NT / nl;
-    m.dc = NT - m.dj * nl;
+    m.j0 = lane / nl;
+    m.c0 = lane - m.j0 * nl;
+    m.dj = 64 / nl;
+    m.dc = 64 - m.dj * nl;
     return m;
 }
 
@@ -319,13 +322,19 @@ __device__ __forceinline__ void em_next(const EmMap& m, int& j, int& c) {
     }
 }
 
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One Stockham stage; tw[m] = exp(-2 pi i m / L) (a table of this length).
-template <typename C, int L, int NS, bool INV, int NT, int MAXL, int LT>
+template <typename C, int L, int NS, bool INV, int MAXL, int LT>
 __device__ __forceinline__ void fft_stage_em(C* s, const C* __restrict__ tw, const EmMap& m) {
     constexpr int R = radix_for<L / NS>::value;
     constexpr int PER = L / R;
     constexpr int TWS = L / (NS * R);
-    constexpr int MAXB = (MAXL * PER + NT - 1) / NT;
+    constexpr int MAXB = (MAXL * PER + 63) / 64;
     C v[MAXB][R];
     int jj[MAXB], cc[MAXB];
     {
@@ -341,7 +350,7 @@ __device__ __forceinline__ void fft_stage_em(C* s, const C* __restrict__ tw, con
             em_next(m, j, c);
         }
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
         const int j = jj[i], c = cc[i];
@@ -361,24 +370,24 @@ __device__ __forceinline__ void fft_stage_em(C* s, const C* __restrict__ tw, con
             for (int r = 0; r < R; ++r) s[(o + r * NS) * LT + c] = v[i][r];
         }
     }
-    __syncthreads();
+    wave_sync();
 }
 
-template <typename C, int L, int NS, bool INV, int NT, int MAXL, int LT>
+template <typename C, int L, int NS, bool INV, int MAXL, int LT>
 __device__ __forceinline__ void fft_stages_em(C* s, const C* __restrict__ tw, const EmMap& m) {
     if constexpr (NS < L) {
         constexpr int R = radix_for<L / NS>::value;
-        fft_stage_em<C, L, NS, INV, NT, MAXL, LT>(s, tw, m);
-        fft_stages_em<C, L, NS * R, INV, NT, MAXL, LT>(s, tw, m);
+        fft_stage_em<C, L, NS, INV, MAXL, LT>(s, tw, m);
+        fft_stages_em<C, L, NS * R, INV, MAXL, LT>(s, tw, m);
     }
 }
 
-// In-place FFT of the m.nl lines; begins with a barrier (the caller's writes)
-// and ends with one (results readable).
-template <typename C, int L, bool INV, int NT, int MAXL, int LT>
-__device__ __forceinline__ void lds_fft_em(C* s, const C* __restrict__ tw, const EmMap& m) {
-    __syncthreads();
-    fft_stages_em<C, L, 1, INV, NT, MAXL, LT>(s, tw, m);
+// In-place FFT of the wavefront's m.nl lines; begins with a wavefront
+// synchronisation (its own writes) and ends with one.
+template <typename C, int L, bool INV, int MAXL, int LT>
+__device__ __forceinline__ void wave_fft_em(C* s, const C* __restrict__ tw, const EmMap& m) {
+    wave_sync();
+    fft_stages_em<C, L, 1, INV, MAXL, LT>(s, tw, m);
 }
 
 // As col_fft, but every stage after the first one runs in LDS, so the whole

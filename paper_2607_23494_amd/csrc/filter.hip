@@ -21,6 +21,7 @@
 // and in float64 across groups and workgroups.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -57,7 +58,8 @@ template <typename T, int N>
 constexpr size_t z_lds_bytes(int nb) {
     using C = typename cplx_of<T>::type;
     constexpr int R = zrows<N>::R, M = N / 2;
-    const size_t lines = size_t(M) * z_lt(nb * R) * sizeof(C) + size_t(R) * N * sizeof(T) + size_t(M) * sizeof(C);
+    const size_t lines = size_t(M) * z_lt(nb * R) * sizeof(C) + size_t(R) * N * sizeof(T) + size_t(R) * N * 2 +
+                         size_t(M) * sizeof(C);
     const size_t red = size_t(kThreads) * 16 * sizeof(double);
     return lines > red ? lines : red;
 }
@@ -388,84 +390,102 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-// Contraction of one row group on the matrix cores:
-//   C[i][j] += sum_c x_i(c) * (delta(c) x_j(c)),  i, j < 32 (bins >= nb are zero),
-// with a = x and b = delta x split as a = a_hi + a_lo, b = b_hi + b_lo in
-// bf16 (PREC 1) or fp16 (PREC 2) and C accumulated as a_hi b_hi + a_hi b_lo +
-// a_lo b_hi by 32x32x16 MFMAs in float32.  Wave w takes a quarter of the
-// group's cells; lane l supplies bin l % 32 at cells 8 (l / 32) .. +7 of each
-// 16-cell step for both operands.  The float32 tile sum is added to float64
-// accumulators once per group.
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
+// Contraction of one row group on the matrix cores.  With y_b(c) =
+// sqrt|delta(c)| x_b(c) and s(c) the sign of delta(c), the group's share is
+//   C[i][j] = sum_c s(c) y_i(c) y_j(c),   i, j < 32,
+// and the split y = y_hi + y_lo in bf16 (PREC 1) or fp16 (PREC 2) gives
+//   C = H + L + L^T + O(y_lo^2),  H = sum_c s y_hi y_hi^T,  L = sum_c s y_lo y_hi^T,
+// i.e. the three hi/lo products of the split with the two mixed ones equal up
+// to a transpose.  Both terms are 32x32x16 MFMAs over 16 cells with the
+// operand B = s y_hi (the sign flips the packed halves with one xor per two
+// cells).  Wave w takes a quarter of the group's cells; lane l supplies bin
+// l % 32 at cells 8 (l / 32) .. +7 of each step; lanes past the last window
+// repeat it (rows and columns >= nb of C are never read).  H is added to the
+// float64 accumulators once per group; L, about 2^-8 of H, stays in float32
+// across groups and is transposed in the final reduction.
+// sr[c] = sqrt|delta(c)|, sgn[c / 2] = the sign bits of cells c, c + 1 at bits
+// 15 and 31.
 template <typename T, int N, int PREC, int LT>
-__device__ __forceinline__ void mfma_contract(const typename cplx_of<T>::type* s, const T* sd, int nb,
-                                              double* acc64) {
+__device__ __forceinline__ void mfma_contract(const typename cplx_of<T>::type* s, const float* sr,
+                                              const uint32_t* sgn, int nb, double* acc64, f32x16_t& accl) {
     using C = typename cplx_of<T>::type;
+    using V = typename std::conditional<PREC == HERMES_PREC_BF16X3, bf16x8_t, f16x8_t>::type;
+    using E = typename std::conditional<PREC == HERMES_PREC_BF16X3, __bf16, _Float16>::type;
     constexpr int R = zrows<N>::R;
     constexpr int CELLS = R * N;
     constexpr int PER_WAVE = CELLS / (kThreads / 64);
     static_assert(PER_WAVE % 16 == 0, "16-cell MFMA steps");
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    const int bin = l % 32, half = l / 32;
+    const int bin = min(l % 32, nb - 1), half = l / 32;
     f32x16_t acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
     for (int step = 0; step < PER_WAVE / 16; ++step) {
         const int c0 = w * PER_WAVE + step * 16 + 8 * half;   // 8 consecutive cells of one row
         const int r = c0 / N, z = c0 - r * N;
-        float x[8], d[8];
         const C* src = s + (z >> 1) * LT + bin * R + r;   // complex element z/2 of the line
+        const float4 r0 = *reinterpret_cast<const float4*>(sr + c0);
+        const float4 r1 = *reinterpret_cast<const float4*>(sr + c0 + 4);
+        const u32x4_t sm = *reinterpret_cast<const u32x4_t*>(sgn + c0 / 2);
+        const float rr[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+        float y[8];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const C v = bin < nb ? src[u * LT] : C{T(0), T(0)};
-            x[2 * u] = float(v.x);
-            x[2 * u + 1] = float(v.y);
+            const C v = src[u * LT];
+            y[2 * u] = float(v.x) * rr[2 * u];
+            y[2 * u + 1] = float(v.y) * rr[2 * u + 1];
         }
+        V hi, lo;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) d[t] = float(sd[c0 + t]);
+        for (int t = 0; t < 8; ++t) {
+            hi[t] = (E)y[t];
+            lo[t] = (E)(y[t] - float(hi[t]));
+        }
+        const V hs = __builtin_bit_cast(V, __builtin_bit_cast(u32x4_t, hi) ^ sm);
         if constexpr (PREC == HERMES_PREC_BF16X3) {
-            bf16x8_t ah, al, bh, bl;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const float a = x[t], b = d[t] * x[t];
-                ah[t] = (__bf16)a;
-                al[t] = (__bf16)(a - float(ah[t]));
-                bh[t] = (__bf16)b;
-                bl[t] = (__bf16)(b - float(bh[t]));
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi, hs, acc, 0, 0, 0);
+            accl = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo, hs, accl, 0, 0, 0);
         } else {
-            f16x8_t ah, al, bh, bl;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const float a = x[t], b = d[t] * x[t];
-                ah[t] = (_Float16)a;
-                al[t] = (_Float16)(a - float(ah[t]));
-                bh[t] = (_Float16)b;
-                bl[t] = (_Float16)(b - float(bh[t]));
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi, hs, acc, 0, 0, 0);
+            accl = __builtin_amdgcn_mfma_f32_32x32x16_f16(lo, hs, accl, 0, 0, 0);
         }
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc64[r] += double(acc[r]);
 }
 
+// Non-temporal load of the complex value at byte offset off from base through
+// a raw buffer resource: a wavefront-uniform base costs scalar instructions
+// only and the per-lane part is one 32-bit offset.
+template <typename C>
+__device__ __forceinline__ C ld_stream_buf(const C* base, unsigned off) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<C*>(base), 0, 0x7fffffff, 0x00020000);
+    if constexpr (sizeof(C) == 8) {
+        return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 2));
+    } else {
+        static_assert(sizeof(C) == 16, "complex float or double");
+        return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 2));
+    }
+}
+
 // Inverse along z of nb windows x R rows per group (the input rows hold the
 // packed Z[0..M-1], M = N/2, in the pair order, written by the y pass), then
-// the epilogue.  Persistent
-// workgroups; the next group's rows are fetched into registers while the
-// current group's epilogue runs (issuing the fetch after the transform keeps
-// those registers free during it), and no other global load is issued until
-// they are consumed (twiddles live in LDS).
+// the epilogue.  Persistent workgroups.  The nb R lines of a group are split
+// into four contiguous runs, one per wavefront: a wavefront loads its lines,
+// stores them to LDS and transforms them on its own (no workgroup barrier),
+// then issues the loads of its lines of the next group, whose latency the
+// epilogue hides; the workgroup synchronises only around the epilogue, which
+// reads every line.  For M >= 64 a lane loads elements lane + 64 i of a
+// line: one wavefront-contiguous run from a uniform base address.
 // Dynamic LDS: the nb R lines of M complex stored element-major with line
 // stride LT = z_lt(NBCAP R) (a compile-time stride keeps every LDS offset of
-// the FFT stages an immediate), the delta rows [R][N], then the twiddles
-// exp(-2 pi i m/M), m < M.  Real sample z of line c sits at float index
-// 2 ((z / 2) LT + c) + z % 2.
+// the FFT stages an immediate), the delta rows [R][N] (sqrt|delta| for the
+// matrix-core contraction), their packed sign bits [R N / 2], then the
+// twiddles exp(-2 pi i m/M), m < M.  Real sample z of line c sits at float
+// index 2 ((z / 2) LT + c) + z % 2.
 // NBCAP bounds nb (registers).
 template <typename T, int N, int EPI, int NBCAP, int PREC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_c2r_z(const typename cplx_of<T>::type* __restrict__ spec,
@@ -479,19 +499,34 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     constexpr int CELLS = R * N;
     constexpr int GROUPS = N * N / R;
     constexpr int MAXLINES = NBCAP * R;
-    constexpr int MAXE = (MAXLINES * M + kThreads - 1) / kThreads;
-    constexpr int DPT = (CELLS + kThreads - 1) / kThreads;
+    constexpr int NW = kThreads / 64;                       // wavefronts
+    constexpr int MAXLW = (MAXLINES + NW - 1) / NW;         // lines per wavefront
+    constexpr int MAXE = (MAXLW * M + 63) / 64;             // elements per lane
+    constexpr int DPT = CELLS / kThreads;   // delta cells per thread (consecutive)
+    static_assert(CELLS % kThreads == 0 && DPT % 2 == 0, "delta cells in pairs");
+    constexpr bool MF = EPI == EPI_CONTRACT && PREC != HERMES_PREC_FP32;
     extern __shared__ double lds_raw[];
     C* s = reinterpret_cast<C*>(lds_raw);
     T* sf = reinterpret_cast<T*>(lds_raw);
     const int nlines = nb * R;
     constexpr int LT = z_lt(MAXLINES);
     T* sd = reinterpret_cast<T*>(s + M * LT);
-    C* twl = reinterpret_cast<C*>(sd + R * N);
-    const int ne = nlines * M;   // positions 0 .. M-1 of every line
-    const EmMap em = em_map<kThreads>(nlines);
+    uint32_t* sgn = reinterpret_cast<uint32_t*>(sd + R * N);
+    C* twl = reinterpret_cast<C*>(sgn + R * N / 2);
     auto at = [&](int line, int z) { return 2 * ((z >> 1) * LT + line) + (z & 1); };
     for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw[M + i];
+
+    // this wavefront's lines [c_lo, c_lo + nlw)
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+    const int c_lo = wv * nlines / NW, nlw = (wv + 1) * nlines / NW - c_lo;
+    const EmMap em = em_map(nlw > 0 ? nlw : 1, lane);
+    C* sw = s + c_lo;
+    // element i of the lane: local line and position
+    auto elem = [&](int i, int& ll, int& pos) {
+        const int e = lane + 64 * i;
+        ll = e / M;
+        pos = e - ll * M;
+    };
 
     // contraction roles: 4x4 bin tiles (I <= J) x cell groups
     const int nt4 = (nb + 3) / 4;
@@ -517,53 +552,60 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     double acc64[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc64[i] = 0.0;
+    f32x16_t accl;   // the L term of the matrix-core contraction
+#pragma unroll
+    for (int i = 0; i < 16; ++i) accl[i] = 0.f;
 
+    typedef T dvec_t __attribute__((ext_vector_type(DPT)));
     C pre[MAXE];
-    T dpre[DPT];
+    dvec_t dpre;
     auto fetch = [&](int g) {
         const int64_t row0 = int64_t(g) * R;
 #pragma unroll
         for (int i = 0; i < MAXE; ++i) {
-            const int e = threadIdx.x + i * kThreads;
-            if (e < ne) {
-                const int line = e / M, pos = e - line * M;
-                const int b = line / R, r = line - b * R;
-                const int64_t row = row0 + r;   // (x, y) = (row / N, row % N)
-                pre[i] = ld_stream(spec + b * bin_stride + (row / N) * plane_stride<N>() + (row % N) * PP + pos);
+            int ll, pos;
+            elem(i, ll, pos);
+            if (ll < nlw) {
+                const int line = c_lo + ll, b = line / R;
+                const int64_t row = row0 + (line - b * R);   // (x, y) = (row / N, row % N)
+                const C* base = spec + b * bin_stride + (row / N) * plane_stride<N>() + (row % N) * PP;
+                if constexpr (M >= 64) {
+                    pre[i] = ld_stream_buf(base, unsigned(pos) * unsigned(sizeof(C)));   // line uniform in i
+                } else {
+                    pre[i] = ld_stream(base + pos);
+                }
             }
         }
-        if (EPI == EPI_CONTRACT) {
-#pragma unroll
-            for (int i = 0; i < DPT; ++i) {
-                const int e = threadIdx.x + i * kThreads;
-                if (e < CELLS) dpre[i] = delta[row0 * N + e];
-            }
-        }
+        if (EPI == EPI_CONTRACT) dpre = *reinterpret_cast<const dvec_t*>(delta + row0 * N + DPT * threadIdx.x);
     };
+    __syncthreads();   // twiddles
     if (blockIdx.x < GROUPS) fetch(blockIdx.x);
     for (int g = blockIdx.x; g < GROUPS; g += gridDim.x) {
         const int64_t row0 = int64_t(g) * R;
 #pragma unroll
         for (int i = 0; i < MAXE; ++i) {
-            const int e = threadIdx.x + i * kThreads;
-            if (e < ne) {
-                const int line = e / M, pos = e - line * M;
-                s[zk_of_pos<N>(pos) * LT + line] = pre[i];
-            }
+            int ll, pos;
+            elem(i, ll, pos);
+            if (ll < nlw) sw[zk_of_pos<N>(pos) * LT + ll] = pre[i];
         }
-        if (EPI == EPI_CONTRACT) {
+        if constexpr (MF) {
 #pragma unroll
-            for (int i = 0; i < DPT; ++i) {
-                const int e = threadIdx.x + i * kThreads;
-                if (e < CELLS) sd[e] = dpre[i];
+            for (int p = 0; p < DPT / 2; ++p) {
+                const float d0 = float(dpre[2 * p]), d1 = float(dpre[2 * p + 1]);
+                sd[DPT * threadIdx.x + 2 * p] = T(sqrtf(fabsf(d0)));
+                sd[DPT * threadIdx.x + 2 * p + 1] = T(sqrtf(fabsf(d1)));
+                sgn[DPT / 2 * threadIdx.x + p] = ((__float_as_uint(d0) >> 16) & 0x8000u) | (__float_as_uint(d1) & 0x80000000u);
             }
+        } else if constexpr (EPI == EPI_CONTRACT) {
+#pragma unroll
+            for (int i = 0; i < DPT; ++i) sd[DPT * threadIdx.x + i] = dpre[i];
         }
-        __syncthreads();
-        lds_fft_em<C, M, true, kThreads, MAXLINES, LT>(s, twl, em);
+        if (nlw > 0) wave_fft_em<C, M, true, MAXLW, LT>(sw, twl, em);
         // the next group's rows load while the epilogue runs
         if (g + int(gridDim.x) < GROUPS) fetch(g + gridDim.x);
-        if constexpr (EPI == EPI_CONTRACT && PREC != HERMES_PREC_FP32) {
-            mfma_contract<T, N, PREC, LT>(s, sd, nb, acc64);
+        __syncthreads();
+        if constexpr (MF) {
+            mfma_contract<T, N, PREC, LT>(s, reinterpret_cast<const float*>(sd), sgn, nb, acc64, accl);
         } else if constexpr (EPI == EPI_CONTRACT) {
             if (cg < cg_n) {
                 float acc[4][4];
@@ -619,16 +661,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 
     // workgroup reduction of the float64 partial sums
     double* red = lds_raw;
-    if constexpr (EPI == EPI_CONTRACT && PREC != HERMES_PREC_FP32) {
-        // acc64[r] of lane l in wave w holds C[i][j], j = l % 32,
-        // i = 8 (r / 4) + 4 (l / 32) + r % 4 (32x32 MFMA accumulator layout)
+    if constexpr (MF) {
+        // acc64[r] (H) and accl[r] (L) of lane l in wave w hold entry (i, j),
+        // j = l % 32, i = 8 (r / 4) + 4 (l / 32) + r % 4 (32x32 MFMA
+        // accumulator layout); C = H + L + L^T
         const int w = threadIdx.x / 64, l = threadIdx.x % 64;
         for (int st = 0; st < 4; ++st) {
             if (w == st) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int i = 8 * (r / 4) + 4 * (l / 32) + (r % 4), j = l % 32;
-                    red[i * 32 + j] = (st == 0 ? 0.0 : red[i * 32 + j]) + acc64[r];
+                    red[i * 32 + j] = (st == 0 ? 0.0 : red[i * 32 + j]) + acc64[r] + double(accl[r]);
+                }
+            }
+            __syncthreads();
+            if (w == st) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int i = 8 * (r / 4) + 4 * (l / 32) + (r % 4), j = l % 32;
+                    red[j * 32 + i] += double(accl[r]);
                 }
             }
             __syncthreads();
