@@ -212,45 +212,60 @@ __device__ __forceinline__ void lds_fft_il(C* s, const C* __restrict__ tw) {
 // writing LDS, which halves the LDS traffic of a load / transform / store
 // sequence.  Starts by writing LDS (the caller synchronises after any earlier
 // reads of the tile) and ends with LDS reads still pending (the caller
-// synchronises before writing the tile again).
-template <typename C, int L, int TC, bool INV, int NT, int TWOFF, int NS, typename FIN>
-__device__ __forceinline__ void col_stages(C* s, const C* __restrict__ tw, FIN& fin) {
+// synchronises before writing the tile again).  col_fft_front runs the
+// register stage and the middle stages (ending with a workgroup barrier),
+// col_fft_last the last stage, so a caller can act between the two.
+template <int L, int NS>
+constexpr int last_stage_ns() {
     constexpr int R = radix_for<L / NS>::value;
     if constexpr (NS * R < L) {
-        fft_stage_il<C, L, TC, NS, INV, NT, TWOFF>(s, tw);
-        col_stages<C, L, TC, INV, NT, TWOFF, NS * R>(s, tw, fin);
+        return last_stage_ns<L, NS * R>();
     } else {
-        // last stage: j < PER = NS, so k = j and the outputs sit at j + r NS
-        constexpr int PER = L / R;
-        constexpr int TOT = TC * PER;
-        static_assert(TOT % NT == 0, "tile must split evenly over the workgroup");
-#pragma unroll
-        for (int i = 0; i < TOT / NT; ++i) {
-            const int b = threadIdx.x + i * NT;
-            const int line = b % TC, j = b / TC;
-            C v[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[r] = s[(j + r * PER) * TC + line];
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                C w = tw[TWOFF + r * j];
-                if (INV) w.y = -w.y;
-                v[r] = c_mul(v[r], w);
-            }
-            butterfly<INV, R>(v);
-            fin(j, line, v, R, NS);   // v[r] is the output at position j + r NS
-        }
+        return NS;
     }
 }
 
-// First stage in registers and the middle stages in LDS as described above;
-// the last stage hands each butterfly's outputs to fin(j, line, v, R, NS)
-// (v[r] at position j + r NS of column `line`).  Items of the last stage are
-// dealt so that lane b % 64 of a wavefront holds column b % TC: with TC <= 64
-// the columns of one position j sit in TC consecutive lanes of one wavefront.
-// Requires L > 8.
-template <typename C, int L, int TC, int VEC, bool INV, int NT, int TWOFF, typename FIN>
-__device__ __forceinline__ void col_fft_fin(C* s, const C* __restrict__ tw, C (&x)[8][VEC], int lc, int j, FIN& fin) {
+template <typename C, int L, int TC, bool INV, int NT, int TWOFF, int NS>
+__device__ __forceinline__ void col_mid_stages(C* s, const C* __restrict__ tw) {
+    constexpr int R = radix_for<L / NS>::value;
+    if constexpr (NS * R < L) {
+        fft_stage_il<C, L, TC, NS, INV, NT, TWOFF>(s, tw);
+        col_mid_stages<C, L, TC, INV, NT, TWOFF, NS * R>(s, tw);
+    }
+}
+
+// last stage: j < PER = NS, so k = j and the outputs sit at j + r NS
+template <typename C, int L, int TC, bool INV, int NT, int TWOFF, typename FIN>
+__device__ __forceinline__ void col_fft_last(C* s, const C* __restrict__ tw, FIN& fin) {
+    constexpr int NS = last_stage_ns<L, 8>();
+    constexpr int R = L / NS;
+    constexpr int PER = L / R;
+    constexpr int TOT = TC * PER;
+    static_assert(TOT % NT == 0, "tile must split evenly over the workgroup");
+#pragma unroll
+    for (int i = 0; i < TOT / NT; ++i) {
+        const int b = threadIdx.x + i * NT;
+        const int line = b % TC, j = b / TC;
+        C v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = s[(j + r * PER) * TC + line];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            C w = tw[TWOFF + r * j];
+            if (INV) w.y = -w.y;
+            v[r] = c_mul(v[r], w);
+        }
+        butterfly<INV, R>(v);
+        fin(j, line, v, R, NS);   // v[r] is the output at position j + r NS
+    }
+}
+
+// First stage in registers and the middle stages in LDS as described above.
+// Items of the last stage are dealt so that lane b % 64 of a wavefront holds
+// column b % TC: with TC <= 64 the columns of one position j sit in TC
+// consecutive lanes of one wavefront.  Requires L > 8.
+template <typename C, int L, int TC, int VEC, bool INV, int NT, int TWOFF>
+__device__ __forceinline__ void col_fft_front(C* s, const C* __restrict__ tw, C (&x)[8][VEC], int lc, int j) {
     static_assert(L > 8 && NT == (TC / VEC) * (L / 8), "one radix-8 butterfly per owned column");
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
@@ -262,7 +277,15 @@ __device__ __forceinline__ void col_fft_fin(C* s, const C* __restrict__ tw, C (&
         for (int r = 0; r < 8; ++r) s[(8 * j + r) * TC + lc + v] = y[r];
     }
     __syncthreads();
-    col_stages<C, L, TC, INV, NT, TWOFF, 8>(s, tw, fin);
+    col_mid_stages<C, L, TC, INV, NT, TWOFF, 8>(s, tw);
+}
+
+// The whole transform; the last stage hands each butterfly's outputs to
+// fin(j, line, v, R, NS) (v[r] at position j + r NS of column `line`).
+template <typename C, int L, int TC, int VEC, bool INV, int NT, int TWOFF, typename FIN>
+__device__ __forceinline__ void col_fft_fin(C* s, const C* __restrict__ tw, C (&x)[8][VEC], int lc, int j, FIN& fin) {
+    col_fft_front<C, L, TC, VEC, INV, NT, TWOFF>(s, tw, x, lc, j);
+    col_fft_last<C, L, TC, INV, NT, TWOFF>(s, tw, fin);
 }
 
 template <typename C, int L, int TC, int VEC, bool INV, int NT, int TWOFF, typename ST>

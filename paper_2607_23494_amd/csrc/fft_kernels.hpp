@@ -80,6 +80,13 @@ __device__ __forceinline__ double2 ld_stream(const double2* p) {
     const f64x2_nt v = __builtin_nontemporal_load(reinterpret_cast<const f64x2_nt*>(p));
     return double2{v.x, v.y};
 }
+// Non-temporal store of one complex value.
+__device__ __forceinline__ void st_stream(float2* p, float2 v) {
+    __builtin_nontemporal_store(f32x2_nt{v.x, v.y}, reinterpret_cast<f32x2_nt*>(p));
+}
+__device__ __forceinline__ void st_stream(double2* p, double2 v) {
+    __builtin_nontemporal_store(f64x2_nt{v.x, v.y}, reinterpret_cast<f64x2_nt*>(p));
+}
 __device__ __forceinline__ float4 ld_stream(const float4* p) {
     const f32x4_nt v = __builtin_nontemporal_load(reinterpret_cast<const f32x4_nt*>(p));
     return float4{v.x, v.y, v.z, v.w};
