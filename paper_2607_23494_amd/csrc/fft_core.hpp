@@ -75,6 +75,8 @@ __device__ __forceinline__ void butterfly(C* v) {
     }
 }
 
+constexpr int radix_of(int rem) { return rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : 2); }
+
 template <int REM> struct radix_for {
     static constexpr int value = (REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : 2);
 };
@@ -351,14 +353,57 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One Stockham stage; tw[m] = exp(-2 pi i m / L) (a table of this length).
-template <typename C, int L, int NS, bool INV, int MAXL, int LT>
+// Per-stage twiddle layout: the factors w^(r k), r = 1 .. R-1, k < NS, of a
+// stage with NS > 1 (w = exp(-2 pi i / (NS R))) sit at tws[off(NS) + (r - 1) NS
+// + k], so the lanes of a wavefront, which take consecutive k, read
+// consecutive entries (a table indexed by r k TWS puts them on a few banks).
+// The stages after the first hold L - R_1 entries in total.
+template <int L>
+constexpr int em_tw_offset(int ns) {
+    int off = 0;
+    for (int st = 1; st < ns; st *= radix_of(L / st))
+        if (st > 1) off += (radix_of(L / st) - 1) * st;
+    return off;
+}
+template <int L>
+constexpr int em_tw_size() {
+    return L - radix_of(L);
+}
+
+// Fill tws from tw[m] = exp(-2 pi i m / L), m < L (threads tid of nt).
+template <typename C, int L>
+__device__ __forceinline__ void em_stage_twiddles(C* tws, const C* __restrict__ tw, int tid, int nt) {
+    for (int e = tid; e < em_tw_size<L>(); e += nt) {
+        int off = 0, idx = 0;
+        for (int st = 1; st < L; st *= radix_of(L / st)) {
+            const int R = radix_of(L / st);
+            if (st == 1) continue;
+            const int n = (R - 1) * st;
+            if (e < off + n) {
+                const int r = 1 + (e - off) / st, k = (e - off) % st;
+                idx = r * k * (L / (st * R));
+                break;
+            }
+            off += n;
+        }
+        tws[e] = tw[idx];
+    }
+}
+
+// One Stockham stage; tws holds the per-stage twiddles above.  FULL: the
+// wavefront owns exactly MAXL lines (m.nl == MAXL), so the item count is a
+// compile-time constant and only the last, partial round is predicated; the
+// loads of the full rounds then complete one butterfly at a time instead of
+// behind a predicated block.
+template <typename C, int L, int NS, bool INV, int MAXL, int LT, bool FULL>
 __device__ __forceinline__ void fft_stage_em(C* s, const C* __restrict__ tw, const EmMap& m) {
     constexpr int R = radix_for<L / NS>::value;
     constexpr int PER = L / R;
-    constexpr int TWS = L / (NS * R);
+    constexpr int TOFF = em_tw_offset<L>(NS);
     constexpr int MAXB = (MAXL * PER + 63) / 64;
+    constexpr int NFULL = FULL ? (MAXL * PER) / 64 : 0;   // rounds valid in every lane
     C v[MAXB][R];
+    C wt[NS > 1 ? MAXB : 1][R];   // twiddles, loaded with the data
     int jj[MAXB], cc[MAXB];
     {
         int j = m.j0, c = m.c0;
@@ -366,9 +411,14 @@ __device__ __forceinline__ void fft_stage_em(C* s, const C* __restrict__ tw, con
         for (int i = 0; i < MAXB; ++i) {
             jj[i] = j;
             cc[i] = c;
-            if (j < PER) {
+            if (i < NFULL || j < PER) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[i][r] = s[(j + r * PER) * LT + c];
+                if constexpr (NS > 1) {
+                    const int k = j & (NS - 1);
+#pragma unroll
+                    for (int r = 1; r < R; ++r) wt[i][r] = tw[TOFF + (r - 1) * NS + k];
+                }
             }
             em_next(m, j, c);
         }
@@ -377,12 +427,12 @@ __device__ __forceinline__ void fft_stage_em(C* s, const C* __restrict__ tw, con
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
         const int j = jj[i], c = cc[i];
-        if (j < PER) {
+        if (i < NFULL || j < PER) {
             const int k = j & (NS - 1);
             if constexpr (NS > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    C w = tw[r * k * TWS];
+                    C w = wt[i][r];
                     if (INV) w.y = -w.y;
                     v[i][r] = c_mul(v[i][r], w);
                 }
@@ -396,21 +446,21 @@ __device__ __forceinline__ void fft_stage_em(C* s, const C* __restrict__ tw, con
     wave_sync();
 }
 
-template <typename C, int L, int NS, bool INV, int MAXL, int LT>
+template <typename C, int L, int NS, bool INV, int MAXL, int LT, bool FULL>
 __device__ __forceinline__ void fft_stages_em(C* s, const C* __restrict__ tw, const EmMap& m) {
     if constexpr (NS < L) {
         constexpr int R = radix_for<L / NS>::value;
-        fft_stage_em<C, L, NS, INV, MAXL, LT>(s, tw, m);
-        fft_stages_em<C, L, NS * R, INV, MAXL, LT>(s, tw, m);
+        fft_stage_em<C, L, NS, INV, MAXL, LT, FULL>(s, tw, m);
+        fft_stages_em<C, L, NS * R, INV, MAXL, LT, FULL>(s, tw, m);
     }
 }
 
 // In-place FFT of the wavefront's m.nl lines; begins with a wavefront
 // synchronisation (its own writes) and ends with one.
-template <typename C, int L, bool INV, int MAXL, int LT>
+template <typename C, int L, bool INV, int MAXL, int LT, bool FULL = false>
 __device__ __forceinline__ void wave_fft_em(C* s, const C* __restrict__ tw, const EmMap& m) {
     wave_sync();
-    fft_stages_em<C, L, 1, INV, MAXL, LT>(s, tw, m);
+    fft_stages_em<C, L, 1, INV, MAXL, LT, FULL>(s, tw, m);
 }
 
 // As col_fft, but every stage after the first one runs in LDS, so the whole

@@ -527,8 +527,8 @@ __device__ __forceinline__ C ld_stream_buf(const C* base, unsigned off) {
 // stride LT = z_lt(NBCAP R) (a compile-time stride keeps every LDS offset of
 // the FFT stages an immediate), the delta rows [R][N] (sqrt|delta| for the
 // matrix-core contraction), their packed sign bits [R N / 2], then the
-// twiddles exp(-2 pi i m/M), m < M.  Real sample z of line c sits at float
-// index 2 ((z / 2) LT + c) + z % 2.
+// per-stage twiddles of the length-M transform (em_stage_twiddles).  Real
+// sample z of line c sits at float index 2 ((z / 2) LT + c) + z % 2.
 // NBCAP bounds nb (registers).
 template <typename T, int N, int EPI, int NBCAP, int PREC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_c2r_z(const typename cplx_of<T>::type* __restrict__ spec,
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     uint32_t* sgn = reinterpret_cast<uint32_t*>(sd + R * N);
     C* twl = reinterpret_cast<C*>(sgn + R * N / 2);
     auto at = [&](int line, int z) { return 2 * ((z >> 1) * LT + line) + (z & 1); };
-    for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw[M + i];
+    em_stage_twiddles<C, M>(twl, tw + M, threadIdx.x, kThreads);
 
     // this wavefront's lines [c_lo, c_lo + nlw)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
@@ -643,7 +643,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
             for (int i = 0; i < DPT; ++i) sd[DPT * threadIdx.x + i] = dpre[i];
         }
-        if (nlw > 0) wave_fft_em<C, M, true, MAXLW, LT>(sw, twl, em);
+        if (nlw == MAXLW)
+            wave_fft_em<C, M, true, MAXLW, LT, true>(sw, twl, em);
+        else if (nlw > 0)
+            wave_fft_em<C, M, true, MAXLW, LT>(sw, twl, em);
         // the next group's rows load while the epilogue runs
         if (g + int(gridDim.x) < GROUPS) fetch(g + gridDim.x);
         __syncthreads();
