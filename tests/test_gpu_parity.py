@@ -217,10 +217,11 @@ def _wide_case(n_bins):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("n_bins", [21, 24])
+@pytest.mark.parametrize("n_bins", [20, 21, 24, 32])
 def test_zeta_wide_batches(hermes, precision, n_bins):
-    """More than 20 radial bins: the batch-cap-32 kernels of the z pass (odd
-    and even bin counts), on a 64^3 grid (8 rows per z-pass group)."""
+    """20 radial bins (every z-pass wavefront owns its full line count) and
+    more: the batch-cap-32 kernels of the z pass, with partial (21, 24) and
+    full (32) wavefront line counts, on a 64^3 grid (8 rows per group)."""
     pos, L, n, edges, ref = _wide_case(n_bins)
     _, _, dk, delta = _gpu_field(hermes, pos, None, L, n, torch.float32)
     lmax = 2
