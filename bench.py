@@ -50,6 +50,7 @@ def algorithmic_bytes(name: str, n: int, nb: int):
         "fwd_y": 2 * spec,
         "fwd_x": 2 * spec,
         "inv_x_window": spec + nb * spec,   # read delta^ once; write nb spectra
+        "inv_x_window2": spec + 2 * nb * spec,   # two m of one l: write 2 nb spectra
         "inv_y": 2 * nb * spec,
         "inv_z_contract": nb * spec + field,  # read nb spectra and delta
     }

@@ -105,23 +105,23 @@ inline size_t spec_bytes(int n, bool dbl) {
 }
 
 // ---------------------------------------------------------------- radial table
-// tab[b * nq + q] = R_b(k_q), k_q = kfac sqrt(q), evaluated in float64.
+// tab[b * nq + q] = R_b(k_q), k_q = kfac sqrt(q), evaluated in float64; one
+// thread per (q, window b = blockIdx.y).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_radial(T* __restrict__ tab, int64_t nq, WinSet ws, double kfac,
                                                      const double* __restrict__ gl) {
     const int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (q >= nq) return;
+    const int b = blockIdx.y;
+    if (q >= nq || b >= ws.n) return;
     const double k = kfac * sqrt(double(q));
-    for (int b = 0; b < ws.n; ++b) {
-        double v;
-        switch (ws.type[b]) {
-            case HERMES_WIN_SHELL: v = w_shell(k, ws.lo[b], ws.hi[b]); break;
-            case HERMES_WIN_SPHERE: v = w_sphere(k * ws.hi[b]); break;
-            case HERMES_WIN_GAUSS: v = exp(-0.5 * (k * ws.hi[b]) * (k * ws.hi[b])); break;
-            default: v = jbar(ws.ell[b], k, ws.lo[b], ws.hi[b], gl); break;
-        }
-        tab[b * nq + q] = T(v);
+    double v;
+    switch (ws.type[b]) {
+        case HERMES_WIN_SHELL: v = w_shell(k, ws.lo[b], ws.hi[b]); break;
+        case HERMES_WIN_SPHERE: v = w_sphere(k * ws.hi[b]); break;
+        case HERMES_WIN_GAUSS: v = exp(-0.5 * (k * ws.hi[b]) * (k * ws.hi[b])); break;
+        default: v = jbar(ws.ell[b], k, ws.lo[b], ws.hi[b], gl); break;
     }
+    tab[b * nq + q] = T(v);
 }
 
 // ---------------------------------------------------------------- kz order
@@ -161,22 +161,23 @@ __device__ __forceinline__ int64_t col_row(int a, int c) {
     return int64_t(c) * (c + 1) / 2 + a;
 }
 
+// One workgroup per (row, window); the window is the slow grid axis, so the
+// workgroups in flight gather from one window's table, which stays in L2.
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_radial_cols(const T* __restrict__ tab, int64_t nq, int nb,
                                                           T* __restrict__ U) {
     constexpr int H = N / 2 + 1, HP = col_pitch<T, N>();
     const int64_t row = blockIdx.x;
+    const int b = blockIdx.y;
     // invert row = c (c + 1) / 2 + a, 0 <= a <= c
     int c = int((sqrt(8.0 * double(row) + 1.0) - 1.0) * 0.5);
     while (int64_t(c + 1) * (c + 2) / 2 <= row) ++c;
     while (int64_t(c) * (c + 1) / 2 > row) --c;
     const int a = int(row - int64_t(c) * (c + 1) / 2);
     const int64_t q0 = int64_t(a) * a + int64_t(c) * c;
-    T* dst = U + row * nb * HP;
-    for (int t = threadIdx.x; t < nb * HP; t += kThreads) {
-        const int b = t / HP, ax = t - b * HP;
-        dst[t] = ax < H ? tab[b * nq + q0 + int64_t(ax) * ax] : T(0);
-    }
+    const T* tb = tab + b * nq + q0;
+    T* dst = U + (row * nb + b) * HP;
+    for (int ax = threadIdx.x; ax < HP; ax += kThreads) dst[ax] = ax < H ? tb[int64_t(ax) * ax] : T(0);
 }
 
 // ---------------------------------------------------------------- pass X
@@ -222,11 +223,15 @@ __device__ __forceinline__ int x_tile_origin(int b) {
     }
 }
 
-template <typename T, int N, int VEC, int NT>
+// NM angular factors (1 or 2: two m of one l, which share the radial table)
+// per launch: yc[a] and out[a] for a < NM; the table runs and delta^ are read
+// once for both.
+template <typename T, int N, int VEC, int NT, int NM>
 __global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* __restrict__ dk,
-                                                    int sh, YlmConst yc, double sre, double sim,
+                                                    int sh, YlmConst yc0, YlmConst yc1, double sre, double sim,
                                                     const double* __restrict__ phi1d,
-                                                    typename cplx_of<T>::type* __restrict__ out,
+                                                    typename cplx_of<T>::type* __restrict__ out0,
+                                                    typename cplx_of<T>::type* __restrict__ out1,
                                                     int64_t bin_stride, int nb, const T* __restrict__ U,
                                                     const typename cplx_of<T>::type* __restrict__ tw) {
     using C = typename cplx_of<T>::type;
@@ -289,23 +294,28 @@ __global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* _
     const T* suf = reinterpret_cast<const T*>(su);
     // raw = delta^ Phi^ A s / N^3 of the tile (A = 1 or the Nyquist-averaged
     // Y^R_lm, s the complex constant), in float64 and rounded once
-    C raw[8][VEC];
+    C raw[NM][8][VEC];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int kx = r0 + i * RPP;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-            raw[i][v] = C{T(0), T(0)};
+#pragma unroll
+            for (int a = 0; a < NM; ++a) raw[a][i][v] = C{T(0), T(0)};
             if (ok[v]) {
                 const int ky = kyv[v], kz = kzv[v];
                 const C d = dk[(int64_t(kx) * N + ky) * (N / 2 + 1) + kz];
-                double f = phi1d[N + kx] * phi1d[N + ky] * phi1d[N + kz];
-                if (sh)
-                    f *= ylm_mode(yc, signed_mode<N>(kx), signed_mode<N>(ky), kz, kx == N / 2, ky == N / 2,
-                                  kz == N / 2);
+                const double f0 = phi1d[N + kx] * phi1d[N + ky] * phi1d[N + kz];
                 const double re = double(d.x) * sre - double(d.y) * sim;
                 const double im = double(d.x) * sim + double(d.y) * sre;
-                raw[i][v] = C{T(re * f), T(im * f)};
+#pragma unroll
+                for (int a = 0; a < NM; ++a) {
+                    double f = f0;
+                    if (sh)
+                        f *= ylm_mode(a ? yc1 : yc0, signed_mode<N>(kx), signed_mode<N>(ky), kz, kx == N / 2,
+                                      ky == N / 2, kz == N / 2);
+                    raw[a][i][v] = C{T(re * f), T(im * f)};
+                }
             }
         }
     }
@@ -313,40 +323,44 @@ __global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* _
     ustore();
     __syncthreads();
     for (int b = 0; b < nb; ++b) {
-        C x[8][VEC];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int ax = abs(signed_mode<N>(r0 + i * RPP));
+        for (int a = 0; a < NM; ++a) {
+            C x[8][VEC];
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                const T r = suf[(lc + v) * HP + ax];
-                x[i][v] = C{raw[i][v].x * r, raw[i][v].y * r};
+            for (int i = 0; i < 8; ++i) {
+                const int ax = abs(signed_mode<N>(r0 + i * RPP));
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const T r = suf[(lc + v) * HP + ax];
+                    x[i][v] = C{raw[a][i][v].x * r, raw[a][i][v].y * r};
+                }
             }
-        }
-        if (b + 1 < nb) uload(b + 1);   // lands during the transform
-        C* ob = out + b * bin_stride + c0;
-        auto st = [&](int p, int line, C val) {
-            const int c = c0 + line;
-            if (c < PLANE && pos_used<N>(c % PP)) st_stream(ob + int64_t(p) * plane_stride<N>() + line, val);
-        };
-        if constexpr (N > 8) {
-            // the next window's runs go to su before this window's stores
-            // are issued (su was last read before the transform's first
-            // barrier): waiting for the loads never waits for those stores
-            col_fft_front<C, N, TC, VEC, true, NT, 0>(s, twl, x, lc, r0);
-            if (b + 1 < nb) ustore();
-            auto fin = [&](int jj, int line, const C* v, int R, int NS) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) st(jj + r * NS, line, v[r]);
+            const bool last = a == NM - 1;   // the last reader of su for window b
+            if (a == 0 && b + 1 < nb) uload(b + 1);   // lands during the transform
+            C* ob = (a ? out1 : out0) + b * bin_stride + c0;
+            auto st = [&](int p, int line, C val) {
+                const int c = c0 + line;
+                if (c < PLANE && pos_used<N>(c % PP)) st_stream(ob + int64_t(p) * plane_stride<N>() + line, val);
             };
-            col_fft_last<C, N, TC, true, NT, 0>(s, twl, fin);
-            __syncthreads();
-        } else {
-            col_fft<C, N, TC, VEC, true, NT, 0>(s, twl, x, lc, r0, st);
-            __syncthreads();
-            if (b + 1 < nb) {
-                ustore();
+            if constexpr (N > 8) {
+                // the next window's runs go to su before this window's last
+                // stores are issued (su was last read before the transform's
+                // first barrier): waiting for the loads never waits for them
+                col_fft_front<C, N, TC, VEC, true, NT, 0>(s, twl, x, lc, r0);
+                if (last && b + 1 < nb) ustore();
+                auto fin = [&](int jj, int line, const C* v, int R, int NS) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) st(jj + r * NS, line, v[r]);
+                };
+                col_fft_last<C, N, TC, true, NT, 0>(s, twl, fin);
                 __syncthreads();
+            } else {
+                col_fft<C, N, TC, VEC, true, NT, 0>(s, twl, x, lc, r0, st);
+                __syncthreads();
+                if (last && b + 1 < nb) {
+                    ustore();
+                    __syncthreads();
+                }
             }
         }
     }
@@ -815,13 +829,14 @@ static void launch_z(const typename cplx_of<T>::type* sp, int64_t bin_stride, in
                        nb, delta, out, ws, part, tw);
 }
 
-// One batch: pass X, Y, Z over nb windows sharing the angular factor.
-template <typename T, int N, int EPI>
-static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, double box_L, const WinSet& ws, int sh,
-                      int ell, int m, bool build_table, void* spec_ws, T* rtab, T* ucol, double* part, T* out,
-                      int precision, hipStream_t stream) {
+// Pass X over nb windows for one angular factor (m), or for two (m, m2) of
+// the same l sharing the radial table, writing spec_ws and spec_ws2.
+template <typename T, int N>
+static void run_x(hermes_ctx ctx, const void* delta_k, double box_L, const WinSet& ws, int sh, int ell, int m,
+                  int m2, bool pair, bool build_table, void* spec_ws, void* spec_ws2, T* rtab, T* ucol,
+                  hipStream_t stream) {
     using C = typename cplx_of<T>::type;
-    constexpr int P = N / 2 + 1, PP = pitch_of<N>();
+    constexpr int PP = pitch_of<N>();
     constexpr int XVEC = win_vec<T>(), XNT = win_threads<T>();
     constexpr int TC = col_cfg<T, N, XVEC, XNT>::TC;
     const C* tw = tw_ptr<T>(ctx->t);
@@ -831,9 +846,9 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
     const int64_t bin_stride = int64_t(N) * plane_stride<N>();
     if (build_table) {
         LaunchScope ls(ctx, stream, "radial_table");
-        hipLaunchKernelGGL((k_radial<T>), dim3((nq + kThreads - 1) / kThreads), dim3(kThreads), 0, stream, rtab, nq,
+        hipLaunchKernelGGL((k_radial<T>), dim3((nq + kThreads - 1) / kThreads, nb), dim3(kThreads), 0, stream, rtab, nq,
                            ws, 2.0 * M_PI / box_L, ctx->t.gl);
-        hipLaunchKernelGGL((k_radial_cols<T, N>), dim3(col_rows(N)), dim3(kThreads), 0, stream, rtab, nq, nb, ucol);
+        hipLaunchKernelGGL((k_radial_cols<T, N>), dim3(col_rows(N), nb), dim3(kThreads), 0, stream, rtab, nq, nb, ucol);
     }
     // scale: angular constant times 1/N^3 (inverse DFT normalisation)
     const double inv = 1.0 / (double(N) * N * N);
@@ -848,12 +863,29 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
         }
     }
     C* sp = static_cast<C*>(spec_ws);
-    {
+    const YlmConst y0 = ylm_const(ell, m);
+    if (pair) {
+        LaunchScope ls(ctx, stream, "inv_x_window2");
+        hipLaunchKernelGGL((k_win_x<T, N, XVEC, XNT, 2>), dim3((plane + TC - 1) / TC), dim3(XNT), 0, stream,
+                           static_cast<const C*>(delta_k), sh, y0, ylm_const(ell, m2), sre, sim, ctx->t.phi1d, sp,
+                           static_cast<C*>(spec_ws2), bin_stride, nb, ucol, tw);
+    } else {
         LaunchScope ls(ctx, stream, "inv_x_window");
-        hipLaunchKernelGGL((k_win_x<T, N, XVEC, XNT>), dim3((plane + TC - 1) / TC), dim3(XNT), 0, stream,
-                           static_cast<const C*>(delta_k), sh, ylm_const(ell, m), sre, sim, ctx->t.phi1d, sp,
-                           bin_stride, nb, ucol, tw);
+        hipLaunchKernelGGL((k_win_x<T, N, XVEC, XNT, 1>), dim3((plane + TC - 1) / TC), dim3(XNT), 0, stream,
+                           static_cast<const C*>(delta_k), sh, y0, y0, sre, sim, ctx->t.phi1d, sp, sp, bin_stride,
+                           nb, ucol, tw);
     }
+}
+
+// Passes Y and Z over the nb windows of one batch spectrum.
+template <typename T, int N, int EPI>
+static void run_yz(hermes_ctx ctx, const T* delta, const WinSet& ws, void* spec_ws, double* part, T* out,
+                   int precision, hipStream_t stream) {
+    using C = typename cplx_of<T>::type;
+    const C* tw = tw_ptr<T>(ctx->t);
+    const int nb = ws.n;
+    const int64_t bin_stride = int64_t(N) * plane_stride<N>();
+    C* sp = static_cast<C*>(spec_ws);
     {
         LaunchScope ls(ctx, stream, "inv_y");
         using YC = ypack_cfg<T, N>;
@@ -879,6 +911,15 @@ static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, doubl
             launch_z<T, N, EPI, kFilterChunk, HERMES_PREC_FP32>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
         }
     }
+}
+
+// One batch: pass X, Y, Z over nb windows sharing the angular factor.
+template <typename T, int N, int EPI>
+static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, double box_L, const WinSet& ws, int sh,
+                      int ell, int m, bool build_table, void* spec_ws, T* rtab, T* ucol, double* part, T* out,
+                      int precision, hipStream_t stream) {
+    run_x<T, N>(ctx, delta_k, box_L, ws, sh, ell, m, m, false, build_table, spec_ws, spec_ws, rtab, ucol, stream);
+    run_yz<T, N, EPI>(ctx, delta, ws, spec_ws, part, out, precision, stream);
 }
 
 // ---------------------------------------------------------------- filter_bins
@@ -974,9 +1015,13 @@ hermes_status filter_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype,
 }
 
 // ---------------------------------------------------------------- zeta_l
+// Two m of one l share a pass X (and its reads of delta^ and the radial
+// table) when a second batch spectrum fits: grids up to 512^3.
+inline bool zeta_pairs(int n) { return n <= 512; }
+
 size_t zeta_workspace(int n, int n_bins) {
     const size_t nq = size_t(qmax_of(n) + 1);
-    return align256(spec_bytes(n, false) * n_bins) + align256(nq * n_bins * sizeof(float)) +
+    return align256(spec_bytes(n, false) * n_bins) * (zeta_pairs(n) ? 2 : 1) + align256(nq * n_bins * sizeof(float)) +
            align256(col_table_bytes(n, n_bins, sizeof(float))) +
            align256(size_t(z_grid_rt(n)) * n_bins * n_bins * sizeof(double));
 }
@@ -992,8 +1037,11 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
         return fail(HERMES_ERR_UNSUPPORTED, "hermes_zeta_l: the matrix-core contraction takes at most 32 bins");
     const size_t nq = size_t(qmax_of(N) + 1);
     char* w = static_cast<char*>(work);
+    const bool pairs = zeta_pairs(N);
     void* spec = w;
     char* tail = w + align256(spec_bytes(N, false) * nb);
+    void* spec2 = tail;
+    if (pairs) tail += align256(spec_bytes(N, false) * nb);
     float* rtab = reinterpret_cast<float*>(tail);
     tail += align256(nq * nb * sizeof(float));
     float* ucol = reinterpret_cast<float*>(tail);
@@ -1015,12 +1063,17 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
             ws.hi[b] = edges.e[b + 1];
             ws.out[b] = b;
         }
-        for (int m = -ell; m <= ell; ++m) {
-            run_batch<float, N, EPI_CONTRACT>(ctx, delta_k, delta, box_L, ws, 1, ell, m, m == -ell, spec,
-                                              rtab, ucol, part, nullptr, precision, stream);
-            LaunchScope ls(ctx, stream, "reduce");
-            hipLaunchKernelGGL(k_reduce_part, dim3(nb * nb), dim3(kThreads), 0, stream, part, grid, nb * nb, scale,
-                               zeta + int64_t(ell) * nb * nb, 1);
+        for (int m = -ell; m <= ell;) {
+            const bool pair = pairs && m < ell;   // (m, m + 1) in one pass X
+            run_x<float, N>(ctx, delta_k, box_L, ws, 1, ell, m, m + 1, pair, m == -ell, spec, spec2, rtab, ucol,
+                            stream);
+            for (int k = 0; k < (pair ? 2 : 1); ++k) {
+                run_yz<float, N, EPI_CONTRACT>(ctx, delta, ws, k ? spec2 : spec, part, nullptr, precision, stream);
+                LaunchScope ls(ctx, stream, "reduce");
+                hipLaunchKernelGGL(k_reduce_part, dim3(nb * nb), dim3(kThreads), 0, stream, part, grid, nb * nb,
+                                   scale, zeta + int64_t(ell) * nb * nb, 1);
+            }
+            m += pair ? 2 : 1;
         }
     }
     return check_launch("hermes_zeta_l");
