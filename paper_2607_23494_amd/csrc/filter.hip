@@ -247,6 +247,7 @@ __global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* _
     __shared__ C s[N * TC];
     __shared__ C twl[N];
     __shared__ V su[NCH];                              // the tile's table runs, column v at [v CPC, (v+1) CPC)
+    __shared__ C raw1[NM > 1 ? 8 * VEC * NT : 1];      // the second factor's tile values, [i][v][thread]
     stage_twiddles<C, N, NT>(twl, tw);
     const int c0 = x_tile_origin<N, PP, TC>(blockIdx.x);
     const int lc = (threadIdx.x % LPR) * VEC, r0 = threadIdx.x / LPR;
@@ -294,14 +295,15 @@ __global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* _
     const T* suf = reinterpret_cast<const T*>(su);
     // raw = delta^ Phi^ A s / N^3 of the tile (A = 1 or the Nyquist-averaged
     // Y^R_lm, s the complex constant), in float64 and rounded once
-    C raw[NM][8][VEC];
+    // (the first factor's in registers, the second's in LDS)
+    C raw[8][VEC];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int kx = r0 + i * RPP;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-#pragma unroll
-            for (int a = 0; a < NM; ++a) raw[a][i][v] = C{T(0), T(0)};
+            raw[i][v] = C{T(0), T(0)};
+            if constexpr (NM > 1) raw1[(i * VEC + v) * NT + threadIdx.x] = C{T(0), T(0)};
             if (ok[v]) {
                 const int ky = kyv[v], kz = kzv[v];
                 const C d = dk[(int64_t(kx) * N + ky) * (N / 2 + 1) + kz];
@@ -314,7 +316,10 @@ __global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* _
                     if (sh)
                         f *= ylm_mode(a ? yc1 : yc0, signed_mode<N>(kx), signed_mode<N>(ky), kz, kx == N / 2,
                                       ky == N / 2, kz == N / 2);
-                    raw[a][i][v] = C{T(re * f), T(im * f)};
+                    if (a == 0)
+                        raw[i][v] = C{T(re * f), T(im * f)};
+                    else
+                        raw1[(i * VEC + v) * NT + threadIdx.x] = C{T(re * f), T(im * f)};
                 }
             }
         }
@@ -332,7 +337,8 @@ __global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* _
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
                     const T r = suf[(lc + v) * HP + ax];
-                    x[i][v] = C{raw[a][i][v].x * r, raw[a][i][v].y * r};
+                    const C w = a ? raw1[(i * VEC + v) * NT + threadIdx.x] : raw[i][v];
+                    x[i][v] = C{w.x * r, w.y * r};
                 }
             }
             const bool last = a == NM - 1;   // the last reader of su for window b
@@ -864,12 +870,17 @@ static void run_x(hermes_ctx ctx, const void* delta_k, double box_L, const WinSe
     }
     C* sp = static_cast<C*>(spec_ws);
     const YlmConst y0 = ylm_const(ell, m);
-    if (pair) {
-        LaunchScope ls(ctx, stream, "inv_x_window2");
-        hipLaunchKernelGGL((k_win_x<T, N, XVEC, XNT, 2>), dim3((plane + TC - 1) / TC), dim3(XNT), 0, stream,
-                           static_cast<const C*>(delta_k), sh, y0, ylm_const(ell, m2), sre, sim, ctx->t.phi1d, sp,
-                           static_cast<C*>(spec_ws2), bin_stride, nb, ucol, tw);
-    } else {
+    bool paired = false;
+    if constexpr (std::is_same<T, float>::value) {   // the 3PCF path (float only)
+        if (pair) {
+            LaunchScope ls(ctx, stream, "inv_x_window2");
+            hipLaunchKernelGGL((k_win_x<T, N, XVEC, XNT, 2>), dim3((plane + TC - 1) / TC), dim3(XNT), 0, stream,
+                               static_cast<const C*>(delta_k), sh, y0, ylm_const(ell, m2), sre, sim, ctx->t.phi1d,
+                               sp, static_cast<C*>(spec_ws2), bin_stride, nb, ucol, tw);
+            paired = true;
+        }
+    }
+    if (!paired) {
         LaunchScope ls(ctx, stream, "inv_x_window");
         hipLaunchKernelGGL((k_win_x<T, N, XVEC, XNT, 1>), dim3((plane + TC - 1) / TC), dim3(XNT), 0, stream,
                            static_cast<const C*>(delta_k), sh, y0, y0, sre, sim, ctx->t.phi1d, sp, sp, bin_stride,
