@@ -5,10 +5,14 @@ One step is the whole path over one synthetic catalogue already resident in
 HBM: B3 assignment of 10^7 marked Neyman-Scott points onto a 512^3 grid,
 contrast and r2c FFT, the 40-bin 2PCF over [2, 200] Mpc/h by Parseval, and
 the 3PCF multipoles l = 0..10 over 20 radial bins in [10, 150] Mpc/h.
-Prints one JSON line on stdout (everything else goes to stderr).
+The same step is then timed with the float32 (vector-unit) contraction, the
+other workloads (64^3 float64, 256^3 redshift space, 10^8 marked points on
+1024^3) and the serving mix are measured, and the FP64 oracle is timed on a
+bounded sample.  Prints one JSON line on stdout (everything else goes to
+stderr).
 
   python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3|fp16x3]
-                  [--compare] [--no-cpu-baseline]
+                  [--no-compare] [--no-configs] [--no-serving] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -25,6 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+MFMA_PEAK_TFLOPS = {"bf16x3": 2500.0, "fp16x3": 2500.0}   # dense bf16 / fp16 matrix cores
 WORKLOAD = "ns512_3pcf"
 L_MAX = 10
 
@@ -75,13 +80,22 @@ def measured_traffic(kernel: str):
 
 def cpu_baseline(n: int, box_L: float, nb_xi: int, nb_zeta: int, l_max: int) -> dict:
     """Time the FP64 oracle on a bounded sample of the same 512^3 workload and
-    extrapolate to one step."""
+    extrapolate to one step.  The oracle's DFTs run on scipy's thread pool
+    (one worker per core); everything else is single-threaded numpy."""
     import numpy as np
     import oracle as O
     from oracle import hermes_oracle as OH
+    from paper_2607_23494_amd import synth
 
     rng = np.random.default_rng(1)
     t = {}
+    wl = synth.WORKLOADS[WORKLOAD]
+    sub = 1_000_000
+    pos = synth.neyman_scott(sub // wl.n_children, wl.n_children, wl.sigma, box_L, seed=wl.seed)
+    marks = synth.lognormal_marks(pos.shape[0], wl.seed)
+    t0 = time.perf_counter()
+    O.assign(pos, marks, box_L, n)
+    t["assign_1e6"] = time.perf_counter() - t0
     delta = rng.standard_normal((n, n, n))
     t0 = time.perf_counter()
     dh = O.dft3(delta)
@@ -102,27 +116,54 @@ def cpu_baseline(n: int, box_L: float, nb_xi: int, nb_zeta: int, l_max: int) -> 
     float(np.sum(da * a))
     t["prod"] = time.perf_counter() - t0
     n_lm = (l_max + 1) ** 2
-    step = (t["dft"] + nb_xi * t["xi_bin"] + n_lm * t["ylm"] + n_lm * nb_zeta * t["field"]
-            + n_lm * nb_zeta * (t["da"] + nb_zeta * t["prod"]))
+    n_pts = wl.n_pts
+    step = (t["assign_1e6"] * n_pts / sub + t["dft"] + nb_xi * t["xi_bin"] + n_lm * t["ylm"]
+            + n_lm * nb_zeta * t["field"] + n_lm * nb_zeta * (t["da"] + nb_zeta * t["prod"]))
     sampled = sum(t.values())
     log(f"cpu baseline sample {sampled:.1f}s: " + ", ".join(f"{k}={v:.2f}s" for k, v in t.items()))
     return {
-        "value": step,
+        "value": round(step, 1),
         "unit": "s",
         "cores": OH._WORKERS,
+        "threads": {"dft": OH._WORKERS, "assignment, windows, products": 1},
         "kind": "oracle",
-        "sample": (f"timed at {n}^3: one forward DFT, one 2PCF bin, one real-SH window, one multipole field "
-                   f"and one delta*a*a product ({sampled:.1f} s of CPU); extrapolated to 1 DFT + {nb_xi} bins + "
-                   f"{n_lm} windows + {n_lm * nb_zeta} fields + {n_lm * nb_zeta * nb_zeta} products. "
-                   f"Assignment not included. FFT threads = cores; elementwise work single-threaded."),
+        "sample_s": {k: round(v, 3) for k, v in t.items()},
+        "sample": (f"timed at {n}^3 ({sampled:.1f} s): the assignment of 1e6 of the 1e7 marked points, one "
+                   f"forward DFT, one 2PCF bin, one real-SH window, one multipole field and one delta*a*a "
+                   f"product; extrapolated (not run) to 1e7 points + 1 DFT + {nb_xi} bins + {n_lm} windows + "
+                   f"{n_lm * nb_zeta} fields + {n_lm * nb_zeta * nb_zeta} products. The DFTs (inside each "
+                   f"multipole field too) use {OH._WORKERS} threads; the elementwise work is single-threaded."),
     }
 
 
-def serving_benchmark(precisions, n_requests: int = 64) -> dict:
-    """The serving workload: requests with Poisson arrivals at 0.7 of the
-    solo service capacity, continuous admission under an HBM budget."""
-    import copy
+def _normwise_dev(a, b) -> float:
+    import numpy as np
+    scale = float(np.max(np.abs(b)))
+    return float(np.max(np.abs(a - b)) / scale) if scale > 0 else float(np.max(np.abs(a - b)))
 
+
+def _result_deviation(mix, solo) -> float:
+    """Largest normwise deviation of one request's outputs in the mix from its
+    solo outputs: per xi row, per zeta_l matrix, per moment column."""
+    dev = 0.0
+    for k, v in solo.outputs.items():
+        m = mix.outputs[k]
+        if k == "zeta":
+            rows = [(m[l], v[l]) for l in range(v.shape[0])]
+        elif k == "cic":
+            rows = [(m[:, p], v[:, p]) for p in range(v.shape[1])]
+        else:
+            rows = [(m[i], v[i]) for i in range(v.shape[0])]
+        for a, b in rows:
+            dev = max(dev, _normwise_dev(a, b))
+    return dev
+
+
+def serving_benchmark(precisions, n_requests: int = 64) -> dict:
+    """The serving workload: one Poisson arrival trace at 0.7 of the solo
+    service capacity of the first precision, served at every precision with
+    continuous admission under an HBM budget; each request's result in the mix
+    is compared with its result served alone."""
     import numpy as np
 
     from paper_2607_23494_amd import serving as S
@@ -132,20 +173,26 @@ def serving_benchmark(precisions, n_requests: int = 64) -> dict:
     log(f"serving workload: {n_requests} requests generated in {time.perf_counter() - t0:.1f}s")
     out = {"workload": f"{n_requests} Neyman-Scott catalogues, 1e5-1e7 points (log-uniform), grids "
                        "128/256/512, random subsets of {2PCF 40 bins, xi_l l<=4 30 bins, 3PCF l<=6 12 bins}; "
-                       "4 slots, 200 GB budget, Poisson arrivals at 0.7 / mean solo service time"}
+                       "4 slots, 200 GB budget, one Poisson arrival trace at 0.7 / mean solo service time of "
+                       f"{precisions[0]}, the same trace for every precision"}
     warm = S.Server(slots=1)
+    rate = None
     for prec in precisions:
-        reqs = copy.copy(base)
-        reqs = [dataclasses_replace(r, precision=prec, arrival=0.0) for r in reqs]
+        reqs = [dataclasses_replace(r, precision=prec, arrival=0.0) for r in base]
         warm.run([dataclasses_replace(reqs[0], rid=-1)])
-        solo = S.Server(slots=1).run(reqs)
-        service = np.array([r.finish - r.admit for r in solo if r.status == "ok"])
+        solo = {r.rid: r for r in S.Server(slots=1).run(reqs)}
+        service = np.array([r.finish - r.admit for r in solo.values() if r.status == "ok"])
         mean = float(service.mean())
-        rate = 0.7 / mean
-        S.poisson_arrivals(reqs, rate, seed=2607_0005)
+        if rate is None:
+            rate = 0.7 / mean
+            S.poisson_arrivals(base, rate, seed=2607_0005)
+        reqs = [dataclasses_replace(r, precision=prec) for r in base]
         res = S.Server(slots=4, budget_bytes=200 << 30).run(reqs)
         summ = S.latency_summary(res)
-        summ.update({"mean_solo_service_s": round(mean, 4), "arrival_rate_per_s": round(rate, 3)})
+        dev = max(_result_deviation(r, solo[r.rid]) for r in res if r.status == "ok" and solo[r.rid].status == "ok")
+        summ.update({"mean_solo_service_s": round(mean, 4), "arrival_rate_per_s": round(rate, 3),
+                     "max_dev_vs_solo": float(f"{dev:.3g}"),
+                     "dev_tolerance": 1e-3 if prec != "fp32" else 1e-5})
         for k in ("p50_s", "p99_s", "throughput_req_per_s"):
             if summ[k] is not None:
                 summ[k] = round(summ[k], 4)
@@ -159,14 +206,138 @@ def dataclasses_replace(obj, **kw):
     return dataclasses.replace(obj, **kw)
 
 
+def time_steps(step, warmup: int, steps: int, hermes, label: str):
+    """W untimed steps, then K timed steps with per-kernel HIP-event timing."""
+    import torch
+    for i in range(warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"{label}: warmup step {i + 1}/{warmup} done")
+    hermes.profile_enable(True)
+    hermes.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = hermes.profile_read()
+    hermes.profile_enable(False)
+    log(f"{label}: {steps} timed steps, {elapsed / steps * 1e3:.1f} ms/step")
+    return elapsed / steps, prof
+
+
+def other_configs(warmup: int, steps: int) -> dict:
+    """The 64^3 float64, 256^3 redshift-space and 1024^3 marked workloads,
+    each timed as one step of its statistics on a resident catalogue."""
+    import numpy as np
+    import torch
+
+    from paper_2607_23494_amd import hermes, synth
+
+    out = {}
+
+    def record(name, step, cells_bins, desc):
+        s, prof = time_steps(step, warmup, steps, hermes, name)
+        out[name] = {"workload": desc, "ms_per_step": round(s * 1e3, 3), "steps": steps, "warmup": warmup,
+                     "cells_bins_per_s": round(cells_bins / s, 1),
+                     "stage_ms": {k: round(v[1] / steps, 3) for k, v in sorted(prof.items())}}
+
+    # 64^3, float64: 2e4 points, 20-bin 2PCF over [5, 50]
+    wl = synth.WORKLOADS["ns64_fp64"]
+    pos = torch.from_numpy(wl.catalogue()[0]).cuda()
+    e = synth.EDGES["ns64_fp64"]
+    n = wl.n_grid
+
+    def step64():
+        eps, sw = hermes.assign(pos, None, wl.box_L, n, dtype=torch.float64)
+        dk, _ = hermes.fft(eps, sw, want_delta=False)
+        hermes.xi(dk, wl.box_L, e)
+    record("ns64_fp64", step64, n ** 3 * (e.size - 1),
+           "2e4 Neyman-Scott points, 64^3, float64: assign, FFT, 20-bin 2PCF")
+
+    # 256^3: 2e6 points with z displacements, 40-bin 2PCF and xi_0,2,4 over 30 bins
+    wl = synth.WORKLOADS["ns256_rsd"]
+    pos = torch.from_numpy(wl.catalogue()[0]).cuda()
+    e40, e30 = synth.EDGES["ns256_rsd"], synth.EDGES["ns256_rsd_ell"]
+    n = wl.n_grid
+
+    def step256():
+        eps, sw = hermes.assign(pos, None, wl.box_L, n)
+        dk, _ = hermes.fft(eps, sw, want_delta=False)
+        hermes.xi(dk, wl.box_L, e40)
+        hermes.xi(dk, wl.box_L, e30, ells=(0, 2, 4))
+    record("ns256_rsd", step256, n ** 3 * ((e40.size - 1) + 3 * (e30.size - 1)),
+           "2e6 Neyman-Scott points with z displacements, 256^3, float32: assign, FFT, 40-bin 2PCF, "
+           "xi_0,2,4 over 30 bins")
+    del pos
+    torch.cuda.empty_cache()
+
+    # 1024^3: 1e8 marked points, marked 2PCF (40 bins) and the unmarked 2PCF on
+    # the mark-weighted and number fields, counts-in-cells moments of the
+    # number field for the sphere and Gaussian at 8 radii
+    wl = synth.WORKLOADS["ns1024_cic"]
+    t0 = time.perf_counter()
+    pos_np, w_np = wl.catalogue()
+    log(f"ns1024 catalogue: {pos_np.shape[0]} points in {time.perf_counter() - t0:.1f}s")
+    pos = torch.from_numpy(pos_np).cuda()
+    w = torch.from_numpy(w_np).cuda()
+    del pos_np, w_np
+    n, L = wl.n_grid, wl.box_L
+    e = synth.EDGES["ns1024_cic"]
+    wins = [("sphere", 0.0, R) for R in synth.CIC_RADII] + [("gauss", 0.0, R) for R in synth.CIC_RADII]
+    eps = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+    sw = torch.empty(1, dtype=torch.float64, device="cuda")
+    dk = torch.empty((n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    fwork = torch.empty(hermes.workspace_size(hermes.OP_FILTER, n, torch.float32, len(wins)), dtype=torch.uint8,
+                        device="cuda")
+    xwork = torch.empty(hermes.workspace_size(hermes.OP_XI, n, torch.float32, e.size - 1, 1), dtype=torch.uint8,
+                        device="cuda")
+
+    def step1024():
+        hermes.assign(pos, w, L, n, eps=eps, sum_w=sw)
+        hermes.fft(eps, sw, want_delta=False, delta_k=dk)
+        hermes.xi(dk, L, e, work=xwork)
+        hermes.assign(pos, None, L, n, eps=eps, sum_w=sw)
+        hermes.fft(eps, sw, want_delta=False, delta_k=dk)
+        hermes.xi(dk, L, e, work=xwork)
+        hermes.filter_bins(dk, L, wins, store_fields=False, moments=True, work=fwork)
+    record("ns1024_cic", step1024, n ** 3 * (2 * (e.size - 1) + len(wins)),
+           "1e8 marked Neyman-Scott points, 1024^3, float32: assign and FFT of the mark-weighted and number "
+           "fields, 40-bin 2PCF of each, counts-in-cells moments (p = 2, 3, 4) of the number field for the "
+           "sphere and Gaussian at 8 radii (16 windows)")
+    del pos, w, eps, dk, fwork, xwork
+    torch.cuda.empty_cache()
+    return out
+
+
+def mfma_rate(prof: dict, n: int, nb: int, precision: str):
+    """Matrix-core rate of the fused z pass: each row group of C cells issues,
+    per wavefront quarter, 2 MFMA 32x32x16 per 16 cells (the hi.hi and lo.hi
+    products), i.e. 2 * 2 * 32 * 32 * 16 / 16 flops per cell; the useful part
+    is the nb x nb block of the 32 x 32 tile."""
+    if precision not in MFMA_PEAK_TFLOPS or "inv_z_contract" not in prof:
+        return None
+    launches, total_ms = prof["inv_z_contract"]
+    avg_s = total_ms / launches / 1e3
+    issued = n ** 3 * 2 * (2 * 32 * 32 * 16) / 16
+    useful = issued * (nb * nb) / (32 * 32)
+    return {"kernel": "inv_z_contract", "avg_launch_ms": round(avg_s * 1e3, 4),
+            "issued_flops": issued, "useful_flops": useful,
+            "issued_tflops": round(issued / avg_s / 1e12, 2), "useful_tflops": round(useful / avg_s / 1e12, 2),
+            "peak": MFMA_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+            "frac": round(issued / avg_s / 1e12 / MFMA_PEAK_TFLOPS[precision], 4)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "fp16x3"])
-    ap.add_argument("--compare", action="store_true",
-                    help="also time one step with the fp32 contraction for the mixed-vs-fp32 ratio")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the step with the float32 contraction (mixed-vs-FP32 ratio)")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 64^3, 256^3 and 1024^3 workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -213,29 +384,15 @@ def main() -> int:
         del a, b
         log("copy calibration: 1 GiB read + 1 GiB write done")
 
-    def step(precision):
-        hermes.assign(pos, w, L, n, eps=eps, sum_w=sw)
-        hermes.fft(eps, sw, delta_k=dk, delta=delta)
-        hermes.xi(dk, L, edges_xi, ells=(0,), out=xi_out, work=xi_work)
-        hermes.zeta_l(delta, dk, L, edges_z, L_MAX, precision=precision, out=zeta_out, work=z_work)
+    def step_at(precision):
+        def step():
+            hermes.assign(pos, w, L, n, eps=eps, sum_w=sw)
+            hermes.fft(eps, sw, delta_k=dk, delta=delta)
+            hermes.xi(dk, L, edges_xi, ells=(0,), out=xi_out, work=xi_work)
+            hermes.zeta_l(delta, dk, L, edges_z, L_MAX, precision=precision, out=zeta_out, work=z_work)
+        return step
 
-    for i in range(args.warmup):
-        step(args.precision)
-        torch.cuda.synchronize()
-        log(f"warmup step {i + 1}/{args.warmup} done")
-
-    hermes.profile_enable(True)
-    hermes.profile_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(args.precision)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = hermes.profile_read()
-    hermes.profile_enable(False)
-    s_per_step = elapsed / args.steps
-    log(f"timed {args.steps} steps: {s_per_step * 1e3:.1f} ms/step")
+    s_per_step, prof = time_steps(step_at(args.precision), args.warmup, args.steps, hermes, args.precision)
 
     stages = {k: round(v[1] / args.steps, 3) for k, v in sorted(prof.items())}
     log("per-step kernel ms: " + json.dumps(stages))
@@ -257,17 +414,17 @@ def main() -> int:
         a_s = tms / nl / 1e3
         ab = algorithmic_bytes(k, n, nb_z)
         passes[k] = {"avg_launch_ms": round(a_s * 1e3, 4), "launches": nl, "algorithmic_bytes": ab,
-                     "achieved_GBps": round(ab / a_s / 1e9, 1), "frac": round(ab / a_s / 1e9 / HBM_PEAK_GBS, 4)}
-
-    extra = {}
-    if args.compare:
-        other = "fp32" if args.precision != "fp32" else None
-        if other:
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            step(other)
-            torch.cuda.synchronize()
-            extra["fp32_s_per_step"] = round(time.perf_counter() - t1, 4)
+                     "achieved_GBps": round(ab / a_s / 1e9, 1), "frac": round(ab / a_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(k)}
+    # the 3PCF stage as a whole against the method's bytes: one spectrum read
+    # and one real field written per filtered field
+    zeta_ms = sum(v[1] for k, v in prof.items() if k.startswith("inv_") or k in ("radial_table", "reduce"))
+    fields = nb_z * (L_MAX + 1) ** 2 * args.steps
+    stage_bytes = fields * (n * n * (n // 2 + 1) * 8 + n ** 3 * 4)
+    stage = {"ms_per_step": round(zeta_ms / args.steps, 2), "fields_per_step": fields // args.steps,
+             "method_bytes_per_step": stage_bytes // args.steps,
+             "achieved_GBps": round(stage_bytes / (zeta_ms / 1e3) / 1e9, 1),
+             "frac": round(stage_bytes / (zeta_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     n_lm = (L_MAX + 1) ** 2
     cells = n ** 3
@@ -292,11 +449,24 @@ def main() -> int:
         "stage_ms": stages,
         "roofline": roofline,
         "passes": passes,
+        "zeta_stage": stage,
+        "mfma": mfma_rate(prof, n, nb_z, args.precision),
     }
-    result.update(extra)
+    if not args.no_compare and args.precision != "fp32":
+        s32, prof32 = time_steps(step_at("fp32"), args.warmup, args.steps, hermes, "fp32")
+        z_mixed = prof["inv_z_contract"][1] / prof["inv_z_contract"][0]
+        z_fp32 = prof32["inv_z_contract"][1] / prof32["inv_z_contract"][0]
+        result["fp32_compare"] = {
+            "ms_per_step": round(s32 * 1e3, 2), "steps": args.steps, "warmup": args.warmup,
+            "speedup_end_to_end": round(s32 / s_per_step, 3),
+            "z_pass_ms_fp32": round(z_fp32, 4), "z_pass_ms_mixed": round(z_mixed, 4),
+            "speedup_z_pass": round(z_fp32 / z_mixed, 3),
+            "stage_ms": {k: round(v[1] / args.steps, 3) for k, v in sorted(prof32.items())}}
+    del pos, w, eps, delta, dk, z_work, xi_work
+    torch.cuda.empty_cache()
+    if not args.no_configs:
+        result["configs"] = other_configs(1, max(1, min(args.steps, 5)))
     if not args.no_serving:
-        del pos, w, eps, delta, dk, z_work, xi_work
-        torch.cuda.empty_cache()
         precs = [args.precision] + (["fp32"] if args.precision != "fp32" else [])
         result["serving"] = serving_benchmark(precs)
     if not args.no_cpu_baseline:

@@ -151,7 +151,8 @@ hermes_status hermes_fft(hermes_ctx ctx, const void* eps, const double* sum_w,
  * no shot-noise subtraction (the self-pair term of Sec. 2.2 Eq. CFpow is left
  * to the caller, who can take it from `shot`).
  *   delta_k  device half spectrum from hermes_fft
- *   edges    host double [n_bins+1], strictly increasing, edges[0] >= 0
+ *   edges    host double [n_bins+1], strictly increasing, edges[0] >= 0,
+ *            every edge < box_L / 2 (ERR_ARG otherwise)
  *   ells     host int [n_ells], even values in [0, HERMES_MAX_LMAX]
  *   los_axis 0, 1 or 2 (plane-parallel line of sight)
  *   xi       device double [n_ells][n_bins]; overwritten
@@ -189,7 +190,8 @@ hermes_status hermes_filter_bins(hermes_ctx ctx, const void* delta_k, int n_grid
  * Float32 FFTs; the contraction per `precision`; float64 across tiles.
  *   delta    device float [N^3]: the contrast written by hermes_fft
  *   delta_k  device complex64 half spectrum from hermes_fft
- *   edges    host double [n_bins+1], strictly increasing, edges[0] >= 0
+ *   edges    host double [n_bins+1], strictly increasing, edges[0] >= 0,
+ *            every edge < box_L / 2 (ERR_ARG otherwise)
  *   l_max    0..HERMES_MAX_LMAX
  *   zeta     device double [l_max+1][n_bins][n_bins]; overwritten
  *   work     device workspace of >= hermes_workspace_size(ZETA, n_bins) */

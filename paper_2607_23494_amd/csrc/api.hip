@@ -134,7 +134,9 @@ static hermes_status build_tables(hermes_ctx c) {
     return HERMES_OK;
 }
 
-static hermes_status get_edges(const double* edges, int n_bins, Edges& out, const char* who) {
+// Bin edges: strictly increasing, edges[0] >= 0 and every edge below L/2 (a
+// separation of L/2 or more reaches the periodic image of the box).
+static hermes_status get_edges(const double* edges, int n_bins, double box_L, Edges& out, const char* who) {
     if (!edges) return fail(HERMES_ERR_ARG, std::string(who) + ": edges is NULL");
     if (n_bins < 1 || n_bins > HERMES_MAX_BINS)
         return fail(HERMES_ERR_ARG, std::string(who) + ": n_bins must be in [1, 64]");
@@ -142,6 +144,8 @@ static hermes_status get_edges(const double* edges, int n_bins, Edges& out, cons
     for (int i = 0; i < n_bins; ++i)
         if (!(edges[i + 1] > edges[i]))
             return fail(HERMES_ERR_ARG, std::string(who) + ": edges must be strictly increasing");
+    if (!(edges[n_bins] < 0.5 * box_L))
+        return fail(HERMES_ERR_ARG, std::string(who) + ": edges must be below L/2");
     for (int i = 0; i <= n_bins; ++i) out.e[i] = edges[i];
     out.n_bins = n_bins;
     return HERMES_OK;
@@ -176,7 +180,7 @@ hermes_status hermes_create(hermes_ctx* out, int device) {
     DeviceGuard g(device);
     hermes_ctx c = new hermes_ctx_s();
     c->device = device;
-    const hermes_status st = build_tables(c);
+    hermes_status st = build_tables(c);
     if (st != HERMES_OK) {
         hermes_destroy(c);
         return st;
@@ -319,7 +323,7 @@ hermes_status hermes_xi(hermes_ctx ctx, const void* delta_k, int n_grid, int dty
         if (ells[i] < 0 || ells[i] > HERMES_MAX_LMAX || (ells[i] & 1))
             return fail(HERMES_ERR_ARG, "hermes_xi: multipoles must be even and in [0, 16]");
     Edges e;
-    hermes_status st = get_edges(edges, n_bins, e, "hermes_xi");
+    hermes_status st = get_edges(edges, n_bins, box_L, e, "hermes_xi");
     if (st != HERMES_OK) return st;
     if (work_bytes < xi_workspace(n_grid, n_ells, n_bins))
         return fail(HERMES_ERR_OOM, "hermes_xi: workspace too small");
@@ -375,7 +379,7 @@ hermes_status hermes_zeta_l(hermes_ctx ctx, const float* delta, const void* delt
     if (precision != HERMES_PREC_FP32 && precision != HERMES_PREC_BF16X3 && precision != HERMES_PREC_FP16X3)
         return fail(HERMES_ERR_ARG, "hermes_zeta_l: unknown precision");
     Edges e;
-    hermes_status st = get_edges(edges, n_bins, e, "hermes_zeta_l");
+    hermes_status st = get_edges(edges, n_bins, box_L, e, "hermes_zeta_l");
     if (st != HERMES_OK) return st;
     if (work_bytes < zeta_workspace(n_grid, n_bins)) return fail(HERMES_ERR_OOM, "hermes_zeta_l: workspace too small");
     DeviceGuard g(ctx->device);

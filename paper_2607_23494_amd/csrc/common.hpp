@@ -16,7 +16,6 @@ namespace hermes {
 constexpr int kThreads = 256;      // threads per workgroup for every kernel
 constexpr int kMaxN = 1024;        // largest grid per axis
 constexpr int kTwTable = 2 * 2048; // twiddle entries: table for length L at [L, 2L)
-constexpr int kGL = 64;            // Gauss-Legendre nodes for bin-averaged j_l
 
 // Per-device constant tables owned by a context.
 struct Tables {
@@ -24,7 +23,7 @@ struct Tables {
     double2* tw64 = nullptr;
     double* phi1d = nullptr;    // sinc^8(pi n~/N) at phi1d[N + i], i in [0, N)
     double* b7dft = nullptr;    // sum_{|d|<=3} B7(d) cos(2 pi d i / N) at b7dft[N + i]
-    double* gl = nullptr;       // kGL nodes then kGL weights on [-1, 1]
+    double* gl = nullptr;       // kGLSub (16) Gauss-Legendre nodes, then their weights, on [-1, 1]
 };
 
 // Optional per-kernel timing: launches are bracketed with HIP events on the

@@ -7,6 +7,7 @@ fallback path.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import threading
@@ -96,6 +97,13 @@ def _stream(device: int, stream=None) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on(stream):
+    """Allocate on the stream the kernels are launched on: the caching
+    allocator then never hands a wrapper's workspace or outputs to work on
+    another stream while the library's kernels may still use them."""
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -145,12 +153,13 @@ def assign(pos: torch.Tensor, weight: torch.Tensor | None, box_L: float, n_grid:
     if weight is not None and (weight.dtype != torch.float32 or weight.numel() != pos.shape[0]
                                or not weight.is_contiguous() or _dev(weight) != dev):
         raise ValueError("weight must be a contiguous float32 [n] tensor on the same device")
-    if eps is None:
-        eps = torch.empty((n_grid, n_grid, n_grid), dtype=dtype, device=pos.device)
-    if sum_w is None:
-        sum_w = torch.empty(1, dtype=torch.float64, device=pos.device)
-    _check(_lib.hermes_assign(context(dev), _ptr(pos), _ptr(weight), pos.shape[0], float(box_L), n_grid,
-                              _dtype_code(eps.dtype), _ptr(eps), _ptr(sum_w), _stream(dev, stream)))
+    with _on(stream):
+        if eps is None:
+            eps = torch.empty((n_grid, n_grid, n_grid), dtype=dtype, device=pos.device)
+        if sum_w is None:
+            sum_w = torch.empty(1, dtype=torch.float64, device=pos.device)
+        _check(_lib.hermes_assign(context(dev), _ptr(pos), _ptr(weight), pos.shape[0], float(box_L), n_grid,
+                                  _dtype_code(eps.dtype), _ptr(eps), _ptr(sum_w), _stream(dev, stream)))
     return eps, sum_w
 
 
@@ -160,12 +169,13 @@ def fft(eps: torch.Tensor, sum_w: torch.Tensor, want_delta: bool = True, delta_k
     dev = _dev(eps)
     n = eps.shape[0]
     cdt = torch.complex64 if eps.dtype == torch.float32 else torch.complex128
-    if delta_k is None:
-        delta_k = torch.empty((n, n, n // 2 + 1), dtype=cdt, device=eps.device)
-    if want_delta and delta is None:
-        delta = torch.empty_like(eps)
-    _check(_lib.hermes_fft(context(dev), _ptr(eps), _ptr(sum_w), n, _dtype_code(eps.dtype), _ptr(delta_k),
-                           _ptr(delta) if want_delta else None, _stream(dev, stream)))
+    with _on(stream):
+        if delta_k is None:
+            delta_k = torch.empty((n, n, n // 2 + 1), dtype=cdt, device=eps.device)
+        if want_delta and delta is None:
+            delta = torch.empty_like(eps)
+        _check(_lib.hermes_fft(context(dev), _ptr(eps), _ptr(sum_w), n, _dtype_code(eps.dtype), _ptr(delta_k),
+                               _ptr(delta) if want_delta else None, _stream(dev, stream)))
     return delta_k, (delta if want_delta else None)
 
 
@@ -181,13 +191,14 @@ def xi(delta_k: torch.Tensor, box_L: float, edges, ells: Sequence[int] = (0,), l
     nb = e.size - 1
     dt = _dtype_code(delta_k.dtype)
     wbytes = workspace_size(OP_XI, n, delta_k.dtype, nb, el.size, dev)
-    w = _workspace(wbytes, dev, work)
-    if out is None:
-        out = torch.empty((el.size, nb), dtype=torch.float64, device=delta_k.device)
-    sh = torch.empty((el.size, nb), dtype=torch.float64, device=delta_k.device) if shot else None
-    _check(_lib.hermes_xi(context(dev), _ptr(delta_k), n, dt, float(box_L), e.ctypes.data_as(ctypes.c_void_p), nb,
-                          el.ctypes.data_as(ctypes.c_void_p), el.size, los_axis, _ptr(out),
-                          _ptr(sh) if shot else None, _ptr(w), wbytes, _stream(dev, stream)))
+    with _on(stream):
+        w = _workspace(wbytes, dev, work)
+        if out is None:
+            out = torch.empty((el.size, nb), dtype=torch.float64, device=delta_k.device)
+        sh = torch.empty((el.size, nb), dtype=torch.float64, device=delta_k.device) if shot else None
+        _check(_lib.hermes_xi(context(dev), _ptr(delta_k), n, dt, float(box_L), e.ctypes.data_as(ctypes.c_void_p),
+                              nb, el.ctypes.data_as(ctypes.c_void_p), el.size, los_axis, _ptr(out),
+                              _ptr(sh) if shot else None, _ptr(w), wbytes, _stream(dev, stream)))
     return (out, sh) if shot else out
 
 
@@ -215,13 +226,14 @@ def filter_bins(delta_k: torch.Tensor, box_L: float, windows, store_fields: bool
     nw = len(win)
     rdt = torch.float32 if delta_k.dtype == torch.complex64 else torch.float64
     wbytes = workspace_size(OP_FILTER, n, rdt, nw, 1, dev)
-    w = _workspace(wbytes, dev, work)
-    if store_fields and out is None:
-        out = torch.empty((nw, n, n, n), dtype=rdt, device=delta_k.device)
-    mom = torch.empty((nw, 3), dtype=torch.float64, device=delta_k.device) if moments else None
-    _check(_lib.hermes_filter_bins(context(dev), _ptr(delta_k), n, _dtype_code(rdt), float(box_L), win, nw,
-                                   _ptr(out) if store_fields else None, _ptr(mom), _ptr(w), wbytes,
-                                   _stream(dev, stream)))
+    with _on(stream):
+        w = _workspace(wbytes, dev, work)
+        if store_fields and out is None:
+            out = torch.empty((nw, n, n, n), dtype=rdt, device=delta_k.device)
+        mom = torch.empty((nw, 3), dtype=torch.float64, device=delta_k.device) if moments else None
+        _check(_lib.hermes_filter_bins(context(dev), _ptr(delta_k), n, _dtype_code(rdt), float(box_L), win, nw,
+                                       _ptr(out) if store_fields else None, _ptr(mom), _ptr(w), wbytes,
+                                       _stream(dev, stream)))
     return (out if store_fields else None), mom
 
 
@@ -234,12 +246,13 @@ def zeta_l(delta: torch.Tensor, delta_k: torch.Tensor, box_L: float, edges, l_ma
     e = _edges_arr(edges)
     nb = e.size - 1
     wbytes = workspace_size(OP_ZETA, n, torch.float32, nb, 1, dev)
-    w = _workspace(wbytes, dev, work)
-    if out is None:
-        out = torch.empty((l_max + 1, nb, nb), dtype=torch.float64, device=delta.device)
-    _check(_lib.hermes_zeta_l(context(dev), _ptr(delta), _ptr(delta_k), n, float(box_L),
-                              e.ctypes.data_as(ctypes.c_void_p), nb, l_max, PREC[precision], _ptr(out), _ptr(w),
-                              wbytes, _stream(dev, stream)))
+    with _on(stream):
+        w = _workspace(wbytes, dev, work)
+        if out is None:
+            out = torch.empty((l_max + 1, nb, nb), dtype=torch.float64, device=delta.device)
+        _check(_lib.hermes_zeta_l(context(dev), _ptr(delta), _ptr(delta_k), n, float(box_L),
+                                  e.ctypes.data_as(ctypes.c_void_p), nb, l_max, PREC[precision], _ptr(out), _ptr(w),
+                                  wbytes, _stream(dev, stream)))
     return out
 
 

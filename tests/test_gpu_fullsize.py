@@ -5,7 +5,9 @@ by one and through closed forms that hold at any size.
 Tolerances as in test_gpu_parity: normwise per statistic, float32 <= 1e-5,
 mixed (bf16/fp16 hi+lo contraction) <= 1e-3.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -17,7 +19,14 @@ from paper_2607_23494_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-ZETA_TOL = {"fp32": 1e-5, "bf16x3": 1e-3}
+ZETA_TOL = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16x3": 1e-3}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    """Oracle spot values written by tests/golden/make_fullsize_spots.py."""
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
 
 
 def normwise(got, ref):
@@ -135,7 +144,7 @@ def three_wave_zeta(waves, n, L, edges, ell):
     return out * (-1) ** ell * (2 * ell + 1) / 8.0
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
 def test_ns512_zeta_three_wave_closed_form(hermes, precision):
     n, L = 512, 1000.0
     edges = synth.EDGES["ns512_3pcf"]
@@ -150,46 +159,42 @@ def test_ns512_zeta_three_wave_closed_form(hermes, precision):
 
 
 # --------------------------------------------------------------------------
-# 512^3 marked catalogue: oracle spot checks
+# 512^3 marked catalogue: oracle spot checks (values from the oracle, stored)
 # --------------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
 def ns512(hermes):
     wl = synth.WORKLOADS["ns512_3pcf"]
     pos, w = wl.catalogue()
-    eps, sw = O.assign(pos, w, wl.box_L, wl.n_grid)
-    od = O.contrast(eps, sw)
-    del eps
-    odh = O.dft3(od)
+    ref = golden("ns512_spots.json")
     eg, swg = hermes.assign(torch.from_numpy(pos).cuda(), torch.from_numpy(w).cuda(), wl.box_L, wl.n_grid)
     dk, delta = hermes.fft(eg, swg)
     del eg
-    edges = synth.EDGES["ns512_3pcf"]
+    edges = np.asarray(ref["zeta_edges"])
     zeta = {p: hermes.zeta_l(delta, dk, wl.box_L, edges, 10, precision=p).cpu().numpy() for p in ZETA_TOL}
-    xi = hermes.xi(dk, wl.box_L, synth.EDGES["ns512_2pcf"]).cpu().numpy()
+    xi = hermes.xi(dk, wl.box_L, np.asarray(ref["xi_edges"])).cpu().numpy()
     del dk, delta
     torch.cuda.empty_cache()
-    return wl, od, odh, zeta, xi
+    return ref, zeta, xi
 
 
 def test_ns512_2pcf_spot_bins(ns512):
-    wl, od, odh, zeta, xi = ns512
-    e = synth.EDGES["ns512_2pcf"]
-    bins = [0, 13, 26, 39]
-    ref = np.array([O.xi_multipoles(odh, wl.box_L, [e[b], e[b + 1]])[0, 0] for b in bins])
-    got = xi[0, bins]
-    assert np.max(np.abs(got - ref)) < 1e-5 * np.max(np.abs(xi))
+    ref, zeta, xi = ns512
+    want = np.asarray(ref["xi"])
+    got = xi[0, ref["xi_bins"]]
+    assert np.max(np.abs(got - want)) < 1e-5 * np.max(np.abs(want))
 
 
-@pytest.mark.parametrize("ell,bins", [(0, [0, 9, 19]), (1, [19]), (2, [5])])
-def test_ns512_zeta_spot(ns512, ell, bins):
-    wl, od, odh, zeta, xi = ns512
-    edges = synth.EDGES["ns512_3pcf"]
-    ref = O.zeta_multipoles(od, odh, wl.box_L, edges, ells=(ell,), bins=bins)[0]
-    for p, tol in ZETA_TOL.items():
-        got = zeta[p][ell][np.ix_(bins, bins)]
-        scale = np.max(np.abs(zeta["fp32"][ell]))
-        assert np.max(np.abs(got - ref)) < tol * scale, (p, ell)
+@pytest.mark.parametrize("precision", list(ZETA_TOL))
+@pytest.mark.parametrize("ell", [0, 1, 2, 5, 10])
+def test_ns512_zeta_spot(ns512, ell, precision):
+    """zeta_l on bins {0, 9, 19} x {0, 9, 19} of the benchmark's 20 bins,
+    normwise over the 3 x 3 spot matrix of each l."""
+    ref, zeta, xi = ns512
+    bins = ref["zeta_bins"]
+    want = np.asarray(ref["zeta"][str(ell)])
+    got = zeta[precision][ell][np.ix_(bins, bins)]
+    assert normwise(got, want) < ZETA_TOL[precision], (precision, ell)
 
 
 # --------------------------------------------------------------------------
@@ -219,3 +224,72 @@ def test_ns1024_plane_wave_cic_and_xi(hermes):
     got = hermes.xi(dk, L, edges).cpu().numpy()[0]
     want = A * A / 2 * ph * O.w_shell(np.full(edges.size - 1, k0), edges[:-1], edges[1:])
     assert normwise(got, want) < 1e-5
+
+
+# --------------------------------------------------------------------------
+# 1024^3: the 10^8-point marked catalogue
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def ns1024_catalogue():
+    wl = synth.WORKLOADS["ns1024_cic"]
+    pos, w = wl.catalogue()
+    return wl, pos, w
+
+
+def test_ns1024_assign_mass_conservation(hermes, ns1024_catalogue):
+    """All 10^8 marked points onto 1024^3: the grid sums to sum_w (partition
+    of unity), summed in float64 on the host over the float32 cells."""
+    wl, pos, w = ns1024_catalogue
+    tp, tw = torch.from_numpy(pos).cuda(), torch.from_numpy(w).cuda()
+    eps, sw = hermes.assign(tp, tw, wl.box_L, wl.n_grid)
+    del tp, tw
+    want = float(np.sum(w, dtype=np.float64))
+    assert abs(sw.item() - want) < 1e-12 * want
+    host = eps.cpu().numpy()
+    del eps
+    torch.cuda.empty_cache()
+    tot = float(np.sum(host, dtype=np.float64))
+    assert abs(tot - want) < 1e-6 * want
+    assert float(host.min()) >= 0.0
+
+
+def test_ns1024_assign_subset_elementwise(hermes, ns1024_catalogue):
+    """Elementwise against the oracle on the first 10^6 points at 1024^3
+    (assignment is linear, so this covers the 1024 kernel's indexing)."""
+    wl, pos, w = ns1024_catalogue
+    sub, ws = pos[:1_000_000], w[:1_000_000]
+    eps, _ = hermes.assign(torch.from_numpy(sub).cuda(), torch.from_numpy(ws).cuda(), wl.box_L, wl.n_grid)
+    got = eps.cpu().numpy()
+    del eps
+    torch.cuda.empty_cache()
+    ref, _ = O.assign(sub, ws, wl.box_L, wl.n_grid)
+    assert normwise(got, ref) < 1e-5
+
+
+def test_ns1024_subset_marked_2pcf_and_cic(hermes, ns1024_catalogue):
+    """End to end at 1024^3 on the first 10^6 points: the 40-bin marked 2PCF
+    of the mark-weighted field and the counts-in-cells moments of the number
+    field for all 16 windows, against the oracle's spot bins and windows."""
+    wl, pos, w = ns1024_catalogue
+    ref = golden("ns1024_subset_spots.json")
+    sub = torch.from_numpy(pos[:ref["n_points"]]).cuda()
+    ws = torch.from_numpy(w[:ref["n_points"]]).cuda()
+    eps, sw = hermes.assign(sub, ws, wl.box_L, wl.n_grid)
+    dk, _ = hermes.fft(eps, sw, want_delta=False)
+    xi = hermes.xi(dk, wl.box_L, np.asarray(ref["xi_edges"])).cpu().numpy()[0]
+    want = np.asarray(ref["xi_marked"])
+    assert np.max(np.abs(xi[ref["xi_bins"]] - want)) < 1e-5 * np.max(np.abs(want))
+    eps, sw = hermes.assign(sub, None, wl.box_L, wl.n_grid, eps=eps, sum_w=sw)
+    dk, _ = hermes.fft(eps, sw, want_delta=False, delta_k=dk)
+    del eps
+    radii = synth.CIC_RADII
+    wins = [("sphere", 0.0, R) for R in radii] + [("gauss", 0.0, R) for R in radii]
+    _, mom = hermes.filter_bins(dk, wl.box_L, wins, store_fields=False, moments=True)
+    mom = mom.cpu().numpy()
+    del dk
+    torch.cuda.empty_cache()
+    for (kind, R), m in zip(ref["cic_windows"], ref["cic_moments"]):
+        i = [j for j, x in enumerate(wins) if x[0] == kind and abs(x[2] - R) < 1e-9][0]
+        for p in range(3):
+            assert abs(mom[i, p] - m[p]) < 1e-5 * abs(m[p]) + 1e-5 * abs(m[0]) ** ((p + 2) / 2), (kind, R, p)

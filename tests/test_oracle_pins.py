@@ -187,6 +187,41 @@ def test_jbar_closed_forms():
     assert np.max(np.abs(O.jbar(7, k, 30 - 1e-5, 30 + 1e-5) - spherical_jn(7, 30 * k))) < 1e-9
 
 
+def _radial_inverse_transform(w_hat, r, kmax):
+    """Real-space kernel of a radial k-space window by numerical Hankel
+    transform: W(r) = (2 pi^2)^-1 int_0^inf k^2 W^(k) sin(kr)/(kr) dk."""
+    def f(k):
+        kr = k * r
+        sinc = 1.0 if kr == 0.0 else math.sin(kr) / kr
+        return k * k * w_hat(k) * sinc
+    val, _ = quad(f, 0.0, kmax, epsabs=1e-16, epsrel=1e-12, limit=400)
+    return val / (2.0 * math.pi ** 2)
+
+
+def test_gauss_window_real_space_kernel():
+    """The Gaussian window of Table A1 (c): its real-space kernel is the
+    normalised 3-D Gaussian of standard deviation R per axis, so it has unit
+    integral and second moment int r^2 W d^3x = 3 R^2.  The oracle's k-space
+    form is transformed back numerically; exp(-k^2 R^2) (6 R^2) or
+    exp(-k^2 R^2 / 8) (3 R^2 / 4) would fail."""
+    R = 6.0
+    kmax = 14.0 / R                      # W^(kmax) = exp(-98)
+
+    def w_hat(k):
+        return float(O.w_gauss(np.array([k]), R)[0])
+
+    def w_real(r):
+        return _radial_inverse_transform(w_hat, r, kmax)
+
+    for r in [0.0, 0.5 * R, R, 2.0 * R, 3.0 * R]:
+        want = (2.0 * math.pi) ** -1.5 / R ** 3 * math.exp(-r * r / (2.0 * R * R))
+        assert abs(w_real(r) - want) < 1e-10 * want, r
+    norm, _ = quad(lambda r: 4.0 * math.pi * r * r * w_real(r), 0.0, 12.0 * R, limit=200)
+    m2, _ = quad(lambda r: 4.0 * math.pi * r ** 4 * w_real(r), 0.0, 12.0 * R, limit=200)
+    assert abs(norm - 1.0) < 1e-9
+    assert abs(m2 - 3.0 * R * R) < 1e-8 * R * R
+
+
 def test_real_sh_addition_theorem_and_orthonormality():
     rng = np.random.default_rng(2)
     a = rng.standard_normal((50, 3))
@@ -508,3 +543,111 @@ def test_multipole_fields_are_real_with_nyquist_average():
     for ell, m in [(1, -1), (1, 1), (3, 2), (5, -4)]:
         a, im = O.multipole_field(dh, L, ell, m, 5.0, 11.0)
         assert im < 1e-14 * max(1.0, np.max(np.abs(a)))
+
+
+# --------------------------------------------------------------------------
+# readout at arbitrary positions and density-derived marks
+# --------------------------------------------------------------------------
+
+def _interior_points(n, L, count, seed):
+    """Points whose 4-node stencils do not wrap (u in [2, N - 3))."""
+    rng = np.random.default_rng(seed)
+    return (rng.uniform(2.0, n - 3.0, (count, 3)) * (L / n)).astype(np.float32)
+
+
+def test_readout_reproduces_polynomials():
+    """B3 reproduces polynomials up to degree 3 through its moments
+    (int B3 = 1, int t^2 B3 = 1/3, odd moments 0): the expansion of the node
+    values l_a, l_a^2, l_a^3 is u, u^2 + 1/3, u^3 + u at every point."""
+    n, L = 16, 40.0
+    pos = _interior_points(n, L, 500, 71)
+    u = pos.astype(np.float64) / (L / n)
+    idx = np.arange(n, dtype=np.float64)
+    lx, ly, lz = np.meshgrid(idx, idx, idx, indexing="ij")
+    assert np.max(np.abs(O.readout(np.full((n, n, n), 2.5), pos, L) - 2.5)) < 1e-13
+    assert np.max(np.abs(O.readout(lx, pos, L) - u[:, 0])) < 1e-12
+    assert np.max(np.abs(O.readout(ly ** 2, pos, L) - (u[:, 1] ** 2 + 1.0 / 3.0))) < 1e-11
+    assert np.max(np.abs(O.readout(lz ** 3, pos, L) - (u[:, 2] ** 3 + u[:, 2]))) < 1e-10
+
+
+def test_readout_on_nodes():
+    """At a node the four B3 values are 1/6, 2/3, 1/6, 0: the readout is the
+    (1, 4, 1)/6 smoothing of the field in each axis (periodic)."""
+    n, L = 8, 16.0
+    f = np.random.default_rng(72).standard_normal((n, n, n))
+    nodes = np.array([[0, 0, 0], [3, 7, 1], [7, 7, 7], [2, 5, 4]])
+    pos = (nodes * (L / n)).astype(np.float32)
+    c = {-1: 1.0 / 6.0, 0: 4.0 / 6.0, 1: 1.0 / 6.0}
+    got = O.readout(f, pos, L)
+    for i, (a, b, d) in enumerate(nodes):
+        want = sum(c[dx] * c[dy] * c[dz] * f[(a + dx) % n, (b + dy) % n, (d + dz) % n]
+                   for dx in c for dy in c for dz in c)
+        assert abs(got[i] - want) < 1e-14
+
+
+def test_readout_is_transpose_of_assignment():
+    """sum_i w_i v_i(f) = sum_l f_l eps_l for any field f: the readout is the
+    adjoint of the (separately pinned) assignment, wrapping included."""
+    n, L = 16, 50.0
+    rng = np.random.default_rng(73)
+    pos = rng.uniform(-L, 2 * L, (700, 3)).astype(np.float32)
+    w = rng.uniform(0.5, 2.0, 700)
+    f = rng.standard_normal((n, n, n))
+    eps, _ = O.assign(pos, w, L, n)
+    lhs = float(np.sum(w * O.readout(f, pos, L)))
+    rhs = float(np.sum(f * eps))
+    assert abs(lhs - rhs) < 1e-11 * abs(rhs)
+
+
+def test_readout_plane_wave_fourier_series():
+    """f_l = cos(2 pi n0.l / N): by Poisson summation each axis contributes
+    g(u) = sum_m B3^(theta + 2 pi m) exp(i (theta + 2 pi m) u) with
+    B3^(w) = (sin(w/2) / (w/2))^4, theta = 2 pi n0_a / N, and the readout is
+    Re prod_a g_a(u_a)."""
+    n, L = 16, 32.0
+    n0 = np.array([3, -5, 8])
+    f = synth.cosine_field(n, [n0])
+    pos = np.random.default_rng(74).uniform(0, L, (200, 3)).astype(np.float32)
+    u = pos.astype(np.float64) / (L / n)
+    m = np.arange(-3000, 3001, dtype=np.float64)
+    prod = np.ones(pos.shape[0], dtype=np.complex128)
+    for a in range(3):
+        om = 2 * np.pi * n0[a] / n + 2 * np.pi * m
+        half = om / 2
+        bh = np.where(half == 0, 1.0, np.sin(half) / np.where(half == 0, 1.0, half)) ** 4
+        prod *= np.sum(bh[None, :] * np.exp(1j * om[None, :] * u[:, a:a + 1]), axis=1)
+    assert np.max(np.abs(O.readout(f, pos, L) - prod.real)) < 1e-10
+
+
+def test_marks_reduce_to_unmarked_and_kinds_agree():
+    """Sec. 3.3.1: alpha = 0 (power law) or p = 0 (inverse density) gives the
+    ordinary 2PCF; a power law with exponent -p is the inverse-density mark
+    with rho_* = epsilon up to the constant (rho_* + 1)^p, and a constant mark
+    factor cancels in the 2PCF."""
+    n, L = 32, 120.0
+    pos = synth.neyman_scott(60, 25, 2.0, L, seed=75)
+    edges = np.linspace(4.0, 40.0, 7)
+    xm, xi, M = O.marked_xi(pos, None, L, n, edges, 8.0, "power_law", 0.0, 0.1)
+    assert np.max(np.abs(xm - xi)) < 1e-12 * np.max(np.abs(xi))
+    assert np.max(np.abs(M - 1.0)) < 1e-12
+    xm0, _, _ = O.marked_xi(pos, None, L, n, edges, 8.0, "inverse_density", 0.0, 1.0)
+    assert np.max(np.abs(xm0 - xi)) < 1e-12 * np.max(np.abs(xi))
+    a, _, _ = O.marked_xi(pos, None, L, n, edges, 8.0, "power_law", -1.0, 0.5, self_term=0.05)
+    b, _, _ = O.marked_xi(pos, None, L, n, edges, 8.0, "inverse_density", 1.0, 0.5, self_term=0.05)
+    assert np.max(np.abs(a - b)) < 1e-10 * np.max(np.abs(a))
+    c, _, _ = O.marked_xi(pos, np.full(pos.shape[0], 3.0, np.float32), L, n, edges, 8.0, "power_law", -1.0, 0.5,
+                          self_term=0.05)
+    assert np.max(np.abs(a - c)) < 1e-10 * np.max(np.abs(a))
+
+
+def test_density_marks_follow_the_environment():
+    """Physics sanity on a clustered catalogue: marks that grow with the local
+    density (alpha > 0) raise the small-scale correlation (M > 1), marks that
+    fall with it (alpha < 0, inverse density p > 0) lower it (M < 1)."""
+    n, L = 32, 120.0
+    pos = synth.neyman_scott(60, 25, 2.0, L, seed=76)
+    edges = np.linspace(3.0, 15.0, 4)
+    _, _, m_up = O.marked_xi(pos, None, L, n, edges, 8.0, "power_law", 0.3, 0.1)
+    _, _, m_dn = O.marked_xi(pos, None, L, n, edges, 8.0, "power_law", -0.3, 0.1)
+    _, _, m_id = O.marked_xi(pos, None, L, n, edges, 8.0, "inverse_density", 1.0, 1.0)
+    assert m_up[0] > 1.0 and m_dn[0] < 1.0 and m_id[0] < 1.0
