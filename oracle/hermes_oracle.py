@@ -7,8 +7,8 @@ benchmark, and by nothing else.  It shares no code with the HIP path.
 Everything here is written for obviousness, not speed: float64 throughout,
 full complex spectra (no Hermitian shortcut), explicit loops over l, m and
 bins.  Library primitives used as single steps: scipy.fft (a DFT), numpy's
-bincount (a histogram), scipy.special (spherical Bessel, Legendre, spherical
-harmonics) and numpy's Gauss-Legendre nodes.
+bincount (a histogram), scipy.special (spherical Bessel, cylindrical Bessel
+J0 and J1, Legendre, spherical harmonics) and numpy's Gauss-Legendre nodes.
 
 Conventions (the paper's notation; section / equation named per function):
   grid node l = (lx, ly, lz), l_a in {0..N-1}, sits at position l*h, h = L/N;
@@ -23,7 +23,7 @@ import os
 
 import numpy as np
 import scipy.fft as sfft
-from scipy.special import eval_legendre, spherical_jn, sph_harm_y
+from scipy.special import eval_legendre, j0, j1, spherical_jn, sph_harm_y
 
 _WORKERS = max(1, os.cpu_count() or 1)
 _GL_POINTS = 64
@@ -476,3 +476,99 @@ def marked_xi(pos, weight, box_L, n, edges, R, kind, exponent, offset, self_term
     eps_m, sw_m = assign(pos, w, box_L, n)
     xi_m = xi_multipoles(dft3(contrast(eps_m, sw_m)), box_L, edges)[0]
     return xi_m, xi, (1.0 + xi_m) / (1.0 + xi)
+
+
+# ----------------------------------------------------------------------------
+# Axisymmetric windows and the anisotropic 2PCF (Sec. 2.2.3, redshift space:
+# circular ring; Table A1 (d)-(i)).  k_par is the line-of-sight component of
+# k, k_perp = |k - k_par e_los|.
+# ----------------------------------------------------------------------------
+
+ANISO_KINDS = ("ring", "ring_bin", "gauss_ring", "disk", "cylinder", "cylshell", "gauss_shell")
+
+
+def ring_bin_j0(kperp, r_perp, d_perp):
+    """<J0(k_perp rho)> over the annulus rho in [r_perp - d/2, r_perp + d/2]
+    with weight rho / (r_perp d) (the finite-width ring of Sec. 2.2.3), by
+    64-point Gauss-Legendre quadrature."""
+    kperp = np.asarray(kperp, dtype=np.float64)
+    x, wq = np.polynomial.legendre.leggauss(_GL_POINTS)
+    a, b = r_perp - 0.5 * d_perp, r_perp + 0.5 * d_perp
+    rho = 0.5 * (b - a) * x + 0.5 * (b + a)
+    wr = 0.5 * (b - a) * wq * rho / (r_perp * d_perp)
+    flat = kperp.reshape(-1)
+    out = np.zeros(flat.shape)
+    for rj, wj in zip(rho, wr):
+        out += wj * j0(flat * rj)
+    return out.reshape(kperp.shape)
+
+
+def _sinc(x):
+    """sin(x) / x with the limit 1 at 0."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.sinc(x / np.pi)
+
+
+def _jinc(x):
+    """2 J1(x) / x with the limit 1 at 0."""
+    x = np.asarray(x, dtype=np.float64)
+    safe = np.where(x == 0.0, 1.0, x)
+    return np.where(x == 0.0, 1.0, 2.0 * j1(safe) / safe)
+
+
+def w_aniso(kind, kpar, kperp, r_perp, r_par, d_perp=0.0, d_par=0.0):
+    """Fourier-space axisymmetric window (Table A1 and Sec. 2.2.3):
+
+      ring        cos(k_par H) J0(k_perp R)                          (i)
+      ring_bin    sinc(k_par dH/2) cos(k_par H) <J0(k_perp rho)>_dR   (finite bins)
+      gauss_ring  cos(k_par H) J0(k_perp R) exp(-k_perp^2 s^2 / 2)    (s = d_perp)
+      disk        2 J1(k_perp R)/(k_perp R) cos(k_par H)              (h)
+      cylinder    2 J1(k_perp R)/(k_perp R) sin(k_par H)/(k_par H)    (f)
+      cylshell    J0(k_perp R) sin(k_par H)/(k_par H)                 (g)
+      gauss_shell (Rg^2 cos(k Rs) + Rs^2 sin(k Rs)/(k Rs)) / (Rs^2 + Rg^2)
+                  exp(-k^2 Rg^2 / 2), k^2 = k_par^2 + k_perp^2,       (d)
+                  Rs = r_perp, Rg = d_perp
+    with R = r_perp, H = r_par.
+    """
+    kpar = np.asarray(kpar, dtype=np.float64)
+    kperp = np.asarray(kperp, dtype=np.float64)
+    if kind == "ring":
+        return np.cos(kpar * r_par) * j0(kperp * r_perp)
+    if kind == "ring_bin":
+        return _sinc(0.5 * kpar * d_par) * np.cos(kpar * r_par) * ring_bin_j0(kperp, r_perp, d_perp)
+    if kind == "gauss_ring":
+        return np.cos(kpar * r_par) * j0(kperp * r_perp) * np.exp(-0.5 * (kperp * d_perp) ** 2)
+    if kind == "disk":
+        return _jinc(kperp * r_perp) * np.cos(kpar * r_par)
+    if kind == "cylinder":
+        return _jinc(kperp * r_perp) * _sinc(kpar * r_par)
+    if kind == "cylshell":
+        return j0(kperp * r_perp) * _sinc(kpar * r_par)
+    if kind == "gauss_shell":
+        k = np.sqrt(kpar * kpar + kperp * kperp)
+        rs, rg = r_perp, d_perp
+        return ((rg * rg * np.cos(k * rs) + rs * rs * _sinc(k * rs)) / (rs * rs + rg * rg)
+                * np.exp(-0.5 * (k * rg) ** 2))
+    raise ValueError(kind)
+
+
+def xi_aniso(delta_hat, box_L, windows, los_axis=2):
+    """xi_W = N^-6 sum_n |delta^_n|^2 Phi^(n) W^(k_par, k_perp) for every
+    window (Sec. 2.2.3 Eq. for xi(r_par, r_perp) as the field-window product;
+    Sec. 3.3.1 Parseval form).  Full spectrum, every mode.
+    ``windows``: tuples (kind, r_perp, r_par[, d_perp[, d_par]]).
+    Returns float64 [len(windows)]."""
+    n = delta_hat.shape[0]
+    nc = float(n) ** 3
+    p = (np.abs(delta_hat) ** 2) * phi_hat(n)
+    k = mode_vectors(n, box_L)
+    kpar = k[los_axis]
+    others = [k[a] for a in range(3) if a != los_axis]
+    kperp = np.sqrt(others[0] ** 2 + others[1] ** 2)
+    out = np.zeros(len(windows))
+    for i, w in enumerate(windows):
+        kind, rp, rl = w[0], float(w[1]), float(w[2])
+        dp = float(w[3]) if len(w) > 3 else 0.0
+        dl = float(w[4]) if len(w) > 4 else 0.0
+        out[i] = np.sum(p * w_aniso(kind, kpar, kperp, rp, rl, dp, dl)) / nc ** 2
+    return out

@@ -651,3 +651,129 @@ def test_density_marks_follow_the_environment():
     _, _, m_dn = O.marked_xi(pos, None, L, n, edges, 8.0, "power_law", -0.3, 0.1)
     _, _, m_id = O.marked_xi(pos, None, L, n, edges, 8.0, "inverse_density", 1.0, 1.0)
     assert m_up[0] > 1.0 and m_dn[0] < 1.0 and m_id[0] < 1.0
+
+
+# --------------------------------------------------------------------------
+# axisymmetric windows and the anisotropic 2PCF
+# --------------------------------------------------------------------------
+
+def _locus_average(kpar, kperp, rho_pts, rho_w, z_pts, z_w, nphi=256):
+    """Average of exp(i k.x) over points at cylindrical radius rho, height z
+    and azimuth phi (uniform), with the given rho and z weights; k lies in the
+    (x, z) plane.  The phi average is a periodic trapezoid rule."""
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    acc = 0.0
+    for rho, wr in zip(rho_pts, rho_w):
+        ring = np.mean(np.exp(1j * kperp * rho * np.cos(phi)))
+        for z, wz in zip(z_pts, z_w):
+            acc += wr * wz * ring * np.exp(1j * kpar * z)
+    return acc
+
+
+def test_axisymmetric_windows_are_locus_averages():
+    """Each window of Table A1 (f)-(i) and the finite-width ring of Sec. 2.2.3
+    equals the average of exp(i k.x) over its real-space locus (ring at
+    z = +-H, disk, cylinder volume, cylinder side wall, annulus x slab),
+    computed by direct quadrature in real space."""
+    R, H, dR, dH = 7.0, 4.0, 2.0, 3.0
+    gx, gw = np.polynomial.legendre.leggauss(48)
+    for kpar, kperp in [(0.13, 0.41), (0.9, 0.05), (0.0, 1.7), (0.6, 0.0), (1.1, 1.3)]:
+        pm = ([H, -H], [0.5, 0.5])
+        ring = _locus_average(kpar, kperp, [R], [1.0], *pm)
+        # disk: area weight rho / (R^2 / 2) on [0, R]
+        rho = 0.5 * R * (gx + 1)
+        disk = _locus_average(kpar, kperp, rho, 0.5 * R * gw * rho / (R * R / 2), *pm)
+        z = H * gx
+        cyl = _locus_average(kpar, kperp, rho, 0.5 * R * gw * rho / (R * R / 2), z, 0.5 * gw)
+        shell = _locus_average(kpar, kperp, [R], [1.0], z, 0.5 * gw)
+        ra = R - dR / 2 + 0.5 * dR * (gx + 1)
+        zz = np.concatenate([H - dH / 2 + 0.5 * dH * (gx + 1), -(H - dH / 2 + 0.5 * dH * (gx + 1))])
+        rbin = _locus_average(kpar, kperp, ra, 0.5 * dR * gw * ra / (R * dR), zz, np.concatenate([gw, gw]) / 4)
+        for kind, want in [("ring", ring), ("disk", disk), ("cylinder", cyl), ("cylshell", shell),
+                           ("ring_bin", rbin)]:
+            got = float(O.w_aniso(kind, kpar, kperp, R, H, dR, dH))
+            assert abs(want.imag) < 1e-12 and abs(got - want.real) < 1e-10, (kind, kpar, kperp)
+
+
+def test_gaussian_ring_transverse_form():
+    """The Gaussian ring's transverse real-space profile given in Sec. 2.2.3,
+    (2 pi s^2)^-1 exp(-(rho^2 + R^2) / (2 s^2)) I0(rho R / s^2), has the 2-D
+    transform J0(k R) exp(-k^2 s^2 / 2) that the window uses."""
+    from scipy.special import i0e
+    R, s = 9.0, 1.5
+
+    def prof(rho):
+        # I0(x) exp(-(rho^2 + R^2)/(2 s^2)) = i0e(x) exp(x - (rho^2 + R^2)/(2 s^2))
+        x = rho * R / s ** 2
+        return i0e(x) * math.exp(x - (rho * rho + R * R) / (2 * s * s)) / (2 * math.pi * s * s)
+    norm, _ = quad(lambda rho: 2 * math.pi * rho * prof(rho), 0, R + 12 * s, points=[R], limit=400)
+    assert abs(norm - 1.0) < 1e-10
+    for kperp in [0.02, 0.3, 0.8, 1.9]:
+        num, _ = quad(lambda rho: 2 * math.pi * rho * prof(rho) * float(O.j0(kperp * rho)), 0, R + 12 * s,
+                      points=[R], limit=400, epsabs=1e-14)
+        want = float(O.w_aniso("gauss_ring", 0.0, kperp, R, 0.0, s))
+        assert abs(num - want) < 1e-10, kperp
+
+
+def test_gaussian_shell_is_a_radial_gaussian_shell():
+    """Table A1 (d) is the 3-D transform of the normalised radial Gaussian
+    shell exp(-(r - Rs)^2 / (2 Rg^2)) (with its mirror image at -Rs): the
+    transform int 4 pi r^2 f(r) sin(kr)/(kr) dr is taken numerically."""
+    Rs, Rg = 12.0, 2.5
+
+    def f(r):
+        return math.exp(-(r - Rs) ** 2 / (2 * Rg * Rg)) + math.exp(-(r + Rs) ** 2 / (2 * Rg * Rg))
+    norm, _ = quad(lambda r: 4 * math.pi * r * r * f(r), 0, Rs + 15 * Rg, limit=400)
+    for k in [1e-3, 0.1, 0.45, 1.2]:
+        num, _ = quad(lambda r: 4 * math.pi * r * r * f(r) * math.sin(k * r) / (k * r), 0, Rs + 15 * Rg, limit=400,
+                      epsabs=1e-14)
+        got = float(O.w_aniso("gauss_shell", 0.6 * k, 0.8 * k, Rs, 0.0, Rg))
+        assert abs(num / norm - got) < 1e-10, k
+
+
+def test_rings_average_to_the_thin_shell():
+    """Averaging thin double rings at r_perp = s sqrt(1 - mu^2), r_par = s mu
+    over mu in [0, 1] gives the isotropic thin shell sin(ks)/(ks)
+    (Table A1 (a)) for every direction of k."""
+    s = 15.0
+    mu, wmu = np.polynomial.legendre.leggauss(96)
+    mu, wmu = 0.5 * (mu + 1), 0.5 * wmu
+    for k, th in [(0.05, 0.3), (0.4, 1.1), (1.3, 2.5), (0.8, 0.0)]:
+        kpar, kperp = k * math.cos(th), k * math.sin(th)
+        avg = sum(w * float(O.w_aniso("ring", kpar, kperp, s * math.sqrt(1 - m * m), s * m)) for m, w in zip(mu, wmu))
+        assert abs(avg - math.sin(k * s) / (k * s)) < 1e-9, (k, th)
+
+
+def test_xi_aniso_pair_sum_plane_wave_and_axes():
+    """xi_W by Parseval equals the real-space pair sum with the window's
+    kernel K(D) = N^-3 sum_n Phi^ W^ exp(2 pi i n.D / N) (N = 8); a plane wave
+    gives (A^2/2) Phi^(n0) W^(k_par0, k_perp0); swapping the line of sight
+    with the field's axes leaves it unchanged."""
+    n, L = 8, 40.0
+    f = np.random.default_rng(81).standard_normal((n, n, n))
+    dh = O.dft3(f)
+    wins = [("ring", 6.0, 5.0), ("cylinder", 4.0, 3.0), ("ring_bin", 7.0, 2.0, 2.0, 3.0)]
+    got = O.xi_aniso(dh, L, wins, los_axis=2)
+    fz = f - f.mean()
+    kx, ky, kz = O.mode_vectors(n, L)
+    kperp = np.sqrt(kx * kx + ky * ky + 0 * kz)
+    for i, w in enumerate(wins):
+        Wk = O.w_aniso(w[0], kz + 0 * kx, kperp + 0 * kz, *[float(x) for x in w[1:]], *([0.0] * (5 - len(w))))
+        K = O.idft3(O.phi_hat(n) * Wk).real
+        want = 0.0
+        for l in itertools.product(range(n), repeat=3):
+            shifted = np.roll(fz, shift=tuple(-np.array(l)), axis=(0, 1, 2))
+            want += K[l] * np.sum(fz * shifted)
+        assert abs(got[i] - want / n ** 3) < 1e-12 * max(1.0, abs(want / n ** 3)), w[0]
+    n, L, A = 32, 100.0, 0.7
+    n0 = np.array([2, -3, 5])
+    dh = O.dft3(synth.cosine_field(n, [n0], [A]))
+    k0 = 2 * np.pi / L * n0
+    ph = np.prod(np.sinc(n0 / n) ** 8)
+    for w in wins:
+        want = A * A / 2 * ph * float(O.w_aniso(w[0], k0[2], math.hypot(k0[0], k0[1]), *[float(x) for x in w[1:]],
+                                                *([0.0] * (5 - len(w)))))
+        assert abs(O.xi_aniso(dh, L, [w], los_axis=2)[0] - want) < 1e-13, w[0]
+    g = O.xi_aniso(dh, L, wins, los_axis=2)
+    dh_t = O.dft3(np.transpose(synth.cosine_field(n, [n0], [A]), (2, 1, 0)))
+    assert np.max(np.abs(O.xi_aniso(dh_t, L, wins, los_axis=0) - g)) < 1e-13
