@@ -293,12 +293,14 @@ def other_configs(warmup: int, steps: int) -> dict:
                         device="cuda")
     xwork = torch.empty(hermes.workspace_size(hermes.OP_XI, n, torch.float32, e.size - 1, 1), dtype=torch.uint8,
                         device="cuda")
+    awork = torch.empty(hermes.workspace_size(hermes.OP_ASSIGN, n, torch.float32, int(pos.shape[0]), 1),
+                        dtype=torch.uint8, device="cuda")
 
     def step1024():
-        hermes.assign(pos, w, L, n, eps=eps, sum_w=sw)
+        hermes.assign(pos, w, L, n, eps=eps, sum_w=sw, work=awork)
         hermes.fft(eps, sw, want_delta=False, delta_k=dk)
         hermes.xi(dk, L, e, work=xwork)
-        hermes.assign(pos, None, L, n, eps=eps, sum_w=sw)
+        hermes.assign(pos, None, L, n, eps=eps, sum_w=sw, work=awork)
         hermes.fft(eps, sw, want_delta=False, delta_k=dk)
         hermes.xi(dk, L, e, work=xwork)
         hermes.filter_bins(dk, L, wins, store_fields=False, moments=True, work=fwork)
@@ -306,7 +308,7 @@ def other_configs(warmup: int, steps: int) -> dict:
            "1e8 marked Neyman-Scott points, 1024^3, float32: assign and FFT of the mark-weighted and number "
            "fields, 40-bin 2PCF of each, counts-in-cells moments (p = 2, 3, 4) of the number field for the "
            "sphere and Gaussian at 8 radii (16 windows)")
-    del pos, w, eps, dk, fwork, xwork
+    del pos, w, eps, dk, fwork, xwork, awork
     torch.cuda.empty_cache()
     return out
 
@@ -376,6 +378,8 @@ def main() -> int:
                           device="cuda")
     z_work = torch.empty(hermes.workspace_size(hermes.OP_ZETA, n, torch.float32, nb_z, 1), dtype=torch.uint8,
                          device="cuda")
+    a_work = torch.empty(hermes.workspace_size(hermes.OP_ASSIGN, n, torch.float32, int(pos_np.shape[0]), 1),
+                         dtype=torch.uint8, device="cuda")
 
     if args.copy_calibration:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -386,7 +390,7 @@ def main() -> int:
 
     def step_at(precision):
         def step():
-            hermes.assign(pos, w, L, n, eps=eps, sum_w=sw)
+            hermes.assign(pos, w, L, n, eps=eps, sum_w=sw, work=a_work)
             hermes.fft(eps, sw, delta_k=dk, delta=delta)
             hermes.xi(dk, L, edges_xi, ells=(0,), out=xi_out, work=xi_work)
             hermes.zeta_l(delta, dk, L, edges_z, L_MAX, precision=precision, out=zeta_out, work=z_work)
@@ -462,7 +466,7 @@ def main() -> int:
             "z_pass_ms_fp32": round(z_fp32, 4), "z_pass_ms_mixed": round(z_mixed, 4),
             "speedup_z_pass": round(z_fp32 / z_mixed, 3),
             "stage_ms": {k: round(v[1] / args.steps, 3) for k, v in sorted(prof32.items())}}
-    del pos, w, eps, delta, dk, z_work, xi_work
+    del pos, w, eps, delta, dk, z_work, xi_work, a_work
     torch.cuda.empty_cache()
     if not args.no_configs:
         result["configs"] = other_configs(1, max(1, min(args.steps, 5)))

@@ -111,25 +111,35 @@ void hermes_destroy(hermes_ctx ctx);
 const char* hermes_last_error(void);
 
 /* Device workspace, in bytes, that `op` needs for an N^3 grid.  n_batch is
- * the number of windows (FILTER) or radial bins (ZETA); n_ells the number of
- * multipoles (XI).  Zero for ASSIGN and FFT, which need none. */
+ * the number of points (ASSIGN), windows (FILTER) or radial bins (ZETA);
+ * n_ells the number of multipoles (XI).  Zero for FFT, which needs none. */
 hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtype,
                                     int n_batch, int n_ells, size_t* bytes);
 
 /* MRA projection of a weighted catalogue (Sec. 3.1, Eq. phi_projection):
  *   eps_l = sum_i w_i prod_a B3(x_{i,a}/h - l_a),  l_a taken mod N,
  * with the centred cubic B-spline B3 as scaling function (64 nodes per
- * point).  Position fractions are formed in float64.
+ * point).  Position fractions are formed in float64.  The taps are summed in
+ * 64-bit fixed point with the power-of-two step 2^-k, k = 61 - ceil(log2
+ * sum_i |w_i|), each tap rounded once to a multiple of it: the grid is the
+ * same bit for bit on every run, and for float64 it carries an absolute error
+ * of at most 2^-(k+1) per tap.
  *   pos    device float32 [n_pts][3], any real values (wrapped into the box)
  *   weight device float32 [n_pts], or NULL for unit weights (Eq. dendis;
- *          marks or physical values as in Eq. weighted_field)
+ *          marks or physical values as in Eq. weighted_field); finite
  *   eps    device [N^3] of dtype; overwritten
- *   sum_w  device double[1]; overwritten with sum_i w_i (float64)
+ *   sum_w  device double[1]; overwritten with sum_i w_i (float64, summed in
+ *          a fixed order)
+ *   work   device workspace of >= hermes_workspace_size(ASSIGN, n_batch =
+ *          n_pts) bytes: the 64-bit grid (8 N^3 bytes), per-tile counts and
+ *          point lists (4 n_pts bytes)
  * n_pts may be 0 (eps is zeroed, sum_w = 0).  ERR_ARG for NULL buffers,
- * n_pts < 0, box_L <= 0 or N not a power of two in [8, 1024]. */
+ * n_pts < 0 or >= 2^32, box_L <= 0 or N not a power of two in [8, 1024];
+ * ERR_OOM if work_bytes is too small. */
 hermes_status hermes_assign(hermes_ctx ctx, const float* pos, const float* weight,
                             int64_t n_pts, double box_L, int n_grid, int dtype,
-                            void* eps, double* sum_w, hipStream_t stream);
+                            void* eps, double* sum_w, void* work, size_t work_bytes,
+                            hipStream_t stream);
 
 /* Density contrast and forward transform (Sec. 4.2; analytic uniform random
  * of Sec. 4.3.1):  delta_l = eps_l / eps_bar - 1, eps_bar = sum_w / N^3,
@@ -199,6 +209,54 @@ hermes_status hermes_zeta_l(hermes_ctx ctx, const float* delta, const void* delt
                             int n_grid, double box_L, const double* edges, int n_bins,
                             int l_max, int precision, double* zeta, void* work,
                             size_t work_bytes, hipStream_t stream);
+
+/* Density-derived marks (Sec. 3.3.1).  With v the value read at a point
+ * (hermes_readout) and rho = max(1 + v - self_term, 0) the local density in
+ * units of the mean (self_term removes a point's own contribution; the clip
+ * keeps the density non-negative):
+ *   POWER_LAW        m = (rho + offset)^exponent           (Eq. power-law-mark,
+ *                                                          offset = epsilon)
+ *   INVERSE_DENSITY  m = ((offset + 1) / (offset + rho))^exponent
+ *                                                          (Eq. inverse-density-mark,
+ *                                                          offset = rho_* / rho_bar) */
+typedef enum hermes_mark_kind {
+    HERMES_MARK_NONE = 0,
+    HERMES_MARK_POWER_LAW = 1,
+    HERMES_MARK_INVERSE_DENSITY = 2
+} hermes_mark_kind;
+
+typedef struct hermes_mark {
+    int32_t kind;
+    int32_t reserved;    /* must be 0 */
+    double exponent;     /* alpha (power law) or p (inverse density) */
+    double offset;       /* epsilon or rho_* / rho_bar; > 0 where rho = 0 would divide by zero */
+    double self_term;    /* subtracted from 1 + v before the clip (contrast units) */
+} hermes_mark;
+
+/* Readout of a coefficient field at arbitrary positions (Sec. 3.1: the
+ * filtered field n_W(x) = sum_l eps~_l phi_l(x) is read at any point, e.g. at
+ * random positions for counts in cells or at the catalogue's points for
+ * density-derived marks):
+ *   v_i = sum_l f_l prod_a B3(x_{i,a}/h - l_a),  l_a mod N  (64 nodes),
+ * the transpose of hermes_assign.  Position fractions are formed in float64.
+ *   field   device [N^3] of dtype (a filtered field from hermes_filter_bins,
+ *           the contrast from hermes_fft, ...)
+ *   pos     device float32 [n_pts][3], any real values (wrapped into the box)
+ *   weight  device float32 [n_pts] or NULL: multiplies each output
+ *   mark    host hermes_mark or NULL (NULL or kind NONE: out_i = w_i v_i)
+ *   out     device [n_pts] of dtype, or NULL: out_i = w_i m(v_i)
+ *   moments device double[3], or NULL: the means over the points of v^2, v^3,
+ *           v^4 (unweighted, unmarked), accumulated in float64 (the order of
+ *           the float64 additions across workgroups is not fixed); zeros for
+ *           n_pts = 0
+ * ERR_ARG for NULL buffers, out and moments both NULL, n_pts < 0, box_L <= 0,
+ * a bad N or dtype, a non-zero reserved field, an unknown mark kind, a
+ * non-finite exponent, offset < 0, or offset = 0 where rho = 0 would divide by
+ * zero (inverse density, or a power law with a negative exponent). */
+hermes_status hermes_readout(hermes_ctx ctx, const void* field, int n_grid, int dtype,
+                             double box_L, const float* pos, const float* weight,
+                             int64_t n_pts, const hermes_mark* mark, void* out,
+                             double* moments, hipStream_t stream);
 
 /* Per-kernel timing for measurement.  While enabled, every kernel launch of
  * this context is bracketed with HIP events recorded on its launch stream;

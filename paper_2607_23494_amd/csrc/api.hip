@@ -180,6 +180,11 @@ hermes_status hermes_create(hermes_ctx* out, int device) {
     DeviceGuard g(device);
     hermes_ctx c = new hermes_ctx_s();
     c->device = device;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+            c->cus = cus;
+    }
     hermes_status st = build_tables(c);
     if (st != HERMES_OK) {
         hermes_destroy(c);
@@ -265,6 +270,9 @@ hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtyp
     if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_workspace_size: bad dtype");
     switch (op) {
         case HERMES_OP_ASSIGN:
+            if (n_batch < 0) return fail(HERMES_ERR_ARG, "hermes_workspace_size: ASSIGN needs n_batch = points >= 0");
+            *bytes = assign_workspace(n_grid, n_batch);
+            return HERMES_OK;
         case HERMES_OP_FFT:
             *bytes = 0;
             return HERMES_OK;
@@ -289,16 +297,18 @@ hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtyp
 }
 
 hermes_status hermes_assign(hermes_ctx ctx, const float* pos, const float* weight, int64_t n_pts,
-                            double box_L, int n_grid, int dtype, void* eps, double* sum_w,
-                            hipStream_t stream) {
-    if (!ctx || !eps || !sum_w || (n_pts > 0 && !pos))
+                            double box_L, int n_grid, int dtype, void* eps, double* sum_w, void* work,
+                            size_t work_bytes, hipStream_t stream) {
+    if (!ctx || !eps || !sum_w || !work || (n_pts > 0 && !pos))
         return fail(HERMES_ERR_ARG, "hermes_assign: NULL argument");
     if (n_pts < 0) return fail(HERMES_ERR_ARG, "hermes_assign: n_pts < 0");
+    if (n_pts > int64_t(UINT32_MAX)) return fail(HERMES_ERR_ARG, "hermes_assign: more than 2^32 - 1 points");
     if (!(box_L > 0.0)) return fail(HERMES_ERR_ARG, "hermes_assign: box_L must be > 0");
     if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_assign: N must be a power of two in [8, 1024]");
     if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_assign: bad dtype");
+    if (work_bytes < assign_workspace(n_grid, n_pts)) return fail(HERMES_ERR_OOM, "hermes_assign: workspace too small");
     DeviceGuard g(ctx->device);
-    return assign_impl(ctx, pos, weight, n_pts, box_L, n_grid, dtype, eps, sum_w, stream);
+    return assign_impl(ctx, pos, weight, n_pts, box_L, n_grid, dtype, eps, sum_w, work, stream);
 }
 
 hermes_status hermes_fft(hermes_ctx ctx, const void* eps, const double* sum_w, int n_grid, int dtype,
@@ -384,6 +394,32 @@ hermes_status hermes_zeta_l(hermes_ctx ctx, const float* delta, const void* delt
     if (work_bytes < zeta_workspace(n_grid, n_bins)) return fail(HERMES_ERR_OOM, "hermes_zeta_l: workspace too small");
     DeviceGuard g(ctx->device);
     return zeta_impl(ctx, delta, delta_k, n_grid, box_L, e, l_max, precision, zeta, work, work_bytes, stream);
+}
+
+hermes_status hermes_readout(hermes_ctx ctx, const void* field, int n_grid, int dtype, double box_L,
+                             const float* pos, const float* weight, int64_t n_pts, const hermes_mark* mark,
+                             void* out, double* moments, hipStream_t stream) {
+    if (!ctx || !field || (n_pts > 0 && !pos)) return fail(HERMES_ERR_ARG, "hermes_readout: NULL argument");
+    if (!out && !moments) return fail(HERMES_ERR_ARG, "hermes_readout: out and moments both NULL");
+    if (n_pts < 0) return fail(HERMES_ERR_ARG, "hermes_readout: n_pts < 0");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_readout: N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_readout: bad dtype");
+    if (!(box_L > 0.0)) return fail(HERMES_ERR_ARG, "hermes_readout: box_L must be > 0");
+    if (mark) {
+        if (mark->reserved != 0) return fail(HERMES_ERR_ARG, "hermes_readout: reserved field must be 0");
+        if (mark->kind != HERMES_MARK_NONE && mark->kind != HERMES_MARK_POWER_LAW &&
+            mark->kind != HERMES_MARK_INVERSE_DENSITY)
+            return fail(HERMES_ERR_ARG, "hermes_readout: unknown mark kind");
+        if (!std::isfinite(mark->exponent) || !std::isfinite(mark->offset) || !std::isfinite(mark->self_term))
+            return fail(HERMES_ERR_ARG, "hermes_readout: mark parameters must be finite");
+        if (mark->offset < 0.0) return fail(HERMES_ERR_ARG, "hermes_readout: mark offset must be >= 0");
+        const bool divides = mark->kind == HERMES_MARK_INVERSE_DENSITY ||
+                             (mark->kind == HERMES_MARK_POWER_LAW && mark->exponent < 0.0);
+        if (divides && !(mark->offset > 0.0))
+            return fail(HERMES_ERR_ARG, "hermes_readout: this mark needs offset > 0");
+    }
+    DeviceGuard g(ctx->device);
+    return readout_impl(ctx, field, n_grid, dtype, box_L, pos, weight, n_pts, mark, out, moments, stream);
 }
 
 }  // extern "C"

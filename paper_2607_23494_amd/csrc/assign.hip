@@ -1,95 +1,360 @@
 // MRA projection of a weighted catalogue onto B3 scaling-function
-// coefficients (Sec. 3.1, Eq. phi_projection), as a wavefront-parallel
-// scatter of 64 taps per point with hardware float atomics.
+// coefficients (Sec. 3.1, Eq. phi_projection).
+//
+// The 64 taps of every point are accumulated per tile of TS^3 cells in LDS
+// and in 64-bit fixed point:
+//   1. prep     count the points of every tile (by the cell of the point),
+//               and the per-block sums of w and |w|
+//   2. scale    sum_w (the output) and the fixed-point scale 2^k, chosen from
+//               sum |w| so that no cell's sum can overflow: every cell is a
+//               sum of contributions of magnitude <= |w_i|, so
+//               |cell| <= sum |w| 2^k <= 2^61
+//   3. scan     exclusive prefix of the tile counts: each tile's list offset
+//   4. scatter  the point indices into per-tile lists
+//   5. tiles    one workgroup per tile: a wavefront loads 64 points, then
+//               for each of them lane t adds tap t (64 distinct cells) to an
+//               LDS region of (TS + 3)^3 cells (the tile and the stencil's
+//               reach, one cell below and two above); the region is then
+//               added to the global accumulator with 64-bit atomics
+//   6. convert  eps = acc 2^-k
+// Each contribution is rounded once to a multiple of 2^-k; integer addition
+// commutes, so the grid is the same bit for bit whatever the order in which
+// points, tiles and workgroups are processed.
+#include <cmath>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace hermes {
 
-// B3 weights of the four nodes i0-1 .. i0+2 for fractional offset t in [0, 1).
-__device__ __forceinline__ void b3_taps(double t, double w[4]) {
-    const double s = 1.0 - t;
-    w[0] = s * s * s / 6.0;
-    w[1] = (4.0 - 6.0 * t * t + 3.0 * t * t * t) / 6.0;
-    w[2] = (4.0 - 6.0 * s * s + 3.0 * s * s * s) / 6.0;
-    w[3] = t * t * t / 6.0;
+constexpr int kAsgTile = 16;       // cells per tile edge (N >= 16; the whole grid below)
+constexpr int kAsgPrepBlocks = 2048;
+constexpr int kScanBlock = 1024;   // entries per block of the tile-offset scan
+constexpr int kTileThreads = 512;  // threads of the per-tile workgroups
+
+template <int N> struct asg_cfg {
+    static constexpr int TS = N < kAsgTile ? N : kAsgTile;
+    static constexpr int NT = N / TS;                // tiles per axis
+    static constexpr int TILES = NT * NT * NT;
+    static constexpr int RG = TS + 3;                // LDS region edge
+    static constexpr int RCELLS = RG * RG * RG;
+};
+
+// Per-call scalars written by k_asg_scale.
+struct AsgScale {
+    double scale;       // 2^k
+    double inv_scale;   // 2^-k
+};
+
+inline int asg_prep_blocks(int64_t n_pts) {
+    const int64_t want = (n_pts + kThreads - 1) / kThreads;
+    return int(want < kAsgPrepBlocks ? (want > 0 ? want : 1) : kAsgPrepBlocks);
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void k_assign(const float* __restrict__ pos,
-                                                     const float* __restrict__ weight,
-                                                     int64_t n_pts, double scale, T* __restrict__ eps,
-                                                     double* __restrict__ sum_w) {
+// Workspace layout (bytes, each part 256-aligned).
+struct AsgLayout {
+    size_t acc, count, off, cursor, blocksum, list, partial, scale, total;
+};
+
+inline AsgLayout asg_layout(int n, int64_t n_pts) {
+    const int ts = n < kAsgTile ? n : kAsgTile;
+    const int64_t tiles = int64_t(n / ts) * (n / ts) * (n / ts);
+    const int64_t nblk = (tiles + kScanBlock - 1) / kScanBlock;
+    AsgLayout l{};
+    size_t at = 0;
+    l.acc = at;
+    at += align256(size_t(n) * n * n * sizeof(int64_t));
+    l.count = at;
+    at += align256(size_t(tiles) * 4);
+    l.off = at;
+    at += align256(size_t(tiles + 1) * 4);
+    l.cursor = at;
+    at += align256(size_t(tiles) * 4);
+    l.blocksum = at;
+    at += align256(size_t(nblk) * 4);
+    l.list = at;
+    at += align256(size_t(n_pts > 0 ? n_pts : 1) * 4);
+    l.partial = at;
+    at += align256(size_t(asg_prep_blocks(n_pts)) * 2 * sizeof(double));
+    l.scale = at;
+    at += align256(sizeof(AsgScale));
+    l.total = at;
+    return l;
+}
+
+size_t assign_workspace(int n, int64_t n_pts) { return asg_layout(n, n_pts).total; }
+
+// Cell of a position along one axis (periodic wrap into [0, N)) and the
+// fractional offset within it, in float64.
+template <int N>
+__device__ __forceinline__ int cell_of(float x, double scale, double& frac) {
+    double u = double(x) * scale;
+    u -= double(N) * floor(u / double(N));
+    const double f = floor(u);
+    int c = int(f);
+    frac = u - f;
+    if (c >= N) {   // u rounded up to N: the next image's node 0
+        c = 0;
+        frac = 0.0;
+    }
+    return c;
+}
+
+// B3 weight of node i0 - 1 + o (o = 0 .. 3) for the fractional offset t in
+// [0, 1): B3 at distance d = |t + 1 - o| < 2, without branches.
+template <typename T>
+__device__ __forceinline__ T b3_tap(T t, int o) {
+    const T d = fabs(t + T(1 - o));
+    const T e = T(2) - d;
+    return d < T(1) ? (T(4) - T(6) * d * d + T(3) * d * d * d) / T(6) : e * e * e / T(6);
+}
+
+// Broadcast of lane j's value (j uniform across the wavefront).
+__device__ __forceinline__ int bcast(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
+__device__ __forceinline__ float bcast(float v, int j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ __forceinline__ double bcast(double v, int j) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), j);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), j);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+template <int N>
+__device__ __forceinline__ int tile_of_point(const float* __restrict__ pos, int64_t i, double scale) {
+    using G = asg_cfg<N>;
+    double f;
+    const int cx = cell_of<N>(pos[3 * i], scale, f);
+    const int cy = cell_of<N>(pos[3 * i + 1], scale, f);
+    const int cz = cell_of<N>(pos[3 * i + 2], scale, f);
+    return ((cx / G::TS) * G::NT + cy / G::TS) * G::NT + cz / G::TS;
+}
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_asg_prep(const float* __restrict__ pos, const float* __restrict__ weight,
+                                                       int64_t n_pts, double scale, uint32_t* __restrict__ count,
+                                                       double* __restrict__ partial) {
     __shared__ double red[kThreads];
-    double wsum = 0.0;
+    double s = 0.0, sa = 0.0;
     const int64_t stride = int64_t(gridDim.x) * kThreads;
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride) {
         const double w = weight ? double(weight[i]) : 1.0;
-        wsum += w;
-        int cell[3];
-        double tap[3][4];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double u = double(pos[3 * i + a]) * scale;     // position in cell units
-            u -= double(N) * floor(u / double(N));         // periodic wrap into [0, N)
-            const double f = floor(u);
-            cell[a] = int(f);
-            b3_taps(u - f, tap[a]);
-        }
-#pragma unroll
-        for (int ox = 0; ox < 4; ++ox) {
-            const int cx = (cell[0] - 1 + ox) & (N - 1);
-            const double wx = w * tap[0][ox];
-#pragma unroll
-            for (int oy = 0; oy < 4; ++oy) {
-                const int cy = (cell[1] - 1 + oy) & (N - 1);
-                const double wxy = wx * tap[1][oy];
-                T* row = eps + (size_t(cx) * N + cy) * N;
-#pragma unroll
-                for (int oz = 0; oz < 4; ++oz) {
-                    const int cz = (cell[2] - 1 + oz) & (N - 1);
-                    unsafeAtomicAdd(row + cz, T(wxy * tap[2][oz]));
-                }
-            }
-        }
+        s += w;
+        sa += fabs(w);
+        atomicAdd(count + tile_of_point<N>(pos, i, scale), 1u);
     }
-    red[threadIdx.x] = wsum;
+    s = block_sum(s, red);
+    sa = block_sum(sa, red);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = s;
+        partial[2 * blockIdx.x + 1] = sa;
+    }
+}
+
+// sum_w and the fixed-point scale 2^k, k = 61 - ceil(log2(sum |w|)), from the
+// per-block partials in block order.
+__global__ void k_asg_scale(const double* __restrict__ partial, int nblocks, double* __restrict__ sum_w,
+                            AsgScale* __restrict__ sc) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0, sa = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        s += partial[2 * b];
+        sa += partial[2 * b + 1];
+    }
+    sum_w[0] = s;
+    int e = 0;
+    if (sa > 0.0) {
+        frexp(sa, &e);   // sa < 2^e
+    }
+    const int k = min(1000, 61 - e);   // 2^k stays finite for tiny weights
+    sc->scale = ldexp(1.0, k);
+    sc->inv_scale = ldexp(1.0, -k);
+}
+
+// Exclusive prefix sum of cnt[0 .. n) in blocks of kScanBlock: the block's
+// prefix to out, its total to blocksum.
+__global__ __launch_bounds__(kScanBlock) void k_scan_block(const uint32_t* __restrict__ cnt, int64_t n,
+                                                           uint32_t* __restrict__ out,
+                                                           uint32_t* __restrict__ blocksum) {
+    __shared__ uint32_t s[kScanBlock];
+    const int64_t i = int64_t(blockIdx.x) * kScanBlock + threadIdx.x;
+    const uint32_t v = i < n ? cnt[i] : 0u;
+    s[threadIdx.x] = v;
     __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int d = 1; d < kScanBlock; d <<= 1) {   // inclusive Hillis-Steele scan
+        const uint32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += t;
         __syncthreads();
     }
-    if (threadIdx.x == 0) unsafeAtomicAdd(sum_w, red[0]);
+    if (i < n) out[i] = s[threadIdx.x] - v;
+    if (threadIdx.x == kScanBlock - 1) blocksum[blockIdx.x] = s[threadIdx.x];
+}
+
+// Exclusive prefix of the block totals (one block; nblk <= kScanBlock), and
+// the grand total at out[n].
+__global__ __launch_bounds__(kScanBlock) void k_scan_totals(uint32_t* __restrict__ blocksum, int nblk,
+                                                            uint32_t* __restrict__ out, int64_t n) {
+    __shared__ uint32_t s[kScanBlock];
+    const uint32_t v = int(threadIdx.x) < nblk ? blocksum[threadIdx.x] : 0u;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanBlock; d <<= 1) {
+        const uint32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (int(threadIdx.x) < nblk) blocksum[threadIdx.x] = s[threadIdx.x] - v;
+    if (threadIdx.x == kScanBlock - 1) out[n] = s[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* __restrict__ out, int64_t n,
+                                                         const uint32_t* __restrict__ blocksum) {
+    const int64_t i = int64_t(blockIdx.x) * kScanBlock + threadIdx.x;
+    if (i < n) out[i] += blocksum[blockIdx.x];
+}
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_asg_scatter(const float* __restrict__ pos, int64_t n_pts, double scale,
+                                                          const uint32_t* __restrict__ off,
+                                                          uint32_t* __restrict__ cursor, uint32_t* __restrict__ list) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride) {
+        const int t = tile_of_point<N>(pos, i, scale);
+        list[off[t] + atomicAdd(cursor + t, 1u)] = uint32_t(i);
+    }
+}
+
+// One workgroup per tile.  A wavefront takes 64 of the tile's points at a
+// time, one per lane (index, weight, cell and fractions, computed once), then
+// walks through them: for point j, lane t adds tap t = (ox, oy, oz) = (t / 16,
+// t / 4 % 4, t % 4), whose cell i0 - 1 + o of the tile's region sits at local
+// index i0 - origin + o in [0, TS + 2] per axis; the 64 lanes hit 64
+// distinct cells.
+template <typename T, int N>
+__global__ __launch_bounds__(kTileThreads) void k_asg_tiles(const float* __restrict__ pos, const float* __restrict__ weight,
+                                                        double scale, const uint32_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ list,
+                                                        const AsgScale* __restrict__ sc,
+                                                        unsigned long long* __restrict__ acc) {
+    using G = asg_cfg<N>;
+    constexpr int TS = G::TS, NT = G::NT, RG = G::RG, RCELLS = G::RCELLS;
+    constexpr int NW = kTileThreads / 64;
+    __shared__ unsigned long long reg[RCELLS];
+    const int tile = blockIdx.x;
+    const uint32_t p0 = off[tile], p1 = off[tile + 1];
+    if (p0 == p1) return;   // uniform: an empty tile adds nothing
+    const int tx = tile / (NT * NT), ty = (tile / NT) % NT, tz = tile % NT;
+    const int ox0 = tx * TS, oy0 = ty * TS, oz0 = tz * TS;
+    for (int c = threadIdx.x; c < RCELLS; c += kTileThreads) reg[c] = 0ull;
+    __syncthreads();
+    const double fxp = sc->scale;
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int ox = lane >> 4, oy = (lane >> 2) & 3, oz = lane & 3;
+    const int tap = (ox * RG + oy) * RG + oz;
+    for (uint32_t k0 = p0 + 64u * wv; k0 < p1; k0 += 64u * NW) {
+        const uint32_t k = k0 + lane;
+        int loc = 0;
+        T fx = T(0), fy = T(0), fz = T(0);
+        double wq = 0.0;
+        if (k < p1) {
+            const uint32_t i = list[k];
+            double frx, fry, frz;
+            const int cx = cell_of<N>(pos[3 * size_t(i)], scale, frx);
+            const int cy = cell_of<N>(pos[3 * size_t(i) + 1], scale, fry);
+            const int cz = cell_of<N>(pos[3 * size_t(i) + 2], scale, frz);
+            loc = ((cx - ox0) * RG + (cy - oy0)) * RG + (cz - oz0);
+            fx = T(frx);
+            fy = T(fry);
+            fz = T(frz);
+            wq = (weight ? double(weight[i]) : 1.0) * fxp;
+        }
+        const int cnt = int(min(64u, p1 - k0));
+        for (int j = 0; j < cnt; ++j) {
+            const T wt = b3_tap<T>(bcast(fx, j), ox) * b3_tap<T>(bcast(fy, j), oy) * b3_tap<T>(bcast(fz, j), oz);
+            const long long q = llrint(bcast(wq, j) * double(wt));
+            atomicAdd(&reg[bcast(loc, j) + tap], (unsigned long long)q);
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < RCELLS; c += kTileThreads) {
+        const unsigned long long v = reg[c];
+        if (v == 0ull) continue;
+        const int lx = c / (RG * RG), ly = (c / RG) % RG, lz = c % RG;
+        const int gx = (ox0 - 1 + lx + N) & (N - 1);
+        const int gy = (oy0 - 1 + ly + N) & (N - 1);
+        const int gz = (oz0 - 1 + lz + N) & (N - 1);
+        atomicAdd(acc + (size_t(gx) * N + gy) * N + gz, v);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_asg_convert(const long long* __restrict__ acc, int64_t n,
+                                                          const AsgScale* __restrict__ sc, T* __restrict__ eps) {
+    const double inv = sc->inv_scale;
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride)
+        eps[i] = T(double(acc[i]) * inv);
 }
 
 template <typename T, int N>
 static hermes_status assign_n(hermes_ctx ctx, const float* pos, const float* weight, int64_t n_pts, double box_L,
-                              void* eps, double* sum_w, hipStream_t stream) {
+                              void* eps, double* sum_w, void* work, hipStream_t stream) {
+    using G = asg_cfg<N>;
     const int64_t cells = int64_t(N) * N * N;
+    const AsgLayout l = asg_layout(N, n_pts);
+    char* w = static_cast<char*>(work);
+    long long* acc = reinterpret_cast<long long*>(w + l.acc);
+    uint32_t* count = reinterpret_cast<uint32_t*>(w + l.count);
+    uint32_t* off = reinterpret_cast<uint32_t*>(w + l.off);
+    uint32_t* cursor = reinterpret_cast<uint32_t*>(w + l.cursor);
+    uint32_t* blocksum = reinterpret_cast<uint32_t*>(w + l.blocksum);
+    uint32_t* list = reinterpret_cast<uint32_t*>(w + l.list);
+    double* partial = reinterpret_cast<double*>(w + l.partial);
+    AsgScale* sc = reinterpret_cast<AsgScale*>(w + l.scale);
+    const double scale = double(N) / box_L;
+    const int pblocks = asg_prep_blocks(n_pts);
     {
         LaunchScope ls(ctx, stream, "fill");
-        launch_fill<T>(static_cast<T*>(eps), cells, T(0), stream);
+        launch_fill<long long>(acc, cells, 0ll, stream);
+        launch_fill<uint32_t>(count, G::TILES, 0u, stream);
+        launch_fill<uint32_t>(cursor, G::TILES, 0u, stream);
+        launch_fill<double>(partial, 2 * int64_t(pblocks), 0.0, stream);
     }
     {
-        LaunchScope ls(ctx, stream, "fill");
-        launch_fill<double>(sum_w, 1, 0.0, stream);
-    }
-    if (n_pts > 0) {
         LaunchScope ls(ctx, stream, "assign");
-        const int64_t want = (n_pts + kThreads - 1) / kThreads;
-        const int blocks = int(want < 8192 ? want : 8192);
-        hipLaunchKernelGGL((k_assign<T, N>), dim3(blocks), dim3(kThreads), 0, stream, pos, weight, n_pts,
-                           double(N) / box_L, static_cast<T*>(eps), sum_w);
+        if (n_pts > 0)
+            hipLaunchKernelGGL((k_asg_prep<N>), dim3(pblocks), dim3(kThreads), 0, stream, pos, weight, n_pts, scale,
+                               count, partial);
+        hipLaunchKernelGGL(k_asg_scale, dim3(1), dim3(64), 0, stream, partial, pblocks, sum_w, sc);
+        const int nblk = (G::TILES + kScanBlock - 1) / kScanBlock;
+        hipLaunchKernelGGL(k_scan_block, dim3(nblk), dim3(kScanBlock), 0, stream, count, int64_t(G::TILES), off,
+                           blocksum);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, stream, blocksum, nblk, off,
+                           int64_t(G::TILES));
+        hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kScanBlock), 0, stream, off, int64_t(G::TILES), blocksum);
+        if (n_pts > 0) {
+            hipLaunchKernelGGL((k_asg_scatter<N>), dim3(pblocks), dim3(kThreads), 0, stream, pos, n_pts, scale, off,
+                               cursor, list);
+            hipLaunchKernelGGL((k_asg_tiles<T, N>), dim3(G::TILES), dim3(kTileThreads), 0, stream, pos, weight, scale, off,
+                               list, sc, reinterpret_cast<unsigned long long*>(acc));
+        }
+        const int64_t want = (cells + kThreads - 1) / kThreads;
+        hipLaunchKernelGGL((k_asg_convert<T>), dim3(int(want < 8192 ? want : 8192)), dim3(kThreads), 0, stream, acc,
+                           cells, sc, static_cast<T*>(eps));
     }
     return check_launch("hermes_assign");
 }
 
 hermes_status assign_impl(hermes_ctx ctx, const float* pos, const float* weight, int64_t n_pts, double box_L,
-                          int n, int dtype, void* eps, double* sum_w, hipStream_t stream) {
-#define HERMES_ASSIGN_CASE(NN)                                                                  \
-    case NN:                                                                                    \
-        return dtype == HERMES_F32 ? assign_n<float, NN>(ctx, pos, weight, n_pts, box_L, eps, sum_w, stream) \
-                                   : assign_n<double, NN>(ctx, pos, weight, n_pts, box_L, eps, sum_w, stream);
+                          int n, int dtype, void* eps, double* sum_w, void* work, hipStream_t stream) {
+#define HERMES_ASSIGN_CASE(NN)                                                                                  \
+    case NN:                                                                                                    \
+        return dtype == HERMES_F32                                                                              \
+                   ? assign_n<float, NN>(ctx, pos, weight, n_pts, box_L, eps, sum_w, work, stream)             \
+                   : assign_n<double, NN>(ctx, pos, weight, n_pts, box_L, eps, sum_w, work, stream);
     switch (n) {
         HERMES_ASSIGN_CASE(8)
         HERMES_ASSIGN_CASE(16)

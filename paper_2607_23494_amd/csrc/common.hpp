@@ -44,6 +44,7 @@ struct Profiler {
 
 struct hermes_ctx_s {
     int device = 0;
+    int cus = 256;                // compute units of the device
     hermes::Tables t;
     hermes::Profiler prof;
 };
@@ -93,8 +94,9 @@ inline int64_t qmax_of(int n) { return 3LL * (n / 2) * (n / 2); }
 // ---------------------------------------------------------------- entry points
 // (implemented per translation unit, dispatched by dtype / N)
 hermes_status assign_impl(hermes_ctx ctx, const float* pos, const float* weight, int64_t n_pts,
-                          double box_L, int n, int dtype, void* eps, double* sum_w,
+                          double box_L, int n, int dtype, void* eps, double* sum_w, void* work,
                           hipStream_t stream);
+size_t assign_workspace(int n, int64_t n_pts);
 hermes_status fft_impl(hermes_ctx ctx, const void* eps, const double* sum_w, int n, int dtype,
                        void* delta_k, void* delta, hipStream_t stream);
 hermes_status xi_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype, double box_L,
@@ -109,5 +111,8 @@ hermes_status zeta_impl(hermes_ctx ctx, const float* delta, const void* delta_k,
                         double box_L, const Edges& edges, int l_max, int precision, double* zeta,
                         void* work, size_t work_bytes, hipStream_t stream);
 size_t zeta_workspace(int n, int n_bins);
+hermes_status readout_impl(hermes_ctx ctx, const void* field, int n, int dtype, double box_L, const float* pos,
+                           const float* weight, int64_t n_pts, const hermes_mark* mark, void* out,
+                           double* moments, hipStream_t stream);
 
 }  // namespace hermes

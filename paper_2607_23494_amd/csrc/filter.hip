@@ -130,11 +130,16 @@ __global__ __launch_bounds__(kThreads) void k_radial(T* __restrict__ tab, int64_
 // 2k + 1 (k <= M/2), so that the packing step of the c2r transform along z
 // combines neighbouring columns.  Positions 0 .. M hold kz = 0 .. M exactly
 // once (position 1 holds kz = M); position M + 1 would repeat kz = M/2 and the
-// positions above it are row padding.
+// positions above it are row padding.  After the y pass a row holds the packed
+// c2r input Z[k], k < M: Z[kz_of_pos(pos)] at every position but 1 (kz = M has
+// no Z), so Z[M/2] stays at position M, in the tile that computes it.
 template <int N> __host__ __device__ constexpr int kz_of_pos(int pos) { return (pos & 1) ? N / 2 - (pos >> 1) : (pos >> 1); }
 template <int N> __host__ __device__ constexpr bool pos_used(int pos) { return pos <= N / 2; }
-// index k of the packed Z[k] that the y pass stores at position pos, 0 <= pos < N/2
-template <int N> __host__ __device__ constexpr int zk_of_pos(int pos) { return pos == 1 ? N / 4 : kz_of_pos<N>(pos); }
+// The z pass reads Z[k], k < M, from M row positions: position 0 and 2 .. M
+// (Z[M/2] at position M).  Slot s in [0, M) of that list: the position it is
+// read from and the index k it holds.
+template <int N> __host__ __device__ constexpr int zslot_pos(int s) { return s == 1 ? N / 2 : s; }
+template <int N> __host__ __device__ constexpr int zk_of_pos(int s) { return s == 1 ? N / 4 : kz_of_pos<N>(s); }
 
 // ---------------------------------------------------------------- column table
 // The radial factor unrolled along x for every (|ky|, kz) column:
@@ -344,9 +349,11 @@ __global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* _
             const bool last = a == NM - 1;   // the last reader of su for window b
             if (a == 0 && b + 1 < nb) uload(b + 1);   // lands during the transform
             C* ob = (a ? out1 : out0) + b * bin_stride + c0;
+            // padding positions above N/2 + 1 hold zeros and are stored too,
+            // so every row is written in whole 128-byte lines
             auto st = [&](int p, int line, C val) {
                 const int c = c0 + line;
-                if (c < PLANE && pos_used<N>(c % PP)) st_stream(ob + int64_t(p) * plane_stride<N>() + line, val);
+                if (c < PLANE) st_stream(ob + int64_t(p) * plane_stride<N>() + line, val);
             };
             if constexpr (N > 8) {
                 // the next window's runs go to su before this window's last
@@ -380,9 +387,9 @@ __global__ __launch_bounds__(NT) void k_win_x(const typename cplx_of<T>::type* _
 // whose output holds samples 2n and 2n+1 in its real and imaginary parts.
 // Columns k and M - k are neighbours in the pair order (kz_of_pos), so a tile
 // of TC consecutive positions holds whole pairs; the pair is combined right
-// after the transform and Z[kz] overwrites X[kz] at its position, except
-// Z[M/2], which goes to position 1 (kz = M has no Z): the z pass then reads
-// the aligned positions 0 .. M-1, Z[zk_of_pos(pos)].  With TC <= 64 the last Stockham stage leaves the two
+// after the transform and Z[kz] overwrites X[kz] at its own position (kz = M
+// at position 1 has no Z and is left as it is), so no tile writes a position
+// that another tile reads.  With TC <= 64 the last Stockham stage leaves the two
 // columns of a pair in neighbouring lanes of one wavefront; wider tiles pair
 // through LDS.  Position M + 1 is loaded as a copy of kz = M/2, the partner of
 // position M.  One 8-byte column per thread and load round.
@@ -422,15 +429,17 @@ __global__ __launch_bounds__((ypack_cfg<T, N>::NT)) void k_inv_y_pack(typename c
     if constexpr (TC <= 64 && N > 8) {
         auto fin = [&](int jj, int line, const C* v, int R, int NS) {
             const int p = c0 + line;
-            const bool store = pos_used<N>(p) && p != 1;
-            const int sp = p == M ? 1 : p;
+            // every position of the row is stored, also position 1 and the
+            // padding above M (values nobody reads), so rows are written in
+            // whole 128-byte lines
+            const bool store = p < PP;
             const C w = twl[kz_of_pos<N>(p) & (N - 1)];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 if (r < R) {
                     const C oth{__shfl_xor(v[r].x, 1), __shfl_xor(v[r].y, 1)};
                     const C z = pack(v[r], oth, w);
-                    if (store) base[int64_t(jj + r * NS) * PP + sp] = z;
+                    if (store) base[int64_t(jj + r * NS) * PP + p] = z;
                 }
             }
         };
@@ -440,8 +449,8 @@ __global__ __launch_bounds__((ypack_cfg<T, N>::NT)) void k_inv_y_pack(typename c
         for (int e = threadIdx.x; e < N * TC; e += NT) {
             const int y = e / TC, q = e - (e / TC) * TC;
             const int p = c0 + q;
-            if (!pos_used<N>(p) || p == 1) continue;
-            base[int64_t(y) * PP + (p == M ? 1 : p)] = pack(s[y * TC + q], s[y * TC + (q ^ 1)], twl[kz_of_pos<N>(p)]);
+            if (p >= PP) continue;
+            base[int64_t(y) * PP + p] = pack(s[y * TC + q], s[y * TC + (q ^ 1)], twl[kz_of_pos<N>(p) & (N - 1)]);
         }
     }
 }
@@ -633,9 +642,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                 const int64_t row = row0 + (line - b * R);   // (x, y) = (row / N, row % N)
                 const C* base = spec + b * bin_stride + (row / N) * plane_stride<N>() + (row % N) * PP;
                 if constexpr (M >= 64) {
-                    pre[i] = ld_stream_buf(base, unsigned(pos) * unsigned(sizeof(C)));   // line uniform in i
+                    pre[i] = ld_stream_buf(base, unsigned(zslot_pos<N>(pos)) * unsigned(sizeof(C)));   // line uniform in i
                 } else {
-                    pre[i] = ld_stream(base + pos);
+                    pre[i] = ld_stream(base + zslot_pos<N>(pos));
                 }
             }
         }
@@ -786,6 +795,344 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     }
 }
 
+// ---------------------------------------------------------------- pass Z, register form
+// For N = 256 and 512 the length-M inverse along z (M = N/2) runs in
+// registers: a line is spread over P lanes holding Q = M/P elements each,
+// element n = p + P q in lane p.  Stage A is a Q-point DFT in registers, the
+// twiddle is w_M^(p a), one wavefront-local transpose through LDS regroups the
+// P values of each a, and stage B is a P-point DFT in registers, leaving
+// X[a + Q c] for c < P (the four-step split of M = P Q).  Each wavefront
+// holds 64/P lines.  The outputs are staged once, as real samples, for the
+// epilogue; the transpose tiles and the staged samples share LDS.
+template <int N> struct zreg_cfg {
+    static constexpr int M = N / 2;
+    static constexpr int P = M >= 256 ? 16 : 8;      // lanes per line
+    static constexpr int Q = M / P;                  // elements per lane
+    static constexpr int LPW = 64 / P;               // lines per wavefront
+    static constexpr int R = zrows<N>::R;            // rows per group
+    static constexpr int CELLS = R * N;
+    static constexpr int TS = 2 * Q * (P + 1);       // floats of one transpose tile, [a][P + 1] complex
+    // floats per bin: the R lines' transpose tiles or the R N staged samples;
+    // BS = 4 (mod 8) puts the 16-byte epilogue reads of 16 consecutive bins on
+    // distinct banks and keeps them 16-byte aligned
+    static constexpr int bs_of() {
+        int b = R * TS > R * N ? R * TS : R * N;
+        while (b % 8 != 4) ++b;
+        return b;
+    }
+    static constexpr int BS = bs_of();
+    static_assert(P <= Q && M == P * Q && 64 % P == 0 && (Q == 8 || Q == 16) && (P == 8 || P == 16), "split");
+    static_assert(LPW % R == 0, "a wavefront holds whole bins");
+};
+
+template <int N> constexpr bool zreg_ok() { return N == 256 || N == 512; }
+
+template <int N, int W>
+constexpr size_t zreg_lds_bytes() {
+    using G = zreg_cfg<N>;
+    const size_t bins = size_t(W) * G::LPW / G::R;
+    const size_t main = bins * G::BS * 4 + size_t(G::CELLS) * 4 + size_t(G::CELLS) / 2 * 4 + size_t(G::M) * 8;
+    const size_t red = size_t(W) * 64 * 16 * sizeof(double);
+    return main > red ? main : red;
+}
+
+// Matrix-core contraction of one row group from the staged samples, with
+// W wavefronts taking 16-cell steps round robin.  With y = sqrt|delta| x,
+// s = sign delta and y = y_hi + y_lo (bf16 or fp16), the group's share
+//   C = sum_c s y y^T = sum_c s (y_hi y_hi^T + y_lo y_hi^T + y_hi y_lo^T) + O(y_lo^2)
+// is three MFMAs per 16 cells into one float32 accumulator (the sign rides on
+// the B operand), added to the float64 accumulators once per group.
+// Accumulator registers q of the 32 x 32 tile that can hold a row below the
+// batch capacity (row 8 (q / 4) + 4 (lane / 32) + q % 4): the first 8 for up
+// to 16 bins, 12 for up to 24, all 16 for 32.
+template <int BINS> constexpr int acc_rows() { return BINS <= 16 ? 8 : (BINS <= 24 ? 12 : 16); }
+
+template <int N, int W, int PREC, int ACC_ROWS>
+__device__ __forceinline__ void mfma_contract_staged(const float* reg, const float* sr, const uint32_t* sgn, int nb,
+                                                     double* acc64) {
+    using G = zreg_cfg<N>;
+    using V = typename std::conditional<PREC == HERMES_PREC_BF16X3, bf16x8_t, f16x8_t>::type;
+    using E = typename std::conditional<PREC == HERMES_PREC_BF16X3, __bf16, _Float16>::type;
+    constexpr int BS = G::BS, STEPS = G::CELLS / 16;
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int bin = min(l % 32, nb - 1), half = l / 32;
+    const float* rb = reg + bin * BS;
+    f32x16_t acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll 1
+    for (int step = w; step < STEPS; step += W) {
+        const int c0 = step * 16 + 8 * half;   // 8 consecutive cells of one row
+        const int rr = c0 / N, z = c0 - rr * N;
+        const float4 x0 = *reinterpret_cast<const float4*>(rb + rr * N + z);
+        const float4 x1 = *reinterpret_cast<const float4*>(rb + rr * N + z + 4);
+        const float4 r0 = *reinterpret_cast<const float4*>(sr + c0);
+        const float4 r1 = *reinterpret_cast<const float4*>(sr + c0 + 4);
+        const u32x4_t sm = *reinterpret_cast<const u32x4_t*>(sgn + c0 / 2);
+        const float y[8] = {x0.x * r0.x, x0.y * r0.y, x0.z * r0.z, x0.w * r0.w,
+                            x1.x * r1.x, x1.y * r1.y, x1.z * r1.z, x1.w * r1.w};
+        V hi, lo;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            hi[t] = (E)y[t];
+            lo[t] = (E)(y[t] - float(hi[t]));
+        }
+        const V hs = __builtin_bit_cast(V, __builtin_bit_cast(u32x4_t, hi) ^ sm);
+        const V ls = __builtin_bit_cast(V, __builtin_bit_cast(u32x4_t, lo) ^ sm);
+        if constexpr (PREC == HERMES_PREC_BF16X3) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi, hs, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo, hs, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi, ls, acc, 0, 0, 0);
+        } else {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi, hs, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(lo, hs, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi, ls, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < ACC_ROWS; ++r) acc64[r] += double(acc[r]);
+}
+
+// Inverse along z of nb windows x R rows per group with W wavefronts
+// (W 64 / P >= nb R lines), then the epilogue, as k_c2r_z.  Persistent
+// workgroups; the loads of the next group are issued once the transform is
+// staged and land during the epilogue.
+template <int N, int EPI, int W, int PREC>
+__global__ __launch_bounds__(W * 64) void k_c2r_zr(const float2* __restrict__ spec, int64_t bin_stride, int nb,
+                                                   const float* __restrict__ delta, float* __restrict__ out,
+                                                   WinSet map, double* __restrict__ part,
+                                                   const float2* __restrict__ tw) {
+    using G = zreg_cfg<N>;
+    constexpr int M = G::M, P = G::P, Q = G::Q, LPW = G::LPW, R = G::R, CELLS = G::CELLS, BS = G::BS;
+    constexpr int TS = G::TS;
+    constexpr int NT = W * 64, PP = pitch_of<N>(), GROUPS = N * N / R;
+    constexpr int BINS = W * LPW / R;
+    constexpr bool MF = EPI == EPI_CONTRACT && PREC != HERMES_PREC_FP32;
+    extern __shared__ double lds_raw[];
+    float* reg = reinterpret_cast<float*>(lds_raw);                // [BINS][BS]
+    float* sd = reg + BINS * BS;                                    // [CELLS]
+    uint32_t* sgn = reinterpret_cast<uint32_t*>(sd + CELLS);        // [CELLS / 2]
+    float2* twm = reinterpret_cast<float2*>(sgn + CELLS / 2);       // [a][p]: exp(-2 pi i p a / M)
+    for (int i = threadIdx.x; i < M; i += NT) {
+        const int a = i / P, pp = i - (i / P) * P;
+        twm[i] = tw[M + pp * a];
+    }
+
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int p = lane % P;
+    const int line = wv * LPW + lane / P;                           // line = bin R + row
+    const bool active = line < nb * R;
+    const int b = line / R, r = line - (line / R) * R;
+    float2* tt = reinterpret_cast<float2*>(reg + b * BS + r * TS);  // transpose tile [a][P + 1]
+    float* stg = reg + b * BS + r * N;                              // staged samples of the line
+
+    // contraction roles (float32 path): 4x4 bin tiles (I <= J) x cell groups
+    const int nt4 = (nb + 3) / 4;
+    const int ntp = nt4 * (nt4 + 1) / 2;
+    const int cg_n = NT / ntp;
+    const int tp = threadIdx.x % ntp, cg = threadIdx.x / ntp;
+    int ti = 0, tj = 0;
+    {
+        int idx = tp;
+        for (int I = 0; I < nt4; ++I) {
+            if (idx < nt4 - I) {
+                ti = I;
+                tj = I + idx;
+                break;
+            }
+            idx -= nt4 - I;
+        }
+    }
+    const int subs = NT / nb;
+    const int mb = threadIdx.x % nb, msub = threadIdx.x / nb;
+
+    double acc64[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc64[i] = 0.0;
+
+    // element n = p + P q of the line sits at its pair-order position: 2 n
+    // below M/2, 2 (M - n) + 1 above, and position M for n = M/2 (q = Q/2,
+    // p = 0); from two per-lane bases the offsets are immediates
+    float2 pre[Q];
+    float4 dpre = float4{0.f, 0.f, 0.f, 0.f};
+    auto fetch = [&](int g) {
+        if (active) {
+            const int64_t row = int64_t(g) * R + r;
+            const float2* base = spec + b * bin_stride + (row / N) * plane_stride<N>() + (row % N) * PP;
+            const float2* lo = base + 2 * p;                 // n = p + P q < M/2: position 2 p + 2 P q
+            const float2* hi = base + (2 * M + 1 - 2 * p);   // n > M/2: position 2 M + 1 - 2 p - 2 P q
+#pragma unroll
+            for (int q = 0; q < Q / 2; ++q) pre[q] = ld_stream(lo + 2 * P * q);
+            pre[Q / 2] = ld_stream(p == 0 ? base + M : hi - 2 * P * (Q / 2));
+#pragma unroll
+            for (int q = Q / 2 + 1; q < Q; ++q) pre[q] = ld_stream(hi - 2 * P * q);
+        }
+        if (EPI == EPI_CONTRACT && threadIdx.x < CELLS / 4)
+            dpre = *reinterpret_cast<const float4*>(delta + int64_t(g) * CELLS + 4 * threadIdx.x);
+    };
+    __syncthreads();   // twiddles
+    if (blockIdx.x < GROUPS) fetch(blockIdx.x);
+    for (int g = blockIdx.x; g < GROUPS; g += gridDim.x) {
+        const int64_t row0 = int64_t(g) * R;
+        if (EPI == EPI_CONTRACT && threadIdx.x < CELLS / 4) {
+            const float d[4] = {dpre.x, dpre.y, dpre.z, dpre.w};
+            const int c = 4 * threadIdx.x;
+            if constexpr (MF) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sd[c + i] = sqrtf(fabsf(d[i]));
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    sgn[c / 2 + i] = ((__float_as_uint(d[2 * i]) >> 16) & 0x8000u) |
+                                     (__float_as_uint(d[2 * i + 1]) & 0x80000000u);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sd[c + i] = d[i];
+            }
+        }
+        float2 v[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = pre[q];
+        if (active) {
+            dft_reg<Q, true>(v);                       // stage A over q
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                const float2 w = twm[a * P + p];       // exp(-2 pi i p a / M); the inverse takes its conjugate
+                v[a] = c_mul(v[a], float2{w.x, -w.y});
+            }
+#pragma unroll
+            for (int a = 0; a < Q; ++a) tt[a * (P + 1) + p] = v[a];
+        }
+        wave_sync();
+        float2 u[Q / P][P];
+        if (active) {
+#pragma unroll
+            for (int h = 0; h < Q / P; ++h) {
+                const int a = p + P * h;
+#pragma unroll
+                for (int j = 0; j < P; ++j) u[h][j] = tt[a * (P + 1) + j];
+                dft_reg<P, true>(u[h]);                // stage B over p: X[a + Q c] = u[h][c]
+            }
+        }
+        wave_sync();
+        if (active) {
+#pragma unroll
+            for (int h = 0; h < Q / P; ++h)
+#pragma unroll
+                for (int c = 0; c < P; ++c) {
+                    const int k = p + P * h + Q * c;   // complex output k: real samples 2k, 2k + 1
+                    *reinterpret_cast<float2*>(stg + 2 * k) = u[h][c];
+                }
+        }
+        // the next group's rows load while the epilogue runs
+        if (g + int(gridDim.x) < GROUPS) fetch(g + gridDim.x);
+        __syncthreads();
+        if constexpr (MF) {
+            mfma_contract_staged<N, W, PREC, acc_rows<W * G::LPW / G::R>()>(reg, sd, sgn, nb, acc64);
+        } else if constexpr (EPI == EPI_CONTRACT) {
+            if (cg < cg_n) {
+                float acc[4][4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[a][c] = 0.f;
+                for (int cell = cg; cell < CELLS; cell += cg_n) {
+                    const int rr = cell / N, z = cell - rr * N;
+                    const float d = sd[cell];
+                    float xa[4], xb[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int b1 = 4 * ti + a, b2 = 4 * tj + a;
+                        xa[a] = b1 < nb ? reg[b1 * BS + rr * N + z] * d : 0.f;
+                        xb[a] = b2 < nb ? reg[b2 * BS + rr * N + z] : 0.f;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(xa[a], xb[c], acc[a][c]);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc64[a * 4 + c] += double(acc[a][c]);
+            }
+        } else {
+            if (out) {
+                for (int e = threadIdx.x; e < nb * CELLS; e += NT) {
+                    const int bb = e / CELLS, rem = e - bb * CELLS;
+                    const int rr = rem / N, z = rem - rr * N;
+                    out[int64_t(map.out[bb]) * N * N * N + (row0 + rr) * N + z] = reg[bb * BS + rr * N + z];
+                }
+            }
+            if (part && msub < subs) {
+                float s2 = 0.f, s3 = 0.f, s4 = 0.f;
+                for (int cell = msub; cell < CELLS; cell += subs) {
+                    const int rr = cell / N, z = cell - rr * N;
+                    const float x = reg[mb * BS + rr * N + z];
+                    const float x2 = x * x;
+                    s2 += x2;
+                    s3 += x2 * x;
+                    s4 += x2 * x2;
+                }
+                acc64[0] += double(s2);
+                acc64[1] += double(s3);
+                acc64[2] += double(s4);
+            }
+        }
+        __syncthreads();
+    }
+
+    // workgroup reduction of the float64 partial sums
+    double* red = lds_raw;
+    if constexpr (MF) {
+        // acc64[q] of lane l in wave w holds entry (i, j) of the 32 x 32 tile,
+        // j = l % 32, i = 8 (q / 4) + 4 (l / 32) + q % 4
+        const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+        for (int st = 0; st < W; ++st) {
+            if (w == st) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int i = 8 * (q / 4) + 4 * (l / 32) + (q % 4), j = l % 32;
+                    red[i * 32 + j] = (st == 0 ? 0.0 : red[i * 32 + j]) + acc64[q];
+                }
+            }
+            __syncthreads();
+        }
+        double* dst = part + int64_t(blockIdx.x) * nb * nb;
+        for (int e = threadIdx.x; e < nb * nb; e += NT) dst[e] = red[(e / nb) * 32 + e % nb];
+    } else if constexpr (EPI == EPI_CONTRACT) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) red[threadIdx.x * 16 + i] = acc64[i];
+        __syncthreads();
+        if (threadIdx.x < ntp) {
+            double sum[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) sum[i] = 0.0;
+            for (int c = 0; c < cg_n; ++c)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) sum[i] += red[(c * ntp + threadIdx.x) * 16 + i];
+            double* dst = part + int64_t(blockIdx.x) * nb * nb;
+            for (int a = 0; a < 4; ++a)
+                for (int c = 0; c < 4; ++c) {
+                    const int b1 = 4 * ti + a, b2 = 4 * tj + c;
+                    if (b1 < nb && b2 < nb) {
+                        dst[b1 * nb + b2] = sum[a * 4 + c];
+                        dst[b2 * nb + b1] = sum[a * 4 + c];
+                    }
+                }
+        }
+    } else if (part) {
+        for (int i = 0; i < 3; ++i) red[threadIdx.x * 3 + i] = acc64[i];
+        __syncthreads();
+        if (threadIdx.x < nb) {
+            double sum[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < subs; ++c)
+                for (int i = 0; i < 3; ++i) sum[i] += red[(c * nb + threadIdx.x) * 3 + i];
+            double* dst = part + (int64_t(blockIdx.x) * nb + threadIdx.x) * 3;
+            for (int i = 0; i < 3; ++i) dst[i] = sum[i];
+        }
+    }
+}
+
 // dst[i] (+)= scale * sum_g part[g * n + i]; one workgroup per output element.
 __global__ __launch_bounds__(kThreads) void k_reduce_part(const double* __restrict__ part, int ngroups, int n,
                                                           double scale, double* __restrict__ dst, int accumulate) {
@@ -825,14 +1172,64 @@ inline int z_grid_rt(int n) {
     return groups < kZGroups ? groups : kZGroups;
 }
 
+// Persistent grid of a z-pass kernel: the workgroups that are resident at
+// once (occupancy query, once per kernel), capped at kZGroups (the partial-sum
+// rows the workspaces hold) and at the group count.
+template <typename KernelT>
+inline int resident_grid(hermes_ctx ctx, KernelT kernel, int threads, size_t lds, int groups) {
+    static std::mutex mu;
+    static std::map<const void*, int> per_cu;   // workgroups per CU, by kernel
+    int v = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = per_cu.find(reinterpret_cast<const void*>(kernel));
+        if (it != per_cu.end()) {
+            v = it->second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, reinterpret_cast<const void*>(kernel), threads, lds) !=
+                    hipSuccess ||
+                v < 1)
+                v = 1;
+            per_cu[reinterpret_cast<const void*>(kernel)] = v;
+        }
+    }
+    return std::min({v * ctx->cus, kZGroups, groups});
+}
+
 template <typename T, int N, int EPI, int NBCAP, int PREC>
-static void launch_z(const typename cplx_of<T>::type* sp, int64_t bin_stride, int nb, const T* delta, T* out,
-                     const WinSet& ws, double* part, const typename cplx_of<T>::type* tw, hipStream_t stream) {
+static int launch_z(hermes_ctx ctx, const typename cplx_of<T>::type* sp, int64_t bin_stride, int nb, const T* delta,
+                    T* out, const WinSet& ws, double* part, const typename cplx_of<T>::type* tw, hipStream_t stream) {
     constexpr int CAP = NBCAP < z_max_batch<T, N>() ? NBCAP : z_max_batch<T, N>();
     const size_t lds = z_lds_bytes<T, N>(CAP);
     allow_lds(k_c2r_z<T, N, EPI, CAP, PREC>, lds);
-    hipLaunchKernelGGL((k_c2r_z<T, N, EPI, CAP, PREC>), dim3(z_grid<N>()), dim3(kThreads), lds, stream, sp, bin_stride,
+    const int grid = resident_grid(ctx, k_c2r_z<T, N, EPI, CAP, PREC>, kThreads, lds, N * N / zrows<N>::R);
+    hipLaunchKernelGGL((k_c2r_z<T, N, EPI, CAP, PREC>), dim3(grid), dim3(kThreads), lds, stream, sp, bin_stride,
                        nb, delta, out, ws, part, tw);
+    return grid;
+}
+
+template <int N, int EPI, int W, int PREC>
+static int launch_zr(hermes_ctx ctx, const float2* sp, int64_t bin_stride, int nb, const float* delta, float* out,
+                     const WinSet& ws, double* part, const float2* tw, hipStream_t stream) {
+    constexpr size_t lds = zreg_lds_bytes<N, W>();
+    allow_lds(k_c2r_zr<N, EPI, W, PREC>, lds);
+    const int grid = resident_grid(ctx, k_c2r_zr<N, EPI, W, PREC>, W * 64, lds, N * N / zrows<N>::R);
+    hipLaunchKernelGGL((k_c2r_zr<N, EPI, W, PREC>), dim3(grid), dim3(W * 64), lds, stream, sp, bin_stride, nb, delta,
+                       out, ws, part, tw);
+    return grid;
+}
+
+// The register-form z pass for float at N = 256, 512: wavefronts for nb
+// windows (nb R lines, 64 / P lines per wavefront) from a small set.
+template <int N, int EPI, int PREC>
+static int launch_zr_nb(hermes_ctx ctx, const float2* sp, int64_t bin_stride, int nb, const float* delta, float* out,
+                        const WinSet& ws, double* part, const float2* tw, hipStream_t stream) {
+    using G = zreg_cfg<N>;
+    const int lines = nb * G::R;
+    if (lines <= 2 * G::LPW) return launch_zr<N, EPI, 2, PREC>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+    if (lines <= 3 * G::LPW) return launch_zr<N, EPI, 3, PREC>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+    if (lines <= 5 * G::LPW) return launch_zr<N, EPI, 5, PREC>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+    return launch_zr<N, EPI, 8, PREC>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
 }
 
 // Pass X over nb windows for one angular factor (m), or for two (m, m2) of
@@ -888,10 +1285,11 @@ static void run_x(hermes_ctx ctx, const void* delta_k, double box_L, const WinSe
     }
 }
 
-// Passes Y and Z over the nb windows of one batch spectrum.
+// Passes Y and Z over the nb windows of one batch spectrum; returns the
+// number of z-pass workgroups (rows of partial sums written to part).
 template <typename T, int N, int EPI>
-static void run_yz(hermes_ctx ctx, const T* delta, const WinSet& ws, void* spec_ws, double* part, T* out,
-                   int precision, hipStream_t stream) {
+static int run_yz(hermes_ctx ctx, const T* delta, const WinSet& ws, void* spec_ws, double* part, T* out,
+                  int precision, hipStream_t stream) {
     using C = typename cplx_of<T>::type;
     const C* tw = tw_ptr<T>(ctx->t);
     const int nb = ws.n;
@@ -903,34 +1301,42 @@ static void run_yz(hermes_ctx ctx, const T* delta, const WinSet& ws, void* spec_
         hipLaunchKernelGGL((k_inv_y_pack<T, N>), dim3(YC::TILES, nb * N), dim3(YC::NT), 0, stream, sp,
                            plane_stride<N>(), tw);
     }
-    {
-        LaunchScope ls(ctx, stream, EPI == EPI_CONTRACT ? "inv_z_contract" : "inv_z_moments");
+    LaunchScope ls(ctx, stream, EPI == EPI_CONTRACT ? "inv_z_contract" : "inv_z_moments");
+    if constexpr (std::is_same<T, float>::value && zreg_ok<N>()) {
+        if constexpr (EPI == EPI_CONTRACT) {
+            if (precision == HERMES_PREC_BF16X3)
+                return launch_zr_nb<N, EPI, HERMES_PREC_BF16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+            if (precision == HERMES_PREC_FP16X3)
+                return launch_zr_nb<N, EPI, HERMES_PREC_FP16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+        }
+        return launch_zr_nb<N, EPI, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+    } else {
         if constexpr (EPI == EPI_CONTRACT) {
             // register capacity: 20 bins (the common case) or the full batch
             const bool small = nb <= 20;
             if (precision == HERMES_PREC_BF16X3) {
-                if (small) launch_z<T, N, EPI, 20, HERMES_PREC_BF16X3>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-                else launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_BF16X3>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+                if (small) return launch_z<T, N, EPI, 20, HERMES_PREC_BF16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+                return launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_BF16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
             } else if (precision == HERMES_PREC_FP16X3) {
-                if (small) launch_z<T, N, EPI, 20, HERMES_PREC_FP16X3>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-                else launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_FP16X3>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+                if (small) return launch_z<T, N, EPI, 20, HERMES_PREC_FP16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+                return launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_FP16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
             } else {
-                if (small) launch_z<T, N, EPI, 20, HERMES_PREC_FP32>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-                else launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_FP32>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+                if (small) return launch_z<T, N, EPI, 20, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+                return launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
             }
         } else {
-            launch_z<T, N, EPI, kFilterChunk, HERMES_PREC_FP32>(sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+            return launch_z<T, N, EPI, kFilterChunk, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
         }
     }
 }
 
 // One batch: pass X, Y, Z over nb windows sharing the angular factor.
 template <typename T, int N, int EPI>
-static void run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, double box_L, const WinSet& ws, int sh,
-                      int ell, int m, bool build_table, void* spec_ws, T* rtab, T* ucol, double* part, T* out,
-                      int precision, hipStream_t stream) {
+static int run_batch(hermes_ctx ctx, const void* delta_k, const T* delta, double box_L, const WinSet& ws, int sh,
+                     int ell, int m, bool build_table, void* spec_ws, T* rtab, T* ucol, double* part, T* out,
+                     int precision, hipStream_t stream) {
     run_x<T, N>(ctx, delta_k, box_L, ws, sh, ell, m, m, false, build_table, spec_ws, spec_ws, rtab, ucol, stream);
-    run_yz<T, N, EPI>(ctx, delta, ws, spec_ws, part, out, precision, stream);
+    return run_yz<T, N, EPI>(ctx, delta, ws, spec_ws, part, out, precision, stream);
 }
 
 // ---------------------------------------------------------------- filter_bins
@@ -973,7 +1379,6 @@ static hermes_status filter_n(hermes_ctx ctx, const void* delta_k, double box_L,
         return ka.m < kb.m;
     });
     const double inv_nc = 1.0 / (double(N) * N * N);
-    const int grid = z_grid<N>();
     size_t i = 0;
     while (i < order.size()) {
         const Key k0 = key(order[i]);
@@ -991,8 +1396,9 @@ static hermes_status filter_n(hermes_ctx ctx, const void* delta_k, double box_L,
             ++ws.n;
             ++i;
         }
-        run_batch<T, N, EPI_MOMENTS>(ctx, delta_k, nullptr, box_L, ws, k0.sh, k0.ell, k0.m, true, spec, rtab,
-                                     ucol, moments ? part : nullptr, static_cast<T*>(out), HERMES_PREC_FP32, stream);
+        const int grid = run_batch<T, N, EPI_MOMENTS>(ctx, delta_k, nullptr, box_L, ws, k0.sh, k0.ell, k0.m, true,
+                                                      spec, rtab, ucol, moments ? part : nullptr,
+                                                      static_cast<T*>(out), HERMES_PREC_FP32, stream);
         if (moments) {
             LaunchScope ls(ctx, stream, "reduce");
             hipLaunchKernelGGL(k_reduce_moments, dim3(ws.n * 3), dim3(kThreads), 0, stream, part, grid, ws, inv_nc,
@@ -1058,7 +1464,6 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
     float* ucol = reinterpret_cast<float*>(tail);
     tail += align256(col_table_bytes(N, nb, sizeof(float)));
     double* part = reinterpret_cast<double*>(tail);
-    const int grid = z_grid<N>();
     const double scale = 1.0 / (4.0 * M_PI * double(N) * N * N);
     {
         LaunchScope ls(ctx, stream, "fill");
@@ -1079,7 +1484,8 @@ static hermes_status zeta_n(hermes_ctx ctx, const float* delta, const void* delt
             run_x<float, N>(ctx, delta_k, box_L, ws, 1, ell, m, m + 1, pair, m == -ell, spec, spec2, rtab, ucol,
                             stream);
             for (int k = 0; k < (pair ? 2 : 1); ++k) {
-                run_yz<float, N, EPI_CONTRACT>(ctx, delta, ws, k ? spec2 : spec, part, nullptr, precision, stream);
+                const int grid =
+                    run_yz<float, N, EPI_CONTRACT>(ctx, delta, ws, k ? spec2 : spec, part, nullptr, precision, stream);
                 LaunchScope ls(ctx, stream, "reduce");
                 hipLaunchKernelGGL(k_reduce_part, dim3(nb * nb), dim3(kThreads), 0, stream, part, grid, nb * nb,
                                    scale, zeta + int64_t(ell) * nb * nb, 1);

@@ -34,6 +34,14 @@ class HermesError(RuntimeError):
         self.status = status
 
 
+class _Mark(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("exponent", ctypes.c_double),
+                ("offset", ctypes.c_double), ("self_term", ctypes.c_double)]
+
+
+MARK = {"none": 0, "power_law": 1, "inverse_density": 2}
+
+
 class _Window(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("ell", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("r_lo", ctypes.c_double), ("r_hi", ctypes.c_double)]
@@ -50,16 +58,17 @@ def _load() -> ctypes.CDLL:
     lib.hermes_destroy.restype = None
     lib.hermes_last_error.restype = ctypes.c_char_p
     lib.hermes_workspace_size.argtypes = [vp, i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
-    lib.hermes_assign.argtypes = [vp, vp, vp, i64, f64, i32, i32, vp, vp, vp]
+    lib.hermes_assign.argtypes = [vp, vp, vp, i64, f64, i32, i32, vp, vp, vp, sz, vp]
     lib.hermes_fft.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
     lib.hermes_xi.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, vp, sz, vp]
     lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
     lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
+    lib.hermes_readout.argtypes = [vp, vp, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp, vp]
     lib.hermes_profile_enable.argtypes = [vp, i32]
     lib.hermes_profile_reset.argtypes = [vp]
     lib.hermes_profile_read.argtypes = [vp, i32, ctypes.c_char_p, sz, ctypes.POINTER(i64), ctypes.POINTER(f64)]
     for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi",
-                 "hermes_filter_bins", "hermes_zeta_l", "hermes_profile_enable", "hermes_profile_reset",
+                 "hermes_filter_bins", "hermes_zeta_l", "hermes_readout", "hermes_profile_enable", "hermes_profile_reset",
                  "hermes_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
@@ -145,7 +154,7 @@ def _workspace(nbytes: int, device: int, work: torch.Tensor | None) -> torch.Ten
 
 def assign(pos: torch.Tensor, weight: torch.Tensor | None, box_L: float, n_grid: int,
            dtype=torch.float32, eps: torch.Tensor | None = None, sum_w: torch.Tensor | None = None,
-           stream=None):
+           work: torch.Tensor | None = None, stream=None):
     """B3 projection of a catalogue: returns (eps [N,N,N], sum_w [1] float64)."""
     dev = _dev(pos)
     if pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3 or not pos.is_contiguous():
@@ -153,13 +162,16 @@ def assign(pos: torch.Tensor, weight: torch.Tensor | None, box_L: float, n_grid:
     if weight is not None and (weight.dtype != torch.float32 or weight.numel() != pos.shape[0]
                                or not weight.is_contiguous() or _dev(weight) != dev):
         raise ValueError("weight must be a contiguous float32 [n] tensor on the same device")
+    wbytes = workspace_size(OP_ASSIGN, n_grid, dtype, int(pos.shape[0]), 1, dev)
     with _on(stream):
+        w = _workspace(wbytes, dev, work)
         if eps is None:
             eps = torch.empty((n_grid, n_grid, n_grid), dtype=dtype, device=pos.device)
         if sum_w is None:
             sum_w = torch.empty(1, dtype=torch.float64, device=pos.device)
         _check(_lib.hermes_assign(context(dev), _ptr(pos), _ptr(weight), pos.shape[0], float(box_L), n_grid,
-                                  _dtype_code(eps.dtype), _ptr(eps), _ptr(sum_w), _stream(dev, stream)))
+                                  _dtype_code(eps.dtype), _ptr(eps), _ptr(sum_w), _ptr(w), wbytes,
+                                  _stream(dev, stream)))
     return eps, sum_w
 
 
@@ -254,6 +266,33 @@ def zeta_l(delta: torch.Tensor, delta_k: torch.Tensor, box_L: float, edges, l_ma
                                   e.ctypes.data_as(ctypes.c_void_p), nb, l_max, PREC[precision], _ptr(out), _ptr(w),
                                   wbytes, _stream(dev, stream)))
     return out
+
+
+def readout(field: torch.Tensor, box_L: float, pos: torch.Tensor, weight: torch.Tensor | None = None,
+            mark: tuple | None = None, want_values: bool = True, moments: bool = False,
+            out: torch.Tensor | None = None, stream=None):
+    """Values of a coefficient field at arbitrary positions, optionally turned
+    into marks and weighted.  mark = (kind, exponent, offset[, self_term]) with
+    kind in MARK.  Returns (values [n_pts] or None, moments [3] float64 or None)."""
+    dev = _dev(field)
+    n = field.shape[0]
+    if pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3 or not pos.is_contiguous():
+        raise ValueError("pos must be a contiguous float32 [n, 3] device tensor")
+    if weight is not None and (weight.dtype != torch.float32 or weight.numel() != pos.shape[0]
+                               or not weight.is_contiguous()):
+        raise ValueError("weight must be a contiguous float32 [n] tensor")
+    mk = None
+    if mark is not None:
+        st = float(mark[3]) if len(mark) > 3 else 0.0
+        mk = _Mark(MARK[mark[0]], 0, float(mark[1]), float(mark[2]), st)
+    with _on(stream):
+        if want_values and out is None:
+            out = torch.empty(pos.shape[0], dtype=field.dtype, device=field.device)
+        mom = torch.empty(3, dtype=torch.float64, device=field.device) if moments else None
+        _check(_lib.hermes_readout(context(dev), _ptr(field), n, _dtype_code(field.dtype), float(box_L), _ptr(pos),
+                                   _ptr(weight), pos.shape[0], ctypes.byref(mk) if mk is not None else None,
+                                   _ptr(out) if want_values else None, _ptr(mom), _stream(dev, stream)))
+    return (out if want_values else None), mom
 
 
 # ----------------------------------------------------------------------------

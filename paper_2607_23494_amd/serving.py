@@ -6,8 +6,11 @@ grid size and a set of statistics (2PCF, 2PCF multipoles, 3PCF multipoles,
 counts-in-cells moments) with a contraction precision.  The loop
 
   * admits a waiting request as soon as a worker slot is free and the
-    request's device-memory model fits the HBM budget that is left (first
-    come, first served; a request larger than the whole budget is rejected);
+    request's device-memory model fits the HBM budget that is left, in
+    arrival order with backfilling: a later request that fits may pass a head
+    that does not, until the head has waited longer than an age bound, after
+    which nothing passes it (a request larger than the whole budget is
+    rejected);
   * runs it on the slot's own HIP stream: assignment and FFT once, then every
     requested statistic on the resident contrast spectrum, so requests on
     different slots overlap on the device;
@@ -75,12 +78,14 @@ def field_bytes(n_grid: int) -> int:
 
 def request_bytes(req: Request, ws_fn: Callable[[str, int, dict], int]) -> int:
     """Device bytes a request holds while it runs: its catalogue, the
-    assignment grid, the resident field, the largest statistic workspace
-    (statistics run one after another on the request's stream) and outputs.
-    ws_fn(kind, n_grid, params) returns a statistic's workspace bytes."""
+    assignment grid, the resident field, the largest workspace (assignment
+    and statistics run one after another on the request's stream) and
+    outputs.  ws_fn(kind, n_grid, params) returns the workspace bytes of the
+    assignment (kind "assign", params {"n_pts"}) or of a statistic."""
     n = req.n_grid
     cat = req.pos.shape[0] * 12 + (req.pos.shape[0] * 4 if req.weight is not None else 0)
-    work = max([ws_fn(k, n, p) for k, p in req.stats.items()] + [0])
+    # the assignment's workspace and the statistics' are used one after another
+    work = max([ws_fn(k, n, p) for k, p in req.stats.items()] + [ws_fn("assign", n, {"n_pts": req.pos.shape[0]})])
     outputs = 0
     for k, p in req.stats.items():
         if k == "cic":
@@ -94,8 +99,25 @@ def request_bytes(req: Request, ws_fn: Callable[[str, int, dict], int]) -> int:
     return cat + n ** 3 * 4 + field_bytes(n) + work + outputs
 
 
+def pick_next(waiting_sizes: list[int], head_wait: float, adm: "Admission", bypass_age: float):
+    """Index of the next waiting request to admit, or None.  The queue is in
+    arrival order; the head goes first if it fits, otherwise the first later
+    request that fits passes it, unless the head has already waited longer
+    than bypass_age (then the queue waits for the head)."""
+    if not waiting_sizes:
+        return None
+    if adm.fits(waiting_sizes[0]):
+        return 0
+    if head_wait > bypass_age:
+        return None
+    for i in range(1, len(waiting_sizes)):
+        if adm.fits(waiting_sizes[i]):
+            return i
+    return None
+
+
 class Admission:
-    """Slot and HBM-budget bookkeeping; first come, first served."""
+    """Slot and HBM-budget bookkeeping."""
 
     def __init__(self, budget_bytes: int, slots: int):
         if budget_bytes <= 0 or slots <= 0:
@@ -125,20 +147,25 @@ class Admission:
 
 
 def schedule(arrivals: list[tuple[float, int]], service: dict[int, float], sizes: dict[int, int],
-             adm: Admission) -> dict[int, tuple[float, float]]:
+             adm: Admission, bypass_age: float = 0.0) -> dict[int, tuple[float, float]]:
     """Discrete-event simulation of the admission policy with given service
-    times (host only; used to test the policy).  Returns rid -> (admit, finish)
-    for admitted requests; oversized ones are absent."""
-    waiting = collections.deque()
+    times (host only; used to test the policy).  bypass_age = 0 is strict
+    first come, first served.  Returns rid -> (admit, finish) for admitted
+    requests; oversized ones are absent."""
+    waiting = []
     running = []          # (finish, rid)
     out = {}
+    arrived = {}
     events = sorted(arrivals)
     i = 0
     now = 0.0
     while i < len(events) or waiting or running:
-        # admit as much of the queue head as fits
-        while waiting and adm.fits(sizes[waiting[0]]):
-            rid = waiting.popleft()
+        while True:
+            head_wait = now - arrived[waiting[0]] if waiting else 0.0
+            j = pick_next([sizes[r] for r in waiting], head_wait, adm, bypass_age)
+            if j is None:
+                break
+            rid = waiting.pop(j)
             adm.admit(sizes[rid])
             running.append((now + service[rid], rid))
             out[rid] = (now, now + service[rid])
@@ -152,6 +179,7 @@ def schedule(arrivals: list[tuple[float, int]], service: dict[int, float], sizes
             i += 1
             if not adm.oversized(sizes[rid]):
                 waiting.append(rid)
+                arrived[rid] = now
         else:
             now = t_fin
             running.sort()
@@ -169,6 +197,8 @@ def _workspace_fn(device: int):
     import torch
 
     def ws(kind, n, p):
+        if kind == "assign":
+            return hermes.workspace_size(hermes.OP_ASSIGN, n, torch.float32, int(p["n_pts"]), 1, device)
         if kind in ("xi", "xi_ell"):
             nb = len(p["edges"]) - 1
             return hermes.workspace_size(hermes.OP_XI, n, torch.float32, nb, len(p.get("ells", (0,))), device)
@@ -230,9 +260,10 @@ class Server:
     slot owns one HIP stream at the default priority."""
 
     def __init__(self, device: int = 0, budget_bytes: int = 200 << 30, slots: int = 4,
-                 cache_bytes: int = 0):
+                 cache_bytes: int = 0, bypass_age: float = 1.0):
         import torch
         self.device = device
+        self.bypass_age = float(bypass_age)
         self.adm = Admission(budget_bytes, slots)
         self.ws_fn = _workspace_fn(device)
         self.cache = FieldCache(cache_bytes)
@@ -313,8 +344,14 @@ class Server:
                         results[req.rid] = res
                         continue
                     waiting.append((req, res))
-                while waiting and self.adm.fits(waiting[0][1].nbytes):
-                    req, res = waiting.popleft()
+                while True:
+                    now = time.perf_counter() - t0
+                    head_wait = now - waiting[0][0].arrival if waiting else 0.0
+                    j = pick_next([x[1].nbytes for x in waiting], head_wait, self.adm, self.bypass_age)
+                    if j is None:
+                        break
+                    req, res = waiting[j]
+                    del waiting[j]
                     self.adm.admit(res.nbytes)
                     res.admit = time.perf_counter() - t0
                     outstanding += 1

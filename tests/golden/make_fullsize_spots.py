@@ -12,11 +12,11 @@ never involved.  Each target writes one JSON file beside this script:
           (L = 2000): the marked 2PCF (mark-weighted field) in bins
           {0, 13, 26, 39} of 40 bins over [2, 200], and counts-in-cells
           moments <delta_W^p>, p = 2, 3, 4 of the number field for the sphere
-          and Gaussian windows at R = 4, 13.1 and 32 (radii 0, 4 and 7 of the
-          geometric set).
+          and Gaussian windows at R = 4 and 32 (the ends of the geometric set).
 
 Usage: python tests/golden/make_fullsize_spots.py ns512|ns1024 [out_dir]
-The 1024^3 target holds about 60 GB of host memory at its peak.
+The 1024^3 target holds about 60 GB of host memory at its peak; it writes its
+file after every window and, when run again, computes only what is missing.
 """
 import json
 import os
@@ -37,7 +37,7 @@ NS512_ELLS = (0, 1, 2, 5, 10)
 NS512_ZBINS = (0, 9, 19)
 XI_BINS = (0, 13, 26, 39)
 NS1024_SUBSET = 1_000_000
-NS1024_RADII_IDX = (0, 4, 7)
+NS1024_RADII_IDX = (0, 7)
 
 
 def log(msg):
@@ -74,43 +74,57 @@ def ns512(out_dir):
 
 def ns1024(out_dir):
     wl = synth.WORKLOADS["ns1024_cic"]
+    path = os.path.join(out_dir, "ns1024_subset_spots.json")
+    out = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            out = json.load(f)
+
+    def save():
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+
     pos, w = wl.catalogue()
     pos, w = pos[:NS1024_SUBSET].copy(), w[:NS1024_SUBSET].copy()
     log(f"subset {pos.shape[0]} points")
     n, L = wl.n_grid, wl.box_L
     e2 = synth.EDGES["ns1024_cic"]
-    # marked 2PCF on the mark-weighted field
-    eps, sw = O.assign(pos, w, L, n)
-    delta = O.contrast(eps, sw)
-    del eps
-    dh = O.dft3(delta)
-    del delta
-    log("marked spectrum done")
-    xi_m = [float(O.xi_multipoles(dh, L, [e2[b], e2[b + 1]])[0, 0]) for b in XI_BINS]
-    del dh
-    log("marked 2PCF spot bins done")
-    # counts in cells on the number field
-    eps, sw = O.assign(pos, None, L, n)
-    delta = O.contrast(eps, sw)
-    del eps
-    dh = O.dft3(delta)
-    del delta
-    log("number spectrum done")
-    radii = [float(synth.CIC_RADII[i]) for i in NS1024_RADII_IDX]
-    wins = [("sphere", R) for R in radii] + [("gauss", R) for R in radii]
-    mom = []
-    for win in wins:
-        mom.append(O.cic_moments(dh, L, [win])[0].tolist())
-        log(f"cic {win} done")
-    out = {
+    out.update({
         "workload": "ns1024_cic subset: first 1e6 points of the 1e8-point marked catalogue, 1024^3, L = 2000",
         "source": "oracle/hermes_oracle.py (assign, contrast, dft3, xi_multipoles, cic_moments)",
-        "n_points": int(pos.shape[0]),
-        "xi_edges": e2.tolist(), "xi_bins": list(XI_BINS), "xi_marked": xi_m,
-        "cic_windows": [[k, R] for k, R in wins], "cic_moments": mom,
-    }
-    with open(os.path.join(out_dir, "ns1024_subset_spots.json"), "w") as f:
-        json.dump(out, f, indent=1)
+        "n_points": int(pos.shape[0]), "xi_edges": e2.tolist(), "xi_bins": list(XI_BINS),
+    })
+    if "xi_marked" not in out:
+        # marked 2PCF on the mark-weighted field
+        eps, sw = O.assign(pos, w, L, n)
+        delta = O.contrast(eps, sw)
+        del eps
+        dh = O.dft3(delta)
+        del delta
+        log("marked spectrum done")
+        out["xi_marked"] = [float(O.xi_multipoles(dh, L, [e2[b], e2[b + 1]])[0, 0]) for b in XI_BINS]
+        del dh
+        save()
+        log("marked 2PCF spot bins done")
+    radii = [float(synth.CIC_RADII[i]) for i in NS1024_RADII_IDX]
+    wins = [["sphere", R] for R in radii] + [["gauss", R] for R in radii]
+    done = {(k, R): m for (k, R), m in zip(out.get("cic_windows", []), out.get("cic_moments", []))}
+    todo = [x for x in wins if (x[0], x[1]) not in done]
+    if todo:
+        # counts in cells on the number field
+        eps, sw = O.assign(pos, None, L, n)
+        delta = O.contrast(eps, sw)
+        del eps
+        dh = O.dft3(delta)
+        del delta
+        log("number spectrum done")
+        for kind, R in todo:
+            done[(kind, R)] = O.cic_moments(dh, L, [(kind, R)])[0].tolist()
+            out["cic_windows"] = [list(k) for k in done]
+            out["cic_moments"] = list(done.values())
+            save()
+            log(f"cic {kind} {R} done")
+    save()
 
 
 if __name__ == "__main__":

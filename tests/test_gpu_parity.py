@@ -58,6 +58,26 @@ def test_assign(hermes, dtype, n):
     assert abs(sw.item() - osw) < 1e-12 * osw
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_assign_bitwise_reproducible_and_order_free(hermes, dtype):
+    """The taps are summed in 64-bit fixed point: repeated calls give the same
+    grid bit for bit, and so does any permutation of the catalogue (sum_w is
+    summed in a fixed order: equal across calls, equal to rounding under a
+    permutation)."""
+    for n, (pos, w, L) in [(64, (*_cat(200, 40, 2.0, 150.0, 1500, marks=True), 150.0)),
+                           (512, (*synth.WORKLOADS["ns512_3pcf"].catalogue(), 1000.0))]:
+        tp, tw = torch.from_numpy(pos).cuda(), torch.from_numpy(w).cuda()
+        e1, s1 = hermes.assign(tp, tw, L, n, dtype=dtype)
+        e2, s2 = hermes.assign(tp, tw, L, n, dtype=dtype)
+        assert torch.equal(e1, e2) and torch.equal(s1, s2), n
+        perm = torch.from_numpy(np.random.default_rng(n).permutation(pos.shape[0])).cuda()
+        e3, s3 = hermes.assign(tp[perm].contiguous(), tw[perm].contiguous(), L, n, dtype=dtype)
+        assert torch.equal(e1, e3), n
+        assert abs(s3.item() - s1.item()) <= 1e-14 * s1.item()
+        del e1, e2, e3
+        torch.cuda.empty_cache()
+
+
 def test_assign_wraps_and_empty(hermes):
     L, n = 50.0, 16
     rng = np.random.default_rng(4)
@@ -268,3 +288,62 @@ def test_errors_are_reported(hermes):
     with pytest.raises(HermesError, match="below L/2"):
         hermes.zeta_l(delta, dk, 10.0, [1.0, 2.0, 6.0], 1)
     hermes.xi(dk, 10.0, [1.0, 4.99])
+
+
+# --------------------------------------------------------------------------
+# grids whose y pass spans several tiles per plane (128^3, 256^3): the column
+# pairs of the c2r packing meet only inside one tile, and nothing a tile
+# reads is written by another
+# --------------------------------------------------------------------------
+
+@functools.lru_cache(maxsize=None)
+def _mid_case(n):
+    L = {128: 400.0, 256: 800.0}[n]
+    pos, _ = _cat(400, 40, 3.0, L, 5400 + n)
+    _, _, od, odh = _oracle_field(pos, None, L, n)
+    edges = np.linspace(10.0, 70.0, 5)
+    lmax = 3 if n == 128 else 2
+    ref = O.zeta_multipoles(od, odh, L, edges, ells=tuple(range(lmax + 1)))
+    return pos, L, edges, lmax, ref, odh
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("n", [128, 256])
+def test_zeta_multi_tile_grids(hermes, n, precision):
+    pos, L, edges, lmax, ref, _ = _mid_case(n)
+    _, _, dk, delta = _gpu_field(hermes, pos, None, L, n, torch.float32)
+    got = hermes.zeta_l(delta, dk, L, edges, lmax, precision=precision).cpu().numpy()
+    for ell in range(lmax + 1):
+        assert normwise(got[ell], ref[ell]) < ZETA_TOL[precision], (n, precision, ell)
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_filter_fields_multi_tile_grids(hermes, n):
+    pos, L, _, _, _, odh = _mid_case(n)
+    _, _, dk, _ = _gpu_field(hermes, pos, None, L, n, torch.float32)
+    wins = [("sphere", 0.0, 12.0), ("shell", 20.0, 28.0), ("sh_shell", 15.0, 25.0, 2, -1)]
+    fields, mom = hermes.filter_bins(dk, L, wins, store_fields=True)
+    fields = fields.cpu().numpy()
+    refs = [O.filtered_field(odh, L, lambda kq: O.w_sphere(kq * 12.0)),
+            O.filtered_field(odh, L, lambda kq: O.w_shell(kq, 20.0, 28.0)),
+            O.multipole_field(odh, L, 2, -1, 15.0, 25.0)[0]]
+    for i, ref in enumerate(refs):
+        assert normwise(fields[i], ref) < 1e-5, (n, wins[i][0])
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_zeta_is_deterministic_across_calls_and_streams(hermes, n):
+    """The contraction has no atomics: the same inputs give bitwise the same
+    result, also when four calls run at once on four streams."""
+    pos, L, edges, lmax, _, _ = _mid_case(n)
+    _, _, dk, delta = _gpu_field(hermes, pos, None, L, n, torch.float32)
+    for precision in ("fp32", "bf16x3"):
+        a = hermes.zeta_l(delta, dk, L, edges, lmax, precision=precision).cpu().numpy()
+        b = hermes.zeta_l(delta, dk, L, edges, lmax, precision=precision).cpu().numpy()
+        assert np.array_equal(a, b), precision
+        streams = [torch.cuda.Stream() for _ in range(4)]
+        torch.cuda.synchronize()
+        outs = [hermes.zeta_l(delta, dk, L, edges, lmax, precision=precision, stream=s) for s in streams]
+        torch.cuda.synchronize()
+        for o in outs:
+            assert np.array_equal(o.cpu().numpy(), a), precision
