@@ -178,6 +178,21 @@ hermes_status hermes_xi(hermes_ctx ctx, const void* delta_k, int n_grid, int dty
                         const int* ells, int n_ells, int los_axis, double* xi,
                         double* shot, void* work, size_t work_bytes, hipStream_t stream);
 
+/* hermes_xi for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same statistic, arguments and errors as hermes_xi, without a workspace.  The
+ * histogram and partial sums live in a 16 MiB scratch array that the library
+ * holds statically on every device it runs on, until the process ends;
+ * nothing is allocated.  ERR_UNSUPPORTED when the call needs more scratch than
+ * that (hermes_workspace_size(XI) > 16 MiB, e.g. two or more multipoles at
+ * 1024^3).  Each call clears what it accumulates before use, but every call on
+ * a device shares the one array: calls that overlap on a device (two streams,
+ * threads or contexts) race and must be serialised by the caller. */
+hermes_status hermes_xi_static(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype,
+                               double box_L, const double* edges, int n_bins,
+                               const int* ells, int n_ells, int los_axis, double* xi,
+                               double* shot, hipStream_t stream);
+
 /* Window-filtered fields (Sec. 4.2: eps_W = iFT[FT(eps) W^ Phi^]) and their
  * counts-in-cells moments (Sec. 3.1 filtered field, Sec. 2.2.2 Eq. varw):
  *   out_w(l) = N^-3 sum_n delta^_n Phi^(n) W^_w(k_n) exp(2 pi i n.l/N)   (real)

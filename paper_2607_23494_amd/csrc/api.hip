@@ -186,6 +186,7 @@ hermes_status hermes_create(hermes_ctx* out, int device) {
             c->cus = cus;
     }
     hermes_status st = build_tables(c);
+    if (st == HERMES_OK) st = xi_static_init(c);
     if (st != HERMES_OK) {
         hermes_destroy(c);
         return st;
@@ -340,6 +341,33 @@ hermes_status hermes_xi(hermes_ctx ctx, const void* delta_k, int n_grid, int dty
     DeviceGuard g(ctx->device);
     return xi_impl(ctx, delta_k, n_grid, dtype, box_L, e, ells, n_ells, los_axis, xi, shot, work, work_bytes,
                    stream);
+}
+
+hermes_status hermes_xi_static(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype, double box_L,
+                               const double* edges, int n_bins, const int* ells, int n_ells, int los_axis,
+                               double* xi, double* shot, hipStream_t stream) {
+    if (!ctx || !delta_k || !xi || !ells) return fail(HERMES_ERR_ARG, "hermes_xi_static: NULL argument");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_xi_static: N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_xi_static: bad dtype");
+    if (!(box_L > 0.0)) return fail(HERMES_ERR_ARG, "hermes_xi_static: box_L must be > 0");
+    if (los_axis < 0 || los_axis > 2) return fail(HERMES_ERR_ARG, "hermes_xi_static: los_axis must be 0, 1 or 2");
+    if (n_ells < 1 || n_ells > HERMES_MAX_ELLS)
+        return fail(HERMES_ERR_ARG, "hermes_xi_static: n_ells must be in [1, 8]");
+    for (int i = 0; i < n_ells; ++i)
+        if (ells[i] < 0 || ells[i] > HERMES_MAX_LMAX || (ells[i] & 1))
+            return fail(HERMES_ERR_ARG, "hermes_xi_static: multipoles must be even and in [0, 16]");
+    Edges e;
+    hermes_status st = get_edges(edges, n_bins, box_L, e, "hermes_xi_static");
+    if (st != HERMES_OK) return st;
+    const size_t need = xi_workspace(n_grid, n_ells, n_bins);
+    if (need > kXiStaticBytes)
+        return fail(HERMES_ERR_UNSUPPORTED, "hermes_xi_static: needs " + std::to_string(need) +
+                                                " bytes of scratch; the static array holds " +
+                                                std::to_string(kXiStaticBytes));
+    if (!ctx->xi_scratch) return fail(HERMES_ERR_HIP, "hermes_xi_static: static scratch not resolved");
+    DeviceGuard g(ctx->device);
+    return xi_impl(ctx, delta_k, n_grid, dtype, box_L, e, ells, n_ells, los_axis, xi, shot, ctx->xi_scratch,
+                   kXiStaticBytes, stream);
 }
 
 hermes_status hermes_filter_bins(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype,

@@ -47,6 +47,7 @@ struct hermes_ctx_s {
     int cus = 256;                // compute units of the device
     hermes::Tables t;
     hermes::Profiler prof;
+    void* xi_scratch = nullptr;   // device address of the static 2PCF scratch array on this device
 };
 
 namespace hermes {
@@ -103,6 +104,9 @@ hermes_status xi_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype, dou
                       const Edges& edges, const int* ells, int n_ells, int los_axis, double* xi,
                       double* shot, void* work, size_t work_bytes, hipStream_t stream);
 size_t xi_workspace(int n, int n_ells, int n_bins);
+// The static scratch array of the allocation-free 2PCF entry point.
+constexpr size_t kXiStaticBytes = size_t(16) << 20;
+hermes_status xi_static_init(hermes_ctx ctx);
 hermes_status filter_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype, double box_L,
                           const hermes_window* win, int n_win, void* out, double* moments,
                           void* work, size_t work_bytes, hipStream_t stream);

@@ -30,6 +30,20 @@ struct EllSet {
 
 constexpr int kXiSplit = 64;   // q-range chunks per (l, bin) in pass 2
 
+// Scratch of hermes_xi_static: one copy per device, resolved to a device
+// address once per context (hermes_create, with the context's device
+// current).  Host code uses only that address, never the array's name.
+static __device__ __align__(256) unsigned char scratch[kXiStaticBytes];
+
+hermes_status xi_static_init(hermes_ctx ctx) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(HERMES_ERR_HIP, std::string("hermes_create: static scratch: ") + hipGetErrorString(e));
+    ctx->xi_scratch = ptr;
+    return HERMES_OK;
+}
+
 // H and Hs [n_ells][nq], then the pass-2 partials of xi and of S.
 size_t xi_workspace(int n, int n_ells, int n_bins) {
     const size_t nq = size_t(qmax_of(n) + 1);

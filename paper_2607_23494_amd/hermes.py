@@ -61,13 +61,14 @@ def _load() -> ctypes.CDLL:
     lib.hermes_assign.argtypes = [vp, vp, vp, i64, f64, i32, i32, vp, vp, vp, sz, vp]
     lib.hermes_fft.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
     lib.hermes_xi.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, vp, sz, vp]
+    lib.hermes_xi_static.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, vp]
     lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
     lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
     lib.hermes_readout.argtypes = [vp, vp, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp, vp]
     lib.hermes_profile_enable.argtypes = [vp, i32]
     lib.hermes_profile_reset.argtypes = [vp]
     lib.hermes_profile_read.argtypes = [vp, i32, ctypes.c_char_p, sz, ctypes.POINTER(i64), ctypes.POINTER(f64)]
-    for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi",
+    for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi", "hermes_xi_static",
                  "hermes_filter_bins", "hermes_zeta_l", "hermes_readout", "hermes_profile_enable", "hermes_profile_reset",
                  "hermes_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
@@ -212,6 +213,29 @@ def xi(delta_k: torch.Tensor, box_L: float, edges, ells: Sequence[int] = (0,), l
                               nb, el.ctypes.data_as(ctypes.c_void_p), el.size, los_axis, _ptr(out),
                               _ptr(sh) if shot else None, _ptr(w), wbytes, _stream(dev, stream)))
     return (out, sh) if shot else out
+
+
+def xi_static(delta_k: torch.Tensor, box_L: float, edges, ells: Sequence[int] = (0,), los_axis: int = 2,
+              out: torch.Tensor | None = None, shot_out: torch.Tensor | None = None, stream=None,
+              shot: bool = False):
+    """hermes_xi_static: as xi() with the library's static scratch instead of a
+    workspace (the library allocates nothing; pass `out` (and `shot_out`) to
+    allocate nothing here either)."""
+    dev = _dev(delta_k)
+    n = delta_k.shape[0]
+    e = _edges_arr(edges)
+    el = np.ascontiguousarray(np.asarray(list(ells), dtype=np.int32))
+    nb = e.size - 1
+    with _on(stream):
+        if out is None:
+            out = torch.empty((el.size, nb), dtype=torch.float64, device=delta_k.device)
+        if shot and shot_out is None:
+            shot_out = torch.empty((el.size, nb), dtype=torch.float64, device=delta_k.device)
+        _check(_lib.hermes_xi_static(context(dev), _ptr(delta_k), n, _dtype_code(delta_k.dtype), float(box_L),
+                                     e.ctypes.data_as(ctypes.c_void_p), nb, el.ctypes.data_as(ctypes.c_void_p),
+                                     el.size, los_axis, _ptr(out), _ptr(shot_out) if shot else None,
+                                     _stream(dev, stream)))
+    return (out, shot_out) if shot else out
 
 
 def make_windows(specs: Iterable) -> ctypes.Array:
