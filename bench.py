@@ -270,6 +270,21 @@ def other_configs(warmup: int, steps: int) -> dict:
     record("ns256_rsd", step256, n ** 3 * ((e40.size - 1) + 3 * (e30.size - 1)),
            "2e6 Neyman-Scott points with z displacements, 256^3, float32: assign, FFT, 40-bin 2PCF, "
            "xi_0,2,4 over 30 bins")
+
+    # the same catalogue: DD(s, mu) with thin ring windows, 46 s x 51 mu
+    rings = synth.smu_rings()
+    xawork = torch.empty(hermes.workspace_size(hermes.OP_XI_ANISO, n, torch.float32, len(rings), 0),
+                         dtype=torch.uint8, device="cuda")
+
+    def step_smu():
+        eps, sw = hermes.assign(pos, None, wl.box_L, n)
+        dk, _ = hermes.fft(eps, sw, want_delta=False)
+        hermes.xi_aniso(dk, wl.box_L, rings, work=xawork)
+    record("ns256_smu", step_smu, n ** 3 * len(rings),
+           "2e6 Neyman-Scott points with z displacements, 256^3, float32: assign, FFT, DD(s, mu) with thin ring "
+           "windows at 46 x 51 (s, mu) bin centres (s in [2, 186], mu in [0, 1])")
+    out["ns256_smu"]["ms_per_window"] = round(out["ns256_smu"]["ms_per_step"] / len(rings), 6)
+    del xawork
     del pos
     torch.cuda.empty_cache()
 

@@ -8,6 +8,8 @@
  *   -> 2PCF and its Legendre multipoles by Parseval  (hermes_xi)
  *   -> window-filtered fields, counts-in-cells moments (hermes_filter_bins)
  *   -> 3PCF multipoles zeta_l(r1, r2)                 (hermes_zeta_l)
+ *   -> anisotropic 2PCF with axisymmetric windows     (hermes_xi_aniso)
+ *   -> field values and density marks at positions    (hermes_readout)
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -90,7 +92,8 @@ typedef enum hermes_op {
     HERMES_OP_FFT = 1,
     HERMES_OP_XI = 2,
     HERMES_OP_FILTER = 3,
-    HERMES_OP_ZETA = 4
+    HERMES_OP_ZETA = 4,
+    HERMES_OP_XI_ANISO = 5
 } hermes_op;
 
 typedef struct hermes_ctx_s* hermes_ctx;
@@ -98,9 +101,10 @@ typedef struct hermes_ctx_s* hermes_ctx;
 #define HERMES_MAX_BINS 64   /* bins per hermes_xi / hermes_zeta_l call */
 #define HERMES_MAX_ELLS 8    /* multipoles per hermes_xi call */
 #define HERMES_MAX_LMAX 16   /* highest 3PCF multipole */
+#define HERMES_MAX_ANISO (1 << 20)   /* windows per hermes_xi_aniso call */
 
 /* Create a context on HIP device `device`; fills *out.  Allocates the
- * context's constant tables (about 0.2 MB) on that device. */
+ * context's constant tables (about 2.6 MB) on that device. */
 hermes_status hermes_create(hermes_ctx* out, int device);
 
 /* Release a context (NULL is ignored).  Not to be called while work that
@@ -111,7 +115,7 @@ void hermes_destroy(hermes_ctx ctx);
 const char* hermes_last_error(void);
 
 /* Device workspace, in bytes, that `op` needs for an N^3 grid.  n_batch is
- * the number of points (ASSIGN), windows (FILTER) or radial bins (ZETA);
+ * the number of points (ASSIGN), windows (FILTER, XI_ANISO) or radial bins (ZETA);
  * n_ells the number of multipoles (XI).  Zero for FFT, which needs none. */
 hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtype,
                                     int n_batch, int n_ells, size_t* bytes);
@@ -224,6 +228,64 @@ hermes_status hermes_zeta_l(hermes_ctx ctx, const float* delta, const void* delt
                             int n_grid, double box_L, const double* edges, int n_bins,
                             int l_max, int precision, double* zeta, void* work,
                             size_t work_bytes, hipStream_t stream);
+
+/* Axisymmetric windows about the line of sight (Sec. 2.2.3 redshift space:
+ * circular ring; Table A1 (d), (f)-(i)).  With k_par the line-of-sight
+ * component of k, k_perp = |k - k_par e_los|, R = r_perp, H = r_par:
+ *   RING         cos(k_par H) J0(k_perp R)                  (thin double ring; A1 (i))
+ *   RING_BIN     sinc(k_par dH / 2) cos(k_par H) <J0(k_perp rho)>, the average
+ *                over the annulus rho in [R - dR/2, R + dR/2] with weight
+ *                rho / (R dR)                               (finite bins, dR = d_perp,
+ *                                                           dH = d_par)
+ *   GAUSS_RING   cos(k_par H) J0(k_perp R) exp(-k_perp^2 s^2 / 2), s = d_perp
+ *                                                           (Gaussian-blurred ring)
+ *   DISK         2 J1(k_perp R) / (k_perp R) cos(k_par H)   (pair of disks; A1 (h))
+ *   CYLINDER     2 J1(k_perp R) / (k_perp R) sinc(k_par H)  (filled, half-height H; A1 (f))
+ *   CYLSHELL     J0(k_perp R) sinc(k_par H)                 (side wall; A1 (g))
+ *   GAUSS_SHELL  (Rg^2 cos(k Rs) + Rs^2 sinc(k Rs)) / (Rs^2 + Rg^2) exp(-k^2 Rg^2 / 2),
+ *                Rs = r_perp, Rg = d_perp, k = |k|        (isotropic; A1 (d))
+ * with sinc x = sin x / x.  Unused parameters are ignored (must still be
+ * finite and >= 0). */
+typedef enum hermes_aniso_kind {
+    HERMES_ANISO_RING = 0,
+    HERMES_ANISO_RING_BIN = 1,
+    HERMES_ANISO_GAUSS_RING = 2,
+    HERMES_ANISO_DISK = 3,
+    HERMES_ANISO_CYLINDER = 4,
+    HERMES_ANISO_CYLSHELL = 5,
+    HERMES_ANISO_GAUSS_SHELL = 6
+} hermes_aniso_kind;
+
+typedef struct hermes_aniso_window {
+    int32_t kind;
+    int32_t reserved;   /* must be 0 */
+    double r_perp;
+    double r_par;
+    double d_perp;
+    double d_par;
+} hermes_aniso_window;
+
+/* Anisotropic 2PCF with axisymmetric windows, by Parseval (Sec. 2.2.3
+ * xi(r_par, r_perp) as the field-window product; Sec. 3.3.1):
+ *   xi[w] = N^-6 sum_n |delta^_n|^2 Phi^(n) W^_w(k_par, k_perp),
+ * Phi^ as in hermes_xi, plane-parallel line of sight along los_axis.  Raw
+ * estimator (no shot-noise subtraction).  The sum is regrouped exactly over
+ * (|n_los|, |n_perp|^2); the grouping's float64 atomics make the last bits
+ * depend on the order of additions.
+ *   delta_k  device half spectrum from hermes_fft
+ *   win      host array of n_win windows, read before the call returns
+ *   xi       device double [n_win]; overwritten
+ *   work     device workspace of >= hermes_workspace_size(XI_ANISO, n_batch =
+ *            n_win) bytes
+ * ERR_ARG for NULL buffers, a bad N, dtype, box_L or los_axis, n_win outside
+ * [1, HERMES_MAX_ANISO], a non-zero reserved field, an unknown kind, a
+ * non-finite or negative parameter, r_perp or r_par >= L/2, RING_BIN with
+ * d_perp <= 0 or r_perp < d_perp / 2, GAUSS_SHELL with r_perp = d_perp = 0;
+ * ERR_OOM if work_bytes is too small. */
+hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype,
+                              double box_L, const hermes_aniso_window* win, int n_win,
+                              int los_axis, double* xi, void* work, size_t work_bytes,
+                              hipStream_t stream);
 
 /* Density-derived marks (Sec. 3.3.1).  With v the value read at a point
  * (hermes_readout) and rho = max(1 + v - self_term, 0) the local density in

@@ -119,6 +119,23 @@ static hermes_status build_tables(hermes_ctx c) {
         gl[i] = gx[i];
         gl[16 + i] = gw[i];
     }
+    // sums of two squares a^2 + b^2 up to 2 (kMaxN/2)^2 (the transverse |n_perp|^2
+    // of the anisotropic 2PCF), their ranks, and how many lie below 2 (N/2)^2
+    const int qmax2 = 2 * (kMaxN / 2) * (kMaxN / 2);
+    std::vector<int> q2rank(size_t(qmax2) + 1, -1), rank2q;
+    for (int a = 0; a * a <= qmax2; ++a)
+        for (int b = a; a * a + b * b <= qmax2; ++b) q2rank[size_t(a) * a + size_t(b) * b] = 0;
+    for (int q = 0; q <= qmax2; ++q)
+        if (q2rank[q] == 0) {
+            q2rank[q] = int(rank2q.size());
+            rank2q.push_back(q);
+        }
+    for (int n = 1, lg = 0; n <= kMaxN; n *= 2, ++lg) {
+        const int lim = 2 * (n / 2) * (n / 2);
+        int cnt = 0;
+        while (cnt < int(rank2q.size()) && rank2q[cnt] <= lim) ++cnt;
+        c->nq2[lg] = cnt;
+    }
     auto up = [](void** dst, const void* src, size_t bytes) -> hipError_t {
         hipError_t e = hipMalloc(dst, bytes);
         if (e != hipSuccess) return e;
@@ -129,7 +146,9 @@ static hermes_status build_tables(hermes_ctx c) {
         (e = up((void**)&c->t.tw64, tw64.data(), tw64.size() * sizeof(double2))) != hipSuccess ||
         (e = up((void**)&c->t.phi1d, phi.data(), phi.size() * sizeof(double))) != hipSuccess ||
         (e = up((void**)&c->t.b7dft, b7.data(), b7.size() * sizeof(double))) != hipSuccess ||
-        (e = up((void**)&c->t.gl, gl.data(), gl.size() * sizeof(double))) != hipSuccess)
+        (e = up((void**)&c->t.gl, gl.data(), gl.size() * sizeof(double))) != hipSuccess ||
+        (e = up((void**)&c->t.q2rank, q2rank.data(), q2rank.size() * sizeof(int))) != hipSuccess ||
+        (e = up((void**)&c->t.rank2q, rank2q.data(), rank2q.size() * sizeof(int))) != hipSuccess)
         return fail(HERMES_ERR_HIP, std::string("hermes_create: ") + hipGetErrorString(e));
     return HERMES_OK;
 }
@@ -209,6 +228,8 @@ void hermes_destroy(hermes_ctx ctx) {
         ctx->prof.pending.clear();
         ctx->prof.pool.clear();
     }
+    (void)hipFree(ctx->t.q2rank);
+    (void)hipFree(ctx->t.rank2q);
     (void)hipFree(ctx->t.tw32);
     (void)hipFree(ctx->t.tw64);
     (void)hipFree(ctx->t.phi1d);
@@ -285,6 +306,11 @@ hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtyp
         case HERMES_OP_FILTER:
             if (n_batch < 1) return fail(HERMES_ERR_ARG, "hermes_workspace_size: FILTER needs n_batch >= 1");
             *bytes = filter_workspace(n_grid, dtype, n_batch);
+            return HERMES_OK;
+        case HERMES_OP_XI_ANISO:
+            if (n_batch < 1 || n_batch > HERMES_MAX_ANISO)
+                return fail(HERMES_ERR_ARG, "hermes_workspace_size: XI_ANISO needs 1..2^20 windows");
+            *bytes = aniso_workspace(ctx, n_grid, n_batch);
             return HERMES_OK;
         case HERMES_OP_ZETA:
             if (dtype != HERMES_F32) return fail(HERMES_ERR_UNSUPPORTED, "hermes_workspace_size: ZETA runs in float32");
@@ -368,6 +394,38 @@ hermes_status hermes_xi_static(hermes_ctx ctx, const void* delta_k, int n_grid, 
     DeviceGuard g(ctx->device);
     return xi_impl(ctx, delta_k, n_grid, dtype, box_L, e, ells, n_ells, los_axis, xi, shot, ctx->xi_scratch,
                    kXiStaticBytes, stream);
+}
+
+hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype, double box_L,
+                              const hermes_aniso_window* win, int n_win, int los_axis, double* xi, void* work,
+                              size_t work_bytes, hipStream_t stream) {
+    if (!ctx || !delta_k || !win || !xi || !work) return fail(HERMES_ERR_ARG, "hermes_xi_aniso: NULL argument");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_xi_aniso: N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_xi_aniso: bad dtype");
+    if (!(box_L > 0.0) || !std::isfinite(box_L)) return fail(HERMES_ERR_ARG, "hermes_xi_aniso: box_L must be > 0");
+    if (los_axis < 0 || los_axis > 2) return fail(HERMES_ERR_ARG, "hermes_xi_aniso: los_axis must be 0, 1 or 2");
+    if (n_win < 1 || n_win > HERMES_MAX_ANISO)
+        return fail(HERMES_ERR_ARG, "hermes_xi_aniso: n_win must be in [1, 2^20]");
+    for (int i = 0; i < n_win; ++i) {
+        const hermes_aniso_window& w = win[i];
+        const std::string at = "hermes_xi_aniso: window " + std::to_string(i) + ": ";
+        if (w.reserved != 0) return fail(HERMES_ERR_ARG, at + "reserved must be 0");
+        if (w.kind < HERMES_ANISO_RING || w.kind > HERMES_ANISO_GAUSS_SHELL)
+            return fail(HERMES_ERR_ARG, at + "unknown kind");
+        const double p[4] = {w.r_perp, w.r_par, w.d_perp, w.d_par};
+        for (double v : p)
+            if (!std::isfinite(v) || v < 0.0) return fail(HERMES_ERR_ARG, at + "parameters must be finite and >= 0");
+        if (!(w.r_perp < 0.5 * box_L) || !(w.r_par < 0.5 * box_L))
+            return fail(HERMES_ERR_ARG, at + "r_perp and r_par must be below L/2");
+        if (w.kind == HERMES_ANISO_RING_BIN && (!(w.d_perp > 0.0) || !(w.r_perp >= 0.5 * w.d_perp)))
+            return fail(HERMES_ERR_ARG, at + "RING_BIN needs d_perp > 0 and r_perp >= d_perp / 2");
+        if (w.kind == HERMES_ANISO_GAUSS_SHELL && !(w.r_perp > 0.0 || w.d_perp > 0.0))
+            return fail(HERMES_ERR_ARG, at + "GAUSS_SHELL needs r_perp > 0 or d_perp > 0");
+    }
+    if (work_bytes < aniso_workspace(ctx, n_grid, n_win))
+        return fail(HERMES_ERR_OOM, "hermes_xi_aniso: workspace too small");
+    DeviceGuard g(ctx->device);
+    return xi_aniso_impl(ctx, delta_k, n_grid, dtype, box_L, win, n_win, los_axis, xi, work, stream);
 }
 
 hermes_status hermes_filter_bins(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype,

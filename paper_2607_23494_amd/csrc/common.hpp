@@ -24,6 +24,8 @@ struct Tables {
     double* phi1d = nullptr;    // sinc^8(pi n~/N) at phi1d[N + i], i in [0, N)
     double* b7dft = nullptr;    // sum_{|d|<=3} B7(d) cos(2 pi d i / N) at b7dft[N + i]
     double* gl = nullptr;       // kGLSub (16) Gauss-Legendre nodes, then their weights, on [-1, 1]
+    int* q2rank = nullptr;      // rank of q among the sums of two squares a^2 + b^2 (-1 if none), q <= 2 (kMaxN/2)^2
+    int* rank2q = nullptr;      // the sums of two squares in increasing order
 };
 
 // Optional per-kernel timing: launches are bracketed with HIP events on the
@@ -48,6 +50,7 @@ struct hermes_ctx_s {
     hermes::Tables t;
     hermes::Profiler prof;
     void* xi_scratch = nullptr;   // device address of the static 2PCF scratch array on this device
+    int nq2[11] = {};             // sums of two squares <= 2 (N/2)^2, indexed by log2 N
 };
 
 namespace hermes {
@@ -73,6 +76,8 @@ private:
 };
 
 inline bool valid_n(int n) { return n >= 8 && n <= kMaxN && (n & (n - 1)) == 0; }
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
 // ---------------------------------------------------------------- types
 template <typename T> struct cplx_of;
@@ -115,6 +120,10 @@ hermes_status zeta_impl(hermes_ctx ctx, const float* delta, const void* delta_k,
                         double box_L, const Edges& edges, int l_max, int precision, double* zeta,
                         void* work, size_t work_bytes, hipStream_t stream);
 size_t zeta_workspace(int n, int n_bins);
+hermes_status xi_aniso_impl(hermes_ctx ctx, const void* delta_k, int n, int dtype, double box_L,
+                            const hermes_aniso_window* win, int n_win, int los_axis, double* xi, void* work,
+                            hipStream_t stream);
+size_t aniso_workspace(hermes_ctx ctx, int n, int n_win);
 hermes_status readout_impl(hermes_ctx ctx, const void* field, int n, int dtype, double box_L, const float* pos,
                            const float* weight, int64_t n_pts, const hermes_mark* mark, void* out,
                            double* moments, hipStream_t stream);

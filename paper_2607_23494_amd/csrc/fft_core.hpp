@@ -488,62 +488,6 @@ __device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw)
     for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[L + i];
 }
 
-// ---------------------------------------------------------------- register DFTs
-// cos and sin of 2 pi m / 16, m = 0 .. 9 (the twiddles inside a 16-point DFT)
-__device__ __forceinline__ void w16(int m, double& c, double& s) {
-    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, h = 0.70710678118654752440;
-    const double cs[10] = {1.0, c1, h, s1, 0.0, -s1, -h, -c1, -1.0, -c1};
-    const double sn[10] = {0.0, s1, h, c1, 1.0, c1, h, s1, 0.0, -s1};
-    c = cs[m];
-    s = sn[m];
-}
-
-// DFT of length 16 of v[0..15] in registers, natural order in and out
-// (16 = 4 x 4: 4-point DFTs over the stride-4 subsequences, twiddles
-// w16^(n1 k2), 4-point DFTs across them).  INV: exponent sign +.
-template <bool INV, typename C>
-__device__ __forceinline__ void dft16(C* v) {
-    using T = typename real_of<C>::type;
-    C a[4][4];
-#pragma unroll
-    for (int n1 = 0; n1 < 4; ++n1) {
-        a[n1][0] = v[n1];
-        a[n1][1] = v[n1 + 4];
-        a[n1][2] = v[n1 + 8];
-        a[n1][3] = v[n1 + 12];
-        dft4<INV>(a[n1][0], a[n1][1], a[n1][2], a[n1][3]);
-    }
-#pragma unroll
-    for (int n1 = 1; n1 < 4; ++n1)
-#pragma unroll
-        for (int k2 = 1; k2 < 4; ++k2) {
-            double c, s;
-            w16(n1 * k2, c, s);
-            const C w{T(c), T(INV ? s : -s)};
-            a[n1][k2] = c_mul(a[n1][k2], w);
-        }
-#pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) {
-        C b0 = a[0][k2], b1 = a[1][k2], b2 = a[2][k2], b3 = a[3][k2];
-        dft4<INV>(b0, b1, b2, b3);
-        v[k2] = b0;
-        v[k2 + 4] = b1;
-        v[k2 + 8] = b2;
-        v[k2 + 12] = b3;
-    }
-}
-
-// DFT of length L in {8, 16} in registers, natural order.
-template <int L, bool INV, typename C>
-__device__ __forceinline__ void dft_reg(C* v) {
-    static_assert(L == 8 || L == 16, "register DFT length");
-    if constexpr (L == 8) {
-        butterfly<INV, 8>(v);
-    } else {
-        dft16<INV>(v);
-    }
-}
-
 // ---------------------------------------------------------------- mode helpers
 // signed mode index of array index i on an axis of length N (Nyquist -> +N/2)
 template <int N> __device__ __forceinline__ int signed_mode(int i) { return i <= N / 2 ? i : i - N; }

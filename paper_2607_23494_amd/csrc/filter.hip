@@ -795,344 +795,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     }
 }
 
-// ---------------------------------------------------------------- pass Z, register form
-// For N = 256 and 512 the length-M inverse along z (M = N/2) runs in
-// registers: a line is spread over P lanes holding Q = M/P elements each,
-// element n = p + P q in lane p.  Stage A is a Q-point DFT in registers, the
-// twiddle is w_M^(p a), one wavefront-local transpose through LDS regroups the
-// P values of each a, and stage B is a P-point DFT in registers, leaving
-// X[a + Q c] for c < P (the four-step split of M = P Q).  Each wavefront
-// holds 64/P lines.  The outputs are staged once, as real samples, for the
-// epilogue; the transpose tiles and the staged samples share LDS.
-template <int N> struct zreg_cfg {
-    static constexpr int M = N / 2;
-    static constexpr int P = M >= 256 ? 16 : 8;      // lanes per line
-    static constexpr int Q = M / P;                  // elements per lane
-    static constexpr int LPW = 64 / P;               // lines per wavefront
-    static constexpr int R = zrows<N>::R;            // rows per group
-    static constexpr int CELLS = R * N;
-    static constexpr int TS = 2 * Q * (P + 1);       // floats of one transpose tile, [a][P + 1] complex
-    // floats per bin: the R lines' transpose tiles or the R N staged samples;
-    // BS = 4 (mod 8) puts the 16-byte epilogue reads of 16 consecutive bins on
-    // distinct banks and keeps them 16-byte aligned
-    static constexpr int bs_of() {
-        int b = R * TS > R * N ? R * TS : R * N;
-        while (b % 8 != 4) ++b;
-        return b;
-    }
-    static constexpr int BS = bs_of();
-    static_assert(P <= Q && M == P * Q && 64 % P == 0 && (Q == 8 || Q == 16) && (P == 8 || P == 16), "split");
-    static_assert(LPW % R == 0, "a wavefront holds whole bins");
-};
-
-template <int N> constexpr bool zreg_ok() { return N == 256 || N == 512; }
-
-template <int N, int W>
-constexpr size_t zreg_lds_bytes() {
-    using G = zreg_cfg<N>;
-    const size_t bins = size_t(W) * G::LPW / G::R;
-    const size_t main = bins * G::BS * 4 + size_t(G::CELLS) * 4 + size_t(G::CELLS) / 2 * 4 + size_t(G::M) * 8;
-    const size_t red = size_t(W) * 64 * 16 * sizeof(double);
-    return main > red ? main : red;
-}
-
-// Matrix-core contraction of one row group from the staged samples, with
-// W wavefronts taking 16-cell steps round robin.  With y = sqrt|delta| x,
-// s = sign delta and y = y_hi + y_lo (bf16 or fp16), the group's share
-//   C = sum_c s y y^T = sum_c s (y_hi y_hi^T + y_lo y_hi^T + y_hi y_lo^T) + O(y_lo^2)
-// is three MFMAs per 16 cells into one float32 accumulator (the sign rides on
-// the B operand), added to the float64 accumulators once per group.
-// Accumulator registers q of the 32 x 32 tile that can hold a row below the
-// batch capacity (row 8 (q / 4) + 4 (lane / 32) + q % 4): the first 8 for up
-// to 16 bins, 12 for up to 24, all 16 for 32.
-template <int BINS> constexpr int acc_rows() { return BINS <= 16 ? 8 : (BINS <= 24 ? 12 : 16); }
-
-template <int N, int W, int PREC, int ACC_ROWS>
-__device__ __forceinline__ void mfma_contract_staged(const float* reg, const float* sr, const uint32_t* sgn, int nb,
-                                                     double* acc64) {
-    using G = zreg_cfg<N>;
-    using V = typename std::conditional<PREC == HERMES_PREC_BF16X3, bf16x8_t, f16x8_t>::type;
-    using E = typename std::conditional<PREC == HERMES_PREC_BF16X3, __bf16, _Float16>::type;
-    constexpr int BS = G::BS, STEPS = G::CELLS / 16;
-    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    const int bin = min(l % 32, nb - 1), half = l / 32;
-    const float* rb = reg + bin * BS;
-    f32x16_t acc;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-#pragma unroll 1
-    for (int step = w; step < STEPS; step += W) {
-        const int c0 = step * 16 + 8 * half;   // 8 consecutive cells of one row
-        const int rr = c0 / N, z = c0 - rr * N;
-        const float4 x0 = *reinterpret_cast<const float4*>(rb + rr * N + z);
-        const float4 x1 = *reinterpret_cast<const float4*>(rb + rr * N + z + 4);
-        const float4 r0 = *reinterpret_cast<const float4*>(sr + c0);
-        const float4 r1 = *reinterpret_cast<const float4*>(sr + c0 + 4);
-        const u32x4_t sm = *reinterpret_cast<const u32x4_t*>(sgn + c0 / 2);
-        const float y[8] = {x0.x * r0.x, x0.y * r0.y, x0.z * r0.z, x0.w * r0.w,
-                            x1.x * r1.x, x1.y * r1.y, x1.z * r1.z, x1.w * r1.w};
-        V hi, lo;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            hi[t] = (E)y[t];
-            lo[t] = (E)(y[t] - float(hi[t]));
-        }
-        const V hs = __builtin_bit_cast(V, __builtin_bit_cast(u32x4_t, hi) ^ sm);
-        const V ls = __builtin_bit_cast(V, __builtin_bit_cast(u32x4_t, lo) ^ sm);
-        if constexpr (PREC == HERMES_PREC_BF16X3) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi, hs, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo, hs, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi, ls, acc, 0, 0, 0);
-        } else {
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi, hs, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(lo, hs, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi, ls, acc, 0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < ACC_ROWS; ++r) acc64[r] += double(acc[r]);
-}
-
-// Inverse along z of nb windows x R rows per group with W wavefronts
-// (W 64 / P >= nb R lines), then the epilogue, as k_c2r_z.  Persistent
-// workgroups; the loads of the next group are issued once the transform is
-// staged and land during the epilogue.
-template <int N, int EPI, int W, int PREC>
-__global__ __launch_bounds__(W * 64) void k_c2r_zr(const float2* __restrict__ spec, int64_t bin_stride, int nb,
-                                                   const float* __restrict__ delta, float* __restrict__ out,
-                                                   WinSet map, double* __restrict__ part,
-                                                   const float2* __restrict__ tw) {
-    using G = zreg_cfg<N>;
-    constexpr int M = G::M, P = G::P, Q = G::Q, LPW = G::LPW, R = G::R, CELLS = G::CELLS, BS = G::BS;
-    constexpr int TS = G::TS;
-    constexpr int NT = W * 64, PP = pitch_of<N>(), GROUPS = N * N / R;
-    constexpr int BINS = W * LPW / R;
-    constexpr bool MF = EPI == EPI_CONTRACT && PREC != HERMES_PREC_FP32;
-    extern __shared__ double lds_raw[];
-    float* reg = reinterpret_cast<float*>(lds_raw);                // [BINS][BS]
-    float* sd = reg + BINS * BS;                                    // [CELLS]
-    uint32_t* sgn = reinterpret_cast<uint32_t*>(sd + CELLS);        // [CELLS / 2]
-    float2* twm = reinterpret_cast<float2*>(sgn + CELLS / 2);       // [a][p]: exp(-2 pi i p a / M)
-    for (int i = threadIdx.x; i < M; i += NT) {
-        const int a = i / P, pp = i - (i / P) * P;
-        twm[i] = tw[M + pp * a];
-    }
-
-    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int p = lane % P;
-    const int line = wv * LPW + lane / P;                           // line = bin R + row
-    const bool active = line < nb * R;
-    const int b = line / R, r = line - (line / R) * R;
-    float2* tt = reinterpret_cast<float2*>(reg + b * BS + r * TS);  // transpose tile [a][P + 1]
-    float* stg = reg + b * BS + r * N;                              // staged samples of the line
-
-    // contraction roles (float32 path): 4x4 bin tiles (I <= J) x cell groups
-    const int nt4 = (nb + 3) / 4;
-    const int ntp = nt4 * (nt4 + 1) / 2;
-    const int cg_n = NT / ntp;
-    const int tp = threadIdx.x % ntp, cg = threadIdx.x / ntp;
-    int ti = 0, tj = 0;
-    {
-        int idx = tp;
-        for (int I = 0; I < nt4; ++I) {
-            if (idx < nt4 - I) {
-                ti = I;
-                tj = I + idx;
-                break;
-            }
-            idx -= nt4 - I;
-        }
-    }
-    const int subs = NT / nb;
-    const int mb = threadIdx.x % nb, msub = threadIdx.x / nb;
-
-    double acc64[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc64[i] = 0.0;
-
-    // element n = p + P q of the line sits at its pair-order position: 2 n
-    // below M/2, 2 (M - n) + 1 above, and position M for n = M/2 (q = Q/2,
-    // p = 0); from two per-lane bases the offsets are immediates
-    float2 pre[Q];
-    float4 dpre = float4{0.f, 0.f, 0.f, 0.f};
-    auto fetch = [&](int g) {
-        if (active) {
-            const int64_t row = int64_t(g) * R + r;
-            const float2* base = spec + b * bin_stride + (row / N) * plane_stride<N>() + (row % N) * PP;
-            const float2* lo = base + 2 * p;                 // n = p + P q < M/2: position 2 p + 2 P q
-            const float2* hi = base + (2 * M + 1 - 2 * p);   // n > M/2: position 2 M + 1 - 2 p - 2 P q
-#pragma unroll
-            for (int q = 0; q < Q / 2; ++q) pre[q] = ld_stream(lo + 2 * P * q);
-            pre[Q / 2] = ld_stream(p == 0 ? base + M : hi - 2 * P * (Q / 2));
-#pragma unroll
-            for (int q = Q / 2 + 1; q < Q; ++q) pre[q] = ld_stream(hi - 2 * P * q);
-        }
-        if (EPI == EPI_CONTRACT && threadIdx.x < CELLS / 4)
-            dpre = *reinterpret_cast<const float4*>(delta + int64_t(g) * CELLS + 4 * threadIdx.x);
-    };
-    __syncthreads();   // twiddles
-    if (blockIdx.x < GROUPS) fetch(blockIdx.x);
-    for (int g = blockIdx.x; g < GROUPS; g += gridDim.x) {
-        const int64_t row0 = int64_t(g) * R;
-        if (EPI == EPI_CONTRACT && threadIdx.x < CELLS / 4) {
-            const float d[4] = {dpre.x, dpre.y, dpre.z, dpre.w};
-            const int c = 4 * threadIdx.x;
-            if constexpr (MF) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) sd[c + i] = sqrtf(fabsf(d[i]));
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-                    sgn[c / 2 + i] = ((__float_as_uint(d[2 * i]) >> 16) & 0x8000u) |
-                                     (__float_as_uint(d[2 * i + 1]) & 0x80000000u);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) sd[c + i] = d[i];
-            }
-        }
-        float2 v[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) v[q] = pre[q];
-        if (active) {
-            dft_reg<Q, true>(v);                       // stage A over q
-#pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                const float2 w = twm[a * P + p];       // exp(-2 pi i p a / M); the inverse takes its conjugate
-                v[a] = c_mul(v[a], float2{w.x, -w.y});
-            }
-#pragma unroll
-            for (int a = 0; a < Q; ++a) tt[a * (P + 1) + p] = v[a];
-        }
-        wave_sync();
-        float2 u[Q / P][P];
-        if (active) {
-#pragma unroll
-            for (int h = 0; h < Q / P; ++h) {
-                const int a = p + P * h;
-#pragma unroll
-                for (int j = 0; j < P; ++j) u[h][j] = tt[a * (P + 1) + j];
-                dft_reg<P, true>(u[h]);                // stage B over p: X[a + Q c] = u[h][c]
-            }
-        }
-        wave_sync();
-        if (active) {
-#pragma unroll
-            for (int h = 0; h < Q / P; ++h)
-#pragma unroll
-                for (int c = 0; c < P; ++c) {
-                    const int k = p + P * h + Q * c;   // complex output k: real samples 2k, 2k + 1
-                    *reinterpret_cast<float2*>(stg + 2 * k) = u[h][c];
-                }
-        }
-        // the next group's rows load while the epilogue runs
-        if (g + int(gridDim.x) < GROUPS) fetch(g + gridDim.x);
-        __syncthreads();
-        if constexpr (MF) {
-            mfma_contract_staged<N, W, PREC, acc_rows<W * G::LPW / G::R>()>(reg, sd, sgn, nb, acc64);
-        } else if constexpr (EPI == EPI_CONTRACT) {
-            if (cg < cg_n) {
-                float acc[4][4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[a][c] = 0.f;
-                for (int cell = cg; cell < CELLS; cell += cg_n) {
-                    const int rr = cell / N, z = cell - rr * N;
-                    const float d = sd[cell];
-                    float xa[4], xb[4];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const int b1 = 4 * ti + a, b2 = 4 * tj + a;
-                        xa[a] = b1 < nb ? reg[b1 * BS + rr * N + z] * d : 0.f;
-                        xb[a] = b2 < nb ? reg[b2 * BS + rr * N + z] : 0.f;
-                    }
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(xa[a], xb[c], acc[a][c]);
-                }
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc64[a * 4 + c] += double(acc[a][c]);
-            }
-        } else {
-            if (out) {
-                for (int e = threadIdx.x; e < nb * CELLS; e += NT) {
-                    const int bb = e / CELLS, rem = e - bb * CELLS;
-                    const int rr = rem / N, z = rem - rr * N;
-                    out[int64_t(map.out[bb]) * N * N * N + (row0 + rr) * N + z] = reg[bb * BS + rr * N + z];
-                }
-            }
-            if (part && msub < subs) {
-                float s2 = 0.f, s3 = 0.f, s4 = 0.f;
-                for (int cell = msub; cell < CELLS; cell += subs) {
-                    const int rr = cell / N, z = cell - rr * N;
-                    const float x = reg[mb * BS + rr * N + z];
-                    const float x2 = x * x;
-                    s2 += x2;
-                    s3 += x2 * x;
-                    s4 += x2 * x2;
-                }
-                acc64[0] += double(s2);
-                acc64[1] += double(s3);
-                acc64[2] += double(s4);
-            }
-        }
-        __syncthreads();
-    }
-
-    // workgroup reduction of the float64 partial sums
-    double* red = lds_raw;
-    if constexpr (MF) {
-        // acc64[q] of lane l in wave w holds entry (i, j) of the 32 x 32 tile,
-        // j = l % 32, i = 8 (q / 4) + 4 (l / 32) + q % 4
-        const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-        for (int st = 0; st < W; ++st) {
-            if (w == st) {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int i = 8 * (q / 4) + 4 * (l / 32) + (q % 4), j = l % 32;
-                    red[i * 32 + j] = (st == 0 ? 0.0 : red[i * 32 + j]) + acc64[q];
-                }
-            }
-            __syncthreads();
-        }
-        double* dst = part + int64_t(blockIdx.x) * nb * nb;
-        for (int e = threadIdx.x; e < nb * nb; e += NT) dst[e] = red[(e / nb) * 32 + e % nb];
-    } else if constexpr (EPI == EPI_CONTRACT) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) red[threadIdx.x * 16 + i] = acc64[i];
-        __syncthreads();
-        if (threadIdx.x < ntp) {
-            double sum[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) sum[i] = 0.0;
-            for (int c = 0; c < cg_n; ++c)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) sum[i] += red[(c * ntp + threadIdx.x) * 16 + i];
-            double* dst = part + int64_t(blockIdx.x) * nb * nb;
-            for (int a = 0; a < 4; ++a)
-                for (int c = 0; c < 4; ++c) {
-                    const int b1 = 4 * ti + a, b2 = 4 * tj + c;
-                    if (b1 < nb && b2 < nb) {
-                        dst[b1 * nb + b2] = sum[a * 4 + c];
-                        dst[b2 * nb + b1] = sum[a * 4 + c];
-                    }
-                }
-        }
-    } else if (part) {
-        for (int i = 0; i < 3; ++i) red[threadIdx.x * 3 + i] = acc64[i];
-        __syncthreads();
-        if (threadIdx.x < nb) {
-            double sum[3] = {0.0, 0.0, 0.0};
-            for (int c = 0; c < subs; ++c)
-                for (int i = 0; i < 3; ++i) sum[i] += red[(c * nb + threadIdx.x) * 3 + i];
-            double* dst = part + (int64_t(blockIdx.x) * nb + threadIdx.x) * 3;
-            for (int i = 0; i < 3; ++i) dst[i] = sum[i];
-        }
-    }
-}
-
 // dst[i] (+)= scale * sum_g part[g * n + i]; one workgroup per output element.
 __global__ __launch_bounds__(kThreads) void k_reduce_part(const double* __restrict__ part, int ngroups, int n,
                                                           double scale, double* __restrict__ dst, int accumulate) {
@@ -1208,30 +870,6 @@ static int launch_z(hermes_ctx ctx, const typename cplx_of<T>::type* sp, int64_t
     return grid;
 }
 
-template <int N, int EPI, int W, int PREC>
-static int launch_zr(hermes_ctx ctx, const float2* sp, int64_t bin_stride, int nb, const float* delta, float* out,
-                     const WinSet& ws, double* part, const float2* tw, hipStream_t stream) {
-    constexpr size_t lds = zreg_lds_bytes<N, W>();
-    allow_lds(k_c2r_zr<N, EPI, W, PREC>, lds);
-    const int grid = resident_grid(ctx, k_c2r_zr<N, EPI, W, PREC>, W * 64, lds, N * N / zrows<N>::R);
-    hipLaunchKernelGGL((k_c2r_zr<N, EPI, W, PREC>), dim3(grid), dim3(W * 64), lds, stream, sp, bin_stride, nb, delta,
-                       out, ws, part, tw);
-    return grid;
-}
-
-// The register-form z pass for float at N = 256, 512: wavefronts for nb
-// windows (nb R lines, 64 / P lines per wavefront) from a small set.
-template <int N, int EPI, int PREC>
-static int launch_zr_nb(hermes_ctx ctx, const float2* sp, int64_t bin_stride, int nb, const float* delta, float* out,
-                        const WinSet& ws, double* part, const float2* tw, hipStream_t stream) {
-    using G = zreg_cfg<N>;
-    const int lines = nb * G::R;
-    if (lines <= 2 * G::LPW) return launch_zr<N, EPI, 2, PREC>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-    if (lines <= 3 * G::LPW) return launch_zr<N, EPI, 3, PREC>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-    if (lines <= 5 * G::LPW) return launch_zr<N, EPI, 5, PREC>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-    return launch_zr<N, EPI, 8, PREC>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-}
-
 // Pass X over nb windows for one angular factor (m), or for two (m, m2) of
 // the same l sharing the radial table, writing spec_ws and spec_ws2.
 template <typename T, int N>
@@ -1302,31 +940,21 @@ static int run_yz(hermes_ctx ctx, const T* delta, const WinSet& ws, void* spec_w
                            plane_stride<N>(), tw);
     }
     LaunchScope ls(ctx, stream, EPI == EPI_CONTRACT ? "inv_z_contract" : "inv_z_moments");
-    if constexpr (std::is_same<T, float>::value && zreg_ok<N>()) {
-        if constexpr (EPI == EPI_CONTRACT) {
-            if (precision == HERMES_PREC_BF16X3)
-                return launch_zr_nb<N, EPI, HERMES_PREC_BF16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-            if (precision == HERMES_PREC_FP16X3)
-                return launch_zr_nb<N, EPI, HERMES_PREC_FP16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-        }
-        return launch_zr_nb<N, EPI, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-    } else {
-        if constexpr (EPI == EPI_CONTRACT) {
-            // register capacity: 20 bins (the common case) or the full batch
-            const bool small = nb <= 20;
-            if (precision == HERMES_PREC_BF16X3) {
-                if (small) return launch_z<T, N, EPI, 20, HERMES_PREC_BF16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-                return launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_BF16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-            } else if (precision == HERMES_PREC_FP16X3) {
-                if (small) return launch_z<T, N, EPI, 20, HERMES_PREC_FP16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-                return launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_FP16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-            } else {
-                if (small) return launch_z<T, N, EPI, 20, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-                return launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
-            }
+    if constexpr (EPI == EPI_CONTRACT) {
+        // register capacity: 20 bins (the common case) or the full batch
+        const bool small = nb <= 20;
+        if (precision == HERMES_PREC_BF16X3) {
+            if (small) return launch_z<T, N, EPI, 20, HERMES_PREC_BF16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+            return launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_BF16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+        } else if (precision == HERMES_PREC_FP16X3) {
+            if (small) return launch_z<T, N, EPI, 20, HERMES_PREC_FP16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+            return launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_FP16X3>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
         } else {
-            return launch_z<T, N, EPI, kFilterChunk, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+            if (small) return launch_z<T, N, EPI, 20, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
+            return launch_z<T, N, EPI, kMaxBatch, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
         }
+    } else {
+        return launch_z<T, N, EPI, kFilterChunk, HERMES_PREC_FP32>(ctx, sp, bin_stride, nb, delta, out, ws, part, tw, stream);
     }
 }
 

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_PKG, "libhermes.so")
 F32, F64 = 0, 1
 PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
 WIN = {"shell": 0, "sphere": 1, "gauss": 2, "sh_shell": 3}
-OP_ASSIGN, OP_FFT, OP_XI, OP_FILTER, OP_ZETA = range(5)
+OP_ASSIGN, OP_FFT, OP_XI, OP_FILTER, OP_ZETA, OP_XI_ANISO = range(6)
+ANISO = {"ring": 0, "ring_bin": 1, "gauss_ring": 2, "disk": 3, "cylinder": 4, "cylshell": 5, "gauss_shell": 6}
 MAX_BINS = 64
 
 
@@ -40,6 +41,11 @@ class _Mark(ctypes.Structure):
 
 
 MARK = {"none": 0, "power_law": 1, "inverse_density": 2}
+
+
+class _AnisoWindow(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("r_perp", ctypes.c_double),
+                ("r_par", ctypes.c_double), ("d_perp", ctypes.c_double), ("d_par", ctypes.c_double)]
 
 
 class _Window(ctypes.Structure):
@@ -62,13 +68,14 @@ def _load() -> ctypes.CDLL:
     lib.hermes_fft.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
     lib.hermes_xi.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, vp, sz, vp]
     lib.hermes_xi_static.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, vp]
+    lib.hermes_xi_aniso.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_AnisoWindow), i32, i32, vp, vp, sz, vp]
     lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
     lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
     lib.hermes_readout.argtypes = [vp, vp, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp, vp]
     lib.hermes_profile_enable.argtypes = [vp, i32]
     lib.hermes_profile_reset.argtypes = [vp]
     lib.hermes_profile_read.argtypes = [vp, i32, ctypes.c_char_p, sz, ctypes.POINTER(i64), ctypes.POINTER(f64)]
-    for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi", "hermes_xi_static",
+    for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi", "hermes_xi_static", "hermes_xi_aniso",
                  "hermes_filter_bins", "hermes_zeta_l", "hermes_readout", "hermes_profile_enable", "hermes_profile_reset",
                  "hermes_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
@@ -213,6 +220,34 @@ def xi(delta_k: torch.Tensor, box_L: float, edges, ells: Sequence[int] = (0,), l
                               nb, el.ctypes.data_as(ctypes.c_void_p), el.size, los_axis, _ptr(out),
                               _ptr(sh) if shot else None, _ptr(w), wbytes, _stream(dev, stream)))
     return (out, sh) if shot else out
+
+
+def make_aniso_windows(specs: Iterable) -> ctypes.Array:
+    """specs: tuples (kind, r_perp, r_par[, d_perp[, d_par]]) with kind in ANISO."""
+    specs = list(specs)
+    arr = (_AnisoWindow * len(specs))()
+    for i, s in enumerate(specs):
+        vals = [float(v) for v in s[1:]] + [0.0] * (5 - len(s))
+        arr[i] = _AnisoWindow(ANISO[s[0]], 0, *vals)
+    return arr
+
+
+def xi_aniso(delta_k: torch.Tensor, box_L: float, windows, los_axis: int = 2, out: torch.Tensor | None = None,
+             work: torch.Tensor | None = None, stream=None):
+    """Anisotropic 2PCF for axisymmetric windows: device float64 [n_windows].
+    windows: tuples (kind, r_perp, r_par[, d_perp[, d_par]]), kind in ANISO."""
+    dev = _dev(delta_k)
+    n = delta_k.shape[0]
+    arr = make_aniso_windows(windows)
+    nw = len(arr)
+    wbytes = workspace_size(OP_XI_ANISO, n, delta_k.dtype, nw, 0, dev)
+    with _on(stream):
+        w = _workspace(wbytes, dev, work)
+        if out is None:
+            out = torch.empty((nw,), dtype=torch.float64, device=delta_k.device)
+        _check(_lib.hermes_xi_aniso(context(dev), _ptr(delta_k), n, _dtype_code(delta_k.dtype), float(box_L), arr, nw,
+                                    los_axis, _ptr(out), _ptr(w), wbytes, _stream(dev, stream)))
+    return out
 
 
 def xi_static(delta_k: torch.Tensor, box_L: float, edges, ells: Sequence[int] = (0,), los_axis: int = 2,

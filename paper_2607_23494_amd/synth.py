@@ -119,3 +119,17 @@ EDGES = {
 
 # counts-in-cells radii: geometric from 4 to 32 Mpc/h, 8 values
 CIC_RADII = 4.0 * 2.0 ** (3.0 * np.arange(8) / 7.0)
+
+# DD(s, mu) with ring binning windows on the 256^3 redshift-space workload:
+# 46 separations x 51 orientations, thin double rings at the bin centres
+# (r_perp = s sqrt(1 - mu^2), r_par = s mu), s in 4 Mpc/h bins over [2, 186],
+# mu in equal bins over [0, 1].
+SMU_S_EDGES = np.linspace(2.0, 186.0, 47)
+SMU_N_MU = 51
+
+
+def smu_rings(s_edges=SMU_S_EDGES, n_mu: int = SMU_N_MU) -> list:
+    """Window specs ("ring", r_perp, r_par), s-major, for every (s, mu) bin."""
+    s = 0.5 * (np.asarray(s_edges[1:]) + np.asarray(s_edges[:-1]))
+    mu = (np.arange(n_mu) + 0.5) / n_mu
+    return [("ring", float(si * np.sqrt(1.0 - m * m)), float(si * m)) for si in s for m in mu]

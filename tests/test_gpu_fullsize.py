@@ -82,6 +82,26 @@ def test_ns256_2pcf_40_bins(hermes, ns256):
     assert normwise(got, ref) < 1e-5
 
 
+def test_ns256_smu_rings_and_axisymmetric_windows(hermes, ns256):
+    """DD(s, mu) with ring windows: the 46 x 51 thin rings at 256^3 in one
+    call, 16 sampled rings against the oracle (on the scale of the whole
+    (s, mu) grid), and one window of each other kind."""
+    wl, pos, odh = ns256
+    tp = torch.from_numpy(pos).cuda()
+    eps, sw = hermes.assign(tp, None, wl.box_L, wl.n_grid)
+    dk, _ = hermes.fft(eps, sw, want_delta=False)
+    rings = synth.smu_rings()
+    assert len(rings) == 46 * 51
+    got = hermes.xi_aniso(dk, wl.box_L, rings).cpu().numpy()
+    pick = np.random.default_rng(12).choice(len(rings), 16, replace=False)
+    ref = O.xi_aniso(odh, wl.box_L, [rings[i] for i in pick])
+    assert np.max(np.abs(got[pick] - ref)) < 1e-5 * np.max(np.abs(got))
+    other = [("ring_bin", 20.0, 10.0, 4.0, 4.0), ("gauss_ring", 10.0, 20.0, 5.0), ("disk", 12.0, 6.0),
+             ("cylinder", 15.0, 8.0), ("cylshell", 9.0, 14.0), ("gauss_shell", 30.0, 0.0, 4.0)]
+    ge = hermes.xi_aniso(dk, wl.box_L, other).cpu().numpy()
+    assert normwise(ge, O.xi_aniso(odh, wl.box_L, other)) < 1e-5
+
+
 def test_ns256_multipoles_and_thomas_expectation(hermes, ns256):
     """xi_l (l = 0, 2, 4; 30 bins) against the oracle, and against the
     expectation of the estimator for a Thomas process with line-of-sight
@@ -224,6 +244,23 @@ def test_ns1024_plane_wave_cic_and_xi(hermes):
     got = hermes.xi(dk, L, edges).cpu().numpy()[0]
     want = A * A / 2 * ph * O.w_shell(np.full(edges.size - 1, k0), edges[:-1], edges[1:])
     assert normwise(got, want) < 1e-5
+
+
+def test_ns512_plane_wave_axisymmetric_windows(hermes):
+    """A plane wave A cos(2 pi n0.l/N) at 512^3: xi_W = (A^2/2) Phi^(n0) W^(k0)
+    for every window kind and line of sight."""
+    n, L, A = 512, 1000.0, 0.8
+    n0 = np.array([3, -5, 7])
+    dk, _ = spectrum_of(hermes, cosine_delta_gpu(n, [tuple(n0)], [A]))
+    k0 = 2 * np.pi / L * n0
+    ph = np.prod(np.sinc(n0 / n) ** 8)
+    wins = [(kind, 25.0, 15.0, 3.0, 2.0) for kind in O.ANISO_KINDS]
+    for los in range(3):
+        kpar = abs(k0[los])
+        kperp = math.sqrt(float(np.sum(k0 ** 2)) - kpar ** 2)
+        got = hermes.xi_aniso(dk, L, wins, los_axis=los).cpu().numpy()
+        want = [A * A / 2 * ph * float(O.w_aniso(w[0], kpar, kperp, *w[1:])) for w in wins]
+        assert normwise(got, want) < 1e-5, los
 
 
 # --------------------------------------------------------------------------
