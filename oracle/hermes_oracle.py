@@ -329,6 +329,22 @@ def filtered_field(delta_hat, box_L, kernel_of_k):
     return idft3(delta_hat * phi_hat(n) * rad).real
 
 
+def cic_window(kind, R):
+    """The radial window W^(|k|) of a counts-in-cells cell: "sphere" (Table A1
+    (b)) or "gauss" (Table A1 (c)) of radius R."""
+    if kind == "sphere":
+        return lambda kq: w_sphere(kq * R)
+    if kind == "gauss":
+        return lambda kq: w_gauss(kq, R)
+    raise ValueError(kind)
+
+
+def field_moments(field):
+    """<f^2>, <f^3>, <f^4>: means over all grid nodes (Sec. 2.2.2 Eq. varw and
+    its higher-order analogues)."""
+    return np.array([np.mean(field ** 2), np.mean(field ** 3), np.mean(field ** 4)])
+
+
 def cic_moments(delta_hat, box_L, windows):
     """<delta_W^p> for p = 2, 3, 4 (mean over all grid nodes) per window.
 
@@ -336,14 +352,7 @@ def cic_moments(delta_hat, box_L, windows):
     """
     out = np.zeros((len(windows), 3))
     for i, (kind, R) in enumerate(windows):
-        if kind == "sphere":
-            fn = lambda kq, R=R: w_sphere(kq * R)
-        elif kind == "gauss":
-            fn = lambda kq, R=R: w_gauss(kq, R)
-        else:
-            raise ValueError(kind)
-        dw = filtered_field(delta_hat, box_L, fn)
-        out[i] = [np.mean(dw ** 2), np.mean(dw ** 3), np.mean(dw ** 4)]
+        out[i] = field_moments(filtered_field(delta_hat, box_L, cic_window(kind, R)))
     return out
 
 

@@ -91,7 +91,7 @@ def ns1024(out_dir):
     e2 = synth.EDGES["ns1024_cic"]
     out.update({
         "workload": "ns1024_cic subset: first 1e6 points of the 1e8-point marked catalogue, 1024^3, L = 2000",
-        "source": "oracle/hermes_oracle.py (assign, contrast, dft3, xi_multipoles, cic_moments)",
+        "source": "oracle/hermes_oracle.py (assign, contrast, dft3, xi_multipoles, filtered_field, cic_window, field_moments)",
         "n_points": int(pos.shape[0]), "xi_edges": e2.tolist(), "xi_bins": list(XI_BINS),
     })
     if "xi_marked" not in out:
@@ -119,7 +119,10 @@ def ns1024(out_dir):
         del delta
         log("number spectrum done")
         for kind, R in todo:
-            done[(kind, R)] = O.cic_moments(dh, L, [(kind, R)])[0].tolist()
+            dw = O.filtered_field(dh, L, O.cic_window(kind, R))
+            log(f"cic {kind} {R} field done")
+            done[(kind, R)] = O.field_moments(dw).tolist()
+            del dw
             out["cic_windows"] = [list(k) for k in done]
             out["cic_moments"] = list(done.values())
             save()
