@@ -422,10 +422,15 @@ def readout(field, pos, box_L):
     point is this 64-node sum, the transpose of the assignment's scatter.
     Returns float64 [n_pts].
     """
+    return interpolate(field, np.asarray(pos, dtype=np.float32).astype(np.float64), box_L)
+
+
+def interpolate(field, x, box_L):
+    """The same 64-node B3 sum at float64 positions x [n, 3] (any real
+    values; node indices are taken mod N)."""
     f = np.asarray(field, dtype=np.float64)
     n = f.shape[0]
-    pos = np.asarray(pos, dtype=np.float32)
-    u = pos.astype(np.float64) / (float(box_L) / n)
+    u = np.asarray(x, dtype=np.float64).reshape(-1, 3) / (float(box_L) / n)
     i0 = np.floor(u).astype(np.int64)
     out = np.zeros(u.shape[0])
     for ox in (-1, 0, 1, 2):
@@ -580,4 +585,106 @@ def xi_aniso(delta_hat, box_L, windows, los_axis=2):
         dp = float(w[3]) if len(w) > 3 else 0.0
         dl = float(w[4]) if len(w) > 4 else 0.0
         out[i] = np.sum(p * w_aniso(kind, kpar, kperp, rp, rl, dp, dl)) / nc ** 2
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Monte-Carlo triangle sampling (Sec. 3.4, particle-based summation, Eq.
+# particle-based-sum; Sec. 4.3.3, the dual-/triplet-sphere 3PCF): triangles
+# with sides r12, r13 and opening angle theta, randomly rotated about a
+# primary vertex that is a catalogue point (dual sphere) or a uniform random
+# point of the box (triplet sphere); the secondary vertices read filtered
+# fields.  Random numbers come from the counter-based Philox4x64-10 generator,
+# so every sample is addressed by its (centre, rotation) indices.
+# ----------------------------------------------------------------------------
+
+_PHILOX_M = (0xD2E7470EE14C6C93, 0xCA5A826395121157)
+_PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)
+_U64 = (1 << 64) - 1
+
+
+def philox4x64(counter, key, rounds=10):
+    """One block of Philox4x64 (Salmon, Moraes, Dror and Shaw, SC'11): four
+    64-bit words from a four-word counter and a two-word key.  Each round
+    multiplies words 0 and 2 by the two constants (128-bit products), mixes
+    the high halves with words 1, 3 and the key, and bumps the key by the
+    Weyl constants."""
+    c0, c1, c2, c3 = (int(v) & _U64 for v in counter)
+    k0, k1 = (int(v) & _U64 for v in key)
+    for _ in range(rounds):
+        p0 = _PHILOX_M[0] * c0
+        p1 = _PHILOX_M[1] * c2
+        c0, c1, c2, c3 = ((p1 >> 64) ^ c1 ^ k0) & _U64, p1 & _U64, ((p0 >> 64) ^ c3 ^ k1) & _U64, p0 & _U64
+        k0 = (k0 + _PHILOX_W[0]) & _U64
+        k1 = (k1 + _PHILOX_W[1]) & _U64
+    return c0, c1, c2, c3
+
+
+def uniform53(word):
+    """A 64-bit word to a double in (0, 1): its top 53 bits plus one half."""
+    return ((int(word) >> 11) + 0.5) * 2.0 ** -53
+
+
+def triangle_frame(c, r, seed):
+    """Unit vectors (u, v) of rotation r about centre c: u uniform on the
+    sphere (cos alpha and phi from two words), v uniform on the circle
+    orthogonal to u (angle psi from the third word), through the orthonormal
+    basis of u built as in Duff et al. (JCGT 2017)."""
+    w = philox4x64((c, r, 0, 0), (seed, 0))
+    cz = 2.0 * uniform53(w[0]) - 1.0
+    phi = 2.0 * np.pi * uniform53(w[1])
+    psi = 2.0 * np.pi * uniform53(w[2])
+    sz = np.sqrt(max(0.0, 1.0 - cz * cz))
+    u = np.array([sz * np.cos(phi), sz * np.sin(phi), cz])
+    s = 1.0 if u[2] >= 0.0 else -1.0
+    a = -1.0 / (s + u[2])
+    b = u[0] * u[1] * a
+    e1 = np.array([1.0 + s * u[0] * u[0] * a, s * b, -s * u[0]])
+    e2 = np.array([b, s + u[1] * u[1] * a, -u[1]])
+    v = np.cos(psi) * e1 + np.sin(psi) * e2
+    return u, v
+
+
+def box_centre(c, seed, box_L):
+    """Primary vertex c of the triplet-sphere scheme: uniform in the box."""
+    w = philox4x64((c, 0, 1, 0), (seed, 0))
+    return np.array([box_L * uniform53(w[0]), box_L * uniform53(w[1]), box_L * uniform53(w[2])])
+
+
+def triplet_thetas(n_theta):
+    """Opening angles at the centres of n_theta equal bins of [0, pi]."""
+    return (np.arange(n_theta) + 0.5) * np.pi / n_theta
+
+
+def triplet_mc(f2, f3, box_L, r12, r13, n_theta, n_rot, seed, centres=None, weights=None, n_box=0, f1=None):
+    """Monte-Carlo triple sums over random triangles (Sec. 3.4 Eq.
+    particle-based-sum; Sec. 4.3.3).
+
+    Primary vertices: the catalogue points ``centres`` (float32 [n, 3]) with
+    ``weights`` (or 1) as the primary factor a (the naked primary vertex of
+    the dual-sphere scheme), or, when ``centres`` is None, ``n_box`` uniform
+    points of the box with a = f1(x) (or 1 without f1; triplet sphere).  For
+    each centre, n_rot rotations (u, v); for each opening angle theta_j the
+    vertices x2 = x + r12 u and x3 = x + r13 (cos theta_j u + sin theta_j v)
+    read f2 and f3 (B3 interpolation).  Returns float64 [n_theta, 4]: the sums
+    of a, a f2(x2), a f3(x3) and a f2(x2) f3(x3) over all (centre, rotation).
+    """
+    thetas = triplet_thetas(n_theta)
+    if centres is not None:
+        xc = np.asarray(centres, dtype=np.float32).astype(np.float64)
+        a = np.ones(xc.shape[0]) if weights is None else np.asarray(weights, dtype=np.float32).astype(np.float64)
+    else:
+        xc = np.array([box_centre(c, seed, box_L) for c in range(n_box)]).reshape(-1, 3)
+        a = np.ones(xc.shape[0]) if f1 is None else interpolate(f1, xc, box_L)
+    n_c = xc.shape[0]
+    frames = [triangle_frame(c, r, seed) for c in range(n_c) for r in range(n_rot)]
+    u = np.array([f[0] for f in frames]).reshape(n_c * n_rot, 3)
+    v = np.array([f[1] for f in frames]).reshape(n_c * n_rot, 3)
+    x = np.repeat(xc, n_rot, axis=0)
+    aa = np.repeat(a, n_rot)
+    v2 = interpolate(f2, x + r12 * u, box_L)
+    out = np.zeros((n_theta, 4))
+    for j, th in enumerate(thetas):
+        v3 = interpolate(f3, x + r13 * (np.cos(th) * u + np.sin(th) * v), box_L)
+        out[j] = [np.sum(aa), np.sum(aa * v2), np.sum(aa * v3), np.sum(aa * v2 * v3)]
     return out

@@ -777,3 +777,88 @@ def test_xi_aniso_pair_sum_plane_wave_and_axes():
     g = O.xi_aniso(dh, L, wins, los_axis=2)
     dh_t = O.dft3(np.transpose(synth.cosine_field(n, [n0], [A]), (2, 1, 0)))
     assert np.max(np.abs(O.xi_aniso(dh_t, L, wins, los_axis=0) - g)) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Monte-Carlo triangles
+# --------------------------------------------------------------------------
+
+def test_philox_is_numpys_philox4x64():
+    """The oracle's Philox4x64-10 block equals numpy's Philox bit generator
+    (which advances its counter by one before each block)."""
+    for key in [(0, 0), (12345, 678), (2 ** 64 - 1, 2 ** 63 + 5)]:
+        for ctr in [(1, 0, 0, 0), (7, 3, 1, 0), (2 ** 64 - 1, 2, 0, 9), (123456789, 987654321, 5, 2 ** 60)]:
+            prev = list(ctr)
+            prev[0] -= 1
+            bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(prev, dtype=np.uint64))
+            want = [int(v) for v in bg.random_raw(4)]
+            assert list(O.philox4x64(ctr, key)) == want, (ctr, key)
+
+
+def test_triangle_frames_are_orthonormal_and_isotropic():
+    """u and v are orthonormal to rounding; over many (centre, rotation)
+    samples both are isotropic (mean 0, second moment I/3 within 4 sigma);
+    the vertices sit at r12, r13 with opening angle theta."""
+    n = 6000
+    us, vs = [], []
+    for i in range(n):
+        u, v = O.triangle_frame(i // 60, i % 60, 2607)
+        assert abs(u @ u - 1) < 1e-14 and abs(v @ v - 1) < 1e-14 and abs(u @ v) < 1e-14
+        us.append(u)
+        vs.append(v)
+    for a in (np.array(us), np.array(vs)):
+        assert np.all(np.abs(a.mean(axis=0)) < 4 * math.sqrt(1 / 3 / n))
+        m2 = a.T @ a / n
+        assert np.all(np.abs(m2 - np.eye(3) / 3) < 4 * math.sqrt(0.1 / n))
+    u, v = O.triangle_frame(3, 4, 11)
+    r12, r13 = 7.0, 11.0
+    for th in O.triplet_thetas(5):
+        d2, d3 = r12 * u, r13 * (math.cos(th) * u + math.sin(th) * v)
+        assert abs(np.linalg.norm(d3) - r13) < 1e-12
+        assert abs(d2 @ d3 - r12 * r13 * math.cos(th)) < 1e-11
+
+
+def test_box_centres_are_uniform():
+    L, n = 50.0, 4000
+    x = np.array([O.box_centre(c, 99, L) for c in range(n)])
+    assert np.all((x > 0) & (x < L))
+    assert np.all(np.abs(x.mean(axis=0) - L / 2) < 4 * L / math.sqrt(12 * n))
+    assert np.all(np.abs(x.var(axis=0) - L * L / 12) < 4 * L * L / math.sqrt(180 * n))
+
+
+def test_triplet_mc_constant_fields_and_weights():
+    """Constant fields give the sums exactly: sum a = total weight times the
+    rotations, and every product scales with the constants."""
+    n, L = 8, 20.0
+    f2 = np.full((n, n, n), 3.0)
+    f3 = np.full((n, n, n), -0.5)
+    pts = np.random.default_rng(1).uniform(0, L, (17, 3)).astype(np.float32)
+    w = np.random.default_rng(2).uniform(0.5, 2.0, 17).astype(np.float32)
+    got = O.triplet_mc(f2, f3, L, 4.0, 6.0, 3, 5, 7, centres=pts, weights=w)
+    W = 5 * float(np.sum(w.astype(np.float64)))
+    assert np.allclose(got, np.tile([W, 3.0 * W, -0.5 * W, -1.5 * W], (3, 1)), rtol=1e-13, atol=0)
+    f1 = np.full((n, n, n), 2.0)
+    got = O.triplet_mc(f2, f3, L, 4.0, 6.0, 2, 4, 7, n_box=9, f1=f1)
+    assert np.allclose(got, np.tile([72.0, 216.0, -36.0, -108.0], (2, 1)), rtol=1e-13, atol=0)
+
+
+def test_triplet_mc_plane_wave_pair_expectation():
+    """Triplet-sphere centres, f2 = f3 = a grid plane wave cos(2 pi n0.l/N):
+    its B3 expansion is sinc^4(pi n0/N) cos(k0.x) up to alias terms of
+    relative size (|n0|/N)^8, so the expected pair product at the two outer
+    vertices is (1/2) Phi^(n0) sin(k0 r23)/(k0 r23) with
+    r23^2 = r12^2 + r13^2 - 2 r12 r13 cos(theta); the Monte-Carlo mean is
+    held to 4 standard errors."""
+    n, L = 32, 64.0
+    n0 = np.array([1, 2, -1])
+    f = synth.cosine_field(n, [n0], [1.0])
+    k0 = 2 * np.pi / L * np.linalg.norm(n0)
+    ph = float(np.prod(np.sinc(n0 / n) ** 8))
+    r12, r13, nth = 9.0, 14.0, 4
+    n_c, n_r = 300, 40
+    got = O.triplet_mc(f, f, L, r12, r13, nth, n_r, 31, n_box=n_c)
+    for j, th in enumerate(O.triplet_thetas(nth)):
+        r23 = math.sqrt(r12 ** 2 + r13 ** 2 - 2 * r12 * r13 * math.cos(th))
+        want = 0.5 * ph * math.sin(k0 * r23) / (k0 * r23)
+        mean = got[j, 3] / got[j, 0]
+        assert abs(mean - want) < 4 * 0.5 / math.sqrt(n_c * n_r), (th, mean, want)
