@@ -237,11 +237,12 @@ def other_configs(warmup: int, steps: int) -> dict:
 
     out = {}
 
-    def record(name, step, cells_bins, desc):
-        s, prof = time_steps(step, warmup, steps, hermes, name)
-        out[name] = {"workload": desc, "ms_per_step": round(s * 1e3, 3), "steps": steps, "warmup": warmup,
-                     "cells_bins_per_s": round(cells_bins / s, 1),
-                     "stage_ms": {k: round(v[1] / steps, 3) for k, v in sorted(prof.items())}}
+    def record(name, step, count, desc, per="cells_bins", n_steps=None):
+        k = steps if n_steps is None else n_steps
+        s, prof = time_steps(step, warmup, k, hermes, name)
+        out[name] = {"workload": desc, "ms_per_step": round(s * 1e3, 3), "steps": k, "warmup": warmup,
+                     f"{per}_per_s": round(count / s, 1),
+                     "stage_ms": {kk: round(v[1] / k, 3) for kk, v in sorted(prof.items())}}
 
     # 64^3, float64: 2e4 points, 20-bin 2PCF over [5, 50]
     wl = synth.WORKLOADS["ns64_fp64"]
@@ -285,6 +286,32 @@ def other_configs(warmup: int, steps: int) -> dict:
            "windows at 46 x 51 (s, mu) bin centres (s in [2, 186], mu in [0, 1])")
     out["ns256_smu"]["ms_per_window"] = round(out["ns256_smu"]["ms_per_step"] / len(rings), 6)
     del xawork
+
+    # DDD(theta; r12 = 20, r13 = 40) by Monte-Carlo triangles, 20 opening
+    # angles, the secondary vertices on the sphere-smoothed (R = 5) contrast:
+    # dual sphere (406,728 catalogue points as primary vertices, 1000
+    # rotations each) and triplet sphere (8e6 box points, 200 rotations)
+    eps, sw = hermes.assign(pos, None, wl.box_L, n)
+    dk, _ = hermes.fft(eps, sw, want_delta=False)
+    fld = hermes.filter_bins(dk, wl.box_L, [("sphere", 0.0, 5.0)], store_fields=True, moments=False)[0][0]
+    del eps, dk
+    cen = pos[:406_728].contiguous()
+    twork = torch.empty(hermes.workspace_size(hermes.OP_TRIPLET, n, torch.float32, 20, 0), dtype=torch.uint8,
+                        device="cuda")
+    tout = torch.empty((20, 4), dtype=torch.float64, device="cuda")
+    for name, n_c, n_rot, kw, desc in [
+            ("ns256_ddd_particle", cen.shape[0], 1000, {"centres": cen},
+             "DDD(theta; 20, 40), 20 angles: 406,728 catalogue points of the 256^3 workload as primary vertices "
+             "x 1000 rotations, sphere-smoothed (R = 5) contrast at the other vertices"),
+            ("ns256_ddd_box", 8_000_000, 200, {"n_box": 8_000_000, "f1": fld},
+             "DDD(theta; 20, 40), 20 angles: 8e6 uniform box points x 200 rotations, sphere-smoothed (R = 5) "
+             "contrast at all three vertices")]:
+        def step_ddd(kw=kw, n_rot=n_rot):
+            hermes.triplet_mc(fld, fld, wl.box_L, 20.0, 40.0, 20, n_rot, 2607, out=tout, work=twork, **kw)
+        combos = n_c * n_rot * 20
+        record(name, step_ddd, combos, desc, per="combinations", n_steps=1)
+        out[name]["ns_per_combination"] = round(out[name]["ms_per_step"] * 1e6 / combos, 4)
+    del fld, cen, twork, tout
     del pos
     torch.cuda.empty_cache()
 

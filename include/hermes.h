@@ -10,6 +10,7 @@
  *   -> 3PCF multipoles zeta_l(r1, r2)                 (hermes_zeta_l)
  *   -> anisotropic 2PCF with axisymmetric windows     (hermes_xi_aniso)
  *   -> field values and density marks at positions    (hermes_readout)
+ *   -> Monte-Carlo triangle sums (dual-/triplet-sphere 3PCF) (hermes_triplet_mc)
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -93,7 +94,8 @@ typedef enum hermes_op {
     HERMES_OP_XI = 2,
     HERMES_OP_FILTER = 3,
     HERMES_OP_ZETA = 4,
-    HERMES_OP_XI_ANISO = 5
+    HERMES_OP_XI_ANISO = 5,
+    HERMES_OP_TRIPLET = 6
 } hermes_op;
 
 typedef struct hermes_ctx_s* hermes_ctx;
@@ -102,6 +104,7 @@ typedef struct hermes_ctx_s* hermes_ctx;
 #define HERMES_MAX_ELLS 8    /* multipoles per hermes_xi call */
 #define HERMES_MAX_LMAX 16   /* highest 3PCF multipole */
 #define HERMES_MAX_ANISO (1 << 20)   /* windows per hermes_xi_aniso call */
+#define HERMES_MAX_THETA 64          /* opening angles per hermes_triplet_mc call */
 
 /* Create a context on HIP device `device`; fills *out.  Allocates the
  * context's constant tables (about 2.6 MB) on that device. */
@@ -115,7 +118,8 @@ void hermes_destroy(hermes_ctx ctx);
 const char* hermes_last_error(void);
 
 /* Device workspace, in bytes, that `op` needs for an N^3 grid.  n_batch is
- * the number of points (ASSIGN), windows (FILTER, XI_ANISO) or radial bins (ZETA);
+ * the number of points (ASSIGN), windows (FILTER, XI_ANISO), radial bins (ZETA) or
+ * opening angles (TRIPLET);
  * n_ells the number of multipoles (XI).  Zero for FFT, which needs none. */
 hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtype,
                                     int n_batch, int n_ells, size_t* bytes);
@@ -286,6 +290,44 @@ hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, i
                               double box_L, const hermes_aniso_window* win, int n_win,
                               int los_axis, double* xi, void* work, size_t work_bytes,
                               hipStream_t stream);
+
+/* Monte-Carlo triangle sums (Sec. 3.4 particle-based summation, Eq.
+ * particle-based-sum; Sec. 4.3.3 dual-/triplet-sphere 3PCF).  Primary
+ * vertices: the n_centres catalogue points `centres` (dual sphere; primary
+ * factor a = weight, or 1 when weights is NULL), or, when centres is NULL,
+ * n_centres uniform points of the box (triplet sphere; a = f1 read at the
+ * point, or 1 when f1 is NULL).  Each primary vertex x gets n_rot random
+ * rotations (u, v), u uniform on the sphere and v uniform on the circle
+ * orthogonal to u; for theta_j = (j + 1/2) pi / n_theta the triangle's other
+ * vertices are x + r12 u and x + r13 (cos theta_j u + sin theta_j v), where
+ * f2 and f3 are read by B3 interpolation (positions in float64).
+ *   out[j] = ( sum a, sum a f2(x2), sum a f3(x3_j), sum a f2(x2) f3(x3_j) )
+ * over all (centre, rotation), accumulated in float64 in a fixed order (the
+ * result is the same on every run).  The ratio of the last to the first is
+ * the Monte-Carlo mean triple product: with filtered contrasts
+ * f = delta_W it estimates the smoothed 3PCF at (r12, r13, theta_j) (box
+ * points with a = 1 + f1), or the particle-weighted pair product of the
+ * dual-sphere scheme.
+ * Random numbers: Philox4x64-10 (Salmon et al., SC'11), key (seed, 0),
+ * counter (centre, rotation, 0, 0) for a rotation's words w0..w2 (cos of the
+ * polar angle 2 u0 - 1, azimuth 2 pi u1, angle of v 2 pi u2) and
+ * (centre, 0, 1, 0) for a box point (L u0, L u1, L u2), u = (w >> 11 + 1/2) 2^-53;
+ * the frame orthogonal to u is built as in Duff et al. (JCGT 2017).
+ *   f1, f2, f3  device [N^3] fields of dtype (f1 NULL unless box points)
+ *   centres     device float32 [n_centres][3] or NULL; weights device float32
+ *               [n_centres] or NULL (only with centres)
+ *   out         device double [n_theta][4]; overwritten
+ *   work        device workspace of >= hermes_workspace_size(TRIPLET, n_batch
+ *               = n_theta) bytes
+ * ERR_ARG for NULL f2, f3, out or work, f1 given with centres, weights
+ * without centres, n_centres < 0, n_rot < 1, n_centres n_rot >= 2^62,
+ * n_theta outside [1, HERMES_MAX_THETA], r12 or r13 negative, not finite or
+ * >= L/2, a bad N, dtype or box_L; ERR_OOM if work_bytes is too small. */
+hermes_status hermes_triplet_mc(hermes_ctx ctx, const void* f1, const void* f2, const void* f3,
+                                int n_grid, int dtype, double box_L, const float* centres,
+                                const float* weights, int64_t n_centres, double r12, double r13,
+                                int n_theta, int n_rot, uint64_t seed, double* out, void* work,
+                                size_t work_bytes, hipStream_t stream);
 
 /* Density-derived marks (Sec. 3.3.1).  With v the value read at a point
  * (hermes_readout) and rho = max(1 + v - self_term, 0) the local density in

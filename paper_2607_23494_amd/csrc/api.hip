@@ -312,6 +312,11 @@ hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtyp
                 return fail(HERMES_ERR_ARG, "hermes_workspace_size: XI_ANISO needs 1..2^20 windows");
             *bytes = aniso_workspace(ctx, n_grid, n_batch);
             return HERMES_OK;
+        case HERMES_OP_TRIPLET:
+            if (n_batch < 1 || n_batch > HERMES_MAX_THETA)
+                return fail(HERMES_ERR_ARG, "hermes_workspace_size: TRIPLET needs 1..64 opening angles");
+            *bytes = triplet_workspace(n_batch);
+            return HERMES_OK;
         case HERMES_OP_ZETA:
             if (dtype != HERMES_F32) return fail(HERMES_ERR_UNSUPPORTED, "hermes_workspace_size: ZETA runs in float32");
             if (n_batch < 1 || n_batch > HERMES_MAX_BINS)
@@ -426,6 +431,31 @@ hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, i
         return fail(HERMES_ERR_OOM, "hermes_xi_aniso: workspace too small");
     DeviceGuard g(ctx->device);
     return xi_aniso_impl(ctx, delta_k, n_grid, dtype, box_L, win, n_win, los_axis, xi, work, stream);
+}
+
+hermes_status hermes_triplet_mc(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, int n_grid,
+                                int dtype, double box_L, const float* centres, const float* weights,
+                                int64_t n_centres, double r12, double r13, int n_theta, int n_rot, uint64_t seed,
+                                double* out, void* work, size_t work_bytes, hipStream_t stream) {
+    if (!ctx || !f2 || !f3 || !out || !work) return fail(HERMES_ERR_ARG, "hermes_triplet_mc: NULL argument");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_triplet_mc: N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_triplet_mc: bad dtype");
+    if (!(box_L > 0.0) || !std::isfinite(box_L)) return fail(HERMES_ERR_ARG, "hermes_triplet_mc: box_L must be > 0");
+    if (centres && f1) return fail(HERMES_ERR_ARG, "hermes_triplet_mc: f1 is read at box points only (centres NULL)");
+    if (!centres && weights) return fail(HERMES_ERR_ARG, "hermes_triplet_mc: weights need centres");
+    if (n_centres < 0) return fail(HERMES_ERR_ARG, "hermes_triplet_mc: n_centres < 0");
+    if (n_rot < 1) return fail(HERMES_ERR_ARG, "hermes_triplet_mc: n_rot must be >= 1");
+    if (n_centres > (int64_t(1) << 62) / n_rot)
+        return fail(HERMES_ERR_ARG, "hermes_triplet_mc: n_centres n_rot must be below 2^62");
+    if (n_theta < 1 || n_theta > HERMES_MAX_THETA)
+        return fail(HERMES_ERR_ARG, "hermes_triplet_mc: n_theta must be in [1, 64]");
+    if (!std::isfinite(r12) || !std::isfinite(r13) || r12 < 0.0 || r13 < 0.0 || !(r12 < 0.5 * box_L) ||
+        !(r13 < 0.5 * box_L))
+        return fail(HERMES_ERR_ARG, "hermes_triplet_mc: r12 and r13 must be in [0, L/2)");
+    if (work_bytes < triplet_workspace(n_theta)) return fail(HERMES_ERR_OOM, "hermes_triplet_mc: workspace too small");
+    DeviceGuard g(ctx->device);
+    return triplet_impl(ctx, f1, f2, f3, n_grid, dtype, box_L, centres, weights, n_centres, r12, r13, n_theta, n_rot,
+                        seed, out, work, stream);
 }
 
 hermes_status hermes_filter_bins(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype,

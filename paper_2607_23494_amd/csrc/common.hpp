@@ -124,6 +124,11 @@ hermes_status xi_aniso_impl(hermes_ctx ctx, const void* delta_k, int n, int dtyp
                             const hermes_aniso_window* win, int n_win, int los_axis, double* xi, void* work,
                             hipStream_t stream);
 size_t aniso_workspace(hermes_ctx ctx, int n, int n_win);
+hermes_status triplet_impl(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, int n, int dtype,
+                           double box_L, const float* centres, const float* weights, int64_t n_centres, double r12,
+                           double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
+                           hipStream_t stream);
+size_t triplet_workspace(int n_theta);
 hermes_status readout_impl(hermes_ctx ctx, const void* field, int n, int dtype, double box_L, const float* pos,
                            const float* weight, int64_t n_pts, const hermes_mark* mark, void* out,
                            double* moments, hipStream_t stream);

@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "interp.hpp"
 #include "kernels.hpp"
 
 namespace hermes {
@@ -21,15 +22,6 @@ struct MarkParams {
     int kind;
     double exponent, offset, self_term;
 };
-
-// B3 weights of the nodes i0-1 .. i0+2 for the fractional offset t in [0, 1).
-__device__ __forceinline__ void b3_weights(double t, double w[4]) {
-    const double s = 1.0 - t;
-    w[0] = s * s * s / 6.0;
-    w[1] = (4.0 - 6.0 * t * t + 3.0 * t * t * t) / 6.0;
-    w[2] = (4.0 - 6.0 * s * s + 3.0 * s * s * s) / 6.0;
-    w[3] = t * t * t / 6.0;
-}
 
 __device__ __forceinline__ double apply_mark(const MarkParams& mk, double v) {
     const double rho = fmax(1.0 + v - mk.self_term, 0.0);
@@ -47,34 +39,9 @@ __global__ __launch_bounds__(kThreads) void k_readout(const T* __restrict__ fiel
     double m2 = 0.0, m3 = 0.0, m4 = 0.0;
     const int64_t stride = int64_t(gridDim.x) * kThreads;
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride) {
-        int cell[3];
-        double tap[3][4];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double u = double(pos[3 * i + a]) * scale;   // position in cell units
-            u -= double(N) * floor(u / double(N));       // periodic wrap into [0, N)
-            const double f = floor(u);
-            cell[a] = int(f);
-            b3_weights(u - f, tap[a]);
-        }
-        int cz[4];
-#pragma unroll
-        for (int oz = 0; oz < 4; ++oz) cz[oz] = (cell[2] - 1 + oz) & (N - 1);
-        double v = 0.0;
-#pragma unroll
-        for (int ox = 0; ox < 4; ++ox) {
-            const int cx = (cell[0] - 1 + ox) & (N - 1);
-            double vx = 0.0;
-#pragma unroll
-            for (int oy = 0; oy < 4; ++oy) {
-                const int cy = (cell[1] - 1 + oy) & (N - 1);
-                const T* row = field + (size_t(cx) * N + cy) * N;
-                const double vy = tap[2][0] * double(row[cz[0]]) + tap[2][1] * double(row[cz[1]]) +
-                                  tap[2][2] * double(row[cz[2]]) + tap[2][3] * double(row[cz[3]]);
-                vx += tap[1][oy] * vy;
-            }
-            v += tap[0][ox] * vx;
-        }
+        const double u[3] = {double(pos[3 * i]) * scale, double(pos[3 * i + 1]) * scale,
+                             double(pos[3 * i + 2]) * scale};   // position in cell units
+        const double v = b3_value<T, N>(field, u);
         if (mom) {
             const double v2 = v * v;
             m2 += v2;

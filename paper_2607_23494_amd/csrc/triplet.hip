@@ -1,0 +1,230 @@
+// Monte-Carlo triangle sums (Sec. 3.4, particle-based summation, Eq.
+// particle-based-sum; Sec. 4.3.3, the dual-/triplet-sphere 3PCF).
+//
+// A sample is a primary vertex x (a catalogue point, or a uniform point of
+// the box drawn from the generator) and a random rotation (u, v): u uniform
+// on the sphere, v uniform on the circle orthogonal to u.  For every opening
+// angle theta_j = (j + 1/2) pi / n_theta the triangle has its second vertex at
+// x + r12 u and its third at x + r13 (cos theta_j u + sin theta_j v); the
+// secondary vertices read the filtered fields f2, f3 by B3 interpolation.
+// The sums over samples of a, a f2, a f3 and a f2 f3 (a = the point's weight,
+// or f1 at a box point) are accumulated in float64.
+//
+// Random numbers are Philox4x64-10 blocks (Salmon, Moraes, Dror and Shaw,
+// SC'11) with counter (centre, rotation, 0, 0) for a rotation and
+// (centre, 0, 1, 0) for a box point, key (seed, 0): every sample can be drawn
+// by any thread, and the oracle draws the same numbers.
+//
+// One thread per sample (grid-stride); per opening angle the wavefront's 64
+// samples are summed by a butterfly over lanes and lane 0 adds them to the
+// wavefront's LDS accumulators, so every sum is formed in a fixed order and
+// the result does not depend on timing.
+#include <cmath>
+
+#include "common.hpp"
+#include "interp.hpp"
+#include "kernels.hpp"
+
+namespace hermes {
+
+constexpr int kTripletBlocks = 2048;   // workgroups of the sampling kernel (grid-stride)
+constexpr int kTripletWaves = kThreads / 64;
+
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull, kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull, kPhiloxW1 = 0xBB67AE8584CAA73Bull;
+
+// Ten Philox4x64 rounds on the counter c with key (k0, k1).
+__device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = kPhiloxM0 * c[0], hi0 = __umul64hi(kPhiloxM0, c[0]);
+        const uint64_t lo1 = kPhiloxM1 * c[2], hi1 = __umul64hi(kPhiloxM1, c[2]);
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+}
+
+// The top 53 bits of a word plus one half, scaled to (0, 1).
+__device__ __forceinline__ double uniform53(uint64_t w) { return (double(w >> 11) + 0.5) * 0x1p-53; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+size_t triplet_workspace(int n_theta) { return align256(size_t(kTripletBlocks) * n_theta * 4 * sizeof(double)); }
+
+template <typename T, int N, bool BOX>
+__global__ __launch_bounds__(kThreads) void k_triplet(const T* __restrict__ f1, const T* __restrict__ f2,
+                                                      const T* __restrict__ f3, const float* __restrict__ centres,
+                                                      const float* __restrict__ weights, int64_t n_centres, int n_rot,
+                                                      double box_L, double r12, double r13, int n_theta,
+                                                      uint64_t seed, double* __restrict__ part) {
+    __shared__ double acc[kTripletWaves][HERMES_MAX_THETA][2];   // per wavefront: sum a f3, sum a f2 f3
+    __shared__ double red[kThreads];
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int j = threadIdx.x; j < kTripletWaves * HERMES_MAX_THETA; j += kThreads) {
+        acc[j / HERMES_MAX_THETA][j % HERMES_MAX_THETA][0] = 0.0;
+        acc[j / HERMES_MAX_THETA][j % HERMES_MAX_THETA][1] = 0.0;
+    }
+    __syncthreads();
+    const double scale = double(N) / box_L;
+    const int64_t total = n_centres * int64_t(n_rot);
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    double s0 = 0.0, s1 = 0.0;
+    // the loop bound is uniform over a wavefront, so all of its lanes take part
+    // in every butterfly
+    for (int64_t base = int64_t(blockIdx.x) * kThreads + wv * 64; base < total; base += stride) {
+        const int64_t s = base + lane;
+        const bool live = s < total;
+        double a = 0.0, v2 = 0.0, x[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 1.0}, v[3] = {1.0, 0.0, 0.0};
+        if (live) {
+            const int64_t c = s / n_rot, r = s - (s / n_rot) * n_rot;
+            if constexpr (BOX) {
+                uint64_t w[4] = {uint64_t(c), 0, 1, 0};
+                philox4x64(w, seed, 0);
+                x[0] = box_L * uniform53(w[0]);
+                x[1] = box_L * uniform53(w[1]);
+                x[2] = box_L * uniform53(w[2]);
+                if (f1) {
+                    const double uc[3] = {x[0] * scale, x[1] * scale, x[2] * scale};
+                    a = b3_value<T, N>(f1, uc);
+                } else {
+                    a = 1.0;
+                }
+            } else {
+                x[0] = double(centres[3 * c]);
+                x[1] = double(centres[3 * c + 1]);
+                x[2] = double(centres[3 * c + 2]);
+                a = weights ? double(weights[c]) : 1.0;
+            }
+            uint64_t w[4] = {uint64_t(c), uint64_t(r), 0, 0};
+            philox4x64(w, seed, 0);
+            const double cz = 2.0 * uniform53(w[0]) - 1.0;
+            const double phi = 2.0 * M_PI * uniform53(w[1]);
+            const double psi = 2.0 * M_PI * uniform53(w[2]);
+            const double sz = sqrt(fmax(0.0, 1.0 - cz * cz));
+            u[0] = sz * cos(phi);
+            u[1] = sz * sin(phi);
+            u[2] = cz;
+            // orthonormal basis of the plane orthogonal to u (Duff et al.,
+            // JCGT 2017), then v at angle psi in it
+            const double sg = u[2] >= 0.0 ? 1.0 : -1.0;
+            const double ia = -1.0 / (sg + u[2]);
+            const double b = u[0] * u[1] * ia;
+            const double e1[3] = {1.0 + sg * u[0] * u[0] * ia, sg * b, -sg * u[0]};
+            const double e2[3] = {b, sg + u[1] * u[1] * ia, -u[1]};
+            const double cp = cos(psi), sp = sin(psi);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[k] = cp * e1[k] + sp * e2[k];
+            const double p2[3] = {(x[0] + r12 * u[0]) * scale, (x[1] + r12 * u[1]) * scale,
+                                  (x[2] + r12 * u[2]) * scale};
+            v2 = b3_value<T, N>(f2, p2);
+        }
+        s0 += a;
+        s1 += a * v2;
+        for (int j = 0; j < n_theta; ++j) {
+            double p3 = 0.0, p23 = 0.0;
+            if (live) {
+                const double th = (double(j) + 0.5) * M_PI / double(n_theta);
+                const double ct = cos(th), st = sin(th);
+                const double q[3] = {(x[0] + r13 * (ct * u[0] + st * v[0])) * scale,
+                                     (x[1] + r13 * (ct * u[1] + st * v[1])) * scale,
+                                     (x[2] + r13 * (ct * u[2] + st * v[2])) * scale};
+                const double v3 = b3_value<T, N>(f3, q);
+                p3 = a * v3;
+                p23 = a * v2 * v3;
+            }
+            p3 = wave_sum(p3);
+            p23 = wave_sum(p23);
+            if (lane == 0) {
+                acc[wv][j][0] += p3;
+                acc[wv][j][1] += p23;
+            }
+        }
+    }
+    const double b0 = block_sum(s0, red);
+    const double b1 = block_sum(s1, red);   // block_sum ends with a barrier: acc is complete
+    for (int j = threadIdx.x; j < n_theta; j += kThreads) {
+        double t3 = 0.0, t23 = 0.0;
+        for (int k = 0; k < kTripletWaves; ++k) {
+            t3 += acc[k][j][0];
+            t23 += acc[k][j][1];
+        }
+        double* dst = part + (int64_t(blockIdx.x) * n_theta + j) * 4;
+        dst[0] = b0;
+        dst[1] = b1;
+        dst[2] = t3;
+        dst[3] = t23;
+    }
+}
+
+__global__ void k_triplet_final(const double* __restrict__ part, int n_blocks, int n_theta, double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_theta * 4) return;
+    double s = 0.0;
+    for (int b = 0; b < n_blocks; ++b) s += part[int64_t(b) * n_theta * 4 + i];
+    out[i] = s;
+}
+
+template <typename T, int N>
+static hermes_status triplet_n(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, double box_L,
+                               const float* centres, const float* weights, int64_t n_centres, double r12,
+                               double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
+                               hipStream_t stream) {
+    double* part = static_cast<double*>(work);
+    const int64_t total = n_centres * int64_t(n_rot);
+    const int64_t want = (total + kThreads - 1) / kThreads;
+    const int blocks = int(want < 1 ? 1 : (want < kTripletBlocks ? want : kTripletBlocks));
+    {
+        LaunchScope ls(ctx, stream, "triplet");
+        if (centres) {
+            hipLaunchKernelGGL((k_triplet<T, N, false>), dim3(blocks), dim3(kThreads), 0, stream,
+                               static_cast<const T*>(f1), static_cast<const T*>(f2), static_cast<const T*>(f3),
+                               centres, weights, n_centres, n_rot, box_L, r12, r13, n_theta, seed, part);
+        } else {
+            hipLaunchKernelGGL((k_triplet<T, N, true>), dim3(blocks), dim3(kThreads), 0, stream,
+                               static_cast<const T*>(f1), static_cast<const T*>(f2), static_cast<const T*>(f3),
+                               centres, weights, n_centres, n_rot, box_L, r12, r13, n_theta, seed, part);
+        }
+    }
+    {
+        LaunchScope ls(ctx, stream, "reduce");
+        hipLaunchKernelGGL(k_triplet_final, dim3((n_theta * 4 + 127) / 128), dim3(128), 0, stream, part, blocks,
+                           n_theta, out);
+    }
+    return check_launch("hermes_triplet_mc");
+}
+
+hermes_status triplet_impl(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, int n, int dtype,
+                           double box_L, const float* centres, const float* weights, int64_t n_centres, double r12,
+                           double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
+                           hipStream_t stream) {
+#define HERMES_TRIPLET_CASE(NN)                                                                                 \
+    case NN:                                                                                                    \
+        return dtype == HERMES_F32 ? triplet_n<float, NN>(ctx, f1, f2, f3, box_L, centres, weights, n_centres,  \
+                                                          r12, r13, n_theta, n_rot, seed, out, work, stream)    \
+                                   : triplet_n<double, NN>(ctx, f1, f2, f3, box_L, centres, weights, n_centres, \
+                                                           r12, r13, n_theta, n_rot, seed, out, work, stream);
+    switch (n) {
+        HERMES_TRIPLET_CASE(8)
+        HERMES_TRIPLET_CASE(16)
+        HERMES_TRIPLET_CASE(32)
+        HERMES_TRIPLET_CASE(64)
+        HERMES_TRIPLET_CASE(128)
+        HERMES_TRIPLET_CASE(256)
+        HERMES_TRIPLET_CASE(512)
+        HERMES_TRIPLET_CASE(1024)
+        default:
+            return fail(HERMES_ERR_ARG, "hermes_triplet_mc: unsupported N");
+    }
+#undef HERMES_TRIPLET_CASE
+}
+
+}  // namespace hermes

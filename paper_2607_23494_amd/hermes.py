@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_PKG, "libhermes.so")
 F32, F64 = 0, 1
 PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
 WIN = {"shell": 0, "sphere": 1, "gauss": 2, "sh_shell": 3}
-OP_ASSIGN, OP_FFT, OP_XI, OP_FILTER, OP_ZETA, OP_XI_ANISO = range(6)
+OP_ASSIGN, OP_FFT, OP_XI, OP_FILTER, OP_ZETA, OP_XI_ANISO, OP_TRIPLET = range(7)
 ANISO = {"ring": 0, "ring_bin": 1, "gauss_ring": 2, "disk": 3, "cylinder": 4, "cylshell": 5, "gauss_shell": 6}
 MAX_BINS = 64
 
@@ -69,13 +69,15 @@ def _load() -> ctypes.CDLL:
     lib.hermes_xi.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, vp, sz, vp]
     lib.hermes_xi_static.argtypes = [vp, vp, i32, i32, f64, vp, i32, vp, i32, i32, vp, vp, vp]
     lib.hermes_xi_aniso.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_AnisoWindow), i32, i32, vp, vp, sz, vp]
+    lib.hermes_triplet_mc.argtypes = [vp, vp, vp, vp, i32, i32, f64, vp, vp, i64, f64, f64, i32, i32,
+                                      ctypes.c_uint64, vp, vp, sz, vp]
     lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
     lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
     lib.hermes_readout.argtypes = [vp, vp, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp, vp]
     lib.hermes_profile_enable.argtypes = [vp, i32]
     lib.hermes_profile_reset.argtypes = [vp]
     lib.hermes_profile_read.argtypes = [vp, i32, ctypes.c_char_p, sz, ctypes.POINTER(i64), ctypes.POINTER(f64)]
-    for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi", "hermes_xi_static", "hermes_xi_aniso",
+    for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi", "hermes_xi_static", "hermes_xi_aniso", "hermes_triplet_mc",
                  "hermes_filter_bins", "hermes_zeta_l", "hermes_readout", "hermes_profile_enable", "hermes_profile_reset",
                  "hermes_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
@@ -247,6 +249,38 @@ def xi_aniso(delta_k: torch.Tensor, box_L: float, windows, los_axis: int = 2, ou
             out = torch.empty((nw,), dtype=torch.float64, device=delta_k.device)
         _check(_lib.hermes_xi_aniso(context(dev), _ptr(delta_k), n, _dtype_code(delta_k.dtype), float(box_L), arr, nw,
                                     los_axis, _ptr(out), _ptr(w), wbytes, _stream(dev, stream)))
+    return out
+
+
+def triplet_mc(f2: torch.Tensor, f3: torch.Tensor, box_L: float, r12: float, r13: float, n_theta: int,
+               n_rot: int, seed: int, centres: torch.Tensor | None = None, weights: torch.Tensor | None = None,
+               n_box: int = 0, f1: torch.Tensor | None = None, out: torch.Tensor | None = None,
+               work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Monte-Carlo triangle sums: device float64 [n_theta, 4] = (sum a, sum a f2,
+    sum a f3, sum a f2 f3) over n_rot rotations of every primary vertex: the
+    points `centres` (weights as a) or, without centres, n_box uniform box
+    points (f1 as a)."""
+    dev = _dev(f2)
+    n = f2.shape[0]
+    for f in (f1, f3):
+        if f is not None and (f.shape != f2.shape or f.dtype != f2.dtype or not f.is_contiguous()):
+            raise ValueError("f1, f2, f3 must share shape and dtype and be contiguous")
+    if centres is not None and (centres.dtype != torch.float32 or centres.dim() != 2 or centres.shape[1] != 3
+                                or not centres.is_contiguous()):
+        raise ValueError("centres must be a contiguous float32 [n, 3] device tensor")
+    if weights is not None and (centres is None or weights.dtype != torch.float32
+                                or weights.numel() != centres.shape[0] or not weights.is_contiguous()):
+        raise ValueError("weights must be a contiguous float32 [n] tensor beside centres")
+    n_c = int(centres.shape[0]) if centres is not None else int(n_box)
+    wbytes = workspace_size(OP_TRIPLET, n, f2.dtype, n_theta, 0, dev)
+    with _on(stream):
+        w = _workspace(wbytes, dev, work)
+        if out is None:
+            out = torch.empty((n_theta, 4), dtype=torch.float64, device=f2.device)
+        _check(_lib.hermes_triplet_mc(context(dev), _ptr(f1), _ptr(f2), _ptr(f3), n, _dtype_code(f2.dtype),
+                                      float(box_L), _ptr(centres), _ptr(weights), n_c, float(r12), float(r13),
+                                      int(n_theta), int(n_rot), int(seed) & ((1 << 64) - 1), _ptr(out), _ptr(w),
+                                      wbytes, _stream(dev, stream)))
     return out
 
 

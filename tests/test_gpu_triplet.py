@@ -1,0 +1,121 @@
+"""Parity of hermes_triplet_mc (Monte-Carlo triangle sums of the dual- and
+triplet-sphere 3PCF) with the FP64 oracle, through the C ABI.
+
+Both sides draw the same Philox4x64-10 numbers, so the comparison is sample
+by sample: the four sums per opening angle must agree to 1e-10 (float64
+fields) or 1e-5 normwise (float32 fields, read in float64).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2607_23494_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def normwise(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    return float(np.max(np.abs(got - ref)) / scale)
+
+
+def _fields(n, L, seed):
+    """Smooth seeded fields: a clustered catalogue's contrast filtered by a
+    sphere (vertex 2) and a Gaussian (vertex 3), and a third for box points."""
+    pos = synth.neyman_scott(60, 30, 2.0, L, seed)
+    eps, sw = O.assign(pos, None, L, n)
+    dh = O.dft3(O.contrast(eps, sw))
+    f2 = O.filtered_field(dh, L, O.cic_window("sphere", 4.0))
+    f3 = O.filtered_field(dh, L, O.cic_window("gauss", 3.0))
+    f1 = 1.0 + O.filtered_field(dh, L, O.cic_window("sphere", 2.0))
+    return pos, f1, f2, f3
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [16, 64])
+def test_triplet_dual_sphere(hermes, dtype, n):
+    L = 100.0
+    pos, _, f2, f3 = _fields(n, L, 8100 + n)
+    w = synth.lognormal_marks(pos.shape[0], 3)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    c = pos[:257]
+    got = hermes.triplet_mc(torch.from_numpy(f2.astype(npdt)).cuda(), torch.from_numpy(f3.astype(npdt)).cuda(), L,
+                            12.0, 20.0, 7, 9, 2607, centres=torch.from_numpy(c).cuda(),
+                            weights=torch.from_numpy(w[:257]).cuda()).cpu().numpy()
+    ref = O.triplet_mc(f2.astype(npdt), f3.astype(npdt), L, 12.0, 20.0, 7, 9, 2607, centres=c, weights=w[:257])
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    for q in range(4):
+        assert normwise(got[:, q], ref[:, q]) < tol, q
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_triplet_box_points(hermes, dtype):
+    """Triplet-sphere scheme: box points from the generator, a = f1 there;
+    also without f1 (a = 1), with a ragged sample count."""
+    n, L = 32, 80.0
+    _, f1, f2, f3 = _fields(n, L, 8200)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    t = lambda a: torch.from_numpy(a.astype(npdt)).cuda()
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    got = hermes.triplet_mc(t(f2), t(f3), L, 10.0, 15.0, 5, 7, 99, n_box=301, f1=t(f1)).cpu().numpy()
+    ref = O.triplet_mc(f2.astype(npdt), f3.astype(npdt), L, 10.0, 15.0, 5, 7, 99, n_box=301, f1=f1.astype(npdt))
+    for q in range(4):
+        assert normwise(got[:, q], ref[:, q]) < tol, q
+    got = hermes.triplet_mc(t(f2), t(f3), L, 10.0, 15.0, 64, 3, 5, n_box=77).cpu().numpy()
+    ref = O.triplet_mc(f2.astype(npdt), f3.astype(npdt), L, 10.0, 15.0, 64, 3, 5, n_box=77)
+    assert np.all(got[:, 0] == 231.0)
+    for q in (1, 2, 3):
+        assert normwise(got[:, q], ref[:, q]) < tol, q
+
+
+def test_triplet_is_deterministic_and_empty(hermes):
+    n, L = 32, 80.0
+    _, _, f2, f3 = _fields(n, L, 8300)
+    t2, t3 = torch.from_numpy(f2).cuda(), torch.from_numpy(f3).cuda()
+    a = hermes.triplet_mc(t2, t3, L, 10.0, 15.0, 20, 50, 1, n_box=20000)
+    b = hermes.triplet_mc(t2, t3, L, 10.0, 15.0, 20, 50, 1, n_box=20000)
+    assert torch.equal(a, b)
+    z = hermes.triplet_mc(t2, t3, L, 10.0, 15.0, 4, 2, 1, n_box=0)
+    assert torch.count_nonzero(z).item() == 0
+
+
+def test_triplet_errors(hermes):
+    from paper_2607_23494_amd.hermes import HermesError
+    f = torch.zeros((16, 16, 16), dtype=torch.float32, device="cuda")
+    c = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(HermesError, match="L/2"):
+        hermes.triplet_mc(f, f, 10.0, 6.0, 1.0, 4, 2, 0, n_box=5)
+    with pytest.raises(HermesError, match="n_theta|opening angles"):
+        hermes.triplet_mc(f, f, 10.0, 1.0, 1.0, 65, 2, 0, n_box=5)
+    with pytest.raises(HermesError, match="n_rot"):
+        hermes.triplet_mc(f, f, 10.0, 1.0, 1.0, 4, 0, 0, n_box=5)
+    with pytest.raises(HermesError, match="box points"):
+        hermes.triplet_mc(f, f, 10.0, 1.0, 1.0, 4, 2, 0, centres=c, f1=f)
+
+
+def test_triplet_256_particle_centres_sampled(hermes):
+    """The 256^3 workload in the benchmark's configuration (every catalogue
+    point a primary vertex, 20 opening angles, r12 = 20, r13 = 40) with
+    fewer rotations; a subset of 500 centres against the oracle, each side
+    on its own sphere-filtered field of the catalogue."""
+    wl = synth.WORKLOADS["ns256_rsd"]
+    pos, _ = wl.catalogue()
+    n, L = wl.n_grid, wl.box_L
+    tp = torch.from_numpy(pos).cuda()
+    eps, sw = hermes.assign(tp, None, L, n)
+    dk, _ = hermes.fft(eps, sw, want_delta=False)
+    fields, _ = hermes.filter_bins(dk, L, [("sphere", 0.0, 5.0)], store_fields=True, moments=False)
+    f = fields[0].contiguous()
+    full = hermes.triplet_mc(f, f, L, 20.0, 40.0, 20, 4, 7, centres=tp).cpu().numpy()
+    assert np.all(full[:, 0] == 4.0 * pos.shape[0])
+    sub = pos[:: 4001].copy()
+    got = hermes.triplet_mc(f, f, L, 20.0, 40.0, 20, 4, 7, centres=torch.from_numpy(sub).cuda()).cpu().numpy()
+    oe, osw = O.assign(pos, None, L, n)
+    of = O.filtered_field(O.dft3(O.contrast(oe, osw)), L, O.cic_window("sphere", 5.0))
+    ref = O.triplet_mc(of, of, L, 20.0, 40.0, 20, 4, 7, centres=sub)
+    for q in (1, 2, 3):
+        assert normwise(got[:, q], ref[:, q]) < 1e-5, q
