@@ -688,3 +688,55 @@ def triplet_mc(f2, f3, box_L, r12, r13, n_theta, n_rot, seed, centres=None, weig
         v3 = interpolate(f3, x + r13 * (np.cos(th) * u + np.sin(th) * v), box_L)
         out[j] = [np.sum(aa), np.sum(aa * v2), np.sum(aa * v3), np.sum(aa * v2 * v3)]
     return out
+
+
+# ----------------------------------------------------------------------------
+# 3PCF monopole through triple connection coefficients (Sec. 3.3.2, Eqs.
+# 3pcfddd, 2-fold-density, 3PCF-ddd-monopole, con-coeff, DDD-vector-product),
+# with the cubic B-spline as scaling function: Gamma_{a,b} is the overlap of
+# three translated B3, nonzero for offsets a, b in [-3, 3]^3.
+# ----------------------------------------------------------------------------
+
+def connection_1d():
+    """gamma[a + 3, b + 3] = int B3(x) B3(x - a) B3(x - b) dx, a, b in [-3, 3]:
+    the one-dimensional factor of Gamma_{a,b} (Eq. con-coeff is a product of
+    three such factors).  The integrand is a polynomial of degree 9 on each
+    unit interval of the support [-2, 2] of B3(x), so 5-point Gauss-Legendre
+    per interval is exact."""
+    xg, wg = np.polynomial.legendre.leggauss(5)
+    g = np.zeros((7, 7))
+    for lo in range(-2, 2):
+        x = lo + 0.5 * (xg + 1.0)
+        w = 0.5 * wg
+        for a in range(-3, 4):
+            for b in range(-3, 4):
+                g[a + 3, b + 3] += np.sum(w * bspline3(x) * bspline3(x - a) * bspline3(x - b))
+    return g
+
+
+def two_fold_coefficients(f1, f2):
+    """Coefficients of the two-fold field (Eq. 3PCF-ddd-monopole):
+    e_l = sum_a f1[l + a] sum_b Gamma_{a,b} f2[l + b], offsets a, b over
+    [-3, 3]^3, node indices mod N, Gamma_{a,b} = prod_d gamma(a_d, b_d)."""
+    f1 = np.asarray(f1, dtype=np.float64)
+    f2 = np.asarray(f2, dtype=np.float64)
+    g = connection_1d()
+    offs = [(x, y, z) for x in range(-3, 4) for y in range(-3, 4) for z in range(-3, 4)]
+    shift = lambda f, o: np.roll(f, shift=(-o[0], -o[1], -o[2]), axis=(0, 1, 2))   # f[l + o]
+    s2 = {b: shift(f2, b) for b in offs}
+    out = np.zeros_like(f1)
+    for a in offs:
+        inner = np.zeros_like(f1)
+        for b in offs:
+            inner += g[a[0] + 3, b[0] + 3] * g[a[1] + 3, b[1] + 3] * g[a[2] + 3, b[2] + 3] * s2[b]
+        out += shift(f1, a) * inner
+    return out
+
+
+def ddd_gamma(eps, f1, f2):
+    """Triplet count of Eq. DDD-vector-product, per node: N^-3 sum_l eps_l
+    e_l(f1, f2), the box mean of the product of the three B3 expansions
+    (with eps = delta and f_i shell-filtered contrasts, the 3PCF monopole of
+    the smoothed fields; a node sum replaced by the exact integral)."""
+    e = two_fold_coefficients(f1, f2)
+    return float(np.sum(np.asarray(eps, dtype=np.float64) * e)) / np.asarray(eps).size

@@ -862,3 +862,47 @@ def test_triplet_mc_plane_wave_pair_expectation():
         want = 0.5 * ph * math.sin(k0 * r23) / (k0 * r23)
         mean = got[j, 3] / got[j, 0]
         assert abs(mean - want) < 4 * 0.5 / math.sqrt(n_c * n_r), (th, mean, want)
+
+
+# --------------------------------------------------------------------------
+# triple connection coefficients
+# --------------------------------------------------------------------------
+
+def test_connection_coefficients_sum_rules():
+    """gamma(a, b) = int B3(x) B3(x-a) B3(x-b) dx: symmetric, even, and by
+    the partition of unity sum_a gamma(a, b) = int B3(x) B3(x-b) dx, the B3
+    autocorrelation at lag b (2416, 1191, 120, 1 over 5040), and
+    sum_{a,b} gamma = int B3 = 1."""
+    g = O.connection_1d()
+    assert np.allclose(g, g.T, atol=1e-16) and np.allclose(g, g[::-1, ::-1], atol=1e-16)
+    auto = np.array([1, 120, 1191, 2416, 1191, 120, 1]) / 5040.0
+    assert np.max(np.abs(g.sum(axis=0) - auto)) < 1e-15
+    assert abs(g.sum() - 1.0) < 1e-15
+    assert g[0, 6] == 0.0   # B3(x+3) and B3(x-3) never overlap
+    # one entry by independent quadrature (scipy adaptive)
+    val, _ = quad(lambda x: float(O.bspline3(np.array([x]))[0] * O.bspline3(np.array([x - 1]))[0]
+                                  * O.bspline3(np.array([x + 2]))[0]), -2, 2, points=[-1, 0, 1], epsabs=1e-15)
+    assert abs(g[1 + 3, -2 + 3] - val) < 1e-14
+
+
+def test_ddd_gamma_is_the_continuous_triple_integral():
+    """N^-3 sum_l eps_l e_l equals the box mean of n n1 n2 for the B3
+    expansions, computed by 5^3-point Gauss-Legendre per cell on fields read
+    with interpolate(); constant fields give the product of the constants."""
+    n, L = 8, 8.0
+    rng = np.random.default_rng(4)
+    e0, e1, e2 = (rng.standard_normal((n, n, n)) for _ in range(3))
+    got = O.ddd_gamma(e0, e1, e2)
+    xg, wg = np.polynomial.legendre.leggauss(5)
+    t, w = 0.5 * (xg + 1.0), 0.5 * wg
+    cells = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
+    tot = 0.0
+    for i, tx in enumerate(t):
+        for j, ty in enumerate(t):
+            for k, tz in enumerate(t):
+                x = cells + np.array([tx, ty, tz])   # box length = n cells of unit size
+                tot += w[i] * w[j] * w[k] * np.sum(O.interpolate(e0, x, L) * O.interpolate(e1, x, L)
+                                                   * O.interpolate(e2, x, L))
+    assert abs(got - tot / n ** 3) < 1e-12 * max(1.0, abs(got))
+    c = np.ones((n, n, n))
+    assert abs(O.ddd_gamma(2 * c, -3 * c, 0.5 * c) + 3.0) < 1e-13
