@@ -312,6 +312,25 @@ def other_configs(warmup: int, steps: int) -> dict:
         record(name, step_ddd, combos, desc, per="combinations", n_steps=1)
         out[name]["ns_per_combination"] = round(out[name]["ms_per_step"] * 1e6 / combos, 4)
     del fld, cen, twork, tout
+
+    # 3PCF monopole through triple connection coefficients: the contrast and
+    # 20 thick-shell filtered fields over [10, 150] (the 3PCF bins), every bin
+    # pair, at 256^3
+    e20 = synth.EDGES["ns512_3pcf"]
+    shells = [("shell", float(e20[i]), float(e20[i + 1])) for i in range(e20.size - 1)]
+    gfields = torch.empty((len(shells), n, n, n), dtype=torch.float32, device="cuda")
+
+    def step_gamma():
+        eps, sw = hermes.assign(pos, None, wl.box_L, n)
+        dk, delta = hermes.fft(eps, sw)
+        hermes.filter_bins(dk, wl.box_L, shells, store_fields=True, moments=False, out=gfields)
+        hermes.ddd_gamma(delta, gfields)
+    npairs = len(shells) * (len(shells) + 1) // 2
+    record("ns256_gamma", step_gamma, n ** 3 * npairs,
+           "2e6 Neyman-Scott points, 256^3, float32: assign, FFT, 20 thick-shell fields over [10, 150], the "
+           "connection-coefficient 3PCF monopole of all 210 bin pairs (exact triple integral of the B3 "
+           "expansions)", per="cells_pairs")
+    del gfields
     del pos
     torch.cuda.empty_cache()
 

@@ -11,6 +11,7 @@
  *   -> anisotropic 2PCF with axisymmetric windows     (hermes_xi_aniso)
  *   -> field values and density marks at positions    (hermes_readout)
  *   -> Monte-Carlo triangle sums (dual-/triplet-sphere 3PCF) (hermes_triplet_mc)
+ *   -> 3PCF monopole through connection coefficients  (hermes_ddd_gamma)
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -95,7 +96,8 @@ typedef enum hermes_op {
     HERMES_OP_FILTER = 3,
     HERMES_OP_ZETA = 4,
     HERMES_OP_XI_ANISO = 5,
-    HERMES_OP_TRIPLET = 6
+    HERMES_OP_TRIPLET = 6,
+    HERMES_OP_DDD_GAMMA = 7
 } hermes_op;
 
 typedef struct hermes_ctx_s* hermes_ctx;
@@ -105,6 +107,7 @@ typedef struct hermes_ctx_s* hermes_ctx;
 #define HERMES_MAX_LMAX 16   /* highest 3PCF multipole */
 #define HERMES_MAX_ANISO (1 << 20)   /* windows per hermes_xi_aniso call */
 #define HERMES_MAX_THETA 64          /* opening angles per hermes_triplet_mc call */
+#define HERMES_MAX_GAMMA_FIELDS 32   /* filtered fields per hermes_ddd_gamma call */
 
 /* Create a context on HIP device `device`; fills *out.  Allocates the
  * context's constant tables (about 2.6 MB) on that device. */
@@ -118,8 +121,8 @@ void hermes_destroy(hermes_ctx ctx);
 const char* hermes_last_error(void);
 
 /* Device workspace, in bytes, that `op` needs for an N^3 grid.  n_batch is
- * the number of points (ASSIGN), windows (FILTER, XI_ANISO), radial bins (ZETA) or
- * opening angles (TRIPLET);
+ * the number of points (ASSIGN), windows (FILTER, XI_ANISO), radial bins (ZETA),
+ * opening angles (TRIPLET) or fields (DDD_GAMMA);
  * n_ells the number of multipoles (XI).  Zero for FFT, which needs none. */
 hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtype,
                                     int n_batch, int n_ells, size_t* bytes);
@@ -328,6 +331,28 @@ hermes_status hermes_triplet_mc(hermes_ctx ctx, const void* f1, const void* f2, 
                                 const float* weights, int64_t n_centres, double r12, double r13,
                                 int n_theta, int n_rot, uint64_t seed, double* out, void* work,
                                 size_t work_bytes, hipStream_t stream);
+
+/* 3PCF monopole through triple connection coefficients (Sec. 3.3.2, Eqs.
+ * 3pcfddd, 3PCF-ddd-monopole, con-coeff, DDD-vector-product), with the cubic
+ * B-spline as scaling function phi:
+ *   out[b1][b2] = N^-3 sum_l eps_l sum_{a,b} Gamma_{a,b} f_b1[l + a] f_b2[l + b],
+ *   Gamma_{a,b} = int phi(x) phi(x - a) phi(x - b) d^3x  (offsets a, b in [-3, 3]^3),
+ * i.e. the box mean of the product of the three B3 expansions, computed as
+ * the exact integral (5-point Gauss-Legendre per cell and axis).  With
+ * eps = delta from hermes_fft and f_b the thick-shell filtered contrasts of
+ * hermes_filter_bins it is the 3PCF monopole of the paper's MRA route; the
+ * node-sum form of zeta_0 (hermes_zeta_l) replaces the integral by the node
+ * values.
+ *   eps     device [N^3] of dtype
+ *   fields  device [n_fields][N^3] of dtype
+ *   out     device double [n_fields][n_fields] (symmetric); overwritten
+ *   work    device workspace of >= hermes_workspace_size(DDD_GAMMA) bytes
+ * Per cell brick the sums are formed in dtype, across bricks in float64 in
+ * a fixed order.  ERR_ARG for NULL buffers, n_fields outside [1, 32], a bad
+ * N or dtype; ERR_OOM if work_bytes is too small. */
+hermes_status hermes_ddd_gamma(hermes_ctx ctx, const void* eps, const void* fields, int n_fields,
+                               int n_grid, int dtype, double* out, void* work, size_t work_bytes,
+                               hipStream_t stream);
 
 /* Density-derived marks (Sec. 3.3.1).  With v the value read at a point
  * (hermes_readout) and rho = max(1 + v - self_term, 0) the local density in

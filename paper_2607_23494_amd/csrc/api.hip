@@ -317,6 +317,9 @@ hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtyp
                 return fail(HERMES_ERR_ARG, "hermes_workspace_size: TRIPLET needs 1..64 opening angles");
             *bytes = triplet_workspace(n_batch);
             return HERMES_OK;
+        case HERMES_OP_DDD_GAMMA:
+            *bytes = gamma_workspace();
+            return HERMES_OK;
         case HERMES_OP_ZETA:
             if (dtype != HERMES_F32) return fail(HERMES_ERR_UNSUPPORTED, "hermes_workspace_size: ZETA runs in float32");
             if (n_batch < 1 || n_batch > HERMES_MAX_BINS)
@@ -456,6 +459,18 @@ hermes_status hermes_triplet_mc(hermes_ctx ctx, const void* f1, const void* f2, 
     DeviceGuard g(ctx->device);
     return triplet_impl(ctx, f1, f2, f3, n_grid, dtype, box_L, centres, weights, n_centres, r12, r13, n_theta, n_rot,
                         seed, out, work, stream);
+}
+
+hermes_status hermes_ddd_gamma(hermes_ctx ctx, const void* eps, const void* fields, int n_fields, int n_grid,
+                               int dtype, double* out, void* work, size_t work_bytes, hipStream_t stream) {
+    if (!ctx || !eps || !fields || !out || !work) return fail(HERMES_ERR_ARG, "hermes_ddd_gamma: NULL argument");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_ddd_gamma: N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_ddd_gamma: bad dtype");
+    if (n_fields < 1 || n_fields > HERMES_MAX_GAMMA_FIELDS)
+        return fail(HERMES_ERR_ARG, "hermes_ddd_gamma: n_fields must be in [1, 32]");
+    if (work_bytes < gamma_workspace()) return fail(HERMES_ERR_OOM, "hermes_ddd_gamma: workspace too small");
+    DeviceGuard g(ctx->device);
+    return gamma_impl(ctx, eps, fields, n_fields, n_grid, dtype, out, work, stream);
 }
 
 hermes_status hermes_filter_bins(hermes_ctx ctx, const void* delta_k, int n_grid, int dtype,

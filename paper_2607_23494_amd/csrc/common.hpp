@@ -129,6 +129,9 @@ hermes_status triplet_impl(hermes_ctx ctx, const void* f1, const void* f2, const
                            double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
                            hipStream_t stream);
 size_t triplet_workspace(int n_theta);
+hermes_status gamma_impl(hermes_ctx ctx, const void* eps, const void* fields, int n_fields, int n, int dtype,
+                         double* out, void* work, hipStream_t stream);
+size_t gamma_workspace();
 hermes_status readout_impl(hermes_ctx ctx, const void* field, int n, int dtype, double box_L, const float* pos,
                            const float* weight, int64_t n_pts, const hermes_mark* mark, void* out,
                            double* moments, hipStream_t stream);

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_PKG, "libhermes.so")
 F32, F64 = 0, 1
 PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
 WIN = {"shell": 0, "sphere": 1, "gauss": 2, "sh_shell": 3}
-OP_ASSIGN, OP_FFT, OP_XI, OP_FILTER, OP_ZETA, OP_XI_ANISO, OP_TRIPLET = range(7)
+OP_ASSIGN, OP_FFT, OP_XI, OP_FILTER, OP_ZETA, OP_XI_ANISO, OP_TRIPLET, OP_DDD_GAMMA = range(8)
 ANISO = {"ring": 0, "ring_bin": 1, "gauss_ring": 2, "disk": 3, "cylinder": 4, "cylshell": 5, "gauss_shell": 6}
 MAX_BINS = 64
 
@@ -71,13 +71,14 @@ def _load() -> ctypes.CDLL:
     lib.hermes_xi_aniso.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_AnisoWindow), i32, i32, vp, vp, sz, vp]
     lib.hermes_triplet_mc.argtypes = [vp, vp, vp, vp, i32, i32, f64, vp, vp, i64, f64, f64, i32, i32,
                                       ctypes.c_uint64, vp, vp, sz, vp]
+    lib.hermes_ddd_gamma.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, sz, vp]
     lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
     lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
     lib.hermes_readout.argtypes = [vp, vp, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp, vp]
     lib.hermes_profile_enable.argtypes = [vp, i32]
     lib.hermes_profile_reset.argtypes = [vp]
     lib.hermes_profile_read.argtypes = [vp, i32, ctypes.c_char_p, sz, ctypes.POINTER(i64), ctypes.POINTER(f64)]
-    for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi", "hermes_xi_static", "hermes_xi_aniso", "hermes_triplet_mc",
+    for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi", "hermes_xi_static", "hermes_xi_aniso", "hermes_triplet_mc", "hermes_ddd_gamma",
                  "hermes_filter_bins", "hermes_zeta_l", "hermes_readout", "hermes_profile_enable", "hermes_profile_reset",
                  "hermes_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
@@ -281,6 +282,27 @@ def triplet_mc(f2: torch.Tensor, f3: torch.Tensor, box_L: float, r12: float, r13
                                       float(box_L), _ptr(centres), _ptr(weights), n_c, float(r12), float(r13),
                                       int(n_theta), int(n_rot), int(seed) & ((1 << 64) - 1), _ptr(out), _ptr(w),
                                       wbytes, _stream(dev, stream)))
+    return out
+
+
+def ddd_gamma(eps: torch.Tensor, fields: torch.Tensor, out: torch.Tensor | None = None,
+              work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """3PCF monopole through connection coefficients: device float64 [nb, nb],
+    out[b1][b2] = box mean of eps(x) f_b1(x) f_b2(x) for the B3 expansions of
+    eps [N,N,N] and fields [nb,N,N,N]."""
+    dev = _dev(eps)
+    n = eps.shape[0]
+    if fields.dim() != 4 or tuple(fields.shape[1:]) != tuple(eps.shape) or fields.dtype != eps.dtype \
+            or not fields.is_contiguous() or not eps.is_contiguous():
+        raise ValueError("fields must be a contiguous [nb, N, N, N] tensor of eps's dtype")
+    nb = fields.shape[0]
+    wbytes = workspace_size(OP_DDD_GAMMA, n, eps.dtype, nb, 0, dev)
+    with _on(stream):
+        w = _workspace(wbytes, dev, work)
+        if out is None:
+            out = torch.empty((nb, nb), dtype=torch.float64, device=eps.device)
+        _check(_lib.hermes_ddd_gamma(context(dev), _ptr(eps), _ptr(fields), nb, n, _dtype_code(eps.dtype), _ptr(out),
+                                     _ptr(w), wbytes, _stream(dev, stream)))
     return out
 
 
