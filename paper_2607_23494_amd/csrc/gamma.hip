@@ -12,13 +12,13 @@
 // factorisation (4 nodes -> 5 points, one axis at a time) instead of
 // contracting the 7^6 offsets of Gamma.
 //
-// A workgroup takes bricks of 1 x 1 x CZ cells: per field it stages the
-// 4 x 4 x (CZ + 3) coefficients in LDS, evaluates the brick's 125 CZ points
-// in three passes, and keeps the point values of e (times the quadrature
-// weight) and of every f_b in LDS; then each thread takes bin pairs
-// (b1 <= b2) and sums e w f_b1 f_b2 over the brick's points.  Per-brick sums
-// are float T, sums across bricks float64; the workgroups' partials are added
-// in a fixed order.
+// A workgroup takes bricks of 1 x 1 x CZ cells: for groups of fields it
+// stages the 4 x 4 x (CZ + 3) coefficients in LDS, evaluates the brick's
+// 125 CZ points in three passes, and keeps the point values of e (times the
+// quadrature weight) and of every f_b in LDS; then each thread takes a 4 x 4
+// tile of bin pairs over a slice of the points (nine LDS reads per sixteen
+// FMAs).  Per-brick sums are float T, sums across bricks float64; the
+// slices and the workgroups' partials are added in a fixed order.
 #include <cmath>
 #include <vector>
 
@@ -32,7 +32,6 @@ constexpr int kGammaS = 125 * kGammaCZ;            // quadrature points per bric
 constexpr int kGammaZS = 5 * kGammaCZ;             // points along z per brick
 constexpr int kGammaRZ = kGammaCZ + 3;             // coefficient nodes along z per brick
 constexpr int kGammaMaxFields = 32;               // bins per call
-constexpr int kGammaMaxPairs = kGammaMaxFields * (kGammaMaxFields + 1) / 2;
 constexpr int kGammaBlocks = 2048;                 // persistent workgroups over the bricks
 
 // B3 at the quadrature points of a unit cell for the four nodes that reach
@@ -77,7 +76,9 @@ static GammaQuad gamma_quad() {
     return g;
 }
 
-size_t gamma_workspace() { return align256(size_t(kGammaBlocks) * kGammaMaxPairs * sizeof(double)); }
+size_t gamma_workspace() {
+    return align256(size_t(kGammaBlocks) * kGammaMaxFields * kGammaMaxFields * sizeof(double));
+}
 
 template <typename KernelT>
 static void allow_lds_gamma(KernelT kernel, size_t bytes) {
@@ -85,110 +86,156 @@ static void allow_lds_gamma(KernelT kernel, size_t bytes) {
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
+// Fields evaluated per barrier group (LDS for the staged coefficients and the
+// two intermediate passes of FG fields).
+template <typename T> constexpr int gamma_fg() { return sizeof(T) == 4 ? 8 : 4; }
+
+template <typename T>
+constexpr size_t gamma_lds_bytes(int nf) {
+    return (size_t(nf + 1) * kGammaS + size_t(gamma_fg<T>()) * (16 * kGammaRZ + 16 * kGammaZS + 20 * kGammaZS)) *
+           sizeof(T);
+}
+
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_ddd_gamma(const T* __restrict__ eps, const T* __restrict__ fields,
                                                         int nf, GammaQuad gq, double* __restrict__ part) {
     constexpr int BRICKS = N * N * (N / kGammaCZ);
+    constexpr int FG = gamma_fg<T>();
     extern __shared__ double lds_raw[];
     T* vals = reinterpret_cast<T*>(lds_raw);                       // [nf + 1][kGammaS]: e w, then f_b
-    T* reg = vals + (nf + 1) * kGammaS;                            // [4][4][kGammaRZ] coefficients
-    T* sa = reg + 16 * kGammaRZ;                                   // [4][4][kGammaZS] after the z pass
-    T* sb = sa + 16 * kGammaZS;                                    // [4][5][kGammaZS] after the y pass
-    const int npairs = nf * (nf + 1) / 2;
-    double acc[(kGammaMaxPairs + kThreads - 1) / kThreads];
+    T* reg = vals + (nf + 1) * kGammaS;                            // [FG][4][4][kGammaRZ] coefficients
+    T* sa = reg + FG * 16 * kGammaRZ;                              // [FG][4][4][kGammaZS] after the z pass
+    T* sb = sa + FG * 16 * kGammaZS;                               // [FG][4][5][kGammaZS] after the y pass
+    // pair roles: 4 x 4 bin tiles (I <= J) x sample slices
+    const int nt4 = (nf + 3) / 4;
+    const int ntp = nt4 * (nt4 + 1) / 2;
+    const int slices = kThreads / ntp;
+    const int tp = threadIdx.x % ntp, slice = threadIdx.x / ntp;
+    int ti = 0, tj = 0;
+    for (int I = 0, idx = tp; I < nt4; ++I) {
+        if (idx < nt4 - I) {
+            ti = I;
+            tj = I + idx;
+            break;
+        }
+        idx -= nt4 - I;
+    }
+    double acc64[16];
 #pragma unroll
-    for (int i = 0; i < (kGammaMaxPairs + kThreads - 1) / kThreads; ++i) acc[i] = 0.0;
+    for (int i = 0; i < 16; ++i) acc64[i] = 0.0;
     for (int brick = blockIdx.x; brick < BRICKS; brick += gridDim.x) {
         const int cz0 = (brick % (N / kGammaCZ)) * kGammaCZ;
         const int cy = (brick / (N / kGammaCZ)) % N;
         const int cx = brick / (N / kGammaCZ) / N;
-        for (int f = 0; f <= nf; ++f) {
-            const T* src = f == 0 ? eps : fields + int64_t(f - 1) * N * N * N;
-            for (int i = threadIdx.x; i < 16 * kGammaRZ; i += kThreads) {
-                const int ox = i / (4 * kGammaRZ), oy = (i / kGammaRZ) % 4, oz = i % kGammaRZ;
+        for (int f0 = 0; f0 <= nf; f0 += FG) {
+            const int fg = nf + 1 - f0 < FG ? nf + 1 - f0 : FG;
+            for (int i = threadIdx.x; i < fg * 16 * kGammaRZ; i += kThreads) {
+                const int f = i / (16 * kGammaRZ), e = i % (16 * kGammaRZ);
+                const int ox = e / (4 * kGammaRZ), oy = (e / kGammaRZ) % 4, oz = e % kGammaRZ;
                 const int x = (cx - 1 + ox) & (N - 1), y = (cy - 1 + oy) & (N - 1), z = (cz0 - 1 + oz) & (N - 1);
+                const T* src = f0 + f == 0 ? eps : fields + int64_t(f0 + f - 1) * N * N * N;
                 reg[i] = src[(int64_t(x) * N + y) * N + z];
             }
             __syncthreads();
-            // z: [ox][oy][k q] = sum_o P[q][o] reg[ox][oy][k + o]
-            for (int i = threadIdx.x; i < 16 * kGammaZS; i += kThreads) {
-                const int oxy = i / kGammaZS, sz = i % kGammaZS, k = sz / 5, q = sz % 5;
-                const T* r = reg + oxy * kGammaRZ + k;
+            // z: [f][ox][oy][k q] = sum_o P[q][o] reg[f][ox][oy][k + o]
+            for (int i = threadIdx.x; i < fg * 16 * kGammaZS; i += kThreads) {
+                const int fo = i / kGammaZS, sz = i % kGammaZS, k = sz / 5, q = sz % 5;
+                const T* r = reg + fo * kGammaRZ + k;
                 sa[i] = T(gq.p[q][0]) * r[0] + T(gq.p[q][1]) * r[1] + T(gq.p[q][2]) * r[2] + T(gq.p[q][3]) * r[3];
             }
             __syncthreads();
-            // y: [ox][qy][sz] = sum_o P[qy][o] sa[ox][o][sz]
-            for (int i = threadIdx.x; i < 20 * kGammaZS; i += kThreads) {
-                const int ox = i / (5 * kGammaZS), qy = (i / kGammaZS) % 5, sz = i % kGammaZS;
-                const T* a = sa + ox * 4 * kGammaZS + sz;
+            // y: [f][ox][qy][sz] = sum_o P[qy][o] sa[f][ox][o][sz]
+            for (int i = threadIdx.x; i < fg * 20 * kGammaZS; i += kThreads) {
+                const int fox = i / (5 * kGammaZS), qy = (i / kGammaZS) % 5, sz = i % kGammaZS;
+                const T* a = sa + fox * 4 * kGammaZS + sz;
                 sb[i] = T(gq.p[qy][0]) * a[0] + T(gq.p[qy][1]) * a[kGammaZS] + T(gq.p[qy][2]) * a[2 * kGammaZS] +
                         T(gq.p[qy][3]) * a[3 * kGammaZS];
             }
             __syncthreads();
-            // x: [qx][qy][sz] = sum_o P[qx][o] sb[o][qy][sz]; e carries the weights
-            T* dst = vals + f * kGammaS;
-            for (int i = threadIdx.x; i < kGammaS; i += kThreads) {
-                const int qx = i / (5 * kGammaZS), rest = i % (5 * kGammaZS);
-                const T* b = sb + rest;
+            // x: [qx][qy][sz] = sum_o P[qx][o] sb[f][o][qy][sz]; e carries the weights
+            for (int i = threadIdx.x; i < fg * kGammaS; i += kThreads) {
+                const int f = i / kGammaS, e = i % kGammaS;
+                const int qx = e / (5 * kGammaZS), rest = e % (5 * kGammaZS);
+                const T* b = sb + f * 20 * kGammaZS + rest;
                 T v = T(gq.p[qx][0]) * b[0] + T(gq.p[qx][1]) * b[5 * kGammaZS] + T(gq.p[qx][2]) * b[10 * kGammaZS] +
                       T(gq.p[qx][3]) * b[15 * kGammaZS];
-                if (f == 0) {
+                if (f0 + f == 0) {
                     const int qy = rest / kGammaZS, qz = (rest % kGammaZS) % 5;
                     v *= T(gq.w[qx] * gq.w[qy] * gq.w[qz]);
                 }
-                dst[i] = v;
+                vals[(f0 + f) * kGammaS + e] = v;
             }
             __syncthreads();
         }
-        // pairs b1 <= b2, thread t takes pairs t, t + 256, ...
+        // the tile's 4 x 4 block of pair sums over this slice's points
+        if (slice < slices) {
+            T acc[4][4];
 #pragma unroll
-        for (int i = 0; i < (kGammaMaxPairs + kThreads - 1) / kThreads; ++i) {
-            const int pr = threadIdx.x + i * kThreads;
-            if (pr < npairs) {
-                int b1 = 0, rem = pr;
-                while (rem >= nf - b1) {
-                    rem -= nf - b1;
-                    ++b1;
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[a][c] = T(0);
+            for (int k = slice; k < kGammaS; k += slices) {
+                const T e = vals[k];
+                T y1[4], y2[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int b1 = 4 * ti + a, b2 = 4 * tj + a;
+                    y1[a] = b1 < nf ? e * vals[(b1 + 1) * kGammaS + k] : T(0);
+                    y2[a] = b2 < nf ? vals[(b2 + 1) * kGammaS + k] : T(0);
                 }
-                const int b2 = b1 + rem;
-                const T* e = vals;
-                const T* p1 = vals + (b1 + 1) * kGammaS;
-                const T* p2 = vals + (b2 + 1) * kGammaS;
-                T s = T(0);
-                for (int k = 0; k < kGammaS; ++k) s += e[k] * p1[k] * p2[k];
-                acc[i] += double(s);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[a][c] += y1[a] * y2[c];
             }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc64[4 * a + c] += double(acc[a][c]);
         }
         __syncthreads();
     }
+    // sum the slices of every tile in a fixed order; the workgroup's full
+    // matrix goes to part[block][b1 * 32 + b2]
+    double* red = lds_raw;
 #pragma unroll
-    for (int i = 0; i < (kGammaMaxPairs + kThreads - 1) / kThreads; ++i) {
-        const int pr = threadIdx.x + i * kThreads;
-        if (pr < npairs) part[int64_t(blockIdx.x) * kGammaMaxPairs + pr] = acc[i];
+    for (int i = 0; i < 16; ++i) red[threadIdx.x * 16 + i] = acc64[i];
+    __syncthreads();
+    if (threadIdx.x < ntp) {
+        double sum[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sum[i] = 0.0;
+        for (int c = 0; c < slices; ++c)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) sum[i] += red[(c * ntp + threadIdx.x) * 16 + i];
+        double* dst = part + int64_t(blockIdx.x) * kGammaMaxFields * kGammaMaxFields;
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 4; ++c) {
+                const int b1 = 4 * ti + a, b2 = 4 * tj + c;
+                if (b1 < nf && b2 < nf) {
+                    dst[b1 * kGammaMaxFields + b2] = sum[4 * a + c];
+                    dst[b2 * kGammaMaxFields + b1] = sum[4 * a + c];
+                }
+            }
     }
 }
 
 __global__ void k_gamma_final(const double* __restrict__ part, int n_blocks, int nf, double scale,
                               double* __restrict__ out) {
-    const int pr = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pr >= nf * (nf + 1) / 2) return;
-    int b1 = 0, rem = pr;
-    while (rem >= nf - b1) {
-        rem -= nf - b1;
-        ++b1;
-    }
-    const int b2 = b1 + rem;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf * nf) return;
+    const int b1 = i / nf, b2 = i % nf;
     double s = 0.0;
-    for (int b = 0; b < n_blocks; ++b) s += part[int64_t(b) * kGammaMaxPairs + pr];
-    out[b1 * nf + b2] = s * scale;
-    out[b2 * nf + b1] = s * scale;
+    for (int b = 0; b < n_blocks; ++b) s += part[int64_t(b) * kGammaMaxFields * kGammaMaxFields + b1 * kGammaMaxFields + b2];
+    out[i] = s * scale;
 }
 
 template <typename T, int N>
 static hermes_status gamma_n(hermes_ctx ctx, const void* eps, const void* fields, int nf, double* out, void* work,
                              hipStream_t stream) {
     static const GammaQuad gq = gamma_quad();
-    const size_t lds = (size_t(nf + 1) * kGammaS + 16 * kGammaRZ + 16 * kGammaZS + 20 * kGammaZS) * sizeof(T);
+    const size_t lds_f = gamma_lds_bytes<T>(nf), lds_r = size_t(kThreads) * 16 * sizeof(double);
+    const size_t lds = lds_f > lds_r ? lds_f : lds_r;
     allow_lds_gamma(k_ddd_gamma<T, N>, lds);
     constexpr int BRICKS = N * N * (N / kGammaCZ);
     const int blocks = BRICKS < kGammaBlocks ? BRICKS : kGammaBlocks;
@@ -201,7 +248,7 @@ static hermes_status gamma_n(hermes_ctx ctx, const void* eps, const void* fields
     {
         LaunchScope ls(ctx, stream, "reduce");
         const double nc = double(N) * N * N;
-        hipLaunchKernelGGL(k_gamma_final, dim3((nf * (nf + 1) / 2 + 127) / 128), dim3(128), 0, stream, part, blocks,
+        hipLaunchKernelGGL(k_gamma_final, dim3((nf * nf + 127) / 128), dim3(128), 0, stream, part, blocks,
                            nf, 1.0 / nc, out);
     }
     return check_launch("hermes_ddd_gamma");
