@@ -15,10 +15,11 @@
 // (centre, 0, 1, 0) for a box point, key (seed, 0): every sample can be drawn
 // by any thread, and the oracle draws the same numbers.
 //
-// One thread per sample (grid-stride); per opening angle the wavefront's 64
-// samples are summed by a butterfly over lanes and lane 0 adds them to the
-// wavefront's LDS accumulators, so every sum is formed in a fixed order and
-// the result does not depend on timing.
+// Fields are read through row-packed copies (four taps per vector load) up
+// to 512^3.  One thread per sample (grid-stride); per opening angle the
+// wavefront's 64 samples are summed by a butterfly over lanes and lane 0 adds
+// them to the wavefront's LDS accumulators, so every sum is formed in a fixed
+// order and the result does not depend on timing.
 #include <cmath>
 
 #include "common.hpp"
@@ -58,11 +59,31 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-size_t triplet_workspace(int n_theta) { return align256(size_t(kTripletBlocks) * n_theta * 4 * sizeof(double)); }
+// Fields are read through row-packed copies (Quad, four times the field)
+// up to N = 512; at 1024^3 (16 GB per packed float field) directly.
+constexpr int kTripletPackMaxN = 512;
+
+size_t triplet_workspace(int n, int dtype, int n_theta) {
+    const size_t part = align256(size_t(kTripletBlocks) * n_theta * 4 * sizeof(double));
+    if (n > kTripletPackMaxN) return part;
+    const size_t elem = dtype == HERMES_F32 ? sizeof(Quad<float>) : sizeof(Quad<double>);
+    return part + 3 * align256(size_t(n) * n * n * elem);
+}
+
+// A field read by the sampling kernel: packed rows or the plain array.
+template <typename T, int N>
+struct FieldRef {
+    const T* f;
+    const Quad<T>* q;
+    __device__ __forceinline__ double at(const double u[3]) const {
+        if constexpr (N <= kTripletPackMaxN) return b3_value_packed<T, N>(q, u);
+        else return b3_value<T, N>(f, u);
+    }
+};
 
 template <typename T, int N, bool BOX>
-__global__ __launch_bounds__(kThreads) void k_triplet(const T* __restrict__ f1, const T* __restrict__ f2,
-                                                      const T* __restrict__ f3, const float* __restrict__ centres,
+__global__ __launch_bounds__(kThreads) void k_triplet(FieldRef<T, N> f1, FieldRef<T, N> f2, FieldRef<T, N> f3,
+                                                      bool has_f1, const float* __restrict__ centres,
                                                       const float* __restrict__ weights, int64_t n_centres, int n_rot,
                                                       double box_L, double r12, double r13, int n_theta,
                                                       uint64_t seed, double* __restrict__ part) {
@@ -92,9 +113,9 @@ __global__ __launch_bounds__(kThreads) void k_triplet(const T* __restrict__ f1, 
                 x[0] = box_L * uniform53(w[0]);
                 x[1] = box_L * uniform53(w[1]);
                 x[2] = box_L * uniform53(w[2]);
-                if (f1) {
+                if (has_f1) {
                     const double uc[3] = {x[0] * scale, x[1] * scale, x[2] * scale};
-                    a = b3_value<T, N>(f1, uc);
+                    a = f1.at(uc);
                 } else {
                     a = 1.0;
                 }
@@ -125,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_triplet(const T* __restrict__ f1, 
             for (int k = 0; k < 3; ++k) v[k] = cp * e1[k] + sp * e2[k];
             const double p2[3] = {(x[0] + r12 * u[0]) * scale, (x[1] + r12 * u[1]) * scale,
                                   (x[2] + r12 * u[2]) * scale};
-            v2 = b3_value<T, N>(f2, p2);
+            v2 = f2.at(p2);
         }
         s0 += a;
         s1 += a * v2;
@@ -137,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void k_triplet(const T* __restrict__ f1, 
                 const double q[3] = {(x[0] + r13 * (ct * u[0] + st * v[0])) * scale,
                                      (x[1] + r13 * (ct * u[1] + st * v[1])) * scale,
                                      (x[2] + r13 * (ct * u[2] + st * v[2])) * scale};
-                const double v3 = b3_value<T, N>(f3, q);
+                const double v3 = f3.at(q);
                 p3 = a * v3;
                 p23 = a * v2 * v3;
             }
@@ -179,19 +200,43 @@ static hermes_status triplet_n(hermes_ctx ctx, const void* f1, const void* f2, c
                                double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
                                hipStream_t stream) {
     double* part = static_cast<double*>(work);
+    FieldRef<T, N> r1{static_cast<const T*>(f1), nullptr}, r2{static_cast<const T*>(f2), nullptr},
+        r3{static_cast<const T*>(f3), nullptr};
+    if constexpr (N <= kTripletPackMaxN) {
+        // pack every distinct field once
+        char* base = static_cast<char*>(work) + align256(size_t(kTripletBlocks) * n_theta * 4 * sizeof(double));
+        const size_t fb = align256(size_t(N) * N * N * sizeof(Quad<T>));
+        Quad<T>* q[3] = {reinterpret_cast<Quad<T>*>(base), reinterpret_cast<Quad<T>*>(base + fb),
+                         reinterpret_cast<Quad<T>*>(base + 2 * fb)};
+        const void* src[3] = {f2, f3, f1};
+        FieldRef<T, N>* dst[3] = {&r2, &r3, &r1};
+        LaunchScope ls(ctx, stream, "pack_rows");
+        for (int i = 0; i < 3; ++i) {
+            if (!src[i]) continue;
+            int same = -1;
+            for (int k = 0; k < i; ++k)
+                if (src[k] == src[i]) same = k;
+            if (same >= 0) {
+                dst[i]->q = dst[same]->q;
+                continue;
+            }
+            dst[i]->q = q[i];
+            const int64_t want = (int64_t(N) * N * N + kThreads - 1) / kThreads;
+            hipLaunchKernelGGL((k_pack_rows<T, N>), dim3(int(want < 8192 ? want : 8192)), dim3(kThreads), 0, stream,
+                               static_cast<const T*>(src[i]), q[i]);
+        }
+    }
     const int64_t total = n_centres * int64_t(n_rot);
     const int64_t want = (total + kThreads - 1) / kThreads;
     const int blocks = int(want < 1 ? 1 : (want < kTripletBlocks ? want : kTripletBlocks));
     {
         LaunchScope ls(ctx, stream, "triplet");
         if (centres) {
-            hipLaunchKernelGGL((k_triplet<T, N, false>), dim3(blocks), dim3(kThreads), 0, stream,
-                               static_cast<const T*>(f1), static_cast<const T*>(f2), static_cast<const T*>(f3),
-                               centres, weights, n_centres, n_rot, box_L, r12, r13, n_theta, seed, part);
+            hipLaunchKernelGGL((k_triplet<T, N, false>), dim3(blocks), dim3(kThreads), 0, stream, r1, r2, r3,
+                               f1 != nullptr, centres, weights, n_centres, n_rot, box_L, r12, r13, n_theta, seed, part);
         } else {
-            hipLaunchKernelGGL((k_triplet<T, N, true>), dim3(blocks), dim3(kThreads), 0, stream,
-                               static_cast<const T*>(f1), static_cast<const T*>(f2), static_cast<const T*>(f3),
-                               centres, weights, n_centres, n_rot, box_L, r12, r13, n_theta, seed, part);
+            hipLaunchKernelGGL((k_triplet<T, N, true>), dim3(blocks), dim3(kThreads), 0, stream, r1, r2, r3,
+                               f1 != nullptr, centres, weights, n_centres, n_rot, box_L, r12, r13, n_theta, seed, part);
         }
     }
     {
