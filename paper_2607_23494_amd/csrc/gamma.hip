@@ -12,7 +12,8 @@
 // factorisation (4 nodes -> 5 points, one axis at a time) instead of
 // contracting the 7^6 offsets of Gamma.
 //
-// A workgroup takes bricks of 1 x 1 x CZ cells: for groups of fields it
+// A workgroup takes bricks of 1 x 1 x CZ cells (in float the next brick's
+// coefficients load into registers meanwhile): for groups of fields it
 // stages the 4 x 4 x (CZ + 3) coefficients in LDS, evaluates the brick's
 // 125 CZ points in three passes, and keeps the point values of e (times the
 // quadrature weight) and of every f_b in LDS; then each thread takes a 4 x 4
@@ -90,10 +91,16 @@ static void allow_lds_gamma(KernelT kernel, size_t bytes) {
 // two intermediate passes of FG fields).
 template <typename T> constexpr int gamma_fg() { return sizeof(T) == 4 ? 8 : 4; }
 
+// float: the next brick's coefficients of every field are loaded into
+// registers while the current brick is evaluated (and all fields'
+// coefficients are staged in LDS at once); float64 stages them per group.
+template <typename T> constexpr bool gamma_prefetch() { return sizeof(T) == 4; }
+constexpr int kGammaPre = ((kGammaMaxFields + 1) * 16 * kGammaRZ + kThreads - 1) / kThreads;
+
 template <typename T>
 constexpr size_t gamma_lds_bytes(int nf) {
-    return (size_t(nf + 1) * kGammaS + size_t(gamma_fg<T>()) * (16 * kGammaRZ + 16 * kGammaZS + 20 * kGammaZS)) *
-           sizeof(T);
+    const size_t regs = size_t(gamma_prefetch<T>() ? nf + 1 : gamma_fg<T>()) * 16 * kGammaRZ;
+    return (size_t(nf + 1) * kGammaS + regs + size_t(gamma_fg<T>()) * (16 * kGammaZS + 20 * kGammaZS)) * sizeof(T);
 }
 
 template <typename T, int N>
@@ -101,10 +108,11 @@ __global__ __launch_bounds__(kThreads) void k_ddd_gamma(const T* __restrict__ ep
                                                         int nf, GammaQuad gq, double* __restrict__ part) {
     constexpr int BRICKS = N * N * (N / kGammaCZ);
     constexpr int FG = gamma_fg<T>();
+    constexpr bool PRE = gamma_prefetch<T>();
     extern __shared__ double lds_raw[];
     T* vals = reinterpret_cast<T*>(lds_raw);                       // [nf + 1][kGammaS]: e w, then f_b
-    T* reg = vals + (nf + 1) * kGammaS;                            // [FG][4][4][kGammaRZ] coefficients
-    T* sa = reg + FG * 16 * kGammaRZ;                              // [FG][4][4][kGammaZS] after the z pass
+    T* reg = vals + (nf + 1) * kGammaS;                            // [nf + 1 or FG][4][4][kGammaRZ] coefficients
+    T* sa = reg + (PRE ? nf + 1 : FG) * 16 * kGammaRZ;             // [FG][4][4][kGammaZS] after the z pass
     T* sb = sa + FG * 16 * kGammaZS;                               // [FG][4][5][kGammaZS] after the y pass
     // pair roles: 4 x 4 bin tiles (I <= J) x sample slices
     const int nt4 = (nf + 3) / 4;
@@ -123,24 +131,58 @@ __global__ __launch_bounds__(kThreads) void k_ddd_gamma(const T* __restrict__ ep
     double acc64[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc64[i] = 0.0;
-    for (int brick = blockIdx.x; brick < BRICKS; brick += gridDim.x) {
+    // coefficient i (field-major: field, ox, oy, oz) of a brick
+    auto coef = [&](int brick, int i) -> T {
         const int cz0 = (brick % (N / kGammaCZ)) * kGammaCZ;
         const int cy = (brick / (N / kGammaCZ)) % N;
         const int cx = brick / (N / kGammaCZ) / N;
-        for (int f0 = 0; f0 <= nf; f0 += FG) {
-            const int fg = nf + 1 - f0 < FG ? nf + 1 - f0 : FG;
-            for (int i = threadIdx.x; i < fg * 16 * kGammaRZ; i += kThreads) {
-                const int f = i / (16 * kGammaRZ), e = i % (16 * kGammaRZ);
-                const int ox = e / (4 * kGammaRZ), oy = (e / kGammaRZ) % 4, oz = e % kGammaRZ;
-                const int x = (cx - 1 + ox) & (N - 1), y = (cy - 1 + oy) & (N - 1), z = (cz0 - 1 + oz) & (N - 1);
-                const T* src = f0 + f == 0 ? eps : fields + int64_t(f0 + f - 1) * N * N * N;
-                reg[i] = src[(int64_t(x) * N + y) * N + z];
+        const int f = i / (16 * kGammaRZ), e = i % (16 * kGammaRZ);
+        const int ox = e / (4 * kGammaRZ), oy = (e / kGammaRZ) % 4, oz = e % kGammaRZ;
+        const int x = (cx - 1 + ox) & (N - 1), y = (cy - 1 + oy) & (N - 1), z = (cz0 - 1 + oz) & (N - 1);
+        const T* src = f == 0 ? eps : fields + int64_t(f - 1) * N * N * N;
+        return src[(int64_t(x) * N + y) * N + z];
+    };
+    const int ncoef = (nf + 1) * 16 * kGammaRZ;
+    T pre[PRE ? kGammaPre : 1];
+    if constexpr (PRE) {
+        if (int(blockIdx.x) < BRICKS) {
+#pragma unroll
+            for (int k = 0; k < kGammaPre; ++k) {
+                const int i = threadIdx.x + k * kThreads;
+                if (i < ncoef) pre[k] = coef(blockIdx.x, i);
+            }
+        }
+    }
+    for (int brick = blockIdx.x; brick < BRICKS; brick += gridDim.x) {
+        if constexpr (PRE) {
+            // stage this brick's coefficients, then load the next brick's
+#pragma unroll
+            for (int k = 0; k < kGammaPre; ++k) {
+                const int i = threadIdx.x + k * kThreads;
+                if (i < ncoef) reg[i] = pre[k];
+            }
+            const int nxt = brick + int(gridDim.x);
+            if (nxt < BRICKS) {
+#pragma unroll
+                for (int k = 0; k < kGammaPre; ++k) {
+                    const int i = threadIdx.x + k * kThreads;
+                    if (i < ncoef) pre[k] = coef(nxt, i);
+                }
             }
             __syncthreads();
+        }
+        for (int f0 = 0; f0 <= nf; f0 += FG) {
+            const int fg = nf + 1 - f0 < FG ? nf + 1 - f0 : FG;
+            if constexpr (!PRE) {
+                for (int i = threadIdx.x; i < fg * 16 * kGammaRZ; i += kThreads)
+                    reg[i] = coef(brick, f0 * 16 * kGammaRZ + i);
+                __syncthreads();
+            }
+            const T* greg = reg + (PRE ? f0 * 16 * kGammaRZ : 0);
             // z: [f][ox][oy][k q] = sum_o P[q][o] reg[f][ox][oy][k + o]
             for (int i = threadIdx.x; i < fg * 16 * kGammaZS; i += kThreads) {
                 const int fo = i / kGammaZS, sz = i % kGammaZS, k = sz / 5, q = sz % 5;
-                const T* r = reg + fo * kGammaRZ + k;
+                const T* r = greg + fo * kGammaRZ + k;
                 sa[i] = T(gq.p[q][0]) * r[0] + T(gq.p[q][1]) * r[1] + T(gq.p[q][2]) * r[2] + T(gq.p[q][3]) * r[3];
             }
             __syncthreads();
