@@ -10,6 +10,18 @@ bins.  Library primitives used as single steps: scipy.fft (a DFT), numpy's
 bincount (a histogram), scipy.special (spherical Bessel, cylindrical Bessel
 J0 and J1, Legendre, spherical harmonics) and numpy's Gauss-Legendre nodes.
 
+Parts: assignment, contrast and DFT; the basis kernel and radial windows;
+the 2PCF and its multipoles by Parseval with the shot-noise factor;
+filtered fields and counts-in-cells moments; 3PCF multipoles; readout at
+arbitrary positions and density marks; axisymmetric windows and the
+anisotropic 2PCF; Monte-Carlo triangle sums with the Philox4x64-10
+generator; the connection-coefficient 3PCF monopole.  Every function is
+pinned by tests/test_oracle_pins.py against an independent route (closed
+forms, brute force on small grids, library routines, invariants); parity is
+unpinned only for the conventions named there (the absolute normalisation
+of zeta_l against the paper's other convention, the choice of B3 for the
+paper's D4 basis).
+
 Conventions (the paper's notation; section / equation named per function):
   grid node l = (lx, ly, lz), l_a in {0..N-1}, sits at position l*h, h = L/N;
   array index [lx, ly, lz], lz fastest;
