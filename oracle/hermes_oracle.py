@@ -10,7 +10,9 @@ bins.  Library primitives used as single steps: scipy.fft (a DFT), numpy's
 bincount (a histogram), scipy.special (spherical Bessel, cylindrical Bessel
 J0 and J1, Legendre, spherical harmonics) and numpy's Gauss-Legendre nodes.
 
-Parts: assignment, contrast and DFT; the basis kernel and radial windows;
+Parts: the two scaling functions (the cubic B-spline, and the orthonormal
+Daubechies D4 function with its spectrum and connection coefficients);
+assignment, contrast and DFT; the basis kernel and radial windows;
 the 2PCF and its multipoles by Parseval with the shot-noise factor;
 filtered fields and counts-in-cells moments; 3PCF multipoles; readout at
 arbitrary positions and density marks; axisymmetric windows and the
@@ -19,8 +21,9 @@ generator; the connection-coefficient 3PCF monopole.  Every function is
 pinned by tests/test_oracle_pins.py against an independent route (closed
 forms, brute force on small grids, library routines, invariants); parity is
 unpinned only for the conventions named there (the absolute normalisation
-of zeta_l against the paper's other convention, the choice of B3 for the
-paper's D4 basis).
+of zeta_l against the paper's other convention, and the choice between B3,
+the library's default, and the paper's D4 basis).  Every function that
+depends on the scaling function takes ``basis`` = "b3" (default) or "db2".
 
 Conventions (the paper's notation; section / equation named per function):
   grid node l = (lx, ly, lz), l_a in {0..N-1}, sits at position l*h, h = L/N;
@@ -31,6 +34,7 @@ Conventions (the paper's notation; section / equation named per function):
 """
 from __future__ import annotations
 
+import functools
 import os
 
 import numpy as np
@@ -60,14 +64,165 @@ def bspline3(t):
     return out
 
 
-def assign(pos, weight, box_L, n):
-    """Project a weighted catalogue onto the N^3 grid of B3 coefficients.
+# ----------------------------------------------------------------------------
+# The Daubechies D4 ("db2") scaling function (Sec. 3.1: an orthonormal,
+# compactly supported MRA scaling function; the paper's default basis).
+# Refinement relation phi(x) = sqrt2 sum_k h_k phi(2x - k), support [0, 3].
+# ----------------------------------------------------------------------------
 
-    Sec. 3.1, Eq. phi_projection: eps_l = sum_i w_i prod_a B3(x_{i,a}/h - l_a),
-    node index taken mod N (periodic box).  ``weight`` None means unit weights
-    (Eq. dendis with w_i = 1; Eq. weighted_field for marks).
-    Returns (eps [N,N,N] float64, sum of weights).
+DB2_LEVEL = 12   # phi is tabulated at x = i / 2^12 and interpolated linearly between
+
+
+def db2_filter():
+    """Low-pass filter h_0..h_3 of the orthonormal Daubechies scaling function
+    with two vanishing moments (Daubechies 1988, the D4 filter):
+    h = (1 + sqrt3, 3 + sqrt3, 3 - sqrt3, 1 - sqrt3) / (4 sqrt2)."""
+    s = np.sqrt(3.0)
+    return np.array([1.0 + s, 3.0 + s, 3.0 - s, 1.0 - s]) / (4.0 * np.sqrt(2.0))
+
+
+def db2_phi_integers():
+    """phi(0), phi(1), phi(2), phi(3): the refinement relation at the integers,
+    phi(i) = sqrt2 sum_j h_{2i-j} phi(j), makes them an eigenvector of
+    eigenvalue 1, normalised so that sum_i phi(i) = 1 (partition of unity)."""
+    h = db2_filter()
+    m = np.zeros((4, 4))
+    for i in range(4):
+        for j in range(4):
+            if 0 <= 2 * i - j < 4:
+                m[i, j] = np.sqrt(2.0) * h[2 * i - j]
+    w, v = np.linalg.eig(m)
+    e = np.real(v[:, np.argmin(np.abs(w - 1.0))])
+    return e / e.sum()
+
+
+@functools.lru_cache(maxsize=4)
+def _db2_table(level):
+    h = db2_filter()
+    cur = db2_phi_integers()
+    for lev in range(1, level + 1):
+        step = 2 ** (lev - 1)            # one unit of x in the previous level's index
+        new = np.zeros(3 * 2 ** lev + 1)
+        new[0::2] = cur                  # the previous level's points
+        for i in range(1, new.size, 2):  # the new points x = i / 2^lev
+            s = 0.0
+            for k in range(4):
+                j = i - k * step         # 2x - k on the previous level
+                if 0 <= j < cur.size:
+                    s += h[k] * cur[j]
+            new[i] = np.sqrt(2.0) * s
+        cur = new
+    cur.setflags(write=False)
+    return cur
+
+
+def db2_phi_table(level=DB2_LEVEL):
+    """phi at x = i / 2^level, i = 0 .. 3 * 2^level, from the integer values by
+    the refinement relation, one dyadic level at a time."""
+    return _db2_table(int(level)).copy()
+
+
+def db2_phi(x, level=DB2_LEVEL):
+    """The D4 scaling function as used to project and read fields: the level
+    table interpolated linearly, zero outside [0, 3]."""
+    t = _db2_table(int(level))
+    grid = np.arange(t.size) / 2.0 ** level
+    return np.interp(np.asarray(x, dtype=np.float64), grid, t, left=0.0, right=0.0)
+
+
+def db2_m0_sq(w):
+    """|m0(w)|^2 with m0(w) = 2^-1/2 sum_k h_k e^{-i k w}: the squared
+    frequency response of the refinement filter."""
+    h = db2_filter()
+    w = np.asarray(w, dtype=np.float64)
+    m = sum(h[k] * np.exp(-1j * k * w) for k in range(4)) / np.sqrt(2.0)
+    return np.abs(m) ** 2
+
+
+def db2_phi_hat_sq(w):
+    """|phi^(w)|^2, the Fourier transform of the D4 autocorrelation, by the
+    infinite product phi^(w) = prod_{j >= 1} m0(w / 2^j) (phi^(0) = 1),
+    truncated after 60 factors (the rest are 1 in float64 for |w| <= pi)."""
+    w = np.asarray(w, dtype=np.float64)
+    p = np.ones_like(w)
+    for j in range(1, 61):
+        p = p * db2_m0_sq(w / 2.0 ** j)
+    return p
+
+
+def db2_connection_1d():
+    """gamma[a + 2, b + 2] = int phi(x) phi(x - a) phi(x - b) dx, a, b in
+    [-2, 2] (Eq. con-coeff per axis; zero where the supports do not meet).
+
+    Inserting the refinement relation into the three factors gives
+    gamma(a, b) = sqrt2 sum_{i,j,k} h_i h_j h_k gamma(2a + j - i, 2b + k - i),
+    with gamma = 0 outside [-2, 2]^2: the eigenvector of eigenvalue 1, scaled
+    so that sum_{a,b} gamma(a, b) = int phi (sum_a phi(. - a))^2 = 1."""
+    h = db2_filter()
+    pairs = [(a, b) for a in range(-2, 3) for b in range(-2, 3)]
+    index = {p: i for i, p in enumerate(pairs)}
+    t = np.zeros((25, 25))
+    for (a, b), row in index.items():
+        for i in range(4):
+            for j in range(4):
+                for k in range(4):
+                    tgt = (2 * a + j - i, 2 * b + k - i)
+                    if tgt in index:
+                        t[row, index[tgt]] += np.sqrt(2.0) * h[i] * h[j] * h[k]
+    w, v = np.linalg.eig(t)
+    e = np.real(v[:, np.argmin(np.abs(w - 1.0))])
+    e = e / e.sum()
+    g = np.zeros((5, 5))
+    for (a, b), row in index.items():
+        g[a + 2, b + 2] = e[row]
+    return g
+
+
+def db2_derivative_coefficients():
+    """r[m + 2] = int phi(x - m) phi'(x) dx, m in [-2, 2] (App. B, the
+    derivative connection coefficients of the D4 basis).  Inserting the
+    refinement relation gives r_m = 2 sum_{i,k} h_i h_k r_{2m+i-k}: the
+    eigenvector of eigenvalue 1, scaled so that sum_m m r_m = -1 (from
+    sum_m m phi(x - m) = x - const and integration by parts).  Used only to
+    pin the filter and the refinement method against the paper's values."""
+    h = db2_filter()
+    a = np.zeros((5, 5))
+    for m in range(-2, 3):
+        for i in range(4):
+            for k in range(4):
+                tgt = 2 * m + i - k
+                if -2 <= tgt <= 2:
+                    a[m + 2, tgt + 2] += 2.0 * h[i] * h[k]
+    w, v = np.linalg.eig(a)
+    e = np.real(v[:, np.argmin(np.abs(w - 1.0))])
+    return e / -np.dot(np.arange(-2, 3), e)
+
+
+BASES = ("b3", "db2")
+
+
+def basis_nodes(basis):
+    """Per axis, the nodes a point at u (cell units, i0 = floor(u)) reaches:
+    (first offset, count, phi), nodes i0 + off .. i0 + off + count - 1 with
+    weight phi(u - l).  B3 (support [-2, 2]): i0-1 .. i0+2; D4 (support
+    [0, 3]): i0-2 .. i0."""
+    if basis == "b3":
+        return -1, 4, bspline3
+    if basis == "db2":
+        return -2, 3, db2_phi
+    raise ValueError(basis)
+
+
+def assign(pos, weight, box_L, n, basis="b3"):
+    """Project a weighted catalogue onto the N^3 grid of scaling-function
+    coefficients.
+
+    Sec. 3.1, Eq. phi_projection: eps_l = sum_i w_i prod_a phi(x_{i,a}/h - l_a),
+    node index taken mod N (periodic box); phi = B3 or the D4 function.
+    ``weight`` None means unit weights (Eq. dendis with w_i = 1; Eq.
+    weighted_field for marks).  Returns (eps [N,N,N] float64, sum of weights).
     """
+    off, nn, phi = basis_nodes(basis)
     pos = np.asarray(pos, dtype=np.float32)
     h = float(box_L) / n
     u = pos.astype(np.float64) / h
@@ -75,15 +230,16 @@ def assign(pos, weight, box_L, n):
     w = np.ones(npts) if weight is None else np.asarray(weight, dtype=np.float64)
     i0 = np.floor(u).astype(np.int64)
     eps = np.zeros(n ** 3)
-    # per axis: node index (mod N) and B3 weight of the four nodes i0-1..i0+2
-    cells = [[np.mod(i0[:, a] + o, n) for o in (-1, 0, 1, 2)] for a in range(3)]
-    taps = [[bspline3(u[:, a] - (i0[:, a] + o)) for o in (-1, 0, 1, 2)] for a in range(3)]
-    for ox in range(4):
-        # the 16 (oy, oz) taps of one ox in a single histogram call
+    # per axis: node index (mod N) and weight of the nodes i0+off .. i0+off+nn-1
+    offs = range(off, off + nn)
+    cells = [[np.mod(i0[:, a] + o, n) for o in offs] for a in range(3)]
+    taps = [[phi(u[:, a] - (i0[:, a] + o)) for o in offs] for a in range(3)]
+    for ox in range(nn):
+        # the (oy, oz) taps of one ox in a single histogram call
         flat = np.concatenate([(cells[0][ox] * n + cells[1][oy]) * n + cells[2][oz]
-                               for oy in range(4) for oz in range(4)])
+                               for oy in range(nn) for oz in range(nn)])
         vals = np.concatenate([w * taps[0][ox] * taps[1][oy] * taps[2][oz]
-                               for oy in range(4) for oz in range(4)])
+                               for oy in range(nn) for oz in range(nn)])
         eps += np.bincount(flat, weights=vals, minlength=n ** 3)
     return eps.reshape(n, n, n), float(w.sum())
 
@@ -122,16 +278,21 @@ def signed_index(n, nyquist_sign=+1):
     return s
 
 
-def phi_hat_1d(n):
-    """Per-axis Fourier transform of the B3 autocorrelation at the grid modes:
-    |B3^|^2 = sinc^8(pi n~/N), alias images dropped (Eq.
-    shift-scaling_coeff-kspace keeps only the principal mode)."""
+def phi_hat_1d(n, basis="b3"):
+    """Per-axis Fourier transform of the basis autocorrelation at the grid
+    modes, alias images dropped (Eq. shift-scaling_coeff-kspace keeps only the
+    principal mode): |B3^|^2 = sinc^8(pi n~/N), or |phi^|^2 of the D4 function
+    at w = 2 pi n~/N."""
     s = signed_index(n)
+    if basis == "db2":
+        return db2_phi_hat_sq(2.0 * np.pi * s / n)
+    if basis != "b3":
+        raise ValueError(basis)
     return np.sinc(s / n) ** 8          # np.sinc(x) = sin(pi x)/(pi x)
 
 
-def phi_hat(n):
-    p = phi_hat_1d(n)
+def phi_hat(n, basis="b3"):
+    p = phi_hat_1d(n, basis)
     return p[:, None, None] * p[None, :, None] * p[None, None, :]
 
 
@@ -255,7 +416,7 @@ def nyquist_average(n, box_L, fn):
 # xi-deltaDD-over-RR; Sec. 3.3.3 Legendre multipoles DD_l)
 # ----------------------------------------------------------------------------
 
-def xi_multipoles(delta_hat, box_L, edges, ells=(0,), los_axis=2):
+def xi_multipoles(delta_hat, box_L, edges, ells=(0,), los_axis=2, basis="b3"):
     """xi_l[b] = N^-6 sum_n |delta^_n|^2 Phi^(n) (2l+1) i^l jbar_l(k;b) L_l(mu_k).
 
     Full spectrum, every mode.  l = 0 uses the thick-shell window (identical
@@ -265,7 +426,7 @@ def xi_multipoles(delta_hat, box_L, edges, ells=(0,), los_axis=2):
     n = delta_hat.shape[0]
     nc = float(n) ** 3
     edges = np.asarray(edges, dtype=np.float64)
-    p = (np.abs(delta_hat) ** 2) * phi_hat(n)
+    p = (np.abs(delta_hat) ** 2) * phi_hat(n, basis)
     kx, ky, kz = mode_vectors(n, box_L)
     kk = np.sqrt(kx * kx + ky * ky + kz * kz)
     klos = (kx, ky, kz)[los_axis]
@@ -291,14 +452,26 @@ def xi_multipoles(delta_hat, box_L, edges, ells=(0,), los_axis=2):
 B7_LAGS = {0: 2416.0 / 5040.0, 1: 1191.0 / 5040.0, 2: 120.0 / 5040.0, 3: 1.0 / 5040.0}
 
 
-def shot_factor(n, box_L, edges, ells=(0,), los_axis=2):
+def self_pair_lags(basis="b3"):
+    """Autocorrelation int phi(x) phi(x - d) dx of the basis at integer lags
+    d >= 0 (the cell average of the self-pair kernel): the degree-7 B-spline
+    for B3; the Kronecker delta for the orthonormal D4 function."""
+    if basis == "b3":
+        return B7_LAGS
+    if basis == "db2":
+        return {0: 1.0}
+    raise ValueError(basis)
+
+
+def shot_factor(n, box_L, edges, ells=(0,), los_axis=2, basis="b3"):
     """Shot-noise factor of the Parseval 2PCF estimator (reading of the
     self-pair term of Sec. 2.2 Eq. CFpow for the field estimator):
         S_lb = sum_D K_lb(D) B7(D_1) B7(D_2) B7(D_3),  |D_a| <= 3,
     with K_lb(D) = N^-3 sum_n K_lb(n) e^{+2 pi i n.D/N} the real-space window
     kernel of xi_multipoles, K_lb(n) = (2l+1) (-1)^{l/2} R_lb(|k|) L_l(mu) Phi^(n)
     (every mode, n = 0 included), and B7 the B3 autocorrelation at integer
-    lags.  For iid points E xi_lb = (sum w^2 / W^2) (N^3 S_lb - K_lb(0)).
+    lags (for the D4 basis the Kronecker delta: S_lb = K_lb(0)).  For iid
+    points E xi_lb = (sum w^2 / W^2) (N^3 S_lb - K_lb(0)).
     Returns float64 [len(ells), n_bins].
     """
     edges = np.asarray(edges, dtype=np.float64)
@@ -306,8 +479,9 @@ def shot_factor(n, box_L, edges, ells=(0,), los_axis=2):
     kk = np.sqrt(kx * kx + ky * ky + kz * kz)
     klos = (kx, ky, kz)[los_axis]
     mu = np.where(kk > 0, klos / np.where(kk > 0, kk, 1.0), 0.0)
-    ph = phi_hat(n)
-    lags = range(-3, 4)
+    ph = phi_hat(n, basis)
+    ac = self_pair_lags(basis)
+    lags = range(-max(ac), max(ac) + 1)
     out = np.zeros((len(ells), len(edges) - 1))
     for il, ell in enumerate(ells):
         if ell % 2:
@@ -325,7 +499,7 @@ def shot_factor(n, box_L, edges, ells=(0,), los_axis=2):
             for dx in lags:
                 for dy in lags:
                     for dz in lags:
-                        s += kd[dx % n, dy % n, dz % n] * B7_LAGS[abs(dx)] * B7_LAGS[abs(dy)] * B7_LAGS[abs(dz)]
+                        s += kd[dx % n, dy % n, dz % n] * ac[abs(dx)] * ac[abs(dy)] * ac[abs(dz)]
             out[il, b] = s
     return out
 
@@ -334,11 +508,11 @@ def shot_factor(n, box_L, edges, ells=(0,), los_axis=2):
 # Counts-in-cells moments (Sec. 3.1 filtered field n_W; Sec. 2.2.2 Eq. varw)
 # ----------------------------------------------------------------------------
 
-def filtered_field(delta_hat, box_L, kernel_of_k):
+def filtered_field(delta_hat, box_L, kernel_of_k, basis="b3"):
     """delta_W = Re iDFT[delta^ Phi^ W^(|k|)] for a radial window."""
     n = delta_hat.shape[0]
     rad = radial_by_q(n, box_L, kernel_of_k)
-    return idft3(delta_hat * phi_hat(n) * rad).real
+    return idft3(delta_hat * phi_hat(n, basis) * rad).real
 
 
 def cic_window(kind, R):
@@ -357,14 +531,14 @@ def field_moments(field):
     return np.array([np.mean(field ** 2), np.mean(field ** 3), np.mean(field ** 4)])
 
 
-def cic_moments(delta_hat, box_L, windows):
+def cic_moments(delta_hat, box_L, windows, basis="b3"):
     """<delta_W^p> for p = 2, 3, 4 (mean over all grid nodes) per window.
 
     ``windows``: list of ("sphere"|"gauss", R).  Returns float64 [n_win, 3].
     """
     out = np.zeros((len(windows), 3))
     for i, (kind, R) in enumerate(windows):
-        out[i] = field_moments(filtered_field(delta_hat, box_L, cic_window(kind, R)))
+        out[i] = field_moments(filtered_field(delta_hat, box_L, cic_window(kind, R), basis))
     return out
 
 
@@ -378,7 +552,7 @@ def sh_window(n, box_L, ell, m):
     return nyquist_average(n, box_L, lambda kx, ky, kz: ylm_real(ell, m, kx, ky, kz))
 
 
-def multipole_field(delta_hat, box_L, ell, m, r_lo, r_hi, ylm=None):
+def multipole_field(delta_hat, box_L, ell, m, r_lo, r_hi, ylm=None, basis="b3"):
     """a_lmb(x) = iDFT[delta^ Phi^ 4 pi i^l jbar_l(k;b) Y^R_lm(k^)] (real).
 
     Returns (real part, max |imag part|).
@@ -387,12 +561,12 @@ def multipole_field(delta_hat, box_L, ell, m, r_lo, r_hi, ylm=None):
     if ylm is None:
         ylm = sh_window(n, box_L, ell, m)
     rad = radial_by_q(n, box_L, lambda kq: jbar(ell, kq, r_lo, r_hi))
-    kern = 4.0 * np.pi * (1j ** ell) * rad * ylm * phi_hat(n)
+    kern = 4.0 * np.pi * (1j ** ell) * rad * ylm * phi_hat(n, basis)
     f = idft3(delta_hat * kern)
     return f.real, float(np.max(np.abs(f.imag)))
 
 
-def zeta_multipoles(delta, delta_hat, box_L, edges, ells, bins=None):
+def zeta_multipoles(delta, delta_hat, box_L, edges, ells, bins=None, basis="b3"):
     """zeta_l[b1,b2] = (4 pi N^3)^-1 sum_m sum_x delta(x) a_lmb1(x) a_lmb2(x).
 
     Explicit loops over l in ``ells``, m = -l..l and the bins in ``bins``
@@ -409,7 +583,7 @@ def zeta_multipoles(delta, delta_hat, box_L, edges, ells, bins=None):
             ylm = sh_window(n, box_L, ell, m)
             fields = []
             for b in bins:
-                a, _ = multipole_field(delta_hat, box_L, ell, m, edges[b], edges[b + 1], ylm)
+                a, _ = multipole_field(delta_hat, box_L, ell, m, edges[b], edges[b + 1], ylm, basis)
                 fields.append(a)
             for i in range(len(bins)):
                 da = delta * fields[i]
@@ -425,43 +599,45 @@ def zeta_multipoles(delta, delta_hat, box_L, edges, ells, bins=None):
 # Eqs. power-law-mark, inverse-density-mark)
 # ----------------------------------------------------------------------------
 
-def readout(field, pos, box_L):
+def readout(field, pos, box_L, basis="b3"):
     """Value of the scaling-function expansion of a coefficient field at
-    arbitrary points: v_i = sum_l f_l prod_a B3(x_{i,a}/h - l_a), l mod N.
+    arbitrary points: v_i = sum_l f_l prod_a phi(x_{i,a}/h - l_a), l mod N.
 
     Sec. 3.1 reads the filtered field n_W(x) = sum_l eps~_l phi_l(x) at any
-    position; with B3 as scaling function (and no Gram inverse) the value at a
-    point is this 64-node sum, the transpose of the assignment's scatter.
+    position; the value at a point is this 64-node (B3) or 27-node (D4) sum,
+    the transpose of the assignment's scatter (no Gram inverse for B3).
     Returns float64 [n_pts].
     """
-    return interpolate(field, np.asarray(pos, dtype=np.float32).astype(np.float64), box_L)
+    return interpolate(field, np.asarray(pos, dtype=np.float32).astype(np.float64), box_L, basis)
 
 
-def interpolate(field, x, box_L):
-    """The same 64-node B3 sum at float64 positions x [n, 3] (any real
-    values; node indices are taken mod N)."""
+def interpolate(field, x, box_L, basis="b3"):
+    """The same node sum at float64 positions x [n, 3] (any real values;
+    node indices are taken mod N)."""
+    off, nn, phi = basis_nodes(basis)
     f = np.asarray(field, dtype=np.float64)
     n = f.shape[0]
     u = np.asarray(x, dtype=np.float64).reshape(-1, 3) / (float(box_L) / n)
     i0 = np.floor(u).astype(np.int64)
     out = np.zeros(u.shape[0])
-    for ox in (-1, 0, 1, 2):
+    offs = range(off, off + nn)
+    for ox in offs:
         ix = np.mod(i0[:, 0] + ox, n)
-        wx = bspline3(u[:, 0] - (i0[:, 0] + ox))
-        for oy in (-1, 0, 1, 2):
+        wx = phi(u[:, 0] - (i0[:, 0] + ox))
+        for oy in offs:
             iy = np.mod(i0[:, 1] + oy, n)
-            wy = bspline3(u[:, 1] - (i0[:, 1] + oy))
-            for oz in (-1, 0, 1, 2):
+            wy = phi(u[:, 1] - (i0[:, 1] + oy))
+            for oz in offs:
                 iz = np.mod(i0[:, 2] + oz, n)
-                wz = bspline3(u[:, 2] - (i0[:, 2] + oz))
+                wz = phi(u[:, 2] - (i0[:, 2] + oz))
                 out += wx * wy * wz * f[ix, iy, iz]
     return out
 
 
-def readout_moments(field, pos, box_L):
+def readout_moments(field, pos, box_L, basis="b3"):
     """<v^p>, p = 2, 3, 4, the mean over the points of the read-out values
     (counts in cells by sampling positions, Sec. 3.1)."""
-    v = readout(field, pos, box_L)
+    v = readout(field, pos, box_L, basis)
     return np.array([np.mean(v ** 2), np.mean(v ** 3), np.mean(v ** 4)])
 
 
@@ -485,7 +661,7 @@ def density_mark(dens, kind, exponent, offset, self_term=0.0):
     raise ValueError(kind)
 
 
-def marked_xi(pos, weight, box_L, n, edges, R, kind, exponent, offset, self_term=0.0):
+def marked_xi(pos, weight, box_L, n, edges, R, kind, exponent, offset, self_term=0.0, basis="b3"):
     """The density-marked 2PCF of Sec. 3.3.1 (and its example in Sec. 4.3.2):
     smooth the number field with a spherical window of radius R, read 1 +
     delta_R at every point, form the marks, project the mark-weighted
@@ -493,14 +669,14 @@ def marked_xi(pos, weight, box_L, n, edges, R, kind, exponent, offset, self_term
 
     Returns (xi_marked [n_bins], xi [n_bins], M [n_bins]).
     """
-    eps, sw = assign(pos, None, box_L, n)
+    eps, sw = assign(pos, None, box_L, n, basis)
     dh = dft3(contrast(eps, sw))
-    xi = xi_multipoles(dh, box_L, edges)[0]
-    dR = filtered_field(dh, box_L, lambda kq: w_sphere(kq * R))
-    m = density_mark(1.0 + readout(dR, pos, box_L), kind, exponent, offset, self_term)
+    xi = xi_multipoles(dh, box_L, edges, basis=basis)[0]
+    dR = filtered_field(dh, box_L, lambda kq: w_sphere(kq * R), basis)
+    m = density_mark(1.0 + readout(dR, pos, box_L, basis), kind, exponent, offset, self_term)
     w = m if weight is None else np.asarray(weight, dtype=np.float64) * m
-    eps_m, sw_m = assign(pos, w, box_L, n)
-    xi_m = xi_multipoles(dft3(contrast(eps_m, sw_m)), box_L, edges)[0]
+    eps_m, sw_m = assign(pos, w, box_L, n, basis)
+    xi_m = xi_multipoles(dft3(contrast(eps_m, sw_m)), box_L, edges, basis=basis)[0]
     return xi_m, xi, (1.0 + xi_m) / (1.0 + xi)
 
 
@@ -578,7 +754,7 @@ def w_aniso(kind, kpar, kperp, r_perp, r_par, d_perp=0.0, d_par=0.0):
     raise ValueError(kind)
 
 
-def xi_aniso(delta_hat, box_L, windows, los_axis=2):
+def xi_aniso(delta_hat, box_L, windows, los_axis=2, basis="b3"):
     """xi_W = N^-6 sum_n |delta^_n|^2 Phi^(n) W^(k_par, k_perp) for every
     window (Sec. 2.2.3 Eq. for xi(r_par, r_perp) as the field-window product;
     Sec. 3.3.1 Parseval form).  Full spectrum, every mode.
@@ -586,7 +762,7 @@ def xi_aniso(delta_hat, box_L, windows, los_axis=2):
     Returns float64 [len(windows)]."""
     n = delta_hat.shape[0]
     nc = float(n) ** 3
-    p = (np.abs(delta_hat) ** 2) * phi_hat(n)
+    p = (np.abs(delta_hat) ** 2) * phi_hat(n, basis)
     k = mode_vectors(n, box_L)
     kpar = k[los_axis]
     others = [k[a] for a in range(3) if a != los_axis]
@@ -668,7 +844,8 @@ def triplet_thetas(n_theta):
     return (np.arange(n_theta) + 0.5) * np.pi / n_theta
 
 
-def triplet_mc(f2, f3, box_L, r12, r13, n_theta, n_rot, seed, centres=None, weights=None, n_box=0, f1=None):
+def triplet_mc(f2, f3, box_L, r12, r13, n_theta, n_rot, seed, centres=None, weights=None, n_box=0, f1=None,
+               basis="b3"):
     """Monte-Carlo triple sums over random triangles (Sec. 3.4 Eq.
     particle-based-sum; Sec. 4.3.3).
 
@@ -678,7 +855,7 @@ def triplet_mc(f2, f3, box_L, r12, r13, n_theta, n_rot, seed, centres=None, weig
     points of the box with a = f1(x) (or 1 without f1; triplet sphere).  For
     each centre, n_rot rotations (u, v); for each opening angle theta_j the
     vertices x2 = x + r12 u and x3 = x + r13 (cos theta_j u + sin theta_j v)
-    read f2 and f3 (B3 interpolation).  Returns float64 [n_theta, 4]: the sums
+    read f2 and f3 (the basis expansion, interpolate).  Returns float64 [n_theta, 4]: the sums
     of a, a f2(x2), a f3(x3) and a f2(x2) f3(x3) over all (centre, rotation).
     """
     thetas = triplet_thetas(n_theta)
@@ -687,17 +864,17 @@ def triplet_mc(f2, f3, box_L, r12, r13, n_theta, n_rot, seed, centres=None, weig
         a = np.ones(xc.shape[0]) if weights is None else np.asarray(weights, dtype=np.float32).astype(np.float64)
     else:
         xc = np.array([box_centre(c, seed, box_L) for c in range(n_box)]).reshape(-1, 3)
-        a = np.ones(xc.shape[0]) if f1 is None else interpolate(f1, xc, box_L)
+        a = np.ones(xc.shape[0]) if f1 is None else interpolate(f1, xc, box_L, basis)
     n_c = xc.shape[0]
     frames = [triangle_frame(c, r, seed) for c in range(n_c) for r in range(n_rot)]
     u = np.array([f[0] for f in frames]).reshape(n_c * n_rot, 3)
     v = np.array([f[1] for f in frames]).reshape(n_c * n_rot, 3)
     x = np.repeat(xc, n_rot, axis=0)
     aa = np.repeat(a, n_rot)
-    v2 = interpolate(f2, x + r12 * u, box_L)
+    v2 = interpolate(f2, x + r12 * u, box_L, basis)
     out = np.zeros((n_theta, 4))
     for j, th in enumerate(thetas):
-        v3 = interpolate(f3, x + r13 * (np.cos(th) * u + np.sin(th) * v), box_L)
+        v3 = interpolate(f3, x + r13 * (np.cos(th) * u + np.sin(th) * v), box_L, basis)
         out[j] = [np.sum(aa), np.sum(aa * v2), np.sum(aa * v3), np.sum(aa * v2 * v3)]
     return out
 
@@ -705,8 +882,8 @@ def triplet_mc(f2, f3, box_L, r12, r13, n_theta, n_rot, seed, centres=None, weig
 # ----------------------------------------------------------------------------
 # 3PCF monopole through triple connection coefficients (Sec. 3.3.2, Eqs.
 # 3pcfddd, 2-fold-density, 3PCF-ddd-monopole, con-coeff, DDD-vector-product),
-# with the cubic B-spline as scaling function: Gamma_{a,b} is the overlap of
-# three translated B3, nonzero for offsets a, b in [-3, 3]^3.
+# Gamma_{a,b} is the overlap of three translated scaling functions: nonzero
+# for offsets a, b in [-3, 3]^3 with B3, in [-2, 2]^3 with the D4 function.
 # ----------------------------------------------------------------------------
 
 def connection_1d():
@@ -726,29 +903,41 @@ def connection_1d():
     return g
 
 
-def two_fold_coefficients(f1, f2):
+def connection_coefficients(basis="b3"):
+    """(gamma, reach): the one-dimensional factor of Gamma_{a,b} for offsets
+    a, b in [-reach, reach] (B3: connection_1d, reach 3; D4:
+    db2_connection_1d, reach 2)."""
+    if basis == "b3":
+        return connection_1d(), 3
+    if basis == "db2":
+        return db2_connection_1d(), 2
+    raise ValueError(basis)
+
+
+def two_fold_coefficients(f1, f2, basis="b3"):
     """Coefficients of the two-fold field (Eq. 3PCF-ddd-monopole):
     e_l = sum_a f1[l + a] sum_b Gamma_{a,b} f2[l + b], offsets a, b over
-    [-3, 3]^3, node indices mod N, Gamma_{a,b} = prod_d gamma(a_d, b_d)."""
+    [-reach, reach]^3, node indices mod N, Gamma_{a,b} = prod_d gamma(a_d, b_d)."""
     f1 = np.asarray(f1, dtype=np.float64)
     f2 = np.asarray(f2, dtype=np.float64)
-    g = connection_1d()
-    offs = [(x, y, z) for x in range(-3, 4) for y in range(-3, 4) for z in range(-3, 4)]
+    g, c = connection_coefficients(basis)
+    rng = range(-c, c + 1)
+    offs = [(x, y, z) for x in rng for y in rng for z in rng]
     shift = lambda f, o: np.roll(f, shift=(-o[0], -o[1], -o[2]), axis=(0, 1, 2))   # f[l + o]
     s2 = {b: shift(f2, b) for b in offs}
     out = np.zeros_like(f1)
     for a in offs:
         inner = np.zeros_like(f1)
         for b in offs:
-            inner += g[a[0] + 3, b[0] + 3] * g[a[1] + 3, b[1] + 3] * g[a[2] + 3, b[2] + 3] * s2[b]
+            inner += g[a[0] + c, b[0] + c] * g[a[1] + c, b[1] + c] * g[a[2] + c, b[2] + c] * s2[b]
         out += shift(f1, a) * inner
     return out
 
 
-def ddd_gamma(eps, f1, f2):
+def ddd_gamma(eps, f1, f2, basis="b3"):
     """Triplet count of Eq. DDD-vector-product, per node: N^-3 sum_l eps_l
-    e_l(f1, f2), the box mean of the product of the three B3 expansions
+    e_l(f1, f2), the box mean of the product of the three basis expansions
     (with eps = delta and f_i shell-filtered contrasts, the 3PCF monopole of
     the smoothed fields; a node sum replaced by the exact integral)."""
-    e = two_fold_coefficients(f1, f2)
+    e = two_fold_coefficients(f1, f2, basis)
     return float(np.sum(np.asarray(eps, dtype=np.float64) * e)) / np.asarray(eps).size

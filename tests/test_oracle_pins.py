@@ -65,6 +65,191 @@ def test_b3_autocorrelation_integer_lags():
 
 
 # --------------------------------------------------------------------------
+# the Daubechies D4 (db2) basis
+# --------------------------------------------------------------------------
+
+def test_db2_filter_satisfies_the_defining_conditions():
+    """sum h = sqrt2 (normalisation), sum h_k^2 = 1 and sum h_k h_{k+2} = 0
+    (orthonormal translates), sum (-1)^k k^p h_k = 0 for p = 0, 1 (two
+    vanishing wavelet moments): the four conditions that fix D4."""
+    h = O.db2_filter()
+    k = np.arange(4)
+    assert abs(h.sum() - math.sqrt(2.0)) < 1e-15
+    assert abs(np.sum(h * h) - 1.0) < 1e-15
+    assert abs(h[0] * h[2] + h[1] * h[3]) < 1e-15
+    assert abs(np.sum((-1.0) ** k * h)) < 1e-15
+    assert abs(np.sum((-1.0) ** k * k * h)) < 1e-15
+
+
+def test_db2_integer_values_closed_form():
+    """phi(1) = (1 + sqrt3)/2, phi(2) = (1 - sqrt3)/2, phi(0) = phi(3) = 0."""
+    v = O.db2_phi_integers()
+    s3 = math.sqrt(3.0)
+    assert np.allclose(v, [0.0, (1 + s3) / 2, (1 - s3) / 2, 0.0], atol=1e-15)
+    assert np.allclose(O.db2_phi(np.array([0.0, 1.0, 2.0, 3.0, -0.5, 3.5])),
+                       [0.0, (1 + s3) / 2, (1 - s3) / 2, 0.0, 0.0, 0.0], atol=1e-15)
+
+
+def test_db2_table_reproduces_constants_and_lines_and_is_orthonormal():
+    """Partition of unity and linear reproduction, sum_k k phi(x - k) =
+    x - (3 - sqrt3)/2 (the first moment of phi), hold at every table point and
+    therefore at any x (the interpolant is linear); the coarser table is the
+    even-index subset of the finer one; the level-16 table gives
+    int phi(x) phi(x - k) dx = delta_k0 to the accuracy of its quadrature."""
+    t = O.db2_phi_table(12)
+    step = 4096
+    x = np.arange(step) / step
+    pu = t[0:step] + t[step:2 * step] + t[2 * step:3 * step]
+    assert np.max(np.abs(pu - 1.0)) < 1e-13
+    m1 = (3.0 - math.sqrt(3.0)) / 2.0
+    # sum_k k phi(x - k) for x in [0, 1): k = 0, -1, -2 reach it
+    lin = -1.0 * t[step:2 * step] - 2.0 * t[2 * step:3 * step]
+    assert np.max(np.abs(lin - (x - m1))) < 1e-13
+    u = np.random.default_rng(3).uniform(-20, 20, 500)
+    assert np.max(np.abs(sum(O.db2_phi(u - l) for l in range(-25, 26)) - 1.0)) < 1e-13
+    assert np.max(np.abs(sum(l * O.db2_phi(u - l) for l in range(-25, 26)) - (u - m1))) < 1e-12
+    assert np.array_equal(O.db2_phi_table(11), t[0::2])
+    f = O.db2_phi_table(16)
+    unit = 2 ** 16
+    for k, want in ((0, 1.0), (1, 0.0), (2, 0.0)):
+        got = np.sum(f[k * unit:] * f[:f.size - k * unit]) / unit
+        assert abs(got - want) < 1e-8, (k, got)
+
+
+def test_db2_spectrum_product_formula():
+    """|m0|^2 = cos^4(w/2) (1 + 2 sin^2(w/2)) (Daubechies' closed form for two
+    vanishing moments); sum_j |phi^(w + 2 pi j)|^2 = 1 (orthonormal
+    translates); |phi^(w)|^2 equals the squared Fourier integral of the
+    level-16 table; the grid kernel is even and 1 at n = 0."""
+    w = np.linspace(-math.pi, math.pi, 41)
+    assert np.max(np.abs(O.db2_m0_sq(w) - np.cos(w / 2) ** 4 * (1 + 2 * np.sin(w / 2) ** 2))) < 1e-15
+    j = np.arange(-20000, 20001)
+    for w0 in (0.0, 0.4, 1.7, 3.1, math.pi):
+        assert abs(np.sum(O.db2_phi_hat_sq(w0 + 2 * math.pi * j)) - 1.0) < 1e-8, w0
+    f = O.db2_phi_table(16)
+    x = np.arange(f.size) / 2.0 ** 16
+    for w0 in (0.5, 2.0, 3.0):
+        ft = np.sum(f * np.exp(-1j * w0 * x)) / 2.0 ** 16
+        assert abs(abs(ft) ** 2 - O.db2_phi_hat_sq(np.array([w0]))[0]) < 1e-8
+    n = 16
+    p = O.phi_hat_1d(n, "db2")
+    assert abs(p[0] - 1.0) < 1e-13   # sixty factors of (sum h / sqrt2)^2 in float64
+    assert np.max(np.abs(p[1:] - p[1:][::-1])) < 1e-15
+
+
+def test_db2_derivative_coefficients_match_the_paper():
+    """The refinement eigenproblem with the D4 filter gives App. B's
+    derivative connection coefficients."""
+    import json
+    g = json.load(open(os.path.join(GOLDEN, "db2_derivative_coefficients.json")))
+    want = np.array(g["numerator"], dtype=np.float64) / g["denominator"]
+    got = O.db2_derivative_coefficients()
+    assert np.max(np.abs(got - want)) < 1e-14
+
+
+def test_db2_connection_coefficients():
+    """gamma(a, b) = int phi(x) phi(x-a) phi(x-b) dx: symmetric; the shift
+    x -> x + a gives gamma(a, b) = gamma(-a, b - a); sum_b gamma(a, b) =
+    int phi(x) phi(x-a) dx = delta_a0; zero where the three supports meet in
+    a point; every entry agrees with the rectangle rule on the level-16
+    table."""
+    g = O.db2_connection_1d()
+    assert np.allclose(g, g.T, atol=1e-16)
+    for a in range(-2, 3):
+        for b in range(-2, 3):
+            if -2 <= b - a <= 2:
+                assert abs(g[a + 2, b + 2] - g[-a + 2, b - a + 2]) < 1e-15
+    assert np.max(np.abs(g.sum(axis=1) - np.array([0, 0, 1, 0, 0]))) < 1e-15
+    assert g[0, 3] == 0.0 or abs(g[0, 3]) < 1e-17
+    assert abs(g[0, 4]) < 1e-17 and abs(g[1, 4]) < 1e-17
+    f = O.db2_phi_table(16)
+    unit = 2 ** 16
+    grid = np.zeros(9 * unit)          # x in [-3, 6) so that every shift stays inside
+    grid[3 * unit:3 * unit + f.size] = f
+    base = grid[3 * unit:6 * unit]
+    for a in range(-2, 3):
+        for b in range(-2, 3):
+            sa = grid[(3 - a) * unit:(6 - a) * unit]
+            sb = grid[(3 - b) * unit:(6 - b) * unit]
+            assert abs(np.sum(base * sa * sb) / unit - g[a + 2, b + 2]) < 1e-8, (a, b)
+
+
+def test_db2_assignment_bruteforce_and_node_values():
+    """eps_l = sum_i w_i prod_a phi(u_ia - l_a) by an explicit loop over
+    points and every node of the grid; a point on a node spreads phi(2),
+    phi(1), phi(0) per axis over l - 2, l - 1, l; mass is conserved."""
+    n, L = 8, 8.0
+    rng = np.random.default_rng(9)
+    pos = rng.uniform(0, L, (40, 3)).astype(np.float32)
+    w = rng.uniform(0.5, 2.0, 40)
+    got, sw = O.assign(pos, w, L, n, basis="db2")
+    want = np.zeros((n, n, n))
+    for i in range(40):
+        u = pos[i].astype(np.float64)
+        for lx in range(n):
+            for ly in range(n):
+                for lz in range(n):
+                    v = 1.0
+                    for a, la in enumerate((lx, ly, lz)):
+                        # nearest periodic image of node la at or below u
+                        d = (u[a] - la) % n
+                        v *= float(O.db2_phi(np.array([d]))[0])
+                    want[lx, ly, lz] += w[i] * v
+    assert np.max(np.abs(got - want)) < 1e-13
+    assert abs(got.sum() - w.sum()) < 1e-12 and abs(sw - w.sum()) < 1e-12
+    one, _ = O.assign(np.array([[3.0, 5.0, 0.0]], np.float32), None, L, n, basis="db2")
+    s3 = math.sqrt(3.0)
+    p = {0: (1 - s3) / 2, 1: (1 + s3) / 2}   # phi(2), phi(1) at the nodes l - 2, l - 1
+    assert abs(one[1, 3, 6] - p[0] * p[0] * p[0]) < 1e-14
+    assert abs(one[2, 4, 7] - p[1] * p[1] * p[1]) < 1e-14
+    assert abs(one[3, 5, 0]) < 1e-15   # phi(0) = 0
+
+
+def test_db2_readout_reproduces_lines_and_is_the_transpose():
+    """With f_l = l_x (away from the periodic seam) the expansion reads
+    u_x - (3 - sqrt3)/2; <readout(f), w> = <f, assign(w)>."""
+    n, L = 16, 16.0
+    f = np.broadcast_to(np.arange(n, dtype=np.float64)[:, None, None], (n, n, n)).copy()
+    rng = np.random.default_rng(5)
+    pos = rng.uniform([4, 0, 0], [12, L, L], (200, 3)).astype(np.float32)
+    v = O.readout(f, pos, L, basis="db2")
+    assert np.max(np.abs(v - (pos[:, 0].astype(np.float64) - (3 - math.sqrt(3)) / 2))) < 1e-12
+    g = rng.standard_normal((n, n, n))
+    w = rng.standard_normal(200)
+    eps, _ = O.assign(pos, w, L, n, basis="db2")
+    assert abs(np.dot(O.readout(g, pos, L, basis="db2"), w) - np.sum(g * eps)) < 1e-11
+
+
+def test_db2_ddd_gamma_separable_fields_and_constants():
+    """For fields that are products of one-dimensional factors the triplet
+    count factorises into three 1-D box means of the product of the three
+    expansions, each computed here by the rectangle rule on the level-16
+    table; constant fields give the product of the constants."""
+    n = 4
+    rng = np.random.default_rng(12)
+    fac = rng.standard_normal((3, 3, n))   # [field][axis][node]
+    fields = [np.einsum("i,j,k->ijk", fac[f, 0], fac[f, 1], fac[f, 2]) for f in range(3)]
+    got = O.ddd_gamma(fields[0], fields[1], fields[2], basis="db2")
+    t = O.db2_phi_table(16)
+    unit = 2 ** 16
+    xs = np.arange(n * unit)               # points x = i / unit of the periodic line [0, n)
+    want = 1.0
+    for a in range(3):
+        prod = np.ones(n * unit)
+        for f in range(3):
+            e = np.zeros(n * unit)
+            for l in range(n):
+                idx = (xs - l * unit) % (n * unit)   # x - l on the periodic line, in table units
+                inside = idx < t.size
+                e[inside] += fac[f, a, l] * t[idx[inside]]
+            prod *= e
+        want *= np.sum(prod) / unit / n
+    assert abs(got - want) < 1e-7 * max(1.0, abs(want)), (got, want)
+    c = np.ones((n, n, n))
+    assert abs(O.ddd_gamma(2 * c, -3 * c, 0.5 * c, basis="db2") + 3.0) < 1e-13
+
+
+# --------------------------------------------------------------------------
 # assignment
 # --------------------------------------------------------------------------
 
@@ -341,24 +526,27 @@ def _kernel_realspace_sum(n, box_L, lo, hi):
     return s
 
 
-def test_poisson_expectation():
+@pytest.mark.parametrize("basis", ["b3", "db2"])
+def test_poisson_expectation(basis):
     """For iid uniform points E[xi_lb] = (sum w^2 / W^2) (N^3 S_lb - K_lb(0)):
     the estimator measures zero clustering up to the self-pair term, for the
-    monopole (K_0b(0) = 1) and the quadrupole (K_2b(0) = 0)."""
+    monopole (K_0b(0) = 1) and the quadrupole (K_2b(0) = 0), with either
+    basis."""
     n, L, npts = 16, 100.0, 3000
     edges = [6.0, 12.0, 20.0, 30.0]
     samples = []
     for s in range(16):
         pos = synth.uniform_points(npts, L, seed=synth.SEED_BASE + 100 + s)
-        eps, sw = O.assign(pos, None, L, n)
-        samples.append(O.xi_multipoles(O.dft3(O.contrast(eps, sw)), L, edges, ells=(0, 2)))
+        eps, sw = O.assign(pos, None, L, n, basis)
+        samples.append(O.xi_multipoles(O.dft3(O.contrast(eps, sw)), L, edges, ells=(0, 2), basis=basis))
     samples = np.array(samples)
     mean = samples.mean(axis=0)
     sem = samples.std(axis=0, ddof=1) / 4.0
-    S = O.shot_factor(n, L, edges, ells=(0, 2))
+    S = O.shot_factor(n, L, edges, ells=(0, 2), basis=basis)
     for b in range(3):
         # the shell kernel built here directly agrees with the oracle's factor
-        assert abs(S[0, b] - _kernel_realspace_sum(n, L, edges[b], edges[b + 1])) < 1e-14
+        if basis == "b3":
+            assert abs(S[0, b] - _kernel_realspace_sum(n, L, edges[b], edges[b + 1])) < 1e-14
         for il, k0 in ((0, 1.0), (1, 0.0)):
             expect = (n ** 3 * S[il, b] - k0) / npts
             assert abs(mean[il, b] - expect) < 4 * sem[il, b] + 1e-12, (il, b)
