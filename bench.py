@@ -330,6 +330,14 @@ def other_configs(warmup: int, steps: int) -> dict:
            "2e6 Neyman-Scott points, 256^3, float32: assign, FFT, 20 thick-shell fields over [10, 150], the "
            "connection-coefficient 3PCF monopole of all 210 bin pairs (exact triple integral of the B3 "
            "expansions)", per="cells_pairs")
+    # the same with the orthonormal Daubechies D4 basis (the paper's exact
+    # stencil route: projection, window kernel and connection coefficients
+    # of D4)
+    with hermes.basis("db2"):
+        record("ns256_gamma_db2", step_gamma, n ** 3 * npairs,
+               "2e6 Neyman-Scott points, 256^3, float32, Daubechies D4 basis: assign, FFT, 20 thick-shell fields "
+               "over [10, 150], the connection-coefficient 3PCF monopole of all 210 bin pairs (D4 triple "
+               "connection coefficients, offsets in [-2, 2]^3)", per="cells_pairs")
     del gfields
     del pos
     torch.cuda.empty_cache()

@@ -3,7 +3,7 @@
  *
  * The library computes, on one GPU, the hot path of the in-situ field-window
  * estimator of clustering statistics:
- *   catalogue -> B3 scaling-function coefficients (hermes_assign)
+ *   catalogue -> scaling-function coefficients     (hermes_assign)
  *   -> density contrast and its 3-D real FFT        (hermes_fft)
  *   -> 2PCF and its Legendre multipoles by Parseval  (hermes_xi)
  *   -> window-filtered fields, counts-in-cells moments (hermes_filter_bins)
@@ -25,6 +25,14 @@
  *  - dtype: HERMES_F32 (float fields, complex64 spectra) or HERMES_F64
  *    (double fields, complex128 spectra).  Positions and weights are always
  *    float32.  Grid-wide reductions are always accumulated in float64.
+ *  - Basis: the scaling function phi of the MRA expansion is a property of
+ *    the context (hermes_set_basis): the centred cubic B-spline B3 (default;
+ *    not orthonormal, 4 nodes per axis) or the orthonormal Daubechies D4
+ *    function (support [0, 3], 3 nodes per axis).  It fixes the
+ *    projection and readout taps, the kernel Phi^ = |phi^|^2 of every
+ *    window, the self-pair kernel of the shot-noise factor and the
+ *    connection coefficients.  Coefficient fields of one basis are only
+ *    meaningful to calls made with the same basis.
  *  - Every device buffer is owned by the caller, including workspace, whose
  *    size hermes_workspace_size() reports.  The library owns only the opaque
  *    context (twiddle, basis-kernel and quadrature tables).  No entry point
@@ -110,8 +118,29 @@ typedef struct hermes_ctx_s* hermes_ctx;
 #define HERMES_MAX_GAMMA_FIELDS 32   /* filtered fields per hermes_ddd_gamma call */
 
 /* Create a context on HIP device `device`; fills *out.  Allocates the
- * context's constant tables (about 2.6 MB) on that device. */
+ * context's constant tables (about 2.7 MB, both bases) on that device.  The
+ * basis starts as HERMES_BASIS_B3. */
 hermes_status hermes_create(hermes_ctx* out, int device);
+
+/* Scaling function of the MRA basis (Sec. 3.1: a compactly supported
+ * scaling function phi, the basis phi_l(x) = prod_a phi(x_a/h - l_a)).
+ *   B3   centred cubic B-spline, support [-2, 2]: a point reaches the nodes
+ *        i0 - 1 .. i0 + 2 per axis (i0 = floor(x/h)); Phi^ per axis
+ *        sinc^8(pi n~/N); not orthonormal (its autocorrelation at integer
+ *        lags is the degree-7 B-spline)
+ *   DB2  Daubechies D4 (the paper's default), orthonormal, support [0, 3]:
+ *        a point reaches the nodes i0 - 2 .. i0 per axis with weights
+ *        phi(x/h - l), phi tabulated at x = i / 2^12 from the refinement
+ *        relation with the D4 filter and interpolated linearly between;
+ *        Phi^ per axis |phi^(2 pi n~/N)|^2 = prod_{j>=1} |m0(w/2^j)|^2; the
+ *        self-pair kernel is the Kronecker delta */
+typedef enum hermes_basis { HERMES_BASIS_B3 = 0, HERMES_BASIS_DB2 = 1 } hermes_basis;
+
+/* Select the basis of every later call on this context (the tables of both
+ * are resident, so calls already queued are unaffected).  ERR_ARG for an
+ * unknown basis.  hermes_get_basis returns the current one (-1 for NULL). */
+hermes_status hermes_set_basis(hermes_ctx ctx, int basis);
+int hermes_get_basis(hermes_ctx ctx);
 
 /* Release a context (NULL is ignored).  Not to be called while work that
  * uses it is still in flight. */
@@ -128,13 +157,14 @@ hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtyp
                                     int n_batch, int n_ells, size_t* bytes);
 
 /* MRA projection of a weighted catalogue (Sec. 3.1, Eq. phi_projection):
- *   eps_l = sum_i w_i prod_a B3(x_{i,a}/h - l_a),  l_a taken mod N,
- * with the centred cubic B-spline B3 as scaling function (64 nodes per
- * point).  Position fractions are formed in float64.  The taps are summed in
- * 64-bit fixed point with the power-of-two step 2^-k, k = 61 - ceil(log2
- * sum_i |w_i|), each tap rounded once to a multiple of it: the grid is the
- * same bit for bit on every run, and for float64 it carries an absolute error
- * of at most 2^-(k+1) per tap.
+ *   eps_l = sum_i w_i prod_a phi(x_{i,a}/h - l_a),  l_a taken mod N,
+ * with the context's scaling function phi (B3: 64 nodes per point; D4: 27).
+ * Position fractions and tap weights are formed in float64.  The taps are
+ * summed in 64-bit fixed point with the power-of-two step 2^-k, k = 61 -
+ * ceil(log2 sum_i |w_i|) (59 - ... for D4, whose taps reach |phi|^3 < 4),
+ * each tap rounded once to a multiple of it: the grid is the same bit for bit
+ * on every run, and for float64 it carries an absolute error of at most
+ * 2^-(k+1) per tap.
  *   pos    device float32 [n_pts][3], any real values (wrapped into the box)
  *   weight device float32 [n_pts], or NULL for unit weights (Eq. dendis;
  *          marks or physical values as in Eq. weighted_field); finite
@@ -167,7 +197,8 @@ hermes_status hermes_fft(hermes_ctx ctx, const void* eps, const double* sum_w,
 /* 2PCF and its Legendre multipoles by Parseval (Sec. 3.3.1 Eq.
  * pair-counting-kspace; Sec. 3.3.3 DD_l with the bin-averaged radial factor):
  *   xi_l[b] = N^-6 sum_n |delta^_n|^2 Phi^(n) (2l+1) i^l jbar_l(k_n; b) L_l(mu_n),
- * Phi^(n) = prod_a sinc^8(pi n~_a / N) (B3 autocorrelation), mu = k_los/|k|,
+ * Phi^(n) = prod_a Phi^_1(n~_a) the basis kernel (B3: sinc^8(pi n~_a / N),
+ * the Fourier transform of the B3 autocorrelation; D4: |phi^|^2), mu = k_los/|k|,
  * jbar_0 = volume-normalised thick shell (Eq. Wshell_k).  Raw estimator:
  * no shot-noise subtraction (the self-pair term of Sec. 2.2 Eq. CFpow is left
  * to the caller, who can take it from `shot`).
@@ -180,7 +211,8 @@ hermes_status hermes_fft(hermes_ctx ctx, const void* eps, const double* sum_w,
  *   shot     device double [n_ells][n_bins] or NULL: the shot-noise factor
  *            S_lb = sum_D K_lb(D) B7(D1) B7(D2) B7(D3) over lags |D_a| <= 3,
  *            K_lb(D) the real-space window kernel above and B7 the degree-7
- *            centred B-spline (the B3 autocorrelation at integer lags); for
+ *            centred B-spline (the B3 autocorrelation at integer lags; with
+ *            D4 the Kronecker delta, S_lb = K_lb(0)); for
  *            iid points of weights w_i, E xi_lb = (sum w^2 / W^2)
  *            (N^3 S_lb - K_lb(n = 0)), K_0b(0) = 1, K_lb(0) = 0 for l > 0
  *   work     device workspace of >= hermes_workspace_size(XI) bytes */
@@ -303,7 +335,8 @@ hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, i
  * rotations (u, v), u uniform on the sphere and v uniform on the circle
  * orthogonal to u; for theta_j = (j + 1/2) pi / n_theta the triangle's other
  * vertices are x + r12 u and x + r13 (cos theta_j u + sin theta_j v), where
- * f2 and f3 are read by B3 interpolation (positions in float64).
+ * f2 and f3 are read through the basis expansion (as hermes_readout;
+ * positions in float64).
  *   out[j] = ( sum a, sum a f2(x2), sum a f3(x3_j), sum a f2(x2) f3(x3_j) )
  * over all (centre, rotation), accumulated in float64 in a fixed order (the
  * result is the same on every run).  The ratio of the last to the first is
@@ -323,7 +356,8 @@ hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, i
  *   work        device workspace of >= hermes_workspace_size(TRIPLET, n_batch
  *               = n_theta) bytes: the partial sums and, for N <= 512, three
  *               row-packed copies of the fields (16 N^3 bytes each in float32,
- *               32 N^3 in float64)
+ *               32 N^3 in float64; four consecutive row nodes per node, of
+ *               which D4 uses three)
  * ERR_ARG for NULL f2, f3, out or work, f1 given with centres, weights
  * without centres, n_centres < 0, n_rot < 1, n_centres n_rot >= 2^62,
  * n_theta outside [1, HERMES_MAX_THETA], r12 or r13 negative, not finite or
@@ -335,16 +369,21 @@ hermes_status hermes_triplet_mc(hermes_ctx ctx, const void* f1, const void* f2, 
                                 size_t work_bytes, hipStream_t stream);
 
 /* 3PCF monopole through triple connection coefficients (Sec. 3.3.2, Eqs.
- * 3pcfddd, 3PCF-ddd-monopole, con-coeff, DDD-vector-product), with the cubic
- * B-spline as scaling function phi:
+ * 3pcfddd, 3PCF-ddd-monopole, con-coeff, DDD-vector-product), with the
+ * context's scaling function phi:
  *   out[b1][b2] = N^-3 sum_l eps_l sum_{a,b} Gamma_{a,b} f_b1[l + a] f_b2[l + b],
- *   Gamma_{a,b} = int phi(x) phi(x - a) phi(x - b) d^3x  (offsets a, b in [-3, 3]^3),
- * i.e. the box mean of the product of the three B3 expansions, computed as
- * the exact integral (5-point Gauss-Legendre per cell and axis).  With
- * eps = delta from hermes_fft and f_b the thick-shell filtered contrasts of
- * hermes_filter_bins it is the 3PCF monopole of the paper's MRA route; the
- * node-sum form of zeta_0 (hermes_zeta_l) replaces the integral by the node
- * values.
+ *   Gamma_{a,b} = int phi(x) phi(x - a) phi(x - b) d^3x = prod_axes gamma(a_i, b_i),
+ * i.e. the box mean of the product of the three basis expansions.  B3
+ * (offsets in [-3, 3]^3): computed as that exact integral (5-point
+ * Gauss-Legendre per cell and axis).  D4 (orthonormal; offsets in [-2, 2]^3,
+ * gamma from the refinement relation): computed through gamma = V diag(lambda)
+ * V^T per axis, out = N^-3 sum_l sum_r lambda_r eps_l F_b1,r[l] F_b2,r[l] with
+ * F_b,r = f_b filtered by the separable five-tap stencil V_r, the exact
+ * stencil sum (Eq. DDD-vector-product: the paper's exact 3PCF monopole of
+ * the smoothed fields).  With eps = delta from hermes_fft and f_b the
+ * thick-shell filtered contrasts of hermes_filter_bins it is the 3PCF
+ * monopole of the paper's MRA route; the node-sum form of zeta_0
+ * (hermes_zeta_l) replaces the integral by the node values.
  *   eps     device [N^3] of dtype
  *   fields  device [n_fields][N^3] of dtype
  *   out     device double [n_fields][n_fields] (symmetric); overwritten
@@ -383,8 +422,8 @@ typedef struct hermes_mark {
  * filtered field n_W(x) = sum_l eps~_l phi_l(x) is read at any point, e.g. at
  * random positions for counts in cells or at the catalogue's points for
  * density-derived marks):
- *   v_i = sum_l f_l prod_a B3(x_{i,a}/h - l_a),  l_a mod N  (64 nodes),
- * the transpose of hermes_assign.  Position fractions are formed in float64.
+ *   v_i = sum_l f_l prod_a phi(x_{i,a}/h - l_a),  l_a mod N  (B3: 64 nodes,
+ * D4: 27), the transpose of hermes_assign.  Position fractions are formed in float64.
  *   field   device [N^3] of dtype (a filtered field from hermes_filter_bins,
  *           the contrast from hermes_fft, ...)
  *   pos     device float32 [n_pts][3], any real values (wrapped into the box)

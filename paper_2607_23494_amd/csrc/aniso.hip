@@ -311,7 +311,7 @@ static hermes_status aniso_n(hermes_ctx ctx, const void* delta_k, double box_L, 
     {
         LaunchScope ls(ctx, stream, "aniso_hist");
         hipLaunchKernelGGL((k_aniso_hist<T, N>), dim3((reps + kThreads - 1) / kThreads), dim3(kThreads), 0, stream,
-                           static_cast<const C*>(delta_k), los, ctx->t.phi1d, ctx->t.q2rank, H);
+                           static_cast<const C*>(delta_k), los, basis_phi1d(ctx), ctx->t.q2rank, H);
     }
     for (int t0 = 0; t0 < sep_tiles; t0 += pl.tb) {
         const int nb = sep_tiles - t0 < pl.tb ? sep_tiles - t0 : pl.tb;

@@ -112,6 +112,16 @@ static hermes_status build_tables(hermes_ctx c) {
                 b7[n + i] = v;
             }
     }
+    // the D4 basis: |phi^|^2 per axis, the self-pair kernel (1: orthonormal)
+    // and the dyadic table of phi
+    std::vector<double> phi_db2(2 * kMaxN, 0.0), ones(2 * kMaxN, 1.0);
+    for (int n = 1; n <= kMaxN; n *= 2)
+        for (int i = 0; i < n; ++i) {
+            const int s = i <= n / 2 ? i : i - n;
+            phi_db2[n + i] = db2_phi_hat_sq(2.0 * M_PI * double(s) / double(n));
+        }
+    const std::vector<double> db2tab = db2_phi_table();
+    if (db2tab.size() != size_t(kDb2Tab)) return fail(HERMES_ERR_HIP, "hermes_create: D4 table size");
     std::vector<double> gx, gw;
     gauss_legendre(16, gx, gw);
     std::vector<double> gl(32);
@@ -146,6 +156,9 @@ static hermes_status build_tables(hermes_ctx c) {
         (e = up((void**)&c->t.tw64, tw64.data(), tw64.size() * sizeof(double2))) != hipSuccess ||
         (e = up((void**)&c->t.phi1d, phi.data(), phi.size() * sizeof(double))) != hipSuccess ||
         (e = up((void**)&c->t.b7dft, b7.data(), b7.size() * sizeof(double))) != hipSuccess ||
+        (e = up((void**)&c->t.phi1d_db2, phi_db2.data(), phi_db2.size() * sizeof(double))) != hipSuccess ||
+        (e = up((void**)&c->t.ones, ones.data(), ones.size() * sizeof(double))) != hipSuccess ||
+        (e = up((void**)&c->t.db2tab, db2tab.data(), db2tab.size() * sizeof(double))) != hipSuccess ||
         (e = up((void**)&c->t.gl, gl.data(), gl.size() * sizeof(double))) != hipSuccess ||
         (e = up((void**)&c->t.q2rank, q2rank.data(), q2rank.size() * sizeof(int))) != hipSuccess ||
         (e = up((void**)&c->t.rank2q, rank2q.data(), rank2q.size() * sizeof(int))) != hipSuccess)
@@ -214,6 +227,16 @@ hermes_status hermes_create(hermes_ctx* out, int device) {
     return HERMES_OK;
 }
 
+hermes_status hermes_set_basis(hermes_ctx ctx, int basis) {
+    if (!ctx) return fail(HERMES_ERR_ARG, "hermes_set_basis: ctx is NULL");
+    if (basis != HERMES_BASIS_B3 && basis != HERMES_BASIS_DB2)
+        return fail(HERMES_ERR_ARG, "hermes_set_basis: unknown basis");
+    ctx->basis = basis;
+    return HERMES_OK;
+}
+
+int hermes_get_basis(hermes_ctx ctx) { return ctx ? ctx->basis : -1; }
+
 void hermes_destroy(hermes_ctx ctx) {
     if (!ctx) return;
     DeviceGuard g(ctx->device);
@@ -234,6 +257,9 @@ void hermes_destroy(hermes_ctx ctx) {
     (void)hipFree(ctx->t.tw64);
     (void)hipFree(ctx->t.phi1d);
     (void)hipFree(ctx->t.b7dft);
+    (void)hipFree(ctx->t.phi1d_db2);
+    (void)hipFree(ctx->t.ones);
+    (void)hipFree(ctx->t.db2tab);
     (void)hipFree(ctx->t.gl);
     delete ctx;
 }

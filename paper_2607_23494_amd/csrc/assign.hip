@@ -1,21 +1,25 @@
-// MRA projection of a weighted catalogue onto B3 scaling-function
-// coefficients (Sec. 3.1, Eq. phi_projection).
+// MRA projection of a weighted catalogue onto scaling-function
+// coefficients (Sec. 3.1, Eq. phi_projection), with B3 (64 taps per point)
+// or the D4 function (27 taps).
 //
-// The 64 taps of every point are accumulated per tile of TS^3 cells in LDS
-// and in 64-bit fixed point:
+// The taps of every point are accumulated per tile of TS^3 cells in LDS and
+// in 64-bit fixed point:
 //   1. prep     count the points of every tile (by the cell of the point),
 //               and the per-block sums of w and |w|
 //   2. scale    sum_w (the output) and the fixed-point scale 2^k, chosen from
 //               sum |w| so that no cell's sum can overflow: every cell is a
-//               sum of contributions of magnitude <= |w_i|, so
-//               |cell| <= sum |w| 2^k <= 2^61
+//               sum of contributions of magnitude <= |w_i| M (M = 1 for B3,
+//               max |phi|^3 < 4 for D4, whose phi reaches (1 + sqrt3)/2), so
+//               |cell| <= sum |w| M 2^k <= 2^61
 //   3. scan     exclusive prefix of the tile counts: each tile's list offset
 //   4. scatter  the point indices into per-tile lists
 //   5. tiles    one workgroup per tile: a wavefront loads 64 points, then
-//               for each of them lane t adds tap t (64 distinct cells) to an
-//               LDS region of (TS + 3)^3 cells (the tile and the stencil's
-//               reach, one cell below and two above); the region is then
-//               added to the global accumulator with 64-bit atomics
+//               for each of them lane t adds tap t (64 distinct cells; D4:
+//               27 taps per half-wavefront, two points at a time) to an LDS
+//               region of (TS + 3)^3 cells (the tile and the stencil's
+//               reach: one cell below and two above for B3, two below for
+//               D4); the region is then added to the global accumulator
+//               with 64-bit atomics
 //   6. convert  eps = acc 2^-k
 // Each contribution is rounded once to a multiple of 2^-k; integer addition
 // commutes, so the grid is the same bit for bit whatever the order in which
@@ -23,6 +27,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "interp.hpp"
 #include "kernels.hpp"
 
 namespace hermes {
@@ -152,9 +157,10 @@ __global__ __launch_bounds__(kThreads) void k_asg_prep(const float* __restrict__
     }
 }
 
-// sum_w and the fixed-point scale 2^k, k = 61 - ceil(log2(sum |w|)), from the
-// per-block partials in block order.
-__global__ void k_asg_scale(const double* __restrict__ partial, int nblocks, double* __restrict__ sum_w,
+// sum_w and the fixed-point scale 2^k, k = 61 - head - ceil(log2(sum |w|)),
+// from the per-block partials in block order (2^head bounds a point's
+// largest tap weight).
+__global__ void k_asg_scale(const double* __restrict__ partial, int nblocks, int head, double* __restrict__ sum_w,
                             AsgScale* __restrict__ sc) {
     if (threadIdx.x != 0) return;
     double s = 0.0, sa = 0.0;
@@ -167,7 +173,7 @@ __global__ void k_asg_scale(const double* __restrict__ partial, int nblocks, dou
     if (sa > 0.0) {
         frexp(sa, &e);   // sa < 2^e
     }
-    const int k = min(1000, 61 - e);   // 2^k stays finite for tiny weights
+    const int k = min(1000, 61 - head - e);   // 2^k stays finite for tiny weights
     sc->scale = ldexp(1.0, k);
     sc->inv_scale = ldexp(1.0, -k);
 }
@@ -229,18 +235,22 @@ __global__ __launch_bounds__(kThreads) void k_asg_scatter(const float* __restric
 
 // One workgroup per tile.  A wavefront takes 64 of the tile's points at a
 // time, one per lane (index, weight, cell and fractions, computed once), then
-// walks through them: for point j, lane t adds tap t = (ox, oy, oz) = (t / 16,
-// t / 4 % 4, t % 4), whose cell i0 - 1 + o of the tile's region sits at local
-// index i0 - origin + o in [0, TS + 2] per axis; the 64 lanes hit 64
-// distinct cells.
-template <typename T, int N>
+// walks through them.  B3: for point j, lane t adds tap t = (ox, oy, oz) =
+// (t / 16, t / 4 % 4, t % 4); D4: lanes 0-26 add the 27 taps (t / 9, t / 3 % 3,
+// t % 3) of point j and lanes 32-58 those of point j + 1.  The cell
+// i0 - LO + o of a tap sits at local index i0 - tile origin + o in
+// [0, TS + 2] per axis of the region, whose origin is LO cells below the
+// tile; the taps of one point hit distinct cells.
+template <typename T, int N, int B>
 __global__ __launch_bounds__(kTileThreads) void k_asg_tiles(const float* __restrict__ pos, const float* __restrict__ weight,
                                                         double scale, const uint32_t* __restrict__ off,
                                                         const uint32_t* __restrict__ list,
                                                         const AsgScale* __restrict__ sc,
+                                                        const double* __restrict__ tab,
                                                         unsigned long long* __restrict__ acc) {
     using G = asg_cfg<N>;
     constexpr int TS = G::TS, NT = G::NT, RG = G::RG, RCELLS = G::RCELLS;
+    constexpr int LO = BasisTaps<B>::LO;
     constexpr int NW = kTileThreads / 64;
     __shared__ unsigned long long reg[RCELLS];
     const int tile = blockIdx.x;
@@ -252,7 +262,13 @@ __global__ __launch_bounds__(kTileThreads) void k_asg_tiles(const float* __restr
     __syncthreads();
     const double fxp = sc->scale;
     const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int ox = lane >> 4, oy = (lane >> 2) & 3, oz = lane & 3;
+    // this lane's tap (and, for D4, which of the two points it serves)
+    const int half = B == HERMES_BASIS_DB2 ? lane >> 5 : 0;
+    const int sub = B == HERMES_BASIS_DB2 ? lane & 31 : lane;
+    const bool on = B == HERMES_BASIS_DB2 ? sub < 27 : true;
+    const int ox = B == HERMES_BASIS_DB2 ? sub / 9 : lane >> 4;
+    const int oy = B == HERMES_BASIS_DB2 ? (sub / 3) % 3 : (lane >> 2) & 3;
+    const int oz = B == HERMES_BASIS_DB2 ? sub % 3 : lane & 3;
     const int tap = (ox * RG + oy) * RG + oz;
     for (uint32_t k0 = p0 + 64u * wv; k0 < p1; k0 += 64u * NW) {
         const uint32_t k = k0 + lane;
@@ -272,10 +288,28 @@ __global__ __launch_bounds__(kTileThreads) void k_asg_tiles(const float* __restr
             wq = (weight ? double(weight[i]) : 1.0) * fxp;
         }
         const int cnt = int(min(64u, p1 - k0));
-        for (int j = 0; j < cnt; ++j) {
-            const T wt = b3_tap<T>(bcast(fx, j), ox) * b3_tap<T>(bcast(fy, j), oy) * b3_tap<T>(bcast(fz, j), oz);
-            const long long q = llrint(bcast(wq, j) * double(wt));
-            atomicAdd(&reg[bcast(loc, j) + tap], (unsigned long long)q);
+        if constexpr (B == HERMES_BASIS_DB2) {
+            for (int j = 0; j < cnt; j += 2) {
+                // lanes of the upper half take point j + 1 (if there is one)
+                const int jj = j + 1 < cnt ? j + 1 : j;
+                const double tx = half ? bcast(double(fx), jj) : bcast(double(fx), j);
+                const double ty = half ? bcast(double(fy), jj) : bcast(double(fy), j);
+                const double tz = half ? bcast(double(fz), jj) : bcast(double(fz), j);
+                const double wj = half ? bcast(wq, jj) : bcast(wq, j);
+                const int lj = half ? bcast(loc, jj) : bcast(loc, j);
+                if (on && (half == 0 || j + 1 < cnt)) {
+                    const double wt = db2_phi(tx + double(LO - ox), tab) * db2_phi(ty + double(LO - oy), tab) *
+                                      db2_phi(tz + double(LO - oz), tab);
+                    const long long q = llrint(wj * wt);
+                    atomicAdd(&reg[lj + tap], (unsigned long long)q);
+                }
+            }
+        } else {
+            for (int j = 0; j < cnt; ++j) {
+                const T wt = b3_tap<T>(bcast(fx, j), ox) * b3_tap<T>(bcast(fy, j), oy) * b3_tap<T>(bcast(fz, j), oz);
+                const long long q = llrint(bcast(wq, j) * double(wt));
+                atomicAdd(&reg[bcast(loc, j) + tap], (unsigned long long)q);
+            }
         }
     }
     __syncthreads();
@@ -283,9 +317,9 @@ __global__ __launch_bounds__(kTileThreads) void k_asg_tiles(const float* __restr
         const unsigned long long v = reg[c];
         if (v == 0ull) continue;
         const int lx = c / (RG * RG), ly = (c / RG) % RG, lz = c % RG;
-        const int gx = (ox0 - 1 + lx + N) & (N - 1);
-        const int gy = (oy0 - 1 + ly + N) & (N - 1);
-        const int gz = (oz0 - 1 + lz + N) & (N - 1);
+        const int gx = (ox0 - LO + lx + N) & (N - 1);
+        const int gy = (oy0 - LO + ly + N) & (N - 1);
+        const int gz = (oz0 - LO + lz + N) & (N - 1);
         atomicAdd(acc + (size_t(gx) * N + gy) * N + gz, v);
     }
 }
@@ -328,7 +362,8 @@ static hermes_status assign_n(hermes_ctx ctx, const float* pos, const float* wei
         if (n_pts > 0)
             hipLaunchKernelGGL((k_asg_prep<N>), dim3(pblocks), dim3(kThreads), 0, stream, pos, weight, n_pts, scale,
                                count, partial);
-        hipLaunchKernelGGL(k_asg_scale, dim3(1), dim3(64), 0, stream, partial, pblocks, sum_w, sc);
+        const int head = ctx->basis == HERMES_BASIS_DB2 ? 2 : 0;
+        hipLaunchKernelGGL(k_asg_scale, dim3(1), dim3(64), 0, stream, partial, pblocks, head, sum_w, sc);
         const int nblk = (G::TILES + kScanBlock - 1) / kScanBlock;
         hipLaunchKernelGGL(k_scan_block, dim3(nblk), dim3(kScanBlock), 0, stream, count, int64_t(G::TILES), off,
                            blocksum);
@@ -338,8 +373,14 @@ static hermes_status assign_n(hermes_ctx ctx, const float* pos, const float* wei
         if (n_pts > 0) {
             hipLaunchKernelGGL((k_asg_scatter<N>), dim3(pblocks), dim3(kThreads), 0, stream, pos, n_pts, scale, off,
                                cursor, list);
-            hipLaunchKernelGGL((k_asg_tiles<T, N>), dim3(G::TILES), dim3(kTileThreads), 0, stream, pos, weight, scale, off,
-                               list, sc, reinterpret_cast<unsigned long long*>(acc));
+            if (ctx->basis == HERMES_BASIS_DB2)
+                hipLaunchKernelGGL((k_asg_tiles<T, N, HERMES_BASIS_DB2>), dim3(G::TILES), dim3(kTileThreads), 0, stream,
+                                   pos, weight, scale, off, list, sc, ctx->t.db2tab,
+                                   reinterpret_cast<unsigned long long*>(acc));
+            else
+                hipLaunchKernelGGL((k_asg_tiles<T, N, HERMES_BASIS_B3>), dim3(G::TILES), dim3(kTileThreads), 0, stream,
+                                   pos, weight, scale, off, list, sc, ctx->t.db2tab,
+                                   reinterpret_cast<unsigned long long*>(acc));
         }
         const int64_t want = (cells + kThreads - 1) / kThreads;
         hipLaunchKernelGGL((k_asg_convert<T>), dim3(int(want < 8192 ? want : 8192)), dim3(kThreads), 0, stream, acc,

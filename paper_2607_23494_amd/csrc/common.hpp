@@ -16,6 +16,8 @@ namespace hermes {
 constexpr int kThreads = 256;      // threads per workgroup for every kernel
 constexpr int kMaxN = 1024;        // largest grid per axis
 constexpr int kTwTable = 2 * 2048; // twiddle entries: table for length L at [L, 2L)
+constexpr int kDb2Level = 12;      // the D4 function is tabulated at x = i / 2^12, x in [0, 3]
+constexpr int kDb2Tab = 3 * (1 << kDb2Level) + 1;
 
 // Per-device constant tables owned by a context.
 struct Tables {
@@ -23,6 +25,9 @@ struct Tables {
     double2* tw64 = nullptr;
     double* phi1d = nullptr;    // sinc^8(pi n~/N) at phi1d[N + i], i in [0, N)
     double* b7dft = nullptr;    // sum_{|d|<=3} B7(d) cos(2 pi d i / N) at b7dft[N + i]
+    double* phi1d_db2 = nullptr;   // |phi^(2 pi n~/N)|^2 of the D4 function, same layout
+    double* ones = nullptr;        // 1 at every index: the D4 self-pair kernel (orthonormal basis)
+    double* db2tab = nullptr;      // D4 phi at x = i / 2^kDb2Level, i < kDb2Tab
     double* gl = nullptr;       // kGLSub (16) Gauss-Legendre nodes, then their weights, on [-1, 1]
     int* q2rank = nullptr;      // rank of q among the sums of two squares a^2 + b^2 (-1 if none), q <= 2 (kMaxN/2)^2
     int* rank2q = nullptr;      // the sums of two squares in increasing order
@@ -47,6 +52,7 @@ struct Profiler {
 struct hermes_ctx_s {
     int device = 0;
     int cus = 256;                // compute units of the device
+    int basis = HERMES_BASIS_B3;  // scaling function of every basis-dependent call
     hermes::Tables t;
     hermes::Profiler prof;
     void* xi_scratch = nullptr;   // device address of the static 2PCF scratch array on this device
@@ -76,6 +82,19 @@ private:
 };
 
 inline bool valid_n(int n) { return n >= 8 && n <= kMaxN && (n & (n - 1)) == 0; }
+
+// ---------------------------------------------------------------- basis
+// Per-axis basis kernel Phi^ and self-pair kernel of the context's basis.
+inline const double* basis_phi1d(hermes_ctx c) {
+    return c->basis == HERMES_BASIS_DB2 ? c->t.phi1d_db2 : c->t.phi1d;
+}
+inline const double* basis_selfdft(hermes_ctx c) {
+    return c->basis == HERMES_BASIS_DB2 ? c->t.ones : c->t.b7dft;
+}
+// Host tables of the D4 function (basis.hip).
+std::vector<double> db2_phi_table();
+double db2_phi_hat_sq(double w);
+void db2_gamma_factors(double lam[5], double vec[5][5]);
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 

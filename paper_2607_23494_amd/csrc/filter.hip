@@ -910,7 +910,7 @@ static void run_x(hermes_ctx ctx, const void* delta_k, double box_L, const WinSe
         if (pair) {
             LaunchScope ls(ctx, stream, "inv_x_window2");
             hipLaunchKernelGGL((k_win_x<T, N, XVEC, XNT, 2>), dim3((plane + TC - 1) / TC), dim3(XNT), 0, stream,
-                               static_cast<const C*>(delta_k), sh, y0, ylm_const(ell, m2), sre, sim, ctx->t.phi1d,
+                               static_cast<const C*>(delta_k), sh, y0, ylm_const(ell, m2), sre, sim, basis_phi1d(ctx),
                                sp, static_cast<C*>(spec_ws2), bin_stride, nb, ucol, tw);
             paired = true;
         }
@@ -918,7 +918,7 @@ static void run_x(hermes_ctx ctx, const void* delta_k, double box_L, const WinSe
     if (!paired) {
         LaunchScope ls(ctx, stream, "inv_x_window");
         hipLaunchKernelGGL((k_win_x<T, N, XVEC, XNT, 1>), dim3((plane + TC - 1) / TC), dim3(XNT), 0, stream,
-                           static_cast<const C*>(delta_k), sh, y0, y0, sre, sim, ctx->t.phi1d, sp, sp, bin_stride,
+                           static_cast<const C*>(delta_k), sh, y0, y0, sre, sim, basis_phi1d(ctx), sp, sp, bin_stride,
                            nb, ucol, tw);
     }
 }

@@ -1,6 +1,6 @@
-// B3 interpolation of a coefficient field at an arbitrary point (Sec. 3.1:
-// the value of n_W(x) = sum_l f_l phi_l(x) at any position), shared by the
-// readout and the Monte-Carlo triangle kernels.
+// Value of a coefficient field's basis expansion at an arbitrary point
+// (Sec. 3.1: n_W(x) = sum_l f_l phi_l(x) read at any position), shared by
+// the readout, Monte-Carlo triangle and assignment kernels.
 #pragma once
 
 #include "common.hpp"
@@ -16,34 +16,67 @@ __device__ __forceinline__ void b3_weights(double t, double w[4]) {
     w[3] = t * t * t / 6.0;
 }
 
-// sum_l f_l prod_a B3(u_a - l_a) over the 64 nodes around u (cell units, any
-// real values; node indices mod N), accumulated in float64.
-template <typename T, int N>
-__device__ __forceinline__ double b3_value(const T* __restrict__ field, const double u[3]) {
+// The D4 function at x in [0, 3]: the dyadic table (spacing 2^-kDb2Level)
+// interpolated linearly.  x = 3 (reachable by rounding) reads phi(3) = 0.
+__device__ __forceinline__ double db2_phi(double x, const double* __restrict__ tab) {
+    const double s = x * double(1 << kDb2Level);
+    int i = int(s);
+    i = i < kDb2Tab - 2 ? i : kDb2Tab - 2;
+    const double f = s - double(i);
+    const double a = tab[i], b = tab[i + 1];
+    return a + f * (b - a);
+}
+
+// Per-axis reach of a point at u = i0 + t (t in [0, 1)): the NT nodes
+// i0 - LO + o, o < NT, with weights phi(t + LO - o).
+template <int B> struct BasisTaps;
+template <> struct BasisTaps<HERMES_BASIS_B3> {
+    static constexpr int NT = 4, LO = 1;
+    __device__ static __forceinline__ void weights(double t, const double* __restrict__, double w[4]) {
+        b3_weights(t, w);
+    }
+};
+template <> struct BasisTaps<HERMES_BASIS_DB2> {
+    static constexpr int NT = 3, LO = 2;
+    __device__ static __forceinline__ void weights(double t, const double* __restrict__ tab, double w[3]) {
+        w[0] = db2_phi(t + 2.0, tab);
+        w[1] = db2_phi(t + 1.0, tab);
+        w[2] = db2_phi(t, tab);
+    }
+};
+
+// sum_l f_l prod_a phi(u_a - l_a) over the NT^3 nodes around u (cell units,
+// any real values; node indices mod N), accumulated in float64.
+template <typename T, int N, int B>
+__device__ __forceinline__ double basis_value(const T* __restrict__ field, const double u[3],
+                                              const double* __restrict__ tab) {
+    using P = BasisTaps<B>;
+    constexpr int NT = P::NT, LO = P::LO;
     int cell[3];
-    double tap[3][4];
+    double tap[3][NT];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double v = u[a];
         v -= double(N) * floor(v / double(N));   // periodic wrap into [0, N)
         const double f = floor(v);
         cell[a] = int(f);
-        b3_weights(v - f, tap[a]);
+        P::weights(v - f, tab, tap[a]);
     }
-    int cz[4];
+    int cz[NT];
 #pragma unroll
-    for (int oz = 0; oz < 4; ++oz) cz[oz] = (cell[2] - 1 + oz) & (N - 1);
+    for (int oz = 0; oz < NT; ++oz) cz[oz] = (cell[2] - LO + oz) & (N - 1);
     double val = 0.0;
 #pragma unroll
-    for (int ox = 0; ox < 4; ++ox) {
-        const int cx = (cell[0] - 1 + ox) & (N - 1);
+    for (int ox = 0; ox < NT; ++ox) {
+        const int cx = (cell[0] - LO + ox) & (N - 1);
         double vx = 0.0;
 #pragma unroll
-        for (int oy = 0; oy < 4; ++oy) {
-            const int cy = (cell[1] - 1 + oy) & (N - 1);
+        for (int oy = 0; oy < NT; ++oy) {
+            const int cy = (cell[1] - LO + oy) & (N - 1);
             const T* row = field + (size_t(cx) * N + cy) * N;
-            const double vy = tap[2][0] * double(row[cz[0]]) + tap[2][1] * double(row[cz[1]]) +
-                              tap[2][2] * double(row[cz[2]]) + tap[2][3] * double(row[cz[3]]);
+            double vy = 0.0;
+#pragma unroll
+            for (int oz = 0; oz < NT; ++oz) vy += tap[2][oz] * double(row[cz[oz]]);
             vx += tap[1][oy] * vy;
         }
         val += tap[0][ox] * vx;
@@ -51,18 +84,14 @@ __device__ __forceinline__ double b3_value(const T* __restrict__ field, const do
     return val;
 }
 
-}  // namespace hermes
-
-namespace hermes {
-
-// A row's four B3 taps in one aligned vector: Quad<T> at node (x, y, z) holds
-// the field at z - 1, z, z + 1, z + 2 (mod N) of row (x, y), so a point's 64
-// taps are 16 vector loads instead of 64 scalar ones.
+// A row's four consecutive nodes in one aligned vector: Quad<T> at node
+// (x, y, z) holds the field at z - LO .. z - LO + 3 (mod N) of row (x, y), so
+// a point's taps along z are one vector load (B3 uses all four, D4 three).
 template <typename T> struct alignas(4 * sizeof(T)) Quad {
     T v[4];
 };
 
-template <typename T, int N>
+template <typename T, int N, int LO>
 __global__ __launch_bounds__(kThreads) void k_pack_rows(const T* __restrict__ f, Quad<T>* __restrict__ out) {
     const int64_t total = int64_t(N) * N * N;
     const int64_t stride = int64_t(gridDim.x) * kThreads;
@@ -71,35 +100,39 @@ __global__ __launch_bounds__(kThreads) void k_pack_rows(const T* __restrict__ f,
         const int z = int(i & (N - 1));
         Quad<T> q;
 #pragma unroll
-        for (int o = 0; o < 4; ++o) q.v[o] = f[row + ((z - 1 + o) & (N - 1))];
+        for (int o = 0; o < 4; ++o) q.v[o] = f[row + ((z - LO + o) & (N - 1))];
         out[i] = q;
     }
 }
 
-// b3_value on a packed field.
-template <typename T, int N>
-__device__ __forceinline__ double b3_value_packed(const Quad<T>* __restrict__ p, const double u[3]) {
+// basis_value on a field packed with the basis's LO.
+template <typename T, int N, int B>
+__device__ __forceinline__ double basis_value_packed(const Quad<T>* __restrict__ p, const double u[3],
+                                                     const double* __restrict__ tab) {
+    using P = BasisTaps<B>;
+    constexpr int NT = P::NT, LO = P::LO;
     int cell[3];
-    double tap[3][4];
+    double tap[3][NT];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double v = u[a];
         v -= double(N) * floor(v / double(N));
         const double f = floor(v);
         cell[a] = int(f);
-        b3_weights(v - f, tap[a]);
+        P::weights(v - f, tab, tap[a]);
     }
     double val = 0.0;
 #pragma unroll
-    for (int ox = 0; ox < 4; ++ox) {
-        const int cx = (cell[0] - 1 + ox) & (N - 1);
+    for (int ox = 0; ox < NT; ++ox) {
+        const int cx = (cell[0] - LO + ox) & (N - 1);
         double vx = 0.0;
 #pragma unroll
-        for (int oy = 0; oy < 4; ++oy) {
-            const int cy = (cell[1] - 1 + oy) & (N - 1);
+        for (int oy = 0; oy < NT; ++oy) {
+            const int cy = (cell[1] - LO + oy) & (N - 1);
             const Quad<T> q = p[(size_t(cx) * N + cy) * N + (cell[2] & (N - 1))];
-            const double vy = tap[2][0] * double(q.v[0]) + tap[2][1] * double(q.v[1]) + tap[2][2] * double(q.v[2]) +
-                              tap[2][3] * double(q.v[3]);
+            double vy = 0.0;
+#pragma unroll
+            for (int oz = 0; oz < NT; ++oz) vy += tap[2][oz] * double(q.v[oz]);
             vx += tap[1][oy] * vy;
         }
         val += tap[0][ox] * vx;

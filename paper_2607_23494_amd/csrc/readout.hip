@@ -3,10 +3,9 @@
 // density-derived marks of Sec. 3.3.1 (Eqs. power-law-mark,
 // inverse-density-mark).
 //
-// With the cubic B-spline as scaling function the value at a point is the
-// 64-node sum v = sum_l f_l prod_a B3(x_a/h - l_a), the transpose of the
-// assignment's scatter: one thread per point gathers its 4 x 4 rows of 4
-// nodes.  Optionally the value becomes a mark and is multiplied by a weight
+// The value at a point is the node sum v = sum_l f_l prod_a phi(x_a/h - l_a)
+// (64 nodes with B3, 27 with the D4 function), the transpose of the
+// assignment's scatter: one thread per point gathers its rows of nodes.  Optionally the value becomes a mark and is multiplied by a weight
 // (the marked catalogue for hermes_assign), and the moments <v^p>, p = 2..4,
 // over the points are accumulated in float64 (counts in cells by sampling
 // positions).
@@ -30,18 +29,18 @@ __device__ __forceinline__ double apply_mark(const MarkParams& mk, double v) {
     return v;
 }
 
-template <typename T, int N>
+template <typename T, int N, int B>
 __global__ __launch_bounds__(kThreads) void k_readout(const T* __restrict__ field, const float* __restrict__ pos,
                                                       const float* __restrict__ weight, int64_t n_pts,
-                                                      double scale, MarkParams mk, T* __restrict__ out,
-                                                      double* __restrict__ mom) {
+                                                      double scale, MarkParams mk, const double* __restrict__ tab,
+                                                      T* __restrict__ out, double* __restrict__ mom) {
     __shared__ double red[kThreads];
     double m2 = 0.0, m3 = 0.0, m4 = 0.0;
     const int64_t stride = int64_t(gridDim.x) * kThreads;
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride) {
         const double u[3] = {double(pos[3 * i]) * scale, double(pos[3 * i + 1]) * scale,
                              double(pos[3 * i + 2]) * scale};   // position in cell units
-        const double v = b3_value<T, N>(field, u);
+        const double v = basis_value<T, N, B>(field, u, tab);
         if (mom) {
             const double v2 = v * v;
             m2 += v2;
@@ -82,8 +81,14 @@ static hermes_status readout_n(hermes_ctx ctx, const void* field, double box_L, 
         LaunchScope ls(ctx, stream, "readout");
         const int64_t want = (n_pts + kThreads - 1) / kThreads;
         const int blocks = int(want < 8192 ? want : 8192);
-        hipLaunchKernelGGL((k_readout<T, N>), dim3(blocks), dim3(kThreads), 0, stream, static_cast<const T*>(field),
-                           pos, weight, n_pts, double(N) / box_L, mk, static_cast<T*>(out), moments);
+        if (ctx->basis == HERMES_BASIS_DB2)
+            hipLaunchKernelGGL((k_readout<T, N, HERMES_BASIS_DB2>), dim3(blocks), dim3(kThreads), 0, stream,
+                               static_cast<const T*>(field), pos, weight, n_pts, double(N) / box_L, mk,
+                               ctx->t.db2tab, static_cast<T*>(out), moments);
+        else
+            hipLaunchKernelGGL((k_readout<T, N, HERMES_BASIS_B3>), dim3(blocks), dim3(kThreads), 0, stream,
+                               static_cast<const T*>(field), pos, weight, n_pts, double(N) / box_L, mk,
+                               ctx->t.db2tab, static_cast<T*>(out), moments);
         if (moments)
             hipLaunchKernelGGL(k_scale3, dim3(1), dim3(64), 0, stream, moments, 1.0 / double(n_pts));
     }

@@ -6,7 +6,8 @@
 // on the sphere, v uniform on the circle orthogonal to u.  For every opening
 // angle theta_j = (j + 1/2) pi / n_theta the triangle has its second vertex at
 // x + r12 u and its third at x + r13 (cos theta_j u + sin theta_j v); the
-// secondary vertices read the filtered fields f2, f3 by B3 interpolation.
+// secondary vertices read the filtered fields f2, f3 through the basis
+// expansion.
 // The sums over samples of a, a f2, a f3 and a f2 f3 (a = the point's weight,
 // or f1 at a box point) are accumulated in float64.
 //
@@ -15,8 +16,8 @@
 // (centre, 0, 1, 0) for a box point, key (seed, 0): every sample can be drawn
 // by any thread, and the oracle draws the same numbers.
 //
-// Fields are read through row-packed copies (four taps per vector load) up
-// to 512^3.  One thread per sample (grid-stride); per opening angle the
+// Fields are read through row-packed copies (a point's taps along z in one
+// vector load) up to 512^3.  One thread per sample (grid-stride); per opening angle the
 // wavefront's 64 samples are summed by a butterfly over lanes and lane 0 adds
 // them to the wavefront's LDS accumulators, so every sum is formed in a fixed
 // order and the result does not depend on timing.
@@ -71,18 +72,19 @@ size_t triplet_workspace(int n, int dtype, int n_theta) {
 }
 
 // A field read by the sampling kernel: packed rows or the plain array.
-template <typename T, int N>
+template <typename T, int N, int B>
 struct FieldRef {
     const T* f;
     const Quad<T>* q;
+    const double* tab;   // the D4 table (unused by B3)
     __device__ __forceinline__ double at(const double u[3]) const {
-        if constexpr (N <= kTripletPackMaxN) return b3_value_packed<T, N>(q, u);
-        else return b3_value<T, N>(f, u);
+        if constexpr (N <= kTripletPackMaxN) return basis_value_packed<T, N, B>(q, u, tab);
+        else return basis_value<T, N, B>(f, u, tab);
     }
 };
 
-template <typename T, int N, bool BOX>
-__global__ __launch_bounds__(kThreads) void k_triplet(FieldRef<T, N> f1, FieldRef<T, N> f2, FieldRef<T, N> f3,
+template <typename T, int N, bool BOX, int B>
+__global__ __launch_bounds__(kThreads) void k_triplet(FieldRef<T, N, B> f1, FieldRef<T, N, B> f2, FieldRef<T, N, B> f3,
                                                       bool has_f1, const float* __restrict__ centres,
                                                       const float* __restrict__ weights, int64_t n_centres, int n_rot,
                                                       double box_L, double r12, double r13, int n_theta,
@@ -194,14 +196,15 @@ __global__ void k_triplet_final(const double* __restrict__ part, int n_blocks, i
     out[i] = s;
 }
 
-template <typename T, int N>
-static hermes_status triplet_n(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, double box_L,
-                               const float* centres, const float* weights, int64_t n_centres, double r12,
-                               double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
-                               hipStream_t stream) {
+template <typename T, int N, int B>
+static hermes_status triplet_nb(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, double box_L,
+                                const float* centres, const float* weights, int64_t n_centres, double r12,
+                                double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
+                                hipStream_t stream) {
     double* part = static_cast<double*>(work);
-    FieldRef<T, N> r1{static_cast<const T*>(f1), nullptr}, r2{static_cast<const T*>(f2), nullptr},
-        r3{static_cast<const T*>(f3), nullptr};
+    const double* tab = ctx->t.db2tab;
+    FieldRef<T, N, B> r1{static_cast<const T*>(f1), nullptr, tab}, r2{static_cast<const T*>(f2), nullptr, tab},
+        r3{static_cast<const T*>(f3), nullptr, tab};
     if constexpr (N <= kTripletPackMaxN) {
         // pack every distinct field once
         char* base = static_cast<char*>(work) + align256(size_t(kTripletBlocks) * n_theta * 4 * sizeof(double));
@@ -209,7 +212,7 @@ static hermes_status triplet_n(hermes_ctx ctx, const void* f1, const void* f2, c
         Quad<T>* q[3] = {reinterpret_cast<Quad<T>*>(base), reinterpret_cast<Quad<T>*>(base + fb),
                          reinterpret_cast<Quad<T>*>(base + 2 * fb)};
         const void* src[3] = {f2, f3, f1};
-        FieldRef<T, N>* dst[3] = {&r2, &r3, &r1};
+        FieldRef<T, N, B>* dst[3] = {&r2, &r3, &r1};
         LaunchScope ls(ctx, stream, "pack_rows");
         for (int i = 0; i < 3; ++i) {
             if (!src[i]) continue;
@@ -222,7 +225,8 @@ static hermes_status triplet_n(hermes_ctx ctx, const void* f1, const void* f2, c
             }
             dst[i]->q = q[i];
             const int64_t want = (int64_t(N) * N * N + kThreads - 1) / kThreads;
-            hipLaunchKernelGGL((k_pack_rows<T, N>), dim3(int(want < 8192 ? want : 8192)), dim3(kThreads), 0, stream,
+            hipLaunchKernelGGL((k_pack_rows<T, N, BasisTaps<B>::LO>), dim3(int(want < 8192 ? want : 8192)),
+                               dim3(kThreads), 0, stream,
                                static_cast<const T*>(src[i]), q[i]);
         }
     }
@@ -232,10 +236,10 @@ static hermes_status triplet_n(hermes_ctx ctx, const void* f1, const void* f2, c
     {
         LaunchScope ls(ctx, stream, "triplet");
         if (centres) {
-            hipLaunchKernelGGL((k_triplet<T, N, false>), dim3(blocks), dim3(kThreads), 0, stream, r1, r2, r3,
+            hipLaunchKernelGGL((k_triplet<T, N, false, B>), dim3(blocks), dim3(kThreads), 0, stream, r1, r2, r3,
                                f1 != nullptr, centres, weights, n_centres, n_rot, box_L, r12, r13, n_theta, seed, part);
         } else {
-            hipLaunchKernelGGL((k_triplet<T, N, true>), dim3(blocks), dim3(kThreads), 0, stream, r1, r2, r3,
+            hipLaunchKernelGGL((k_triplet<T, N, true, B>), dim3(blocks), dim3(kThreads), 0, stream, r1, r2, r3,
                                f1 != nullptr, centres, weights, n_centres, n_rot, box_L, r12, r13, n_theta, seed, part);
         }
     }
@@ -245,6 +249,18 @@ static hermes_status triplet_n(hermes_ctx ctx, const void* f1, const void* f2, c
                            n_theta, out);
     }
     return check_launch("hermes_triplet_mc");
+}
+
+template <typename T, int N>
+static hermes_status triplet_n(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, double box_L,
+                               const float* centres, const float* weights, int64_t n_centres, double r12,
+                               double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
+                               hipStream_t stream) {
+    if (ctx->basis == HERMES_BASIS_DB2)
+        return triplet_nb<T, N, HERMES_BASIS_DB2>(ctx, f1, f2, f3, box_L, centres, weights, n_centres, r12, r13,
+                                                  n_theta, n_rot, seed, out, work, stream);
+    return triplet_nb<T, N, HERMES_BASIS_B3>(ctx, f1, f2, f3, box_L, centres, weights, n_centres, r12, r13, n_theta,
+                                             n_rot, seed, out, work, stream);
 }
 
 hermes_status triplet_impl(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, int n, int dtype,

@@ -13,8 +13,9 @@
 // Optionally the same passes give the shot-noise factor of each bin,
 //   S_lb = N^-3 sum_n K_lb(n) B~(n),  K_lb(n) = (2l+1) (-1)^{l/2} R_lb(q) L_l(mu) Phi^(n),
 // B~(n) = prod_a sum_{|d|<=3} B7(d) e^{2 pi i n_a d / N} (the B3 autocorrelation
-// at integer lags), i.e. the kernel summed against the self-pair term of the
-// assigned field: for iid points E xi_lb = (sum w^2 / W^2) (N^3 S_lb - K_lb(0)).
+// at integer lags; 1 for the orthonormal D4 basis), i.e. the kernel summed
+// against the self-pair term of the assigned field: for iid points
+// E xi_lb = (sum w^2 / W^2) (N^3 S_lb - K_lb(0)).
 // Its histogram Hs includes the mode n = 0.
 #include "common.hpp"
 #include "fft_core.hpp"
@@ -158,7 +159,7 @@ static hermes_status xi_n(hermes_ctx ctx, const void* delta_k, double box_L, con
     {
         LaunchScope ls(ctx, stream, "xi_hist");
         hipLaunchKernelGGL((k_xi_hist<T, N>), dim3((reps + kThreads - 1) / kThreads), dim3(kThreads), 0, stream,
-                           static_cast<const C*>(delta_k), ells, los, ctx->t.phi1d, ctx->t.b7dft, H, Hs, nq);
+                           static_cast<const C*>(delta_k), ells, los, basis_phi1d(ctx), basis_selfdft(ctx), H, Hs, nq);
     }
     {
         LaunchScope ls(ctx, stream, "xi_sum");

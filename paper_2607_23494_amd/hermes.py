@@ -75,12 +75,15 @@ def _load() -> ctypes.CDLL:
     lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
     lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
     lib.hermes_readout.argtypes = [vp, vp, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp, vp]
+    lib.hermes_set_basis.argtypes = [vp, i32]
+    lib.hermes_get_basis.argtypes = [vp]
+    lib.hermes_get_basis.restype = ctypes.c_int
     lib.hermes_profile_enable.argtypes = [vp, i32]
     lib.hermes_profile_reset.argtypes = [vp]
     lib.hermes_profile_read.argtypes = [vp, i32, ctypes.c_char_p, sz, ctypes.POINTER(i64), ctypes.POINTER(f64)]
     for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi", "hermes_xi_static", "hermes_xi_aniso", "hermes_triplet_mc", "hermes_ddd_gamma",
                  "hermes_filter_bins", "hermes_zeta_l", "hermes_readout", "hermes_profile_enable", "hermes_profile_reset",
-                 "hermes_profile_read"):
+                 "hermes_profile_read", "hermes_set_basis"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -104,6 +107,34 @@ def context(device: int) -> ctypes.c_void_p:
             _check(_lib.hermes_create(ctypes.byref(c), device))
             _ctx[device] = c
         return c
+
+
+BASES = {"b3": 0, "db2": 1}
+
+
+def set_basis(name: str, device: int = 0) -> None:
+    """Scaling function of every later call on the device's context: "b3"
+    (the centred cubic B-spline, default) or "db2" (the orthonormal
+    Daubechies D4 function)."""
+    if name not in BASES:
+        raise ValueError(f"unknown basis {name!r}")
+    _check(_lib.hermes_set_basis(context(device), BASES[name]))
+
+
+def get_basis(device: int = 0) -> str:
+    code = _lib.hermes_get_basis(context(device))
+    return {v: k for k, v in BASES.items()}[code]
+
+
+@contextlib.contextmanager
+def basis(name: str, device: int = 0):
+    """Run a block of calls with the given basis, then restore the previous one."""
+    prev = get_basis(device)
+    set_basis(name, device)
+    try:
+        yield
+    finally:
+        set_basis(prev, device)
 
 
 def _dev(t: torch.Tensor) -> int:
