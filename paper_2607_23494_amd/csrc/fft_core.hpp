@@ -11,6 +11,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "kernels.hpp"
 
 namespace hermes {
 
@@ -345,12 +346,6 @@ __device__ __forceinline__ void em_next(const EmMap& m, int& j, int& c) {
         c -= m.nl;
         ++j;
     }
-}
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Per-stage twiddle layout: the factors w^(r k), r = 1 .. R-1, k < NS, of a

@@ -21,14 +21,16 @@
 //    stencil prod V[o_i][q_i]: P_f[q][o] = V[o][q], P_e picks the node
 //    itself (o = 2), W = lambda.
 //
-// A workgroup takes bricks of 1 x 1 x CZ cells (in float the next brick's
-// coefficients load into registers meanwhile): for groups of fields it
-// stages the NT x NT x (CZ + NT - 1) coefficients in LDS, evaluates the
-// brick's 125 CZ points in three passes, and keeps the point values of e
-// (times W) and of every f_b in LDS; then each thread takes a 4 x 4 tile of
-// bin pairs over a slice of the points (nine LDS reads per sixteen FMAs).
-// Per-brick sums are float T, sums across bricks float64; the slices and
-// the workgroups' partials are added in a fixed order.
+// A workgroup takes bricks of 1 x 1 x CZ cells.  Its wavefronts share out
+// the fields: a wavefront stages a field's NT x NT x (CZ + NT - 1)
+// coefficients in its own LDS scratch (loaded into registers while its
+// previous field was evaluated), evaluates the brick's 125 CZ points in
+// three passes synchronising only itself, and writes the point values (e
+// times W, or f_b) to LDS.  After one barrier each thread takes a 4 x 4 tile
+// of bin pairs over a slice of the points (nine LDS reads per sixteen FMAs);
+// a second barrier frees the values.  Per-brick sums are float T, sums
+// across bricks float64; the slices and the workgroups' partials are added
+// in a fixed order.
 #include <cmath>
 #include <vector>
 
@@ -52,6 +54,13 @@ struct GammaOps {
     double pe[5][5];
     double pf[5][5];
     double w[5];
+};
+
+// The same in the field type, passed to the kernel (uniform operands).
+template <typename T> struct GammaOpsT {
+    T pe[5][5];
+    T pf[5][5];
+    T w[5];
 };
 
 static GammaOps gamma_ops_b3() {
@@ -103,6 +112,19 @@ static GammaOps gamma_ops_db2() {
     return g;
 }
 
+template <typename T>
+static GammaOpsT<T> gamma_ops_cast(const GammaOps& g) {
+    GammaOpsT<T> o{};
+    for (int q = 0; q < 5; ++q) {
+        o.w[q] = T(g.w[q]);
+        for (int k = 0; k < 5; ++k) {
+            o.pe[q][k] = T(g.pe[q][k]);
+            o.pf[q][k] = T(g.pf[q][k]);
+        }
+    }
+    return o;
+}
+
 size_t gamma_workspace() {
     return align256(size_t(kGammaBlocks) * kGammaMaxFields * kGammaMaxFields * sizeof(double));
 }
@@ -113,40 +135,42 @@ static void allow_lds_gamma(KernelT kernel, size_t bytes) {
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
-// Fields evaluated per barrier group (LDS for the staged coefficients and the
-// two intermediate passes of FG fields; 32 fields fit in 160 KB of LDS).
-template <typename T, int NT> constexpr int gamma_fg() {
-    return sizeof(T) == 4 ? (NT == 4 ? 8 : 4) : (NT == 4 ? 4 : 2);
-}
-
-// float: the next brick's coefficients of every field are loaded into
-// registers while the current brick is evaluated (and all fields'
-// coefficients are staged in LDS at once); float64 stages them per group.
-template <typename T> constexpr bool gamma_prefetch() { return sizeof(T) == 4; }
-template <int NT> constexpr int gamma_pre() {
-    return ((kGammaMaxFields + 1) * NT * NT * gamma_rz<NT>() + kThreads - 1) / kThreads;
+// Per-wavefront scratch (elements): the field's staged coefficients, which
+// the y-pass output later overwrites, then the z-pass output.
+template <int NT> constexpr int gamma_nc() { return NT * NT * gamma_rz<NT>(); }
+template <int NT> constexpr int gamma_scr() {
+    return (gamma_nc<NT>() > NT * 5 * kGammaZS ? gamma_nc<NT>() : NT * 5 * kGammaZS) + NT * NT * kGammaZS;
 }
 
 template <typename T, int NT>
-constexpr size_t gamma_lds_bytes(int nf) {
-    constexpr int FG = gamma_fg<T, NT>();
-    const size_t regs = size_t(gamma_prefetch<T>() ? nf + 1 : FG) * NT * NT * gamma_rz<NT>();
-    return (size_t(nf + 1) * kGammaS + regs + size_t(FG) * (NT * NT * kGammaZS + NT * 5 * kGammaZS)) * sizeof(T);
+constexpr size_t gamma_lds_bytes(int nf, int ne) {
+    return (size_t(nf + 1) * kGammaS + size_t(ne) * gamma_scr<NT>() + 5 * kGammaZS) * sizeof(T);
 }
 
+// One workgroup per brick at a time (persistent over the bricks).  Each of
+// the first `ne` wavefronts evaluates every ne-th field on its own: it stages
+// the field's NT x NT x RZ coefficients (loaded into registers while the
+// previous field was evaluated) in its LDS scratch and runs the z, y and x
+// passes, synchronising only itself; a work item of a pass reads NT inputs
+// and writes the five points q (the operators are uniform).  Then the block
+// forms the pair sums.
 template <typename T, int N, int NT>
 __global__ __launch_bounds__(kThreads) void k_ddd_gamma(const T* __restrict__ eps, const T* __restrict__ fields,
-                                                        int nf, GammaOps gq, double* __restrict__ part) {
+                                                        int nf, int ne, GammaOpsT<T> gq, double* __restrict__ part) {
     constexpr int BRICKS = N * N * (N / kGammaCZ);
-    constexpr int FG = gamma_fg<T, NT>();
-    constexpr bool PRE = gamma_prefetch<T>();
     constexpr int RZ = gamma_rz<NT>(), NN = NT * NT, LO = NT == 4 ? 1 : 2;
-    constexpr int NPRE = gamma_pre<NT>();
+    constexpr int NC = gamma_nc<NT>(), PL = (NC + 63) / 64;
+    constexpr int SB = NT * 5 * kGammaZS;
+    constexpr int ZS = kGammaZS;
     extern __shared__ double lds_raw[];
-    T* vals = reinterpret_cast<T*>(lds_raw);                       // [nf + 1][kGammaS]: e w, then f_b
-    T* reg = vals + (nf + 1) * kGammaS;                            // [nf + 1 or FG][NT][NT][RZ] coefficients
-    T* sa = reg + (PRE ? nf + 1 : FG) * NN * RZ;                   // [FG][NT][NT][kGammaZS] after the z pass
-    T* sb = sa + FG * NN * kGammaZS;                               // [FG][NT][5][kGammaZS] after the y pass
+    T* vals = reinterpret_cast<T*>(lds_raw);                        // [nf + 1][kGammaS]: e w, then f_b
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;   // wv: uniform
+    T* scr = vals + (nf + 1) * kGammaS + wv * gamma_scr<NT>();
+    T* rg = scr;                                                    // [NT][NT][RZ] coefficients
+    T* sbw = scr;                                                   // [NT][5][ZS] after the y pass
+    T* saw = scr + (NC > SB ? NC : SB);                             // [NT][NT][ZS] after the z pass
+    T* wyz = vals + (nf + 1) * kGammaS + ne * gamma_scr<NT>();      // [5][ZS]: w[qy] w[qz] of the e points
+    for (int i = threadIdx.x; i < 5 * ZS; i += kThreads) wyz[i] = gq.w[i / ZS] * gq.w[(i % ZS) % 5];
     // pair roles: 4 x 4 bin tiles (I <= J) x sample slices
     const int nt4 = (nf + 3) / 4;
     const int ntp = nt4 * (nt4 + 1) / 2;
@@ -164,93 +188,90 @@ __global__ __launch_bounds__(kThreads) void k_ddd_gamma(const T* __restrict__ ep
     double acc64[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc64[i] = 0.0;
-    // coefficient i (field-major: field, ox, oy, oz) of a brick
-    auto coef = [&](int brick, int i) -> T {
+    // this lane's coefficients of field f for a brick (field-major: ox, oy, oz)
+    auto load = [&](int brick, int f, T (&r)[PL]) {
         const int cz0 = (brick % (N / kGammaCZ)) * kGammaCZ;
         const int cy = (brick / (N / kGammaCZ)) % N;
         const int cx = brick / (N / kGammaCZ) / N;
-        const int f = i / (NN * RZ), e = i % (NN * RZ);
-        const int ox = e / (NT * RZ), oy = (e / RZ) % NT, oz = e % RZ;
-        const int x = (cx - LO + ox) & (N - 1), y = (cy - LO + oy) & (N - 1), z = (cz0 - LO + oz) & (N - 1);
         const T* src = f == 0 ? eps : fields + int64_t(f - 1) * N * N * N;
-        return src[(int64_t(x) * N + y) * N + z];
+#pragma unroll
+        for (int p = 0; p < PL; ++p) {
+            const int i = lane + 64 * p;
+            if (i < NC) {
+                const int ox = i / (NT * RZ), oy = (i / RZ) % NT, oz = i % RZ;
+                const int x = (cx - LO + ox) & (N - 1), y = (cy - LO + oy) & (N - 1), z = (cz0 - LO + oz) & (N - 1);
+                r[p] = src[(int64_t(x) * N + y) * N + z];
+            }
+        }
     };
-    const int ncoef = (nf + 1) * NN * RZ;
-    T pre[PRE ? NPRE : 1];
-    if constexpr (PRE) {
-        if (int(blockIdx.x) < BRICKS) {
-#pragma unroll
-            for (int k = 0; k < NPRE; ++k) {
-                const int i = threadIdx.x + k * kThreads;
-                if (i < ncoef) pre[k] = coef(blockIdx.x, i);
-            }
-        }
-    }
+    const bool evaluates = wv < ne;
+    T cur[PL];
+    if (evaluates && int(blockIdx.x) < BRICKS) load(blockIdx.x, wv, cur);
+    __syncthreads();   // wyz
     for (int brick = blockIdx.x; brick < BRICKS; brick += gridDim.x) {
-        if constexpr (PRE) {
-            // stage this brick's coefficients, then load the next brick's
+        if (evaluates) {
+            for (int f = wv; f <= nf; f += ne) {
 #pragma unroll
-            for (int k = 0; k < NPRE; ++k) {
-                const int i = threadIdx.x + k * kThreads;
-                if (i < ncoef) reg[i] = pre[k];
-            }
-            const int nxt = brick + int(gridDim.x);
-            if (nxt < BRICKS) {
-#pragma unroll
-                for (int k = 0; k < NPRE; ++k) {
-                    const int i = threadIdx.x + k * kThreads;
-                    if (i < ncoef) pre[k] = coef(nxt, i);
+                for (int p = 0; p < PL; ++p)
+                    if (lane + 64 * p < NC) rg[lane + 64 * p] = cur[p];
+                // the next (brick, field) of this wavefront loads meanwhile
+                int f2 = f + ne, b2 = brick;
+                if (f2 > nf) {
+                    f2 = wv;
+                    b2 = brick + int(gridDim.x);
                 }
-            }
-            __syncthreads();
-        }
-        for (int f0 = 0; f0 <= nf; f0 += FG) {
-            const int fg = nf + 1 - f0 < FG ? nf + 1 - f0 : FG;
-            if constexpr (!PRE) {
-                for (int i = threadIdx.x; i < fg * NN * RZ; i += kThreads)
-                    reg[i] = coef(brick, f0 * NN * RZ + i);
-                __syncthreads();
-            }
-            const T* greg = reg + (PRE ? f0 * NN * RZ : 0);
-            // z: [f][ox][oy][k q] = sum_o P[q][o] reg[f][ox][oy][k + o]
-            for (int i = threadIdx.x; i < fg * NN * kGammaZS; i += kThreads) {
-                const int fo = i / kGammaZS, sz = i % kGammaZS, k = sz / 5, q = sz % 5;
-                const double(&P)[5][5] = f0 + fo / NN == 0 ? gq.pe : gq.pf;
-                const T* r = greg + fo * RZ + k;
-                T v = T(0);
+                if (b2 < BRICKS) load(b2, f2, cur);
+                wave_sync();
+                const T(&P)[5][5] = f == 0 ? gq.pe : gq.pf;
+                // z: saw[ox][oy][k q] = sum_o P[q][o] rg[ox][oy][k + o]
+                for (int it = lane; it < NN * kGammaCZ; it += 64) {
+                    const int row = it / kGammaCZ, k = it % kGammaCZ;
+                    T in[NT];
 #pragma unroll
-                for (int o = 0; o < NT; ++o) v += T(P[q][o]) * r[o];
-                sa[i] = v;
-            }
-            __syncthreads();
-            // y: [f][ox][qy][sz] = sum_o P[qy][o] sa[f][ox][o][sz]
-            for (int i = threadIdx.x; i < fg * NT * 5 * kGammaZS; i += kThreads) {
-                const int fox = i / (5 * kGammaZS), qy = (i / kGammaZS) % 5, sz = i % kGammaZS;
-                const double(&P)[5][5] = f0 + fox / NT == 0 ? gq.pe : gq.pf;
-                const T* a = sa + fox * NT * kGammaZS + sz;
-                T v = T(0);
+                    for (int o = 0; o < NT; ++o) in[o] = rg[row * RZ + k + o];
 #pragma unroll
-                for (int o = 0; o < NT; ++o) v += T(P[qy][o]) * a[o * kGammaZS];
-                sb[i] = v;
-            }
-            __syncthreads();
-            // x: [qx][qy][sz] = sum_o P[qx][o] sb[f][o][qy][sz]; e carries the weights
-            for (int i = threadIdx.x; i < fg * kGammaS; i += kThreads) {
-                const int f = i / kGammaS, e = i % kGammaS;
-                const int qx = e / (5 * kGammaZS), rest = e % (5 * kGammaZS);
-                const double(&P)[5][5] = f0 + f == 0 ? gq.pe : gq.pf;
-                const T* b = sb + f * NT * 5 * kGammaZS + rest;
-                T v = T(0);
+                    for (int q = 0; q < 5; ++q) {
+                        T v = T(0);
 #pragma unroll
-                for (int o = 0; o < NT; ++o) v += T(P[qx][o]) * b[o * 5 * kGammaZS];
-                if (f0 + f == 0) {
-                    const int qy = rest / kGammaZS, qz = (rest % kGammaZS) % 5;
-                    v *= T(gq.w[qx] * gq.w[qy] * gq.w[qz]);
+                        for (int o = 0; o < NT; ++o) v += P[q][o] * in[o];
+                        saw[row * ZS + k * 5 + q] = v;
+                    }
                 }
-                vals[(f0 + f) * kGammaS + e] = v;
+                wave_sync();
+                // y: sbw[ox][qy][sz] = sum_o P[qy][o] saw[ox][o][sz]
+                for (int it = lane; it < NT * ZS; it += 64) {
+                    const int ox = it / ZS, sz = it % ZS;
+                    T in[NT];
+#pragma unroll
+                    for (int o = 0; o < NT; ++o) in[o] = saw[(ox * NT + o) * ZS + sz];
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        T v = T(0);
+#pragma unroll
+                        for (int o = 0; o < NT; ++o) v += P[q][o] * in[o];
+                        sbw[(ox * 5 + q) * ZS + sz] = v;
+                    }
+                }
+                wave_sync();
+                // x: vals[f][qx][qy][sz] = sum_o P[qx][o] sbw[o][qy][sz]; e carries the weights
+                T* dst = vals + f * kGammaS;
+                for (int it = lane; it < 5 * ZS; it += 64) {
+                    T in[NT];
+#pragma unroll
+                    for (int o = 0; o < NT; ++o) in[o] = sbw[o * 5 * ZS + it];
+                    const T wt = f == 0 ? wyz[it] : T(1);
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        T v = T(0);
+#pragma unroll
+                        for (int o = 0; o < NT; ++o) v += P[q][o] * in[o];
+                        dst[q * 5 * ZS + it] = f == 0 ? v * (gq.w[q] * wt) : v;
+                    }
+                }
+                wave_sync();
             }
-            __syncthreads();
         }
+        __syncthreads();
         // the tile's 4 x 4 block of pair sums over this slice's points
         if (slice < slices) {
             T acc[4][4];
@@ -315,19 +336,23 @@ __global__ void k_gamma_final(const double* __restrict__ part, int n_blocks, int
 }
 
 template <typename T, int N, int NT>
-static hermes_status gamma_nb(hermes_ctx ctx, const void* eps, const void* fields, int nf, const GammaOps& gq,
+static hermes_status gamma_nb(hermes_ctx ctx, const void* eps, const void* fields, int nf, const GammaOps& g64,
                               double* out, void* work, hipStream_t stream) {
-    const size_t lds_f = gamma_lds_bytes<T, NT>(nf), lds_r = size_t(kThreads) * 16 * sizeof(double);
+    // as many evaluating wavefronts (4, 2 or 1) as the LDS holds scratch for
+    int ne = kThreads / 64;
+    while (ne > 1 && gamma_lds_bytes<T, NT>(nf, ne) > size_t(160) * 1024) ne /= 2;
+    const size_t lds_f = gamma_lds_bytes<T, NT>(nf, ne), lds_r = size_t(kThreads) * 16 * sizeof(double);
     const size_t lds = lds_f > lds_r ? lds_f : lds_r;
     if (lds > size_t(160) * 1024) return fail(HERMES_ERR_UNSUPPORTED, "hermes_ddd_gamma: too many fields for LDS");
     allow_lds_gamma(k_ddd_gamma<T, N, NT>, lds);
+    const GammaOpsT<T> gq = gamma_ops_cast<T>(g64);
     constexpr int BRICKS = N * N * (N / kGammaCZ);
     const int blocks = BRICKS < kGammaBlocks ? BRICKS : kGammaBlocks;
     double* part = static_cast<double*>(work);
     {
         LaunchScope ls(ctx, stream, "ddd_gamma");
         hipLaunchKernelGGL((k_ddd_gamma<T, N, NT>), dim3(blocks), dim3(kThreads), lds, stream,
-                           static_cast<const T*>(eps), static_cast<const T*>(fields), nf, gq, part);
+                           static_cast<const T*>(eps), static_cast<const T*>(fields), nf, ne, gq, part);
     }
     {
         LaunchScope ls(ctx, stream, "reduce");

@@ -21,6 +21,15 @@ inline void launch_fill(T* p, int64_t n, T v, hipStream_t stream) {
     hipLaunchKernelGGL((k_fill<T>), dim3(blocks), dim3(kThreads), 0, stream, p, n, v);
 }
 
+// Order the LDS accesses of one wavefront: its lanes' earlier writes are
+// visible to its later reads (a wavefront's LDS operations complete in
+// order; the fences keep the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Block-wide float64 sum; every thread passes its value, thread 0 gets the
 // total.  `scratch` holds kThreads doubles.
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
