@@ -44,6 +44,7 @@ constexpr int kGammaS = 125 * kGammaCZ;            // points per brick
 constexpr int kGammaZS = 5 * kGammaCZ;             // points along z per brick
 constexpr int kGammaMaxFields = 32;               // bins per call
 constexpr int kGammaBlocks = 2048;                 // persistent workgroups over the bricks
+constexpr int kGammaThreads = 512;                 // eight wavefronts per workgroup
 
 // Coefficient nodes along z per brick.
 template <int NT> constexpr int gamma_rz() { return kGammaCZ + NT - 1; }
@@ -155,7 +156,7 @@ constexpr size_t gamma_lds_bytes(int nf, int ne) {
 // and writes the five points q (the operators are uniform).  Then the block
 // forms the pair sums.
 template <typename T, int N, int NT>
-__global__ __launch_bounds__(kThreads) void k_ddd_gamma(const T* __restrict__ eps, const T* __restrict__ fields,
+__global__ __launch_bounds__(kGammaThreads) void k_ddd_gamma(const T* __restrict__ eps, const T* __restrict__ fields,
                                                         int nf, int ne, GammaOpsT<T> gq, double* __restrict__ part) {
     constexpr int BRICKS = N * N * (N / kGammaCZ);
     constexpr int RZ = gamma_rz<NT>(), NN = NT * NT, LO = NT == 4 ? 1 : 2;
@@ -170,11 +171,11 @@ __global__ __launch_bounds__(kThreads) void k_ddd_gamma(const T* __restrict__ ep
     T* sbw = scr;                                                   // [NT][5][ZS] after the y pass
     T* saw = scr + (NC > SB ? NC : SB);                             // [NT][NT][ZS] after the z pass
     T* wyz = vals + (nf + 1) * kGammaS + ne * gamma_scr<NT>();      // [5][ZS]: w[qy] w[qz] of the e points
-    for (int i = threadIdx.x; i < 5 * ZS; i += kThreads) wyz[i] = gq.w[i / ZS] * gq.w[(i % ZS) % 5];
+    for (int i = threadIdx.x; i < 5 * ZS; i += kGammaThreads) wyz[i] = gq.w[i / ZS] * gq.w[(i % ZS) % 5];
     // pair roles: 4 x 4 bin tiles (I <= J) x sample slices
     const int nt4 = (nf + 3) / 4;
     const int ntp = nt4 * (nt4 + 1) / 2;
-    const int slices = kThreads / ntp;
+    const int slices = kGammaThreads / ntp;
     const int tp = threadIdx.x % ntp, slice = threadIdx.x / ntp;
     int ti = 0, tj = 0;
     for (int I = 0, idx = tp; I < nt4; ++I) {
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void k_ddd_gamma(const T* __restrict__ ep
             }
         }
     };
-    const bool evaluates = wv < ne;
+    const bool evaluates = wv < ne && wv <= nf;   // a wavefront with a field (its first is wv)
     T cur[PL];
     if (evaluates && int(blockIdx.x) < BRICKS) load(blockIdx.x, wv, cur);
     __syncthreads();   // wyz
@@ -338,10 +339,10 @@ __global__ void k_gamma_final(const double* __restrict__ part, int n_blocks, int
 template <typename T, int N, int NT>
 static hermes_status gamma_nb(hermes_ctx ctx, const void* eps, const void* fields, int nf, const GammaOps& g64,
                               double* out, void* work, hipStream_t stream) {
-    // as many evaluating wavefronts (4, 2 or 1) as the LDS holds scratch for
-    int ne = kThreads / 64;
+    // as many evaluating wavefronts (8, 4, 2 or 1) as the LDS holds scratch for
+    int ne = kGammaThreads / 64;
     while (ne > 1 && gamma_lds_bytes<T, NT>(nf, ne) > size_t(160) * 1024) ne /= 2;
-    const size_t lds_f = gamma_lds_bytes<T, NT>(nf, ne), lds_r = size_t(kThreads) * 16 * sizeof(double);
+    const size_t lds_f = gamma_lds_bytes<T, NT>(nf, ne), lds_r = size_t(kGammaThreads) * 16 * sizeof(double);
     const size_t lds = lds_f > lds_r ? lds_f : lds_r;
     if (lds > size_t(160) * 1024) return fail(HERMES_ERR_UNSUPPORTED, "hermes_ddd_gamma: too many fields for LDS");
     allow_lds_gamma(k_ddd_gamma<T, N, NT>, lds);
@@ -351,7 +352,7 @@ static hermes_status gamma_nb(hermes_ctx ctx, const void* eps, const void* field
     double* part = static_cast<double*>(work);
     {
         LaunchScope ls(ctx, stream, "ddd_gamma");
-        hipLaunchKernelGGL((k_ddd_gamma<T, N, NT>), dim3(blocks), dim3(kThreads), lds, stream,
+        hipLaunchKernelGGL((k_ddd_gamma<T, N, NT>), dim3(blocks), dim3(kGammaThreads), lds, stream,
                            static_cast<const T*>(eps), static_cast<const T*>(fields), nf, ne, gq, part);
     }
     {

@@ -97,3 +97,24 @@ def test_ddd_gamma_errors(hermes):
         hermes.ddd_gamma(e, torch.zeros((33, 8, 8, 8), device="cuda"))
     with pytest.raises(ValueError):
         hermes.ddd_gamma(e, torch.zeros((2, 8, 8, 4), device="cuda"))
+
+
+@pytest.mark.parametrize("basis", ["b3", "db2"])
+def test_ddd_gamma_fewer_fields_than_wavefronts(hermes, basis):
+    """One, two and three fields (fewer than the workgroup's wavefronts) at
+    256^3: constant fields give the product of the constants; a random
+    8^3 case with one field against the oracle."""
+    n = 256
+    with hermes.basis(basis):
+        k = torch.full((n, n, n), 2.0, device="cuda")
+        for nf in (1, 2, 3):
+            fc = torch.stack([torch.full((n, n, n), float(i + 1), device="cuda") for i in range(nf)])
+            got = hermes.ddd_gamma(k, fc).cpu().numpy()
+            want = 2.0 * np.outer(np.arange(1, nf + 1), np.arange(1, nf + 1))
+            assert np.max(np.abs(got - want) / want) < 1e-5, nf
+        rng = np.random.default_rng(31)
+        e = rng.standard_normal((8, 8, 8))
+        f = rng.standard_normal((1, 8, 8, 8))
+        got = hermes.ddd_gamma(torch.from_numpy(e).cuda(), torch.from_numpy(f).cuda()).cpu().numpy()
+        ref = O.ddd_gamma(e, f[0], f[0], basis=basis)
+        assert abs(got[0, 0] - ref) < 1e-10 * max(1.0, abs(ref))
