@@ -111,7 +111,8 @@ template <typename T>
 __device__ __forceinline__ T b3_tap(T t, int o) {
     const T d = fabs(t + T(1 - o));
     const T e = T(2) - d;
-    return d < T(1) ? (T(4) - T(6) * d * d + T(3) * d * d * d) / T(6) : e * e * e / T(6);
+    constexpr T kSixth = T(1) / T(6);
+    return d < T(1) ? (T(4) - T(6) * d * d + T(3) * d * d * d) * kSixth : e * e * e * kSixth;
 }
 
 // Broadcast of lane j's value (j uniform across the wavefront).

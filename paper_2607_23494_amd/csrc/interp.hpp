@@ -7,13 +7,16 @@
 
 namespace hermes {
 
-// B3 weights of the nodes i0-1 .. i0+2 for the fractional offset t in [0, 1).
+// B3 weights of the nodes i0-1 .. i0+2 for the fractional offset t in [0, 1)
+// (multiplied by the rounded 1/6 rather than divided: one rounding more, no
+// division sequence).
 __device__ __forceinline__ void b3_weights(double t, double w[4]) {
+    constexpr double kSixth = 1.0 / 6.0;
     const double s = 1.0 - t;
-    w[0] = s * s * s / 6.0;
-    w[1] = (4.0 - 6.0 * t * t + 3.0 * t * t * t) / 6.0;
-    w[2] = (4.0 - 6.0 * s * s + 3.0 * s * s * s) / 6.0;
-    w[3] = t * t * t / 6.0;
+    w[0] = s * s * s * kSixth;
+    w[1] = (4.0 - 6.0 * t * t + 3.0 * t * t * t) * kSixth;
+    w[2] = (4.0 - 6.0 * s * s + 3.0 * s * s * s) * kSixth;
+    w[3] = t * t * t * kSixth;
 }
 
 // The D4 function at x in [0, 3]: the dyadic table (spacing 2^-kDb2Level)

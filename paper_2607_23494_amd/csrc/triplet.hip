@@ -91,10 +91,16 @@ __global__ __launch_bounds__(kThreads) void k_triplet(FieldRef<T, N, B> f1, Fiel
                                                       uint64_t seed, double* __restrict__ part) {
     __shared__ double acc[kTripletWaves][HERMES_MAX_THETA][2];   // per wavefront: sum a f3, sum a f2 f3
     __shared__ double red[kThreads];
+    __shared__ double cs[HERMES_MAX_THETA][2];                    // cos, sin of the opening angles
     const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
     for (int j = threadIdx.x; j < kTripletWaves * HERMES_MAX_THETA; j += kThreads) {
         acc[j / HERMES_MAX_THETA][j % HERMES_MAX_THETA][0] = 0.0;
         acc[j / HERMES_MAX_THETA][j % HERMES_MAX_THETA][1] = 0.0;
+    }
+    for (int j = threadIdx.x; j < n_theta; j += kThreads) {
+        const double th = (double(j) + 0.5) * M_PI / double(n_theta);
+        cs[j][0] = cos(th);
+        cs[j][1] = sin(th);
     }
     __syncthreads();
     const double scale = double(N) / box_L;
@@ -155,8 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_triplet(FieldRef<T, N, B> f1, Fiel
         for (int j = 0; j < n_theta; ++j) {
             double p3 = 0.0, p23 = 0.0;
             if (live) {
-                const double th = (double(j) + 0.5) * M_PI / double(n_theta);
-                const double ct = cos(th), st = sin(th);
+                const double ct = cs[j][0], st = cs[j][1];
                 const double q[3] = {(x[0] + r13 * (ct * u[0] + st * v[0])) * scale,
                                      (x[1] + r13 * (ct * u[1] + st * v[1])) * scale,
                                      (x[2] + r13 * (ct * u[2] + st * v[2])) * scale};
