@@ -87,60 +87,4 @@ __device__ __forceinline__ double basis_value(const T* __restrict__ field, const
     return val;
 }
 
-// A row's four consecutive nodes in one aligned vector: Quad<T> at node
-// (x, y, z) holds the field at z - LO .. z - LO + 3 (mod N) of row (x, y), so
-// a point's taps along z are one vector load (B3 uses all four, D4 three).
-template <typename T> struct alignas(4 * sizeof(T)) Quad {
-    T v[4];
-};
-
-template <typename T, int N, int LO>
-__global__ __launch_bounds__(kThreads) void k_pack_rows(const T* __restrict__ f, Quad<T>* __restrict__ out) {
-    const int64_t total = int64_t(N) * N * N;
-    const int64_t stride = int64_t(gridDim.x) * kThreads;
-    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < total; i += stride) {
-        const int64_t row = i & ~int64_t(N - 1);
-        const int z = int(i & (N - 1));
-        Quad<T> q;
-#pragma unroll
-        for (int o = 0; o < 4; ++o) q.v[o] = f[row + ((z - LO + o) & (N - 1))];
-        out[i] = q;
-    }
-}
-
-// basis_value on a field packed with the basis's LO.
-template <typename T, int N, int B>
-__device__ __forceinline__ double basis_value_packed(const Quad<T>* __restrict__ p, const double u[3],
-                                                     const double* __restrict__ tab) {
-    using P = BasisTaps<B>;
-    constexpr int NT = P::NT, LO = P::LO;
-    int cell[3];
-    double tap[3][NT];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double v = u[a];
-        v -= double(N) * floor(v / double(N));
-        const double f = floor(v);
-        cell[a] = int(f);
-        P::weights(v - f, tab, tap[a]);
-    }
-    double val = 0.0;
-#pragma unroll
-    for (int ox = 0; ox < NT; ++ox) {
-        const int cx = (cell[0] - LO + ox) & (N - 1);
-        double vx = 0.0;
-#pragma unroll
-        for (int oy = 0; oy < NT; ++oy) {
-            const int cy = (cell[1] - LO + oy) & (N - 1);
-            const Quad<T> q = p[(size_t(cx) * N + cy) * N + (cell[2] & (N - 1))];
-            double vy = 0.0;
-#pragma unroll
-            for (int oz = 0; oz < NT; ++oz) vy += tap[2][oz] * double(q.v[oz]);
-            vx += tap[1][oy] * vy;
-        }
-        val += tap[0][ox] * vx;
-    }
-    return val;
-}
-
 }  // namespace hermes

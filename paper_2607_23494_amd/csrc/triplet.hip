@@ -16,8 +16,10 @@
 // (centre, 0, 1, 0) for a box point, key (seed, 0): every sample can be drawn
 // by any thread, and the oracle draws the same numbers.
 //
-// Fields are read through row-packed copies (a point's taps along z in one
-// vector load) up to 512^3.  One thread per sample (grid-stride); per opening angle the
+// Fields are read through tile-packed copies (each node holds the 4 x 4
+// (y, z) block of nodes a point in its cell reaches, so a read is four
+// 64-byte loads, one per x plane) up to 512^3 in float32 and 256^3 in
+// float64.  One thread per sample (grid-stride); per opening angle the
 // wavefront's 64 samples are summed by a butterfly over lanes and lane 0 adds
 // them to the wavefront's LDS accumulators, so every sum is formed in a fixed
 // order and the result does not depend on timing.
@@ -60,25 +62,84 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Fields are read through row-packed copies (Quad, four times the field)
-// up to N = 512; at 1024^3 (16 GB per packed float field) directly.
-constexpr int kTripletPackMaxN = 512;
+// Tile-packed copies: sixteen times the field (8.6 GB per float32 field at
+// 512^3); larger grids read the plain array.
+template <typename T> constexpr int tile_max_n() { return sizeof(T) == 4 ? 512 : 256; }
+
+// The 4 x 4 block of a node: Tile<T> at (x, y, z) holds the field at
+// (x, y - LO + a, z - LO + b), a, b < 4 (indices mod N), a-major.
+template <typename T> struct alignas(16 * sizeof(T)) Tile {
+    T v[16];
+};
 
 size_t triplet_workspace(int n, int dtype, int n_theta) {
     const size_t part = align256(size_t(kTripletBlocks) * n_theta * 4 * sizeof(double));
-    if (n > kTripletPackMaxN) return part;
-    const size_t elem = dtype == HERMES_F32 ? sizeof(Quad<float>) : sizeof(Quad<double>);
+    const bool f32 = dtype == HERMES_F32;
+    if (n > (f32 ? tile_max_n<float>() : tile_max_n<double>())) return part;
+    const size_t elem = f32 ? sizeof(Tile<float>) : sizeof(Tile<double>);
     return part + 3 * align256(size_t(n) * n * n * elem);
 }
 
-// A field read by the sampling kernel: packed rows or the plain array.
+template <typename T, int N, int LO>
+__global__ __launch_bounds__(kThreads) void k_pack_tiles(const T* __restrict__ f, Tile<T>* __restrict__ out) {
+    const int64_t total = int64_t(N) * N * N;
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < total; i += stride) {
+        const int64_t plane = i & ~(int64_t(N) * N - 1);
+        const int y = int((i / N) & (N - 1)), z = int(i & (N - 1));
+        Tile<T> t;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                t.v[a * 4 + b] = f[plane + int64_t((y - LO + a) & (N - 1)) * N + ((z - LO + b) & (N - 1))];
+        out[i] = t;
+    }
+}
+
+// basis_value on a tile-packed field: one tile per x plane of the stencil.
+template <typename T, int N, int B>
+__device__ __forceinline__ double basis_value_tiles(const Tile<T>* __restrict__ p, const double u[3],
+                                                    const double* __restrict__ tab) {
+    using P = BasisTaps<B>;
+    constexpr int NT = P::NT, LO = P::LO;
+    int cell[3];
+    double tap[3][NT];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double v = u[a];
+        v -= double(N) * floor(v / double(N));   // periodic wrap into [0, N)
+        const double f = floor(v);
+        cell[a] = int(f);
+        P::weights(v - f, tab, tap[a]);
+    }
+    const size_t yz = size_t(cell[1] & (N - 1)) * N + (cell[2] & (N - 1));
+    double val = 0.0;
+#pragma unroll
+    for (int ox = 0; ox < NT; ++ox) {
+        const int cx = (cell[0] - LO + ox) & (N - 1);
+        const Tile<T> t = p[size_t(cx) * N * N + yz];
+        double vx = 0.0;
+#pragma unroll
+        for (int oy = 0; oy < NT; ++oy) {
+            double vy = 0.0;
+#pragma unroll
+            for (int oz = 0; oz < NT; ++oz) vy += tap[2][oz] * double(t.v[oy * 4 + oz]);
+            vx += tap[1][oy] * vy;
+        }
+        val += tap[0][ox] * vx;
+    }
+    return val;
+}
+
+// A field read by the sampling kernel: tiles or the plain array.
 template <typename T, int N, int B>
 struct FieldRef {
     const T* f;
-    const Quad<T>* q;
+    const Tile<T>* t;
     const double* tab;   // the D4 table (unused by B3)
     __device__ __forceinline__ double at(const double u[3]) const {
-        if constexpr (N <= kTripletPackMaxN) return basis_value_packed<T, N, B>(q, u, tab);
+        if constexpr (N <= tile_max_n<T>()) return basis_value_tiles<T, N, B>(t, u, tab);
         else return basis_value<T, N, B>(f, u, tab);
     }
 };
@@ -210,29 +271,27 @@ static hermes_status triplet_nb(hermes_ctx ctx, const void* f1, const void* f2, 
     const double* tab = ctx->t.db2tab;
     FieldRef<T, N, B> r1{static_cast<const T*>(f1), nullptr, tab}, r2{static_cast<const T*>(f2), nullptr, tab},
         r3{static_cast<const T*>(f3), nullptr, tab};
-    if constexpr (N <= kTripletPackMaxN) {
+    if constexpr (N <= tile_max_n<T>()) {
         // pack every distinct field once
         char* base = static_cast<char*>(work) + align256(size_t(kTripletBlocks) * n_theta * 4 * sizeof(double));
-        const size_t fb = align256(size_t(N) * N * N * sizeof(Quad<T>));
-        Quad<T>* q[3] = {reinterpret_cast<Quad<T>*>(base), reinterpret_cast<Quad<T>*>(base + fb),
-                         reinterpret_cast<Quad<T>*>(base + 2 * fb)};
+        const size_t fb = align256(size_t(N) * N * N * sizeof(Tile<T>));
         const void* src[3] = {f2, f3, f1};
         FieldRef<T, N, B>* dst[3] = {&r2, &r3, &r1};
-        LaunchScope ls(ctx, stream, "pack_rows");
+        LaunchScope ls(ctx, stream, "pack_tiles");
         for (int i = 0; i < 3; ++i) {
             if (!src[i]) continue;
             int same = -1;
             for (int k = 0; k < i; ++k)
                 if (src[k] == src[i]) same = k;
             if (same >= 0) {
-                dst[i]->q = dst[same]->q;
+                dst[i]->t = dst[same]->t;
                 continue;
             }
-            dst[i]->q = q[i];
+            Tile<T>* t = reinterpret_cast<Tile<T>*>(base + size_t(i) * fb);
+            dst[i]->t = t;
             const int64_t want = (int64_t(N) * N * N + kThreads - 1) / kThreads;
-            hipLaunchKernelGGL((k_pack_rows<T, N, BasisTaps<B>::LO>), dim3(int(want < 8192 ? want : 8192)),
-                               dim3(kThreads), 0, stream,
-                               static_cast<const T*>(src[i]), q[i]);
+            hipLaunchKernelGGL((k_pack_tiles<T, N, BasisTaps<B>::LO>), dim3(int(want < 8192 ? want : 8192)),
+                               dim3(kThreads), 0, stream, static_cast<const T*>(src[i]), t);
         }
     }
     const int64_t total = n_centres * int64_t(n_rot);

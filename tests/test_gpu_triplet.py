@@ -119,3 +119,26 @@ def test_triplet_256_particle_centres_sampled(hermes):
     ref = O.triplet_mc(of, of, L, 20.0, 40.0, 20, 4, 7, centres=sub)
     for q in (1, 2, 3):
         assert normwise(got[:, q], ref[:, q]) < 1e-5, q
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_triplet_512_tiles_and_direct_reads(hermes, dtype):
+    """512^3: float32 fields go through tile-packed copies, float64 fields
+    are read directly; both against the oracle on a two-wave field, with
+    catalogue centres and box points (f1 a third field)."""
+    n, L = 512, 1000.0
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    f2 = synth.cosine_field(n, [np.array([3, -5, 7]), np.array([11, 2, -4])], [0.6, 0.3]).astype(npdt)
+    f1 = (1.0 + synth.cosine_field(n, [np.array([1, 2, 3])], [0.2])).astype(npdt)
+    t2, t1 = torch.from_numpy(f2).cuda(), torch.from_numpy(f1).cuda()
+    rng = np.random.default_rng(512)
+    c = rng.uniform(0, L, (300, 3)).astype(np.float32)
+    tol = 1e-5 if dtype == torch.float32 else 1e-10
+    got = hermes.triplet_mc(t2, t2, L, 20.0, 40.0, 6, 3, 91, centres=torch.from_numpy(c).cuda()).cpu().numpy()
+    ref = O.triplet_mc(f2, f2, L, 20.0, 40.0, 6, 3, 91, centres=c)
+    for q in range(4):
+        assert normwise(got[:, q], ref[:, q]) < tol, q
+    got = hermes.triplet_mc(t2, t2, L, 15.0, 35.0, 4, 2, 17, n_box=257, f1=t1).cpu().numpy()
+    ref = O.triplet_mc(f2, f2, L, 15.0, 35.0, 4, 2, 17, n_box=257, f1=f1)
+    for q in range(4):
+        assert normwise(got[:, q], ref[:, q]) < tol, q
