@@ -351,6 +351,38 @@ def other_configs(warmup: int, steps: int) -> dict:
     del pos
     torch.cuda.empty_cache()
 
+    # counts in cells by random spheres (Sec. 3.1): the 512^3 field of the
+    # 1e7-point catalogue smoothed with spheres of R = 10, 15, 20, each read
+    # at 1e8 uniform random positions (values and their moments)
+    wl = synth.WORKLOADS["ns512_3pcf"]
+    pos_np, w_np = wl.catalogue()
+    n, L = wl.n_grid, wl.box_L
+    cpos = torch.from_numpy(pos_np).cuda()
+    cw = torch.from_numpy(w_np).cuda()
+    del pos_np, w_np
+    eps, sw = hermes.assign(cpos, None, L, n)
+    dk, _ = hermes.fft(eps, sw, want_delta=False)
+    del eps, cpos, cw
+    spheres = [("sphere", 0.0, R) for R in (10.0, 15.0, 20.0)]
+    cfields, _ = hermes.filter_bins(dk, L, spheres, store_fields=True, moments=False)
+    del dk
+    g = torch.Generator(device="cuda").manual_seed(2607)
+    rpos = (torch.rand((100_000_000, 3), device="cuda", generator=g) * L).contiguous()
+    vals = torch.empty(100_000_000, dtype=torch.float32, device="cuda")
+    moms = torch.empty((3, 3), dtype=torch.float64, device="cuda")
+    rwork = torch.empty(hermes.workspace_size(hermes.OP_READOUT, n, torch.float32, 100_000_000),
+                        dtype=torch.uint8, device="cuda")
+
+    def step_cic_random():
+        for i in range(len(spheres)):
+            hermes.readout(cfields[i], L, rpos, out=vals, moments_out=moms[i], work=rwork)
+    record("ns512_cic_random", step_cic_random, 3 * 100_000_000,
+           "counts in cells by random spheres: the 512^3 contrast of the 1e7-point catalogue smoothed with "
+           "spheres of R = 10, 15, 20, each read at 1e8 uniform random positions (values and moments)",
+           per="readouts")
+    del cfields, rpos, vals, moms, rwork
+    torch.cuda.empty_cache()
+
     # 1024^3: 1e8 marked points, marked 2PCF (40 bins) and the unmarked 2PCF on
     # the mark-weighted and number fields, counts-in-cells moments of the
     # number field for the sphere and Gaussian at 8 radii

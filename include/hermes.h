@@ -105,7 +105,8 @@ typedef enum hermes_op {
     HERMES_OP_ZETA = 4,
     HERMES_OP_XI_ANISO = 5,
     HERMES_OP_TRIPLET = 6,
-    HERMES_OP_DDD_GAMMA = 7
+    HERMES_OP_DDD_GAMMA = 7,
+    HERMES_OP_READOUT = 8
 } hermes_op;
 
 typedef struct hermes_ctx_s* hermes_ctx;
@@ -150,8 +151,8 @@ void hermes_destroy(hermes_ctx ctx);
 const char* hermes_last_error(void);
 
 /* Device workspace, in bytes, that `op` needs for an N^3 grid.  n_batch is
- * the number of points (ASSIGN), windows (FILTER, XI_ANISO), radial bins (ZETA),
- * opening angles (TRIPLET) or fields (DDD_GAMMA);
+ * the number of points (ASSIGN, READOUT), windows (FILTER, XI_ANISO), radial
+ * bins (ZETA), opening angles (TRIPLET) or fields (DDD_GAMMA);
  * n_ells the number of multipoles (XI).  Zero for FFT, which needs none. */
 hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtype,
                                     int n_batch, int n_ells, size_t* bytes);
@@ -435,14 +436,24 @@ typedef struct hermes_mark {
  *           v^4 (unweighted, unmarked), accumulated in float64 (the order of
  *           the float64 additions across workgroups is not fixed); zeros for
  *           n_pts = 0
+ *   work    device workspace of >= hermes_workspace_size(READOUT, n_batch =
+ *           n_pts) bytes, or NULL.  With it, calls of 2^16 to 2^31 - 1 points
+ *           first bucket the points by 16^3-cell tiles (counts, offsets, a
+ *           4-byte index and a copy of the position per point, 16 bytes) and
+ *           read them tile by tile, which keeps
+ *           the gathers of neighbouring threads in one region of the field;
+ *           the size is 0 outside that range.  NULL reads the points in the
+ *           given order.  Values land at their points' indices either way.
  * ERR_ARG for NULL buffers, out and moments both NULL, n_pts < 0, box_L <= 0,
  * a bad N or dtype, a non-zero reserved field, an unknown mark kind, a
  * non-finite exponent, offset < 0, or offset = 0 where rho = 0 would divide by
- * zero (inverse density, or a power law with a negative exponent). */
+ * zero (inverse density, or a power law with a negative exponent); ERR_OOM if
+ * work is given and work_bytes is too small. */
 hermes_status hermes_readout(hermes_ctx ctx, const void* field, int n_grid, int dtype,
                              double box_L, const float* pos, const float* weight,
                              int64_t n_pts, const hermes_mark* mark, void* out,
-                             double* moments, hipStream_t stream);
+                             double* moments, void* work, size_t work_bytes,
+                             hipStream_t stream);
 
 /* Per-kernel timing for measurement.  While enabled, every kernel launch of
  * this context is bracketed with HIP events recorded on its launch stream;

@@ -346,6 +346,10 @@ hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtyp
         case HERMES_OP_DDD_GAMMA:
             *bytes = gamma_workspace();
             return HERMES_OK;
+        case HERMES_OP_READOUT:
+            if (n_batch < 0) return fail(HERMES_ERR_ARG, "hermes_workspace_size: READOUT needs n_batch >= 0");
+            *bytes = readout_workspace(n_grid, n_batch);
+            return HERMES_OK;
         case HERMES_OP_ZETA:
             if (dtype != HERMES_F32) return fail(HERMES_ERR_UNSUPPORTED, "hermes_workspace_size: ZETA runs in float32");
             if (n_batch < 1 || n_batch > HERMES_MAX_BINS)
@@ -556,7 +560,7 @@ hermes_status hermes_zeta_l(hermes_ctx ctx, const float* delta, const void* delt
 
 hermes_status hermes_readout(hermes_ctx ctx, const void* field, int n_grid, int dtype, double box_L,
                              const float* pos, const float* weight, int64_t n_pts, const hermes_mark* mark,
-                             void* out, double* moments, hipStream_t stream) {
+                             void* out, double* moments, void* work, size_t work_bytes, hipStream_t stream) {
     if (!ctx || !field || (n_pts > 0 && !pos)) return fail(HERMES_ERR_ARG, "hermes_readout: NULL argument");
     if (!out && !moments) return fail(HERMES_ERR_ARG, "hermes_readout: out and moments both NULL");
     if (n_pts < 0) return fail(HERMES_ERR_ARG, "hermes_readout: n_pts < 0");
@@ -576,8 +580,10 @@ hermes_status hermes_readout(hermes_ctx ctx, const void* field, int n_grid, int 
         if (divides && !(mark->offset > 0.0))
             return fail(HERMES_ERR_ARG, "hermes_readout: this mark needs offset > 0");
     }
+    if (work && work_bytes < readout_workspace(n_grid, n_pts))
+        return fail(HERMES_ERR_OOM, "hermes_readout: workspace too small");
     DeviceGuard g(ctx->device);
-    return readout_impl(ctx, field, n_grid, dtype, box_L, pos, weight, n_pts, mark, out, moments, stream);
+    return readout_impl(ctx, field, n_grid, dtype, box_L, pos, weight, n_pts, mark, out, moments, work, stream);
 }
 
 }  // extern "C"

@@ -26,22 +26,18 @@
 // points, tiles and workgroups are processed.
 #include <cmath>
 
+#include "bucket.hpp"
 #include "common.hpp"
 #include "interp.hpp"
 #include "kernels.hpp"
 
 namespace hermes {
 
-constexpr int kAsgTile = 16;       // cells per tile edge (N >= 16; the whole grid below)
 constexpr int kAsgPrepBlocks = 2048;
-constexpr int kScanBlock = 1024;   // entries per block of the tile-offset scan
 constexpr int kTileThreads = 512;  // threads of the per-tile workgroups
 
-template <int N> struct asg_cfg {
-    static constexpr int TS = N < kAsgTile ? N : kAsgTile;
-    static constexpr int NT = N / TS;                // tiles per axis
-    static constexpr int TILES = NT * NT * NT;
-    static constexpr int RG = TS + 3;                // LDS region edge
+template <int N> struct asg_cfg : tile_grid<N> {
+    static constexpr int RG = tile_grid<N>::TS + 3;   // LDS region edge
     static constexpr int RCELLS = RG * RG * RG;
 };
 
@@ -62,7 +58,7 @@ struct AsgLayout {
 };
 
 inline AsgLayout asg_layout(int n, int64_t n_pts) {
-    const int ts = n < kAsgTile ? n : kAsgTile;
+    const int ts = n < kBucketTile ? n : kBucketTile;
     const int64_t tiles = int64_t(n / ts) * (n / ts) * (n / ts);
     const int64_t nblk = (tiles + kScanBlock - 1) / kScanBlock;
     AsgLayout l{};
@@ -89,22 +85,6 @@ inline AsgLayout asg_layout(int n, int64_t n_pts) {
 
 size_t assign_workspace(int n, int64_t n_pts) { return asg_layout(n, n_pts).total; }
 
-// Cell of a position along one axis (periodic wrap into [0, N)) and the
-// fractional offset within it, in float64.
-template <int N>
-__device__ __forceinline__ int cell_of(float x, double scale, double& frac) {
-    double u = double(x) * scale;
-    u -= double(N) * floor(u / double(N));
-    const double f = floor(u);
-    int c = int(f);
-    frac = u - f;
-    if (c >= N) {   // u rounded up to N: the next image's node 0
-        c = 0;
-        frac = 0.0;
-    }
-    return c;
-}
-
 // B3 weight of node i0 - 1 + o (o = 0 .. 3) for the fractional offset t in
 // [0, 1): B3 at distance d = |t + 1 - o| < 2, without branches.
 template <typename T>
@@ -125,16 +105,6 @@ __device__ __forceinline__ double bcast(double v, int j) {
     const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), j);
     const int hi = __builtin_amdgcn_readlane(int(b >> 32), j);
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
-template <int N>
-__device__ __forceinline__ int tile_of_point(const float* __restrict__ pos, int64_t i, double scale) {
-    using G = asg_cfg<N>;
-    double f;
-    const int cx = cell_of<N>(pos[3 * i], scale, f);
-    const int cy = cell_of<N>(pos[3 * i + 1], scale, f);
-    const int cz = cell_of<N>(pos[3 * i + 2], scale, f);
-    return ((cx / G::TS) * G::NT + cy / G::TS) * G::NT + cz / G::TS;
 }
 
 template <int N>
@@ -177,61 +147,6 @@ __global__ void k_asg_scale(const double* __restrict__ partial, int nblocks, int
     const int k = min(1000, 61 - head - e);   // 2^k stays finite for tiny weights
     sc->scale = ldexp(1.0, k);
     sc->inv_scale = ldexp(1.0, -k);
-}
-
-// Exclusive prefix sum of cnt[0 .. n) in blocks of kScanBlock: the block's
-// prefix to out, its total to blocksum.
-__global__ __launch_bounds__(kScanBlock) void k_scan_block(const uint32_t* __restrict__ cnt, int64_t n,
-                                                           uint32_t* __restrict__ out,
-                                                           uint32_t* __restrict__ blocksum) {
-    __shared__ uint32_t s[kScanBlock];
-    const int64_t i = int64_t(blockIdx.x) * kScanBlock + threadIdx.x;
-    const uint32_t v = i < n ? cnt[i] : 0u;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int d = 1; d < kScanBlock; d <<= 1) {   // inclusive Hillis-Steele scan
-        const uint32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0u;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    if (i < n) out[i] = s[threadIdx.x] - v;
-    if (threadIdx.x == kScanBlock - 1) blocksum[blockIdx.x] = s[threadIdx.x];
-}
-
-// Exclusive prefix of the block totals (one block; nblk <= kScanBlock), and
-// the grand total at out[n].
-__global__ __launch_bounds__(kScanBlock) void k_scan_totals(uint32_t* __restrict__ blocksum, int nblk,
-                                                            uint32_t* __restrict__ out, int64_t n) {
-    __shared__ uint32_t s[kScanBlock];
-    const uint32_t v = int(threadIdx.x) < nblk ? blocksum[threadIdx.x] : 0u;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int d = 1; d < kScanBlock; d <<= 1) {
-        const uint32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0u;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    if (int(threadIdx.x) < nblk) blocksum[threadIdx.x] = s[threadIdx.x] - v;
-    if (threadIdx.x == kScanBlock - 1) out[n] = s[threadIdx.x];
-}
-
-__global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* __restrict__ out, int64_t n,
-                                                         const uint32_t* __restrict__ blocksum) {
-    const int64_t i = int64_t(blockIdx.x) * kScanBlock + threadIdx.x;
-    if (i < n) out[i] += blocksum[blockIdx.x];
-}
-
-template <int N>
-__global__ __launch_bounds__(kThreads) void k_asg_scatter(const float* __restrict__ pos, int64_t n_pts, double scale,
-                                                          const uint32_t* __restrict__ off,
-                                                          uint32_t* __restrict__ cursor, uint32_t* __restrict__ list) {
-    const int64_t stride = int64_t(gridDim.x) * kThreads;
-    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride) {
-        const int t = tile_of_point<N>(pos, i, scale);
-        list[off[t] + atomicAdd(cursor + t, 1u)] = uint32_t(i);
-    }
 }
 
 // One workgroup per tile.  A wavefront takes 64 of the tile's points at a
@@ -365,15 +280,10 @@ static hermes_status assign_n(hermes_ctx ctx, const float* pos, const float* wei
                                count, partial);
         const int head = ctx->basis == HERMES_BASIS_DB2 ? 2 : 0;
         hipLaunchKernelGGL(k_asg_scale, dim3(1), dim3(64), 0, stream, partial, pblocks, head, sum_w, sc);
-        const int nblk = (G::TILES + kScanBlock - 1) / kScanBlock;
-        hipLaunchKernelGGL(k_scan_block, dim3(nblk), dim3(kScanBlock), 0, stream, count, int64_t(G::TILES), off,
-                           blocksum);
-        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, stream, blocksum, nblk, off,
-                           int64_t(G::TILES));
-        hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kScanBlock), 0, stream, off, int64_t(G::TILES), blocksum);
+        launch_tile_scan(count, int64_t(G::TILES), off, blocksum, stream);
         if (n_pts > 0) {
-            hipLaunchKernelGGL((k_asg_scatter<N>), dim3(pblocks), dim3(kThreads), 0, stream, pos, n_pts, scale, off,
-                               cursor, list);
+            hipLaunchKernelGGL((k_bucket_scatter<N>), dim3(pblocks), dim3(kThreads), 0, stream, pos, n_pts, scale,
+                               off, cursor, list);
             if (ctx->basis == HERMES_BASIS_DB2)
                 hipLaunchKernelGGL((k_asg_tiles<T, N, HERMES_BASIS_DB2>), dim3(G::TILES), dim3(kTileThreads), 0, stream,
                                    pos, weight, scale, off, list, sc, ctx->t.db2tab,

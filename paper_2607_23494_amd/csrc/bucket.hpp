@@ -1,0 +1,121 @@
+// Bucketing of points by tiles of E^3 cells (E = 16 unless given): per-tile
+// counts, their exclusive prefix sum, and the point indices scattered into
+// per-tile lists.
+// Shared by the assignment (one workgroup accumulates a tile's points in
+// LDS) and the readout (points are read tile by tile, so that neighbouring
+// threads gather from one region of the field).
+#pragma once
+
+#include "common.hpp"
+
+namespace hermes {
+
+constexpr int kBucketTile = 16;    // cells per tile edge (N >= 16; the whole grid below)
+constexpr int kScanBlock = 1024;   // entries per block of the tile-offset scan
+
+template <int N, int E = kBucketTile> struct tile_grid {
+    static constexpr int TS = N < E ? N : E;
+    static constexpr int NT = N / TS;                // tiles per axis
+    static constexpr int TILES = NT * NT * NT;
+};
+
+// Cell of a position along one axis (periodic wrap into [0, N)) and the
+// fractional offset within it, in float64.
+template <int N>
+__device__ __forceinline__ int cell_of(float x, double scale, double& frac) {
+    double u = double(x) * scale;
+    u -= double(N) * floor(u / double(N));
+    const double f = floor(u);
+    int c = int(f);
+    frac = u - f;
+    if (c >= N) {   // u rounded up to N: the next image's node 0
+        c = 0;
+        frac = 0.0;
+    }
+    return c;
+}
+
+template <int N, int E = kBucketTile>
+__device__ __forceinline__ int tile_of_point(const float* __restrict__ pos, int64_t i, double scale) {
+    using G = tile_grid<N, E>;
+    double f;
+    const int cx = cell_of<N>(pos[3 * i], scale, f);
+    const int cy = cell_of<N>(pos[3 * i + 1], scale, f);
+    const int cz = cell_of<N>(pos[3 * i + 2], scale, f);
+    return ((cx / G::TS) * G::NT + cy / G::TS) * G::NT + cz / G::TS;
+}
+
+template <int N, int E = kBucketTile>
+__global__ __launch_bounds__(kThreads) void k_bucket_count(const float* __restrict__ pos, int64_t n_pts, double scale,
+                                                           uint32_t* __restrict__ count) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride)
+        atomicAdd(count + tile_of_point<N, E>(pos, i, scale), 1u);
+}
+
+// Exclusive prefix sum of cnt[0 .. n) in blocks of kScanBlock: the block's
+// prefix to out, its total to blocksum.
+static __global__ __launch_bounds__(kScanBlock) void k_scan_block(const uint32_t* __restrict__ cnt, int64_t n,
+                                                                  uint32_t* __restrict__ out,
+                                                                  uint32_t* __restrict__ blocksum) {
+    __shared__ uint32_t s[kScanBlock];
+    const int64_t i = int64_t(blockIdx.x) * kScanBlock + threadIdx.x;
+    const uint32_t v = i < n ? cnt[i] : 0u;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanBlock; d <<= 1) {   // inclusive Hillis-Steele scan
+        const uint32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) out[i] = s[threadIdx.x] - v;
+    if (threadIdx.x == kScanBlock - 1) blocksum[blockIdx.x] = s[threadIdx.x];
+}
+
+// Exclusive prefix of the block totals (one block; nblk <= kScanBlock), and
+// the grand total at out[n].
+static __global__ __launch_bounds__(kScanBlock) void k_scan_totals(uint32_t* __restrict__ blocksum, int nblk,
+                                                                   uint32_t* __restrict__ out, int64_t n) {
+    __shared__ uint32_t s[kScanBlock];
+    const uint32_t v = int(threadIdx.x) < nblk ? blocksum[threadIdx.x] : 0u;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanBlock; d <<= 1) {
+        const uint32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (int(threadIdx.x) < nblk) blocksum[threadIdx.x] = s[threadIdx.x] - v;
+    if (threadIdx.x == kScanBlock - 1) out[n] = s[threadIdx.x];
+}
+
+static __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* __restrict__ out, int64_t n,
+                                                                const uint32_t* __restrict__ blocksum) {
+    const int64_t i = int64_t(blockIdx.x) * kScanBlock + threadIdx.x;
+    if (i < n) out[i] += blocksum[blockIdx.x];
+}
+
+// off[0 .. tiles] = exclusive prefix of count (off[tiles] = total).
+inline void launch_tile_scan(const uint32_t* count, int64_t tiles, uint32_t* off, uint32_t* blocksum,
+                             hipStream_t stream) {
+    const int nblk = int((tiles + kScanBlock - 1) / kScanBlock);
+    hipLaunchKernelGGL(k_scan_block, dim3(nblk), dim3(kScanBlock), 0, stream, count, tiles, off, blocksum);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, stream, blocksum, nblk, off, tiles);
+    hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kScanBlock), 0, stream, off, tiles, blocksum);
+}
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_bucket_scatter(const float* __restrict__ pos, int64_t n_pts,
+                                                             double scale, const uint32_t* __restrict__ off,
+                                                             uint32_t* __restrict__ cursor,
+                                                             uint32_t* __restrict__ list) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride) {
+        const int t = tile_of_point<N>(pos, i, scale);
+        list[off[t] + atomicAdd(cursor + t, 1u)] = uint32_t(i);
+    }
+}
+
+}  // namespace hermes

@@ -5,12 +5,18 @@
 //
 // The value at a point is the node sum v = sum_l f_l prod_a phi(x_a/h - l_a)
 // (64 nodes with B3, 27 with the D4 function), the transpose of the
-// assignment's scatter: one thread per point gathers its rows of nodes.  Optionally the value becomes a mark and is multiplied by a weight
-// (the marked catalogue for hermes_assign), and the moments <v^p>, p = 2..4,
-// over the points are accumulated in float64 (counts in cells by sampling
+// assignment's scatter: one thread per point gathers its rows of nodes.
+// Large calls first bucket the points by tiles of 8^3 cells (16^3 at 1024^3;
+// the positions are copied in bucket order beside the point indices)
+// and read them tile by tile, so that neighbouring threads gather from one
+// region of the field; each value is still written at its point's index.
+// Optionally the value becomes a mark and is multiplied by a weight (the
+// marked catalogue for hermes_assign), and the moments <v^p>, p = 2..4, over
+// the points are accumulated in float64 (counts in cells by sampling
 // positions).
 #include <cmath>
 
+#include "bucket.hpp"
 #include "common.hpp"
 #include "interp.hpp"
 #include "kernels.hpp"
@@ -29,17 +35,78 @@ __device__ __forceinline__ double apply_mark(const MarkParams& mk, double v) {
     return v;
 }
 
+// Points below this count are read in the given order (no workspace).
+constexpr int64_t kReadoutBucketMin = int64_t(1) << 16;
+
+// Bucket edge: 8 cells while the tile count stays within the offset scan's
+// reach (kScanBlock^2 tiles), else 16.
+constexpr int rd_edge(int n) { return (n / 8) * (n / 8) * (n / 8) <= kScanBlock * kScanBlock ? 8 : 16; }
+
+static bool readout_buckets(int64_t n_pts) { return n_pts >= kReadoutBucketMin && n_pts <= INT32_MAX; }
+
+// Workspace layout (bytes, each part 256-aligned): tile counts, offsets,
+// cursors, scan block sums, the point list and the positions in list order.
+struct RdLayout {
+    size_t count, off, cursor, blocksum, list, spos, total;
+};
+
+static RdLayout rd_layout(int n, int64_t n_pts) {
+    const int ts = n < rd_edge(n) ? n : rd_edge(n);
+    const int64_t tiles = int64_t(n / ts) * (n / ts) * (n / ts);
+    const int64_t nblk = (tiles + kScanBlock - 1) / kScanBlock;
+    RdLayout l{};
+    size_t at = 0;
+    l.count = at;
+    at += align256(size_t(tiles) * 4);
+    l.off = at;
+    at += align256(size_t(tiles + 1) * 4);
+    l.cursor = at;
+    at += align256(size_t(tiles) * 4);
+    l.blocksum = at;
+    at += align256(size_t(nblk) * 4);
+    l.list = at;
+    at += align256(size_t(n_pts) * 4);
+    l.spos = at;
+    at += align256(size_t(n_pts) * 12);
+    l.total = at;
+    return l;
+}
+
+// The bucket scatter of the readout: point i goes to slot off[t] + cursor of
+// its tile t, which receives its index and its position.
+template <int N, int E>
+__global__ __launch_bounds__(kThreads) void k_readout_scatter(const float* __restrict__ pos, int64_t n_pts,
+                                                              double scale, const uint32_t* __restrict__ off,
+                                                              uint32_t* __restrict__ cursor,
+                                                              uint32_t* __restrict__ list, float* __restrict__ spos) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride) {
+        const int t = tile_of_point<N, E>(pos, i, scale);
+        const uint32_t k = off[t] + atomicAdd(cursor + t, 1u);
+        list[k] = uint32_t(i);
+        spos[3 * size_t(k)] = pos[3 * i];
+        spos[3 * size_t(k) + 1] = pos[3 * i + 1];
+        spos[3 * size_t(k) + 2] = pos[3 * i + 2];
+    }
+}
+
+size_t readout_workspace(int n, int64_t n_pts) { return readout_buckets(n_pts) ? rd_layout(n, n_pts).total : 0; }
+
+// Point j of the launch is point list[j] at position pos[j] (bucketed: pos
+// holds the positions in list order) or point j.
 template <typename T, int N, int B>
 __global__ __launch_bounds__(kThreads) void k_readout(const T* __restrict__ field, const float* __restrict__ pos,
                                                       const float* __restrict__ weight, int64_t n_pts,
                                                       double scale, MarkParams mk, const double* __restrict__ tab,
-                                                      T* __restrict__ out, double* __restrict__ mom) {
+                                                      const uint32_t* __restrict__ list, T* __restrict__ out,
+                                                      double* __restrict__ mom) {
     __shared__ double red[kThreads];
     double m2 = 0.0, m3 = 0.0, m4 = 0.0;
     const int64_t stride = int64_t(gridDim.x) * kThreads;
-    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride) {
-        const double u[3] = {double(pos[3 * i]) * scale, double(pos[3 * i + 1]) * scale,
-                             double(pos[3 * i + 2]) * scale};   // position in cell units
+    for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n_pts; j += stride) {
+        const int64_t i = list ? int64_t(list[j]) : j;
+        const double u[3] = {double(pos[3 * j]) * scale, double(pos[3 * j + 1]) * scale,
+                             double(pos[3 * j + 2]) * scale};   // position in cell units
         const double v = basis_value<T, N, B>(field, u, tab);
         if (mom) {
             const double v2 = v * v;
@@ -72,23 +139,48 @@ __global__ void k_scale3(double* __restrict__ mom, double s) {
 template <typename T, int N>
 static hermes_status readout_n(hermes_ctx ctx, const void* field, double box_L, const float* pos,
                                const float* weight, int64_t n_pts, const MarkParams& mk, void* out,
-                               double* moments, hipStream_t stream) {
+                               double* moments, void* work, hipStream_t stream) {
     if (moments) {
         LaunchScope ls(ctx, stream, "fill");
         launch_fill<double>(moments, 3, 0.0, stream);
     }
     if (n_pts > 0) {
-        LaunchScope ls(ctx, stream, "readout");
+        const double scale = double(N) / box_L;
         const int64_t want = (n_pts + kThreads - 1) / kThreads;
         const int blocks = int(want < 8192 ? want : 8192);
+        const uint32_t* list = nullptr;
+        const float* rpos = pos;
+        if (work && readout_buckets(n_pts)) {
+            constexpr int E = rd_edge(N);
+            using G = tile_grid<N, E>;
+            const RdLayout l = rd_layout(N, n_pts);
+            char* w = static_cast<char*>(work);
+            uint32_t* count = reinterpret_cast<uint32_t*>(w + l.count);
+            uint32_t* off = reinterpret_cast<uint32_t*>(w + l.off);
+            uint32_t* cursor = reinterpret_cast<uint32_t*>(w + l.cursor);
+            uint32_t* blocksum = reinterpret_cast<uint32_t*>(w + l.blocksum);
+            uint32_t* lst = reinterpret_cast<uint32_t*>(w + l.list);
+            float* spos = reinterpret_cast<float*>(w + l.spos);
+            LaunchScope ls(ctx, stream, "bucket");
+            launch_fill<uint32_t>(count, G::TILES, 0u, stream);
+            launch_fill<uint32_t>(cursor, G::TILES, 0u, stream);
+            hipLaunchKernelGGL((k_bucket_count<N, E>), dim3(blocks), dim3(kThreads), 0, stream, pos, n_pts, scale,
+                               count);
+            launch_tile_scan(count, int64_t(G::TILES), off, blocksum, stream);
+            hipLaunchKernelGGL((k_readout_scatter<N, E>), dim3(blocks), dim3(kThreads), 0, stream, pos, n_pts, scale,
+                               off, cursor, lst, spos);
+            list = lst;
+            rpos = spos;
+        }
+        LaunchScope ls(ctx, stream, "readout");
         if (ctx->basis == HERMES_BASIS_DB2)
             hipLaunchKernelGGL((k_readout<T, N, HERMES_BASIS_DB2>), dim3(blocks), dim3(kThreads), 0, stream,
-                               static_cast<const T*>(field), pos, weight, n_pts, double(N) / box_L, mk,
-                               ctx->t.db2tab, static_cast<T*>(out), moments);
+                               static_cast<const T*>(field), rpos, weight, n_pts, scale, mk, ctx->t.db2tab, list,
+                               static_cast<T*>(out), moments);
         else
             hipLaunchKernelGGL((k_readout<T, N, HERMES_BASIS_B3>), dim3(blocks), dim3(kThreads), 0, stream,
-                               static_cast<const T*>(field), pos, weight, n_pts, double(N) / box_L, mk,
-                               ctx->t.db2tab, static_cast<T*>(out), moments);
+                               static_cast<const T*>(field), rpos, weight, n_pts, scale, mk, ctx->t.db2tab, list,
+                               static_cast<T*>(out), moments);
         if (moments)
             hipLaunchKernelGGL(k_scale3, dim3(1), dim3(64), 0, stream, moments, 1.0 / double(n_pts));
     }
@@ -97,7 +189,7 @@ static hermes_status readout_n(hermes_ctx ctx, const void* field, double box_L, 
 
 hermes_status readout_impl(hermes_ctx ctx, const void* field, int n, int dtype, double box_L, const float* pos,
                            const float* weight, int64_t n_pts, const hermes_mark* mark, void* out,
-                           double* moments, hipStream_t stream) {
+                           double* moments, void* work, hipStream_t stream) {
     MarkParams mk{HERMES_MARK_NONE, 0.0, 0.0, 0.0};
     if (mark) {
         mk.kind = mark->kind;
@@ -108,8 +200,8 @@ hermes_status readout_impl(hermes_ctx ctx, const void* field, int n, int dtype, 
 #define HERMES_READOUT_CASE(NN)                                                                                \
     case NN:                                                                                                   \
         return dtype == HERMES_F32                                                                             \
-                   ? readout_n<float, NN>(ctx, field, box_L, pos, weight, n_pts, mk, out, moments, stream)   \
-                   : readout_n<double, NN>(ctx, field, box_L, pos, weight, n_pts, mk, out, moments, stream);
+                   ? readout_n<float, NN>(ctx, field, box_L, pos, weight, n_pts, mk, out, moments, work, stream) \
+                   : readout_n<double, NN>(ctx, field, box_L, pos, weight, n_pts, mk, out, moments, work, stream);
     switch (n) {
         HERMES_READOUT_CASE(8)
         HERMES_READOUT_CASE(16)

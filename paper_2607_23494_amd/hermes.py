@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_PKG, "libhermes.so")
 F32, F64 = 0, 1
 PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
 WIN = {"shell": 0, "sphere": 1, "gauss": 2, "sh_shell": 3}
-OP_ASSIGN, OP_FFT, OP_XI, OP_FILTER, OP_ZETA, OP_XI_ANISO, OP_TRIPLET, OP_DDD_GAMMA = range(8)
+OP_ASSIGN, OP_FFT, OP_XI, OP_FILTER, OP_ZETA, OP_XI_ANISO, OP_TRIPLET, OP_DDD_GAMMA, OP_READOUT = range(9)
 ANISO = {"ring": 0, "ring_bin": 1, "gauss_ring": 2, "disk": 3, "cylinder": 4, "cylshell": 5, "gauss_shell": 6}
 MAX_BINS = 64
 
@@ -74,7 +74,7 @@ def _load() -> ctypes.CDLL:
     lib.hermes_ddd_gamma.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, sz, vp]
     lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
     lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
-    lib.hermes_readout.argtypes = [vp, vp, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp, vp]
+    lib.hermes_readout.argtypes = [vp, vp, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp, vp, sz, vp]
     lib.hermes_set_basis.argtypes = [vp, i32]
     lib.hermes_get_basis.argtypes = [vp]
     lib.hermes_get_basis.restype = ctypes.c_int
@@ -416,10 +416,16 @@ def zeta_l(delta: torch.Tensor, delta_k: torch.Tensor, box_L: float, edges, l_ma
 
 def readout(field: torch.Tensor, box_L: float, pos: torch.Tensor, weight: torch.Tensor | None = None,
             mark: tuple | None = None, want_values: bool = True, moments: bool = False,
-            out: torch.Tensor | None = None, stream=None):
+            out: torch.Tensor | None = None, stream=None, moments_out: torch.Tensor | None = None,
+            work: torch.Tensor | None = None):
     """Values of a coefficient field at arbitrary positions, optionally turned
     into marks and weighted.  mark = (kind, exponent, offset[, self_term]) with
-    kind in MARK.  Returns (values [n_pts] or None, moments [3] float64 or None)."""
+    kind in MARK.  Returns (values [n_pts] or None, moments [3] float64 or None);
+    moments_out, a float64 [3] device tensor, receives the moments in place."""
+    if moments_out is not None:
+        if moments_out.dtype != torch.float64 or moments_out.numel() != 3 or not moments_out.is_contiguous():
+            raise ValueError("moments_out must be a contiguous float64 [3] tensor")
+        moments = True
     dev = _dev(field)
     n = field.shape[0]
     if pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3 or not pos.is_contiguous():
@@ -434,10 +440,15 @@ def readout(field: torch.Tensor, box_L: float, pos: torch.Tensor, weight: torch.
     with _on(stream):
         if want_values and out is None:
             out = torch.empty(pos.shape[0], dtype=field.dtype, device=field.device)
-        mom = torch.empty(3, dtype=torch.float64, device=field.device) if moments else None
+        mom = moments_out if moments_out is not None else (
+            torch.empty(3, dtype=torch.float64, device=field.device) if moments else None)
+        n_pts = int(pos.shape[0])
+        nbytes = workspace_size(OP_READOUT, n, field.dtype, n_pts, device=dev) if n_pts <= 2 ** 31 - 1 else 0
+        ws = _workspace(nbytes, dev, work) if nbytes > 0 else None
         _check(_lib.hermes_readout(context(dev), _ptr(field), n, _dtype_code(field.dtype), float(box_L), _ptr(pos),
-                                   _ptr(weight), pos.shape[0], ctypes.byref(mk) if mk is not None else None,
-                                   _ptr(out) if want_values else None, _ptr(mom), _stream(dev, stream)))
+                                   _ptr(weight), n_pts, ctypes.byref(mk) if mk is not None else None,
+                                   _ptr(out) if want_values else None, _ptr(mom), _ptr(ws),
+                                   ws.numel() * ws.element_size() if ws is not None else 0, _stream(dev, stream)))
     return (out if want_values else None), mom
 
 
