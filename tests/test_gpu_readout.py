@@ -178,3 +178,25 @@ def test_readout_bucketed_matches_direct_and_oracle(hermes, dtype, basis):
         torch.cuda.synchronize()
         assert torch.equal(got, direct)
         assert torch.allclose(mom, dmom, rtol=1e-12, atol=0)
+
+
+def test_readout_ns512_random_spheres_bench_configuration(hermes):
+    """The random-sphere counts-in-cells launch of the benchmark: 10^8
+    uniform random positions read from a 512^3 float32 field through the
+    bucketed path; 20 000 sampled positions against the oracle, and the
+    moments against those of the values read back."""
+    n, L = 512, 1000.0
+    f = _field(n, 513, torch.float32)
+    tf = torch.from_numpy(f).cuda()
+    g = torch.Generator(device="cuda").manual_seed(2607)
+    rpos = (torch.rand((100_000_000, 3), device="cuda", generator=g) * L).contiguous()
+    vals, mom = hermes.readout(tf, L, rpos, moments=True)
+    idx = torch.from_numpy(np.random.default_rng(10).choice(100_000_000, 20000, replace=False)).cuda()
+    sub = rpos[idx].cpu().numpy()
+    ref = O.readout(f, sub, L)
+    assert normwise(vals[idx].cpu().numpy(), ref) < 1e-5
+    v = vals.double()
+    want = torch.stack([(v ** 2).mean(), (v ** 3).mean(), (v ** 4).mean()]).cpu().numpy()
+    scale = torch.stack([(v.abs() ** 2).mean(), (v.abs() ** 3).mean(), (v.abs() ** 4).mean()]).cpu().numpy()
+    got = mom.cpu().numpy()
+    assert np.max(np.abs(got - want) / scale) < 1e-6   # the kernel's values before their float32 rounding
