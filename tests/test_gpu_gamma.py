@@ -118,3 +118,26 @@ def test_ddd_gamma_fewer_fields_than_wavefronts(hermes, basis):
         got = hermes.ddd_gamma(torch.from_numpy(e).cuda(), torch.from_numpy(f).cuda()).cpu().numpy()
         ref = O.ddd_gamma(e, f[0], f[0], basis=basis)
         assert abs(got[0, 0] - ref) < 1e-10 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("basis", ["b3", "db2"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ddd_gamma_thirty_two_fields(hermes, basis, dtype):
+    """The largest call, 32 fields (float64 D4 then evaluates with fewer
+    wavefronts to fit its LDS): the leading 20 x 20 block equals the 20-field
+    call, the matrix is symmetric, and three pairs match the oracle."""
+    n = 8
+    rng = np.random.default_rng(320)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    e = rng.standard_normal((n, n, n)).astype(npdt)
+    f = rng.standard_normal((32, n, n, n)).astype(npdt)
+    te, tf = torch.from_numpy(e).cuda(), torch.from_numpy(f).cuda()
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    with hermes.basis(basis):
+        full = hermes.ddd_gamma(te, tf).cpu().numpy()
+        part = hermes.ddd_gamma(te, tf[:20].contiguous()).cpu().numpy()
+    assert np.array_equal(full, full.T)
+    assert normwise(full[:20, :20], part) < tol
+    for b1, b2 in ((0, 31), (17, 25), (31, 31)):
+        ref = O.ddd_gamma(e, f[b1], f[b2], basis=basis)
+        assert abs(full[b1, b2] - ref) < tol * max(1.0, np.max(np.abs(full))), (b1, b2)

@@ -200,3 +200,19 @@ def test_readout_ns512_random_spheres_bench_configuration(hermes):
     scale = torch.stack([(v.abs() ** 2).mean(), (v.abs() ** 3).mean(), (v.abs() ** 4).mean()]).cpu().numpy()
     got = mom.cpu().numpy()
     assert np.max(np.abs(got - want) / scale) < 1e-6   # the kernel's values before their float32 rounding
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_readout_bucketed_marks_and_weights(hermes, dtype):
+    """Density marks times weights through the bucketed path (2e5 points):
+    each output lands at its own point's index."""
+    L, n = 120.0, 32
+    rng = np.random.default_rng(66)
+    pos = rng.uniform(0, L, (200_000, 3)).astype(np.float32)
+    w = rng.lognormal(0.0, 0.5, 200_000).astype(np.float32)
+    f = (0.3 * _field(n, 77, dtype)).astype(np.float32 if dtype == torch.float32 else np.float64)
+    mark = ("power_law", 0.7, 0.1, 0.02)
+    got, _ = hermes.readout(torch.from_numpy(f).cuda(), L, torch.from_numpy(pos).cuda(),
+                            weight=torch.from_numpy(w).cuda(), mark=mark)
+    ref = w.astype(np.float64) * O.density_mark(1.0 + O.readout(f, pos, L), *mark)
+    assert normwise(got.cpu().numpy(), ref) < TOL[dtype]
