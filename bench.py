@@ -368,17 +368,17 @@ def other_configs(warmup: int, steps: int) -> dict:
     del dk
     g = torch.Generator(device="cuda").manual_seed(2607)
     rpos = (torch.rand((100_000_000, 3), device="cuda", generator=g) * L).contiguous()
-    vals = torch.empty(100_000_000, dtype=torch.float32, device="cuda")
+    vals = torch.empty((3, 100_000_000), dtype=torch.float32, device="cuda")
     moms = torch.empty((3, 3), dtype=torch.float64, device="cuda")
     rwork = torch.empty(hermes.workspace_size(hermes.OP_READOUT, n, torch.float32, 100_000_000),
                         dtype=torch.uint8, device="cuda")
 
     def step_cic_random():
-        for i in range(len(spheres)):
-            hermes.readout(cfields[i], L, rpos, out=vals, moments_out=moms[i], work=rwork)
+        hermes.readout_fields(cfields, L, rpos, out=vals, moments_out=moms, work=rwork)
     record("ns512_cic_random", step_cic_random, 3 * 100_000_000,
            "counts in cells by random spheres: the 512^3 contrast of the 1e7-point catalogue smoothed with "
-           "spheres of R = 10, 15, 20, each read at 1e8 uniform random positions (values and moments)",
+           "spheres of R = 10, 15, 20, all read at the same 1e8 uniform random positions (values and moments "
+           "p = 2, 3, 4 of each)",
            per="readouts")
     del cfields, rpos, vals, moms, rwork
     torch.cuda.empty_cache()

@@ -117,6 +117,7 @@ typedef struct hermes_ctx_s* hermes_ctx;
 #define HERMES_MAX_ANISO (1 << 20)   /* windows per hermes_xi_aniso call */
 #define HERMES_MAX_THETA 64          /* opening angles per hermes_triplet_mc call */
 #define HERMES_MAX_GAMMA_FIELDS 32   /* filtered fields per hermes_ddd_gamma call */
+#define HERMES_MAX_READOUT_FIELDS 64 /* fields per hermes_readout_fields call */
 
 /* Create a context on HIP device `device`; fills *out.  Allocates the
  * context's constant tables (about 2.7 MB, both bases) on that device.  The
@@ -454,6 +455,18 @@ hermes_status hermes_readout(hermes_ctx ctx, const void* field, int n_grid, int 
                              int64_t n_pts, const hermes_mark* mark, void* out,
                              double* moments, void* work, size_t work_bytes,
                              hipStream_t stream);
+
+/* hermes_readout of n_fields fields at the same points (e.g. one field
+ * smoothed at several radii, the counts in random spheres of Sec. 3.1): the
+ * points are bucketed once.  fields is device [n_fields][N^3] of dtype; out,
+ * if not NULL, is [n_fields][n_pts]; moments, if not NULL, is double
+ * [n_fields][3].  The workspace is the same as hermes_readout's for n_pts
+ * points.  ERR_ARG as hermes_readout, and for n_fields outside
+ * [1, HERMES_MAX_READOUT_FIELDS]. */
+hermes_status hermes_readout_fields(hermes_ctx ctx, const void* fields, int n_fields, int n_grid,
+                                    int dtype, double box_L, const float* pos, const float* weight,
+                                    int64_t n_pts, const hermes_mark* mark, void* out, double* moments,
+                                    void* work, size_t work_bytes, hipStream_t stream);
 
 /* Per-kernel timing for measurement.  While enabled, every kernel launch of
  * this context is bracketed with HIP events recorded on its launch stream;

@@ -558,32 +558,50 @@ hermes_status hermes_zeta_l(hermes_ctx ctx, const float* delta, const void* delt
     return zeta_impl(ctx, delta, delta_k, n_grid, box_L, e, l_max, precision, zeta, work, work_bytes, stream);
 }
 
+static hermes_status readout_checked(const char* who, hermes_ctx ctx, const void* fields, int n_fields, int n_grid,
+                                     int dtype, double box_L, const float* pos, const float* weight, int64_t n_pts,
+                                     const hermes_mark* mark, void* out, double* moments, void* work,
+                                     size_t work_bytes, hipStream_t stream) {
+    const std::string w(who);
+    if (!ctx || !fields || (n_pts > 0 && !pos)) return fail(HERMES_ERR_ARG, w + ": NULL argument");
+    if (n_fields < 1 || n_fields > HERMES_MAX_READOUT_FIELDS)
+        return fail(HERMES_ERR_ARG, w + ": n_fields must be in [1, 64]");
+    if (!out && !moments) return fail(HERMES_ERR_ARG, w + ": out and moments both NULL");
+    if (n_pts < 0) return fail(HERMES_ERR_ARG, w + ": n_pts < 0");
+    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, w + ": N must be a power of two in [8, 1024]");
+    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, w + ": bad dtype");
+    if (!(box_L > 0.0)) return fail(HERMES_ERR_ARG, w + ": box_L must be > 0");
+    if (mark) {
+        if (mark->reserved != 0) return fail(HERMES_ERR_ARG, w + ": reserved field must be 0");
+        if (mark->kind != HERMES_MARK_NONE && mark->kind != HERMES_MARK_POWER_LAW &&
+            mark->kind != HERMES_MARK_INVERSE_DENSITY)
+            return fail(HERMES_ERR_ARG, w + ": unknown mark kind");
+        if (!std::isfinite(mark->exponent) || !std::isfinite(mark->offset) || !std::isfinite(mark->self_term))
+            return fail(HERMES_ERR_ARG, w + ": mark parameters must be finite");
+        if (mark->offset < 0.0) return fail(HERMES_ERR_ARG, w + ": mark offset must be >= 0");
+        const bool divides = mark->kind == HERMES_MARK_INVERSE_DENSITY ||
+                             (mark->kind == HERMES_MARK_POWER_LAW && mark->exponent < 0.0);
+        if (divides && !(mark->offset > 0.0)) return fail(HERMES_ERR_ARG, w + ": this mark needs offset > 0");
+    }
+    if (work && work_bytes < readout_workspace(n_grid, n_pts)) return fail(HERMES_ERR_OOM, w + ": workspace too small");
+    DeviceGuard g(ctx->device);
+    return readout_impl(ctx, fields, n_fields, n_grid, dtype, box_L, pos, weight, n_pts, mark, out, moments, work,
+                        stream);
+}
+
 hermes_status hermes_readout(hermes_ctx ctx, const void* field, int n_grid, int dtype, double box_L,
                              const float* pos, const float* weight, int64_t n_pts, const hermes_mark* mark,
                              void* out, double* moments, void* work, size_t work_bytes, hipStream_t stream) {
-    if (!ctx || !field || (n_pts > 0 && !pos)) return fail(HERMES_ERR_ARG, "hermes_readout: NULL argument");
-    if (!out && !moments) return fail(HERMES_ERR_ARG, "hermes_readout: out and moments both NULL");
-    if (n_pts < 0) return fail(HERMES_ERR_ARG, "hermes_readout: n_pts < 0");
-    if (!valid_n(n_grid)) return fail(HERMES_ERR_ARG, "hermes_readout: N must be a power of two in [8, 1024]");
-    if (dtype != HERMES_F32 && dtype != HERMES_F64) return fail(HERMES_ERR_ARG, "hermes_readout: bad dtype");
-    if (!(box_L > 0.0)) return fail(HERMES_ERR_ARG, "hermes_readout: box_L must be > 0");
-    if (mark) {
-        if (mark->reserved != 0) return fail(HERMES_ERR_ARG, "hermes_readout: reserved field must be 0");
-        if (mark->kind != HERMES_MARK_NONE && mark->kind != HERMES_MARK_POWER_LAW &&
-            mark->kind != HERMES_MARK_INVERSE_DENSITY)
-            return fail(HERMES_ERR_ARG, "hermes_readout: unknown mark kind");
-        if (!std::isfinite(mark->exponent) || !std::isfinite(mark->offset) || !std::isfinite(mark->self_term))
-            return fail(HERMES_ERR_ARG, "hermes_readout: mark parameters must be finite");
-        if (mark->offset < 0.0) return fail(HERMES_ERR_ARG, "hermes_readout: mark offset must be >= 0");
-        const bool divides = mark->kind == HERMES_MARK_INVERSE_DENSITY ||
-                             (mark->kind == HERMES_MARK_POWER_LAW && mark->exponent < 0.0);
-        if (divides && !(mark->offset > 0.0))
-            return fail(HERMES_ERR_ARG, "hermes_readout: this mark needs offset > 0");
-    }
-    if (work && work_bytes < readout_workspace(n_grid, n_pts))
-        return fail(HERMES_ERR_OOM, "hermes_readout: workspace too small");
-    DeviceGuard g(ctx->device);
-    return readout_impl(ctx, field, n_grid, dtype, box_L, pos, weight, n_pts, mark, out, moments, work, stream);
+    return readout_checked("hermes_readout", ctx, field, 1, n_grid, dtype, box_L, pos, weight, n_pts, mark, out,
+                           moments, work, work_bytes, stream);
+}
+
+hermes_status hermes_readout_fields(hermes_ctx ctx, const void* fields, int n_fields, int n_grid, int dtype,
+                                    double box_L, const float* pos, const float* weight, int64_t n_pts,
+                                    const hermes_mark* mark, void* out, double* moments, void* work,
+                                    size_t work_bytes, hipStream_t stream) {
+    return readout_checked("hermes_readout_fields", ctx, fields, n_fields, n_grid, dtype, box_L, pos, weight, n_pts,
+                           mark, out, moments, work, work_bytes, stream);
 }
 
 }  // extern "C"

@@ -151,8 +151,8 @@ size_t triplet_workspace(int n, int dtype, int n_theta);
 hermes_status gamma_impl(hermes_ctx ctx, const void* eps, const void* fields, int n_fields, int n, int dtype,
                          double* out, void* work, hipStream_t stream);
 size_t gamma_workspace();
-hermes_status readout_impl(hermes_ctx ctx, const void* field, int n, int dtype, double box_L, const float* pos,
-                           const float* weight, int64_t n_pts, const hermes_mark* mark, void* out,
+hermes_status readout_impl(hermes_ctx ctx, const void* fields, int n_fields, int n, int dtype, double box_L,
+                           const float* pos, const float* weight, int64_t n_pts, const hermes_mark* mark, void* out,
                            double* moments, void* work, hipStream_t stream);
 size_t readout_workspace(int n, int64_t n_pts);
 

@@ -136,13 +136,14 @@ __global__ void k_scale3(double* __restrict__ mom, double s) {
     if (threadIdx.x < 3) mom[threadIdx.x] *= s;
 }
 
+// Every field of the call is read at the same points, after one bucketing.
 template <typename T, int N>
-static hermes_status readout_n(hermes_ctx ctx, const void* field, double box_L, const float* pos,
+static hermes_status readout_n(hermes_ctx ctx, const void* fields, int n_fields, double box_L, const float* pos,
                                const float* weight, int64_t n_pts, const MarkParams& mk, void* out,
                                double* moments, void* work, hipStream_t stream) {
     if (moments) {
         LaunchScope ls(ctx, stream, "fill");
-        launch_fill<double>(moments, 3, 0.0, stream);
+        launch_fill<double>(moments, 3 * int64_t(n_fields), 0.0, stream);
     }
     if (n_pts > 0) {
         const double scale = double(N) / box_L;
@@ -172,23 +173,25 @@ static hermes_status readout_n(hermes_ctx ctx, const void* field, double box_L, 
             list = lst;
             rpos = spos;
         }
-        LaunchScope ls(ctx, stream, "readout");
-        if (ctx->basis == HERMES_BASIS_DB2)
-            hipLaunchKernelGGL((k_readout<T, N, HERMES_BASIS_DB2>), dim3(blocks), dim3(kThreads), 0, stream,
-                               static_cast<const T*>(field), rpos, weight, n_pts, scale, mk, ctx->t.db2tab, list,
-                               static_cast<T*>(out), moments);
-        else
-            hipLaunchKernelGGL((k_readout<T, N, HERMES_BASIS_B3>), dim3(blocks), dim3(kThreads), 0, stream,
-                               static_cast<const T*>(field), rpos, weight, n_pts, scale, mk, ctx->t.db2tab, list,
-                               static_cast<T*>(out), moments);
-        if (moments)
-            hipLaunchKernelGGL(k_scale3, dim3(1), dim3(64), 0, stream, moments, 1.0 / double(n_pts));
+        for (int f = 0; f < n_fields; ++f) {
+            LaunchScope ls(ctx, stream, "readout");
+            const T* fld = static_cast<const T*>(fields) + int64_t(f) * N * N * N;
+            T* o = out ? static_cast<T*>(out) + int64_t(f) * n_pts : nullptr;
+            double* m = moments ? moments + 3 * f : nullptr;
+            if (ctx->basis == HERMES_BASIS_DB2)
+                hipLaunchKernelGGL((k_readout<T, N, HERMES_BASIS_DB2>), dim3(blocks), dim3(kThreads), 0, stream, fld,
+                                   rpos, weight, n_pts, scale, mk, ctx->t.db2tab, list, o, m);
+            else
+                hipLaunchKernelGGL((k_readout<T, N, HERMES_BASIS_B3>), dim3(blocks), dim3(kThreads), 0, stream, fld,
+                                   rpos, weight, n_pts, scale, mk, ctx->t.db2tab, list, o, m);
+            if (m) hipLaunchKernelGGL(k_scale3, dim3(1), dim3(64), 0, stream, m, 1.0 / double(n_pts));
+        }
     }
     return check_launch("hermes_readout");
 }
 
-hermes_status readout_impl(hermes_ctx ctx, const void* field, int n, int dtype, double box_L, const float* pos,
-                           const float* weight, int64_t n_pts, const hermes_mark* mark, void* out,
+hermes_status readout_impl(hermes_ctx ctx, const void* fields, int n_fields, int n, int dtype, double box_L,
+                           const float* pos, const float* weight, int64_t n_pts, const hermes_mark* mark, void* out,
                            double* moments, void* work, hipStream_t stream) {
     MarkParams mk{HERMES_MARK_NONE, 0.0, 0.0, 0.0};
     if (mark) {
@@ -200,8 +203,10 @@ hermes_status readout_impl(hermes_ctx ctx, const void* field, int n, int dtype, 
 #define HERMES_READOUT_CASE(NN)                                                                                \
     case NN:                                                                                                   \
         return dtype == HERMES_F32                                                                             \
-                   ? readout_n<float, NN>(ctx, field, box_L, pos, weight, n_pts, mk, out, moments, work, stream) \
-                   : readout_n<double, NN>(ctx, field, box_L, pos, weight, n_pts, mk, out, moments, work, stream);
+                   ? readout_n<float, NN>(ctx, fields, n_fields, box_L, pos, weight, n_pts, mk, out, moments,   \
+                                          work, stream)                                                          \
+                   : readout_n<double, NN>(ctx, fields, n_fields, box_L, pos, weight, n_pts, mk, out, moments,  \
+                                           work, stream);
     switch (n) {
         HERMES_READOUT_CASE(8)
         HERMES_READOUT_CASE(16)

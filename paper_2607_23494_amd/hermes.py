@@ -75,6 +75,8 @@ def _load() -> ctypes.CDLL:
     lib.hermes_filter_bins.argtypes = [vp, vp, i32, i32, f64, ctypes.POINTER(_Window), i32, vp, vp, vp, sz, vp]
     lib.hermes_zeta_l.argtypes = [vp, vp, vp, i32, f64, vp, i32, i32, i32, vp, vp, sz, vp]
     lib.hermes_readout.argtypes = [vp, vp, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp, vp, sz, vp]
+    lib.hermes_readout_fields.argtypes = [vp, vp, i32, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp,
+                                          vp, sz, vp]
     lib.hermes_set_basis.argtypes = [vp, i32]
     lib.hermes_get_basis.argtypes = [vp]
     lib.hermes_get_basis.restype = ctypes.c_int
@@ -83,7 +85,7 @@ def _load() -> ctypes.CDLL:
     lib.hermes_profile_read.argtypes = [vp, i32, ctypes.c_char_p, sz, ctypes.POINTER(i64), ctypes.POINTER(f64)]
     for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi", "hermes_xi_static", "hermes_xi_aniso", "hermes_triplet_mc", "hermes_ddd_gamma",
                  "hermes_filter_bins", "hermes_zeta_l", "hermes_readout", "hermes_profile_enable", "hermes_profile_reset",
-                 "hermes_profile_read", "hermes_set_basis"):
+                 "hermes_profile_read", "hermes_set_basis", "hermes_readout_fields"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -449,6 +451,45 @@ def readout(field: torch.Tensor, box_L: float, pos: torch.Tensor, weight: torch.
                                    _ptr(weight), n_pts, ctypes.byref(mk) if mk is not None else None,
                                    _ptr(out) if want_values else None, _ptr(mom), _ptr(ws),
                                    ws.numel() * ws.element_size() if ws is not None else 0, _stream(dev, stream)))
+    return (out if want_values else None), mom
+
+
+def readout_fields(fields: torch.Tensor, box_L: float, pos: torch.Tensor, weight: torch.Tensor | None = None,
+                   mark: tuple | None = None, want_values: bool = True, moments: bool = False,
+                   out: torch.Tensor | None = None, moments_out: torch.Tensor | None = None,
+                   work: torch.Tensor | None = None, stream=None):
+    """readout() of several fields [k, N, N, N] at the same positions (one
+    bucketing).  Returns (values [k, n_pts] or None, moments [k, 3] or None)."""
+    dev = _dev(fields)
+    if fields.dim() != 4 or not fields.is_contiguous():
+        raise ValueError("fields must be a contiguous [k, N, N, N] device tensor")
+    k, n = int(fields.shape[0]), int(fields.shape[1])
+    if pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3 or not pos.is_contiguous():
+        raise ValueError("pos must be a contiguous float32 [n, 3] device tensor")
+    if weight is not None and (weight.dtype != torch.float32 or weight.numel() != pos.shape[0]
+                               or not weight.is_contiguous()):
+        raise ValueError("weight must be a contiguous float32 [n] tensor")
+    if moments_out is not None:
+        if moments_out.dtype != torch.float64 or moments_out.numel() != 3 * k or not moments_out.is_contiguous():
+            raise ValueError("moments_out must be a contiguous float64 [k, 3] tensor")
+        moments = True
+    mk = None
+    if mark is not None:
+        st = float(mark[3]) if len(mark) > 3 else 0.0
+        mk = _Mark(MARK[mark[0]], 0, float(mark[1]), float(mark[2]), st)
+    n_pts = int(pos.shape[0])
+    with _on(stream):
+        if want_values and out is None:
+            out = torch.empty((k, n_pts), dtype=fields.dtype, device=fields.device)
+        mom = moments_out if moments_out is not None else (
+            torch.empty((k, 3), dtype=torch.float64, device=fields.device) if moments else None)
+        nbytes = workspace_size(OP_READOUT, n, fields.dtype, n_pts, device=dev) if n_pts <= 2 ** 31 - 1 else 0
+        ws = _workspace(nbytes, dev, work) if nbytes > 0 else None
+        _check(_lib.hermes_readout_fields(context(dev), _ptr(fields), k, n, _dtype_code(fields.dtype), float(box_L),
+                                          _ptr(pos), _ptr(weight), n_pts, ctypes.byref(mk) if mk is not None else None,
+                                          _ptr(out) if want_values else None, _ptr(mom), _ptr(ws),
+                                          ws.numel() * ws.element_size() if ws is not None else 0,
+                                          _stream(dev, stream)))
     return (out if want_values else None), mom
 
 

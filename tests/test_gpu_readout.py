@@ -216,3 +216,24 @@ def test_readout_bucketed_marks_and_weights(hermes, dtype):
                             weight=torch.from_numpy(w).cuda(), mark=mark)
     ref = w.astype(np.float64) * O.density_mark(1.0 + O.readout(f, pos, L), *mark)
     assert normwise(got.cpu().numpy(), ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_readout_fields_equals_single_reads(hermes, dtype):
+    """Three fields at the same 2e5 points in one call (one bucketing): each
+    row bit for bit the single-field read, moments to rounding; errors."""
+    from paper_2607_23494_amd.hermes import HermesError
+    n, L = 32, 50.0
+    f = np.stack([_field(n, 900 + k, dtype) for k in range(3)])
+    rng = np.random.default_rng(8)
+    pos = torch.from_numpy(rng.uniform(-L, 2 * L, (200_000, 3)).astype(np.float32)).cuda()
+    tf = torch.from_numpy(f).cuda()
+    vals, mom = hermes.readout_fields(tf, L, pos, moments=True)
+    for k in range(3):
+        v1, m1 = hermes.readout(tf[k], L, pos, moments=True)
+        assert torch.equal(vals[k], v1)
+        assert torch.allclose(mom[k], m1, rtol=1e-12, atol=0)
+    ref = O.readout(f[1], pos.cpu().numpy(), L)
+    assert normwise(vals[1].cpu().numpy(), ref) < TOL[dtype]
+    with pytest.raises(HermesError):
+        hermes.readout_fields(torch.zeros((65, 8, 8, 8), device="cuda"), L, pos[:10].contiguous())
