@@ -304,3 +304,21 @@ def test_basis_selection_and_errors(hermes):
         hermes.set_basis("haar")
     assert _lib.hermes_set_basis(context(0), 7) == 1
     assert _lib.hermes_get_basis(None) == -1
+
+
+def test_db2_assign_512_subset_and_full_catalogue(hermes):
+    """D4 assignment at 512^3: a 10^6-point subset of the 512^3 workload's
+    catalogue elementwise against the oracle, and the full 10^7 marked
+    catalogue's mass (sum of eps = sum of weights, partition of unity)."""
+    wl = synth.WORKLOADS["ns512_3pcf"]
+    pos, w = wl.catalogue()
+    n, L = wl.n_grid, wl.box_L
+    sub, sw_sub = pos[::10].copy(), w[::10].copy()
+    eps, sw = hermes.assign(torch.from_numpy(sub).cuda(), torch.from_numpy(sw_sub).cuda(), L, n)
+    oe, osw = O.assign(sub, sw_sub, L, n, basis=B)
+    assert normwise(eps.cpu().numpy(), oe) < 1e-5
+    assert abs(sw.item() - osw) < 1e-12 * osw
+    del oe
+    eps, sw = hermes.assign(torch.from_numpy(pos).cuda(), torch.from_numpy(w).cuda(), L, n)
+    total = float(eps.double().sum())
+    assert abs(total - sw.item()) < 1e-6 * sw.item()
