@@ -358,9 +358,9 @@ hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, i
  *   work        device workspace of >= hermes_workspace_size(TRIPLET, n_batch
  *               = n_theta) bytes: the partial sums and three tile-packed
  *               copies of the fields, for N <= 512 in float32 (64 N^3 bytes
- *               each) and N <= 256 in float64 (128 N^3 bytes each); a node's
- *               tile holds the 4 x 4 (y, z) block of nodes that points in its
- *               cell reach (D4 uses 3 x 3 of it)
+ *               each) and N <= 256 in float64 (128 N^3 bytes each); a tile
+ *               holds, for a pair of x planes, the 4 x 4 (y, z) block of
+ *               nodes that points in a cell reach (D4 uses 3 x 3 of it)
  * ERR_ARG for NULL f2, f3, out or work, f1 given with centres, weights
  * without centres, n_centres < 0, n_rot < 1, n_centres n_rot >= 2^62,
  * n_theta outside [1, HERMES_MAX_THETA], r12 or r13 negative, not finite or

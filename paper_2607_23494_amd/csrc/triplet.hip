@@ -16,9 +16,9 @@
 // (centre, 0, 1, 0) for a box point, key (seed, 0): every sample can be drawn
 // by any thread, and the oracle draws the same numbers.
 //
-// Fields are read through tile-packed copies (each node holds the 4 x 4
-// (y, z) block of nodes a point in its cell reaches, so a read is four
-// 64-byte loads, one per x plane) up to 512^3 in float32 and 256^3 in
+// Fields are read through tile-packed copies (each tile holds, for a pair of
+// x planes, the 4 x 4 (y, z) block of nodes a point in its cell reaches, so
+// a read is two or three 128-byte loads) up to 512^3 in float32 and 256^3 in
 // float64.  One thread per sample (grid-stride); per opening angle the
 // wavefront's 64 samples are summed by a butterfly over lanes and lane 0 adds
 // them to the wavefront's LDS accumulators, so every sum is formed in a fixed
@@ -66,10 +66,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 // 512^3); larger grids read the plain array.
 template <typename T> constexpr int tile_max_n() { return sizeof(T) == 4 ? 512 : 256; }
 
-// The 4 x 4 block of a node: Tile<T> at (x, y, z) holds the field at
-// (x, y - LO + a, z - LO + b), a, b < 4 (indices mod N), a-major.
-template <typename T> struct alignas(16 * sizeof(T)) Tile {
-    T v[16];
+// The 2 x 4 x 4 block of a pair of x planes: Tile<T> at (x2, y, z) holds the
+// field at (2 x2 + i, y - LO + a, z - LO + b), i < 2, a, b < 4 (indices mod
+// N), in that order: one 128-byte line in float32.  A point's nodes along x
+// fall in two or three consecutive pairs.
+template <typename T> struct alignas(32 * sizeof(T)) Tile {
+    T v[32];
 };
 
 size_t triplet_workspace(int n, int dtype, int n_theta) {
@@ -77,32 +79,37 @@ size_t triplet_workspace(int n, int dtype, int n_theta) {
     const bool f32 = dtype == HERMES_F32;
     if (n > (f32 ? tile_max_n<float>() : tile_max_n<double>())) return part;
     const size_t elem = f32 ? sizeof(Tile<float>) : sizeof(Tile<double>);
-    return part + 3 * align256(size_t(n) * n * n * elem);
+    return part + 3 * align256(size_t(n / 2) * n * n * elem);
 }
 
 template <typename T, int N, int LO>
 __global__ __launch_bounds__(kThreads) void k_pack_tiles(const T* __restrict__ f, Tile<T>* __restrict__ out) {
-    const int64_t total = int64_t(N) * N * N;
+    const int64_t total = int64_t(N / 2) * N * N;
     const int64_t stride = int64_t(gridDim.x) * kThreads;
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < total; i += stride) {
-        const int64_t plane = i & ~(int64_t(N) * N - 1);
+        const int x2 = int(i / (int64_t(N) * N));
         const int y = int((i / N) & (N - 1)), z = int(i & (N - 1));
         Tile<T> t;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int xi = 0; xi < 2; ++xi)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                t.v[a * 4 + b] = f[plane + int64_t((y - LO + a) & (N - 1)) * N + ((z - LO + b) & (N - 1))];
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    t.v[(xi * 4 + a) * 4 + b] =
+                        f[(int64_t(2 * x2 + xi) * N + ((y - LO + a) & (N - 1))) * N + ((z - LO + b) & (N - 1))];
         out[i] = t;
     }
 }
 
-// basis_value on a tile-packed field: one tile per x plane of the stencil.
+// basis_value on a tile-packed field: the (y, z) taps of each plane of the
+// two or three pairs that hold the point's x nodes, then the x taps.
 template <typename T, int N, int B>
 __device__ __forceinline__ double basis_value_tiles(const Tile<T>* __restrict__ p, const double u[3],
                                                     const double* __restrict__ tab) {
     using P = BasisTaps<B>;
     constexpr int NT = P::NT, LO = P::LO;
+    constexpr int NP = NT / 2 + 1;   // pairs that can hold the x nodes
     int cell[3];
     double tap[3][NT];
 #pragma unroll
@@ -113,21 +120,38 @@ __device__ __forceinline__ double basis_value_tiles(const Tile<T>* __restrict__ 
         cell[a] = int(f);
         P::weights(v - f, tab, tap[a]);
     }
+    const int x0 = (cell[0] - LO) & (N - 1), odd = x0 & 1, last = (odd + NT - 1) >> 1;
     const size_t yz = size_t(cell[1] & (N - 1)) * N + (cell[2] & (N - 1));
+    double s[2 * NP];   // s[2 k + i]: plane i of pair k, (y, z) taps applied
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        s[2 * k] = 0.0;
+        s[2 * k + 1] = 0.0;
+        if (k <= last) {
+            const int x2 = ((x0 >> 1) + k) & (N / 2 - 1);
+            const Tile<T> t = p[size_t(x2) * N * N + yz];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                double vx = 0.0;
+#pragma unroll
+                for (int oy = 0; oy < NT; ++oy) {
+                    double vy = 0.0;
+#pragma unroll
+                    for (int oz = 0; oz < NT; ++oz) vy += tap[2][oz] * double(t.v[(i * 4 + oy) * 4 + oz]);
+                    vx += tap[1][oy] * vy;
+                }
+                s[2 * k + i] = vx;
+            }
+        }
+    }
+    // node ox is plane ox + odd of the loaded run: a bit select keeps the
+    // indices of s static (no private-memory copy of s)
+    const unsigned long long pick = 0ull - static_cast<unsigned long long>(odd);
     double val = 0.0;
 #pragma unroll
     for (int ox = 0; ox < NT; ++ox) {
-        const int cx = (cell[0] - LO + ox) & (N - 1);
-        const Tile<T> t = p[size_t(cx) * N * N + yz];
-        double vx = 0.0;
-#pragma unroll
-        for (int oy = 0; oy < NT; ++oy) {
-            double vy = 0.0;
-#pragma unroll
-            for (int oz = 0; oz < NT; ++oz) vy += tap[2][oz] * double(t.v[oy * 4 + oz]);
-            vx += tap[1][oy] * vy;
-        }
-        val += tap[0][ox] * vx;
+        const unsigned long long a = __double_as_longlong(s[ox]), b = __double_as_longlong(s[ox + 1]);
+        val += tap[0][ox] * __longlong_as_double(static_cast<long long>((a & ~pick) | (b & pick)));
     }
     return val;
 }
@@ -274,7 +298,7 @@ static hermes_status triplet_nb(hermes_ctx ctx, const void* f1, const void* f2, 
     if constexpr (N <= tile_max_n<T>()) {
         // pack every distinct field once
         char* base = static_cast<char*>(work) + align256(size_t(kTripletBlocks) * n_theta * 4 * sizeof(double));
-        const size_t fb = align256(size_t(N) * N * N * sizeof(Tile<T>));
+        const size_t fb = align256(size_t(N / 2) * N * N * sizeof(Tile<T>));
         const void* src[3] = {f2, f3, f1};
         FieldRef<T, N, B>* dst[3] = {&r2, &r3, &r1};
         LaunchScope ls(ctx, stream, "pack_tiles");
@@ -289,7 +313,7 @@ static hermes_status triplet_nb(hermes_ctx ctx, const void* f1, const void* f2, 
             }
             Tile<T>* t = reinterpret_cast<Tile<T>*>(base + size_t(i) * fb);
             dst[i]->t = t;
-            const int64_t want = (int64_t(N) * N * N + kThreads - 1) / kThreads;
+            const int64_t want = (int64_t(N / 2) * N * N + kThreads - 1) / kThreads;
             hipLaunchKernelGGL((k_pack_tiles<T, N, BasisTaps<B>::LO>), dim3(int(want < 8192 ? want : 8192)),
                                dim3(kThreads), 0, stream, static_cast<const T*>(src[i]), t);
         }
