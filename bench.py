@@ -306,8 +306,8 @@ def other_configs(warmup: int, steps: int) -> dict:
     fld = hermes.filter_bins(dk, wl.box_L, [("sphere", 0.0, 5.0)], store_fields=True, moments=False)[0][0]
     del eps, dk
     cen = pos[:406_728].contiguous()
-    twork = torch.empty(hermes.workspace_size(hermes.OP_TRIPLET, n, torch.float32, 20, 0), dtype=torch.uint8,
-                        device="cuda")
+    twork = torch.empty(hermes.workspace_size(hermes.OP_TRIPLET, n, torch.float32, 20, 8_000_000),
+                        dtype=torch.uint8, device="cuda")
     tout = torch.empty((20, 4), dtype=torch.float64, device="cuda")
     for name, n_c, n_rot, kw, desc in [
             ("ns256_ddd_particle", cen.shape[0], 1000, {"centres": cen},

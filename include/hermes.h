@@ -154,7 +154,9 @@ const char* hermes_last_error(void);
 /* Device workspace, in bytes, that `op` needs for an N^3 grid.  n_batch is
  * the number of points (ASSIGN, READOUT), windows (FILTER, XI_ANISO), radial
  * bins (ZETA), opening angles (TRIPLET) or fields (DDD_GAMMA);
- * n_ells the number of multipoles (XI).  Zero for FFT, which needs none. */
+ * n_ells the number of multipoles (XI), or the number of primary vertices
+ * (TRIPLET: 0 gives the minimum, which runs the direct path; see
+ * hermes_triplet_mc).  Zero for FFT, which needs none. */
 hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtype,
                                     int n_batch, int n_ells, size_t* bytes);
 
@@ -356,11 +358,22 @@ hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, i
  *               [n_centres] or NULL (only with centres)
  *   out         device double [n_theta][4]; overwritten
  *   work        device workspace of >= hermes_workspace_size(TRIPLET, n_batch
- *               = n_theta) bytes: the partial sums and three tile-packed
- *               copies of the fields, for N <= 512 in float32 (64 N^3 bytes
- *               each) and N <= 256 in float64 (128 N^3 bytes each); a tile
- *               holds, for a pair of x planes, the 4 x 4 (y, z) block of
- *               nodes that points in a cell reach (D4 uses 3 x 3 of it)
+ *               = n_theta, n_ells = 0) bytes: the partial sums and three
+ *               tile-packed copies of the fields, for N <= 512 in float32
+ *               (64 N^3 bytes each) and N <= 256 in float64 (128 N^3 bytes
+ *               each); a tile holds, for a pair of x planes, the 4 x 4 (y, z)
+ *               block of nodes that points in a cell reach (D4 uses 3 x 3 of
+ *               it).  Sized with n_ells = n_centres (< 2^31), it also holds
+ *               the bucket lists of the block-local path (about 20 bytes per
+ *               centre plus 12 bytes per bucket), which is taken when the
+ *               fields are float32, f2 == f3 (one array) and the reach fits
+ *               the staged region: E + 2 (floor(max(r12, r13) N / L) + 2) +
+ *               NT - 1 <= 32, with E = 4 cells per bucket edge for N <= 256
+ *               (8 at 512, 16 at 1024) and NT = 4 (B3) or 3 (D4).  There the
+ *               centres are sorted by bucket (stable, so a bucket's centres
+ *               stay in index order) and a workgroup stages the 32^3 nodes
+ *               around its bucket in LDS; both paths draw the same samples and
+ *               agree to rounding
  * ERR_ARG for NULL f2, f3, out or work, f1 given with centres, weights
  * without centres, n_centres < 0, n_rot < 1, n_centres n_rot >= 2^62,
  * n_theta outside [1, HERMES_MAX_THETA], r12 or r13 negative, not finite or

@@ -341,7 +341,8 @@ hermes_status hermes_workspace_size(hermes_ctx ctx, int op, int n_grid, int dtyp
         case HERMES_OP_TRIPLET:
             if (n_batch < 1 || n_batch > HERMES_MAX_THETA)
                 return fail(HERMES_ERR_ARG, "hermes_workspace_size: TRIPLET needs 1..64 opening angles");
-            *bytes = triplet_workspace(n_grid, dtype, n_batch);
+            if (n_ells < 0) return fail(HERMES_ERR_ARG, "hermes_workspace_size: TRIPLET needs n_ells (centres) >= 0");
+            *bytes = triplet_workspace(n_grid, dtype, n_batch, n_ells);
             return HERMES_OK;
         case HERMES_OP_DDD_GAMMA:
             *bytes = gamma_workspace();
@@ -485,11 +486,11 @@ hermes_status hermes_triplet_mc(hermes_ctx ctx, const void* f1, const void* f2, 
     if (!std::isfinite(r12) || !std::isfinite(r13) || r12 < 0.0 || r13 < 0.0 || !(r12 < 0.5 * box_L) ||
         !(r13 < 0.5 * box_L))
         return fail(HERMES_ERR_ARG, "hermes_triplet_mc: r12 and r13 must be in [0, L/2)");
-    if (work_bytes < triplet_workspace(n_grid, dtype, n_theta))
+    if (work_bytes < triplet_workspace(n_grid, dtype, n_theta, 0))
         return fail(HERMES_ERR_OOM, "hermes_triplet_mc: workspace too small");
     DeviceGuard g(ctx->device);
     return triplet_impl(ctx, f1, f2, f3, n_grid, dtype, box_L, centres, weights, n_centres, r12, r13, n_theta, n_rot,
-                        seed, out, work, stream);
+                        seed, out, work, work_bytes, stream);
 }
 
 hermes_status hermes_ddd_gamma(hermes_ctx ctx, const void* eps, const void* fields, int n_fields, int n_grid,

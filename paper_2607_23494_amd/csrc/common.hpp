@@ -146,8 +146,8 @@ size_t aniso_workspace(hermes_ctx ctx, int n, int n_win);
 hermes_status triplet_impl(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, int n, int dtype,
                            double box_L, const float* centres, const float* weights, int64_t n_centres, double r12,
                            double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
-                           hipStream_t stream);
-size_t triplet_workspace(int n, int dtype, int n_theta);
+                           size_t work_bytes, hipStream_t stream);
+size_t triplet_workspace(int n, int dtype, int n_theta, int64_t n_centres);
 hermes_status gamma_impl(hermes_ctx ctx, const void* eps, const void* fields, int n_fields, int n, int dtype,
                          double* out, void* work, hipStream_t stream);
 size_t gamma_workspace();

@@ -23,11 +23,15 @@
 // wavefront's 64 samples are summed by a butterfly over lanes and lane 0 adds
 // them to the wavefront's LDS accumulators, so every sum is formed in a fixed
 // order and the result does not depend on timing.
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
+#include "bucket.hpp"
 #include "common.hpp"
 #include "interp.hpp"
 #include "kernels.hpp"
+#include "sort.hpp"
 
 namespace hermes {
 
@@ -62,6 +66,51 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Primary vertex c: a uniform point of the box from the generator, or
+// catalogue point c, mapped into [0, L) when WRAP (the block-local path
+// buckets centres by it).
+template <bool BOX, bool WRAP>
+__device__ __forceinline__ void centre_of(int64_t c, const float* __restrict__ centres, double box_L, uint64_t seed,
+                                          double x[3]) {
+    if constexpr (BOX) {
+        uint64_t w[4] = {uint64_t(c), 0, 1, 0};
+        philox4x64(w, seed, 0);
+        x[0] = box_L * uniform53(w[0]);
+        x[1] = box_L * uniform53(w[1]);
+        x[2] = box_L * uniform53(w[2]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            x[a] = double(centres[3 * c + a]);
+            if constexpr (WRAP) x[a] -= box_L * floor(x[a] / box_L);
+        }
+    }
+}
+
+// Rotation r of centre c: u uniform on the sphere, v uniform on the circle
+// orthogonal to u.
+__device__ __forceinline__ void rotation_of(int64_t c, int64_t r, uint64_t seed, double u[3], double v[3]) {
+    uint64_t w[4] = {uint64_t(c), uint64_t(r), 0, 0};
+    philox4x64(w, seed, 0);
+    const double cz = 2.0 * uniform53(w[0]) - 1.0;
+    const double phi = 2.0 * M_PI * uniform53(w[1]);
+    const double psi = 2.0 * M_PI * uniform53(w[2]);
+    const double sz = sqrt(fmax(0.0, 1.0 - cz * cz));
+    u[0] = sz * cos(phi);
+    u[1] = sz * sin(phi);
+    u[2] = cz;
+    // orthonormal basis of the plane orthogonal to u (Duff et al., JCGT
+    // 2017), then v at angle psi in it
+    const double sg = u[2] >= 0.0 ? 1.0 : -1.0;
+    const double ia = -1.0 / (sg + u[2]);
+    const double b = u[0] * u[1] * ia;
+    const double e1[3] = {1.0 + sg * u[0] * u[0] * ia, sg * b, -sg * u[0]};
+    const double e2[3] = {b, sg + u[1] * u[1] * ia, -u[1]};
+    const double cp = cos(psi), sp = sin(psi);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = cp * e1[k] + sp * e2[k];
+}
+
 // Tile-packed copies: sixteen times the field (8.6 GB per float32 field at
 // 512^3); larger grids read the plain array.
 template <typename T> constexpr int tile_max_n() { return sizeof(T) == 4 ? 512 : 256; }
@@ -74,7 +123,8 @@ template <typename T> struct alignas(32 * sizeof(T)) Tile {
     T v[32];
 };
 
-size_t triplet_workspace(int n, int dtype, int n_theta) {
+// Partial sums and tile-packed copies (the direct path).
+static size_t triplet_workspace_direct(int n, int dtype, int n_theta) {
     const size_t part = align256(size_t(kTripletBlocks) * n_theta * 4 * sizeof(double));
     const bool f32 = dtype == HERMES_F32;
     if (n > (f32 ? tile_max_n<float>() : tile_max_n<double>())) return part;
@@ -200,12 +250,8 @@ __global__ __launch_bounds__(kThreads) void k_triplet(FieldRef<T, N, B> f1, Fiel
         double a = 0.0, v2 = 0.0, x[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 1.0}, v[3] = {1.0, 0.0, 0.0};
         if (live) {
             const int64_t c = s / n_rot, r = s - (s / n_rot) * n_rot;
+            centre_of<BOX, false>(c, centres, box_L, seed, x);
             if constexpr (BOX) {
-                uint64_t w[4] = {uint64_t(c), 0, 1, 0};
-                philox4x64(w, seed, 0);
-                x[0] = box_L * uniform53(w[0]);
-                x[1] = box_L * uniform53(w[1]);
-                x[2] = box_L * uniform53(w[2]);
                 if (has_f1) {
                     const double uc[3] = {x[0] * scale, x[1] * scale, x[2] * scale};
                     a = f1.at(uc);
@@ -213,30 +259,9 @@ __global__ __launch_bounds__(kThreads) void k_triplet(FieldRef<T, N, B> f1, Fiel
                     a = 1.0;
                 }
             } else {
-                x[0] = double(centres[3 * c]);
-                x[1] = double(centres[3 * c + 1]);
-                x[2] = double(centres[3 * c + 2]);
                 a = weights ? double(weights[c]) : 1.0;
             }
-            uint64_t w[4] = {uint64_t(c), uint64_t(r), 0, 0};
-            philox4x64(w, seed, 0);
-            const double cz = 2.0 * uniform53(w[0]) - 1.0;
-            const double phi = 2.0 * M_PI * uniform53(w[1]);
-            const double psi = 2.0 * M_PI * uniform53(w[2]);
-            const double sz = sqrt(fmax(0.0, 1.0 - cz * cz));
-            u[0] = sz * cos(phi);
-            u[1] = sz * sin(phi);
-            u[2] = cz;
-            // orthonormal basis of the plane orthogonal to u (Duff et al.,
-            // JCGT 2017), then v at angle psi in it
-            const double sg = u[2] >= 0.0 ? 1.0 : -1.0;
-            const double ia = -1.0 / (sg + u[2]);
-            const double b = u[0] * u[1] * ia;
-            const double e1[3] = {1.0 + sg * u[0] * u[0] * ia, sg * b, -sg * u[0]};
-            const double e2[3] = {b, sg + u[1] * u[1] * ia, -u[1]};
-            const double cp = cos(psi), sp = sin(psi);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) v[k] = cp * e1[k] + sp * e2[k];
+            rotation_of(c, r, seed, u, v);
             const double p2[3] = {(x[0] + r12 * u[0]) * scale, (x[1] + r12 * u[1]) * scale,
                                   (x[2] + r12 * u[2]) * scale};
             v2 = f2.at(p2);
@@ -286,13 +311,327 @@ __global__ void k_triplet_final(const double* __restrict__ part, int n_blocks, i
     out[i] = s;
 }
 
+// ---------------------------------------------------------------- block-local path
+// For float32 fields with f2 and f3 the same array, the centres are
+// bucketed by blocks of E^3 cells and a workgroup stages the nodes around
+// its block (a kTriReg^3 region, 128 KB of LDS) once, then draws every
+// sample of the block's centres from it: the 1 + n_theta reads of a sample
+// become LDS reads instead of gathers of 128-byte lines from L2.  Usable when
+// the triangles' reach fits the region: E + 2 M + NT - 1 <= kTriReg with the
+// margin M = floor(max(r12, r13) N / L) + 2 cells.  Workgroups take the
+// buckets in a fixed round-robin order, so the sums keep a fixed order.
+constexpr int kTriReg = 32;             // region edge (nodes)
+constexpr int kTriThreads = 1024;       // one workgroup per CU (the region's LDS)
+constexpr int kTriWaves = kTriThreads / 64;
+
+// Bucket edge in cells: 4, or 8 or 16 where the bucket count would exceed
+// the offset scan's reach (kScanBlock^2).
+__host__ __device__ constexpr int tri_blk(int n) {
+    return int64_t(n / 4) * (n / 4) * (n / 4) <= int64_t(kScanBlock) * kScanBlock   ? 4
+           : int64_t(n / 8) * (n / 8) * (n / 8) <= int64_t(kScanBlock) * kScanBlock ? 8
+                                                                                    : 16;
+}
+inline int64_t tri_buckets(int n) {
+    const int nb = n / tri_blk(n);
+    return int64_t(nb) * nb * nb;
+}
+
+// Bucket arrays of the block-local path (bytes, each part 256-aligned):
+// bucket keys, the centre list in bucket order (centres of one bucket in
+// index order), per-bucket counts, their offsets and the scan's block sums,
+// then the sort's buffers.
+struct TriLayout {
+    size_t key, list, count, off, blocksum, sort, total;
+};
+
+static TriLayout tri_layout(int n, int64_t n_c) {
+    const int64_t k = tri_buckets(n);
+    const int64_t nblk = (k + kScanBlock - 1) / kScanBlock;
+    TriLayout l{};
+    size_t at = 0;
+    l.key = at;
+    at += align256(size_t(n_c) * 4);
+    l.list = at;
+    at += align256(size_t(n_c) * 4);
+    l.count = at;
+    at += align256(size_t(k) * 4);
+    l.off = at;
+    at += align256(size_t(k + 1) * 4);
+    l.blocksum = at;
+    at += align256(size_t(nblk) * 4);
+    l.sort = at;
+    at += sort_layout(n_c).total;
+    l.total = at;
+    return l;
+}
+
+// The direct path's workspace, then (float32, 1 <= n_c < 2^31) the bucket
+// arrays of the block-local path; a workspace sized without them runs the
+// direct path.
+size_t triplet_workspace(int n, int dtype, int n_theta, int64_t n_c) {
+    const size_t direct = triplet_workspace_direct(n, dtype, n_theta);
+    if (dtype != HERMES_F32 || n_c < 1 || n_c > INT32_MAX) return direct;
+    return direct + tri_layout(n, n_c).total;
+}
+
+// Bucket of every centre (its cell, clamped to the grid, divided by E).
+template <int N, bool BOX>
+__global__ __launch_bounds__(kThreads) void k_tri_keys(const float* __restrict__ centres, int64_t n_c, double box_L,
+                                                       uint64_t seed, uint32_t* __restrict__ key,
+                                                       uint32_t* __restrict__ count) {
+    constexpr int E = tri_blk(N), NB = N / E;
+    const double scale = double(N) / box_L;
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_c; i += stride) {
+        double x[3];
+        centre_of<BOX, true>(i, centres, box_L, seed, x);
+        int b[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int cell = int(floor(x[a] * scale));
+            cell = cell < 0 ? 0 : (cell > N - 1 ? N - 1 : cell);
+            b[a] = cell / E;
+        }
+        const uint32_t k = uint32_t((b[0] * NB + b[1]) * NB + b[2]);
+        key[i] = k;
+        atomicAdd(count + k, 1u);
+    }
+}
+
+// The basis expansion at u (cell units) from the staged region: region index
+// t along an axis holds node o - M - LO + t, so the nodes of a point in cell c
+// start at index c - o + M.
+template <int B>
+__device__ __forceinline__ double region_value(const float* __restrict__ reg, const double u[3], const int o[3],
+                                               int marg, const double* __restrict__ tab) {
+    using P = BasisTaps<B>;
+    constexpr int NT = P::NT;
+    int rel[3];
+    double tap[3][NT];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double f = floor(u[a]);
+        rel[a] = int(f) - o[a] + marg;
+        P::weights(u[a] - f, tab, tap[a]);
+    }
+    const float* p = reg + (rel[0] * kTriReg + rel[1]) * kTriReg + rel[2];
+    double val = 0.0;
+#pragma unroll
+    for (int ox = 0; ox < NT; ++ox) {
+        double vx = 0.0;
+#pragma unroll
+        for (int oy = 0; oy < NT; ++oy) {
+            double vy = 0.0;
+#pragma unroll
+            for (int oz = 0; oz < NT; ++oz) vy += tap[2][oz] * double(p[(ox * kTriReg + oy) * kTriReg + oz]);
+            vx += tap[1][oy] * vy;
+        }
+        val += tap[0][ox] * vx;
+    }
+    return val;
+}
+
+__device__ __forceinline__ double block_sum_tri(double v, double* scratch) {
+    scratch[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kTriThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) scratch[threadIdx.x] += scratch[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = scratch[0];
+    __syncthreads();
+    return r;
+}
+
+inline size_t tri_lds_bytes(int n_theta) {
+    return size_t(kTriReg) * kTriReg * kTriReg * sizeof(float) + size_t(kTriWaves) * n_theta * 2 * sizeof(double) +
+           size_t(n_theta) * 2 * sizeof(double) + size_t(kTriThreads) * sizeof(double);
+}
+
+// F1R: f1 is the staged field too (read at the centre, inside the block).
+template <int N, bool BOX, int B, bool F1R>
+__global__ __launch_bounds__(kTriThreads) void k_triplet_blocks(
+    const float* __restrict__ f1, const float* __restrict__ f23, const double* __restrict__ tab, bool has_f1,
+    const float* __restrict__ centres, const float* __restrict__ weights, int n_rot, double box_L, double r12,
+    double r13, int n_theta, uint64_t seed, int marg, const uint32_t* __restrict__ off,
+    const uint32_t* __restrict__ list, double* __restrict__ part) {
+    constexpr int E = tri_blk(N), NB = N / E, LO = BasisTaps<B>::LO;
+    constexpr int64_t K = int64_t(NB) * NB * NB;
+    constexpr int RV = kTriReg * kTriReg * kTriReg;
+    extern __shared__ double lds_raw[];
+    float* reg = reinterpret_cast<float*>(lds_raw);
+    double* acc = lds_raw + RV / 2;                 // [wave][j][2]: sum a f3, sum a f2 f3
+    double* cs = acc + kTriWaves * n_theta * 2;     // [j][2]: cos, sin of the opening angles
+    double* red = cs + n_theta * 2;                 // [kTriThreads]
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int j = threadIdx.x; j < kTriWaves * n_theta * 2; j += kTriThreads) acc[j] = 0.0;
+    for (int j = threadIdx.x; j < n_theta; j += kTriThreads) {
+        const double th = (double(j) + 0.5) * M_PI / double(n_theta);
+        cs[2 * j] = cos(th);
+        cs[2 * j + 1] = sin(th);
+    }
+    const double scale = double(N) / box_L;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t b = blockIdx.x; b < K; b += gridDim.x) {
+        const uint32_t lo = off[b], hi = off[b + 1];
+        if (lo == hi) continue;   // uniform over the workgroup
+        const int o[3] = {int(b / (NB * NB)) * E, int((b / NB) % NB) * E, int(b % NB) * E};
+        __syncthreads();   // the previous block's reads (and the set-up above) are done
+        for (int e = threadIdx.x; e < RV; e += kTriThreads) {
+            const int i = e / (kTriReg * kTriReg), j = (e / kTriReg) % kTriReg, k = e % kTriReg;
+            const int gx = (o[0] - marg - LO + i) & (N - 1), gy = (o[1] - marg - LO + j) & (N - 1),
+                      gz = (o[2] - marg - LO + k) & (N - 1);
+            reg[e] = f23[(int64_t(gx) * N + gy) * N + gz];
+        }
+        __syncthreads();
+        const int64_t tot = int64_t(hi - lo) * n_rot;
+        // the loop bound is uniform over a wavefront: every lane takes part in
+        // every butterfly
+        for (int64_t base = int64_t(wv) * 64; base < tot; base += kTriThreads) {
+            const int64_t s = base + lane;
+            const bool live = s < tot;
+            double a = 0.0, v2 = 0.0, x[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 1.0}, v[3] = {1.0, 0.0, 0.0};
+            if (live) {
+                const int64_t k = s / n_rot, r = s - k * n_rot;
+                const int64_t c = list[lo + k];
+                centre_of<BOX, true>(c, centres, box_L, seed, x);
+                if constexpr (BOX) {
+                    if (has_f1) {
+                        const double uc[3] = {x[0] * scale, x[1] * scale, x[2] * scale};
+                        if constexpr (F1R) a = region_value<B>(reg, uc, o, marg, tab);
+                        else a = basis_value<float, N, B>(f1, uc, tab);
+                    } else {
+                        a = 1.0;
+                    }
+                } else {
+                    a = weights ? double(weights[c]) : 1.0;
+                }
+                rotation_of(c, r, seed, u, v);
+                const double p2[3] = {(x[0] + r12 * u[0]) * scale, (x[1] + r12 * u[1]) * scale,
+                                      (x[2] + r12 * u[2]) * scale};
+                v2 = region_value<B>(reg, p2, o, marg, tab);
+            }
+            s0 += a;
+            s1 += a * v2;
+            for (int j = 0; j < n_theta; ++j) {
+                double p3 = 0.0, p23 = 0.0;
+                if (live) {
+                    const double ct = cs[2 * j], st = cs[2 * j + 1];
+                    const double q[3] = {(x[0] + r13 * (ct * u[0] + st * v[0])) * scale,
+                                         (x[1] + r13 * (ct * u[1] + st * v[1])) * scale,
+                                         (x[2] + r13 * (ct * u[2] + st * v[2])) * scale};
+                    const double v3 = region_value<B>(reg, q, o, marg, tab);
+                    p3 = a * v3;
+                    p23 = a * v2 * v3;
+                }
+                p3 = wave_sum(p3);
+                p23 = wave_sum(p23);
+                if (lane == 0) {
+                    acc[(wv * n_theta + j) * 2] += p3;
+                    acc[(wv * n_theta + j) * 2 + 1] += p23;
+                }
+            }
+        }
+    }
+    const double b0 = block_sum_tri(s0, red);
+    const double b1 = block_sum_tri(s1, red);   // ends with a barrier: acc is complete
+    for (int j = threadIdx.x; j < n_theta; j += kTriThreads) {
+        double t3 = 0.0, t23 = 0.0;
+        for (int k = 0; k < kTriWaves; ++k) {
+            t3 += acc[(k * n_theta + j) * 2];
+            t23 += acc[(k * n_theta + j) * 2 + 1];
+        }
+        double* dst = part + (int64_t(blockIdx.x) * n_theta + j) * 4;
+        dst[0] = b0;
+        dst[1] = b1;
+        dst[2] = t3;
+        dst[3] = t23;
+    }
+}
+
+template <int N, bool BOX, int B, bool F1R>
+static void launch_blocks(int grid, size_t lds, hipStream_t stream, const float* f1, const float* f23,
+                          const double* tab, const float* centres, const float* weights, int n_rot, double box_L,
+                          double r12, double r13, int n_theta, uint64_t seed, int marg, const uint32_t* off,
+                          const uint32_t* list, double* part) {
+    auto kern = k_triplet_blocks<N, BOX, B, F1R>;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(lds));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kTriThreads), lds, stream, f1, f23, tab, f1 != nullptr, centres,
+                       weights, n_rot, box_L, r12, r13, n_theta, seed, marg, off, list, part);
+}
+
+template <int N, int B>
+static hermes_status triplet_blocks(hermes_ctx ctx, const float* f1, const float* f23, double box_L,
+                                    const float* centres, const float* weights, int64_t n_centres, double r12,
+                                    double r13, int n_theta, int n_rot, uint64_t seed, int marg, double* out,
+                                    void* work, hipStream_t stream) {
+    double* part = static_cast<double*>(work);
+    char* base = static_cast<char*>(work) + triplet_workspace_direct(N, HERMES_F32, n_theta);
+    const TriLayout l = tri_layout(N, n_centres);
+    uint32_t* key = reinterpret_cast<uint32_t*>(base + l.key);
+    uint32_t* list = reinterpret_cast<uint32_t*>(base + l.list);
+    uint32_t* count = reinterpret_cast<uint32_t*>(base + l.count);
+    uint32_t* off = reinterpret_cast<uint32_t*>(base + l.off);
+    uint32_t* blocksum = reinterpret_cast<uint32_t*>(base + l.blocksum);
+    const int64_t nk = tri_buckets(N);
+    const bool box = centres == nullptr;
+    {
+        LaunchScope ls(ctx, stream, "bucket");
+        launch_fill<uint32_t>(count, nk, 0u, stream);
+        const int64_t want = (n_centres + kThreads - 1) / kThreads;
+        const int g = int(want < 8192 ? want : 8192);
+        if (box)
+            hipLaunchKernelGGL((k_tri_keys<N, true>), dim3(g), dim3(kThreads), 0, stream, centres, n_centres, box_L,
+                               seed, key, count);
+        else
+            hipLaunchKernelGGL((k_tri_keys<N, false>), dim3(g), dim3(kThreads), 0, stream, centres, n_centres, box_L,
+                               seed, key, count);
+        launch_tile_scan(count, nk, off, blocksum, stream);
+        radix_sort_indices(key, n_centres, uint32_t(nk - 1), list, base + l.sort, stream);
+    }
+    const int grid = int(std::min<int64_t>({nk, int64_t(ctx->cus), int64_t(kTripletBlocks)}));
+    const size_t lds = tri_lds_bytes(n_theta);
+    const double* tab = ctx->t.db2tab;
+    {
+        LaunchScope ls(ctx, stream, "triplet");
+        if (!box)
+            launch_blocks<N, false, B, false>(grid, lds, stream, nullptr, f23, tab, centres, weights, n_rot, box_L,
+                                              r12, r13, n_theta, seed, marg, off, list, part);
+        else if (f1 == f23)
+            launch_blocks<N, true, B, true>(grid, lds, stream, f1, f23, tab, centres, weights, n_rot, box_L, r12,
+                                            r13, n_theta, seed, marg, off, list, part);
+        else
+            launch_blocks<N, true, B, false>(grid, lds, stream, f1, f23, tab, centres, weights, n_rot, box_L, r12,
+                                             r13, n_theta, seed, marg, off, list, part);
+    }
+    {
+        LaunchScope ls(ctx, stream, "reduce");
+        hipLaunchKernelGGL(k_triplet_final, dim3((n_theta * 4 + 127) / 128), dim3(128), 0, stream, part, grid,
+                           n_theta, out);
+    }
+    return check_launch("hermes_triplet_mc");
+}
+
 template <typename T, int N, int B>
 static hermes_status triplet_nb(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, double box_L,
                                 const float* centres, const float* weights, int64_t n_centres, double r12,
                                 double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
-                                hipStream_t stream) {
+                                size_t work_bytes, hipStream_t stream) {
     double* part = static_cast<double*>(work);
     const double* tab = ctx->t.db2tab;
+    if constexpr (std::is_same<T, float>::value) {
+        // block-local path: f2 and f3 one array, the reach within the region,
+        // the bucket arrays in the workspace
+        const double reach = std::max(r12, r13) * double(N) / box_L;
+        const int marg = int(std::floor(reach)) + 2;
+        if (f2 == f3 && n_centres >= 1 && n_centres <= INT32_MAX &&
+            tri_blk(N) + 2 * marg + BasisTaps<B>::NT - 1 <= kTriReg &&
+            work_bytes >= triplet_workspace(N, HERMES_F32, n_theta, n_centres))
+            return triplet_blocks<N, B>(ctx, static_cast<const float*>(f1), static_cast<const float*>(f2), box_L,
+                                        centres, weights, n_centres, r12, r13, n_theta, n_rot, seed, marg, out, work,
+                                        stream);
+    }
     FieldRef<T, N, B> r1{static_cast<const T*>(f1), nullptr, tab}, r2{static_cast<const T*>(f2), nullptr, tab},
         r3{static_cast<const T*>(f3), nullptr, tab};
     if constexpr (N <= tile_max_n<T>()) {
@@ -343,24 +682,25 @@ template <typename T, int N>
 static hermes_status triplet_n(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, double box_L,
                                const float* centres, const float* weights, int64_t n_centres, double r12,
                                double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
-                               hipStream_t stream) {
+                               size_t work_bytes, hipStream_t stream) {
     if (ctx->basis == HERMES_BASIS_DB2)
         return triplet_nb<T, N, HERMES_BASIS_DB2>(ctx, f1, f2, f3, box_L, centres, weights, n_centres, r12, r13,
-                                                  n_theta, n_rot, seed, out, work, stream);
+                                                  n_theta, n_rot, seed, out, work, work_bytes, stream);
     return triplet_nb<T, N, HERMES_BASIS_B3>(ctx, f1, f2, f3, box_L, centres, weights, n_centres, r12, r13, n_theta,
-                                             n_rot, seed, out, work, stream);
+                                             n_rot, seed, out, work, work_bytes, stream);
 }
 
 hermes_status triplet_impl(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, int n, int dtype,
                            double box_L, const float* centres, const float* weights, int64_t n_centres, double r12,
                            double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
-                           hipStream_t stream) {
-#define HERMES_TRIPLET_CASE(NN)                                                                                 \
-    case NN:                                                                                                    \
-        return dtype == HERMES_F32 ? triplet_n<float, NN>(ctx, f1, f2, f3, box_L, centres, weights, n_centres,  \
-                                                          r12, r13, n_theta, n_rot, seed, out, work, stream)    \
-                                   : triplet_n<double, NN>(ctx, f1, f2, f3, box_L, centres, weights, n_centres, \
-                                                           r12, r13, n_theta, n_rot, seed, out, work, stream);
+                           size_t work_bytes, hipStream_t stream) {
+#define HERMES_TRIPLET_CASE(NN)                                                                                    \
+    case NN:                                                                                                       \
+        return dtype == HERMES_F32                                                                                 \
+                   ? triplet_n<float, NN>(ctx, f1, f2, f3, box_L, centres, weights, n_centres, r12, r13, n_theta, \
+                                          n_rot, seed, out, work, work_bytes, stream)                             \
+                   : triplet_n<double, NN>(ctx, f1, f2, f3, box_L, centres, weights, n_centres, r12, r13, n_theta, \
+                                           n_rot, seed, out, work, work_bytes, stream);
     switch (n) {
         HERMES_TRIPLET_CASE(8)
         HERMES_TRIPLET_CASE(16)

@@ -306,9 +306,16 @@ def triplet_mc(f2: torch.Tensor, f3: torch.Tensor, box_L: float, r12: float, r13
                                 or weights.numel() != centres.shape[0] or not weights.is_contiguous()):
         raise ValueError("weights must be a contiguous float32 [n] tensor beside centres")
     n_c = int(centres.shape[0]) if centres is not None else int(n_box)
-    wbytes = workspace_size(OP_TRIPLET, n, f2.dtype, n_theta, 0, dev)
+    # a workspace of the minimum size runs the direct path; one sized with the
+    # centre count also holds the block-local path's bucket lists
+    wmin = workspace_size(OP_TRIPLET, n, f2.dtype, n_theta, 0, dev)
     with _on(stream):
-        w = _workspace(wbytes, dev, work)
+        if work is None:
+            w = _workspace(workspace_size(OP_TRIPLET, n, f2.dtype, n_theta, n_c if n_c < 2 ** 31 else 0, dev), dev,
+                           None)
+        else:
+            w = _workspace(wmin, dev, work)
+        wbytes = w.numel() * w.element_size()
         if out is None:
             out = torch.empty((n_theta, 4), dtype=torch.float64, device=f2.device)
         _check(_lib.hermes_triplet_mc(context(dev), _ptr(f1), _ptr(f2), _ptr(f3), n, _dtype_code(f2.dtype),

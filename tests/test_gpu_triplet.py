@@ -142,3 +142,76 @@ def test_triplet_512_tiles_and_direct_reads(hermes, dtype):
     ref = O.triplet_mc(f2, f2, L, 15.0, 35.0, 4, 2, 17, n_box=257, f1=f1)
     for q in range(4):
         assert normwise(got[:, q], ref[:, q]) < tol, q
+
+
+def _stages(hermes, fn):
+    hermes.profile_enable(True)
+    hermes.profile_reset()
+    out = fn().cpu().numpy()
+    torch.cuda.synchronize()
+    st = set(hermes.profile_read())
+    hermes.profile_enable(False)
+    return out, st
+
+
+def test_triplet_block_local_path(hermes):
+    """float32 fields with f2 = f3 and a reach within the staged region take
+    the block-local path (centres bucketed by block, the field around each
+    block in LDS): against the oracle, and against the direct path (a
+    workspace of the minimum size) on the same samples, for weighted
+    catalogue centres (some on the box faces and outside the box) and for
+    box points with f1 the staged field, another field, or none."""
+    n, L = 64, 100.0
+    pos, f1, f2, _ = _fields(n, L, 8400)
+    w = synth.lognormal_marks(pos.shape[0], 5)[:300]
+    c = pos[:300].copy()
+    c[0] = [0.0, 0.0, 0.0]
+    c[1] = [L, L, L]
+    c[2] = [-3.5, 101.25, 50.0]
+    c[3] = np.nextafter(np.float32(L), np.float32(0))
+    f2 = f2.astype(np.float32)
+    f1 = f1.astype(np.float32)
+    t2, t1 = torch.from_numpy(f2).cuda(), torch.from_numpy(f1).cuda()
+    r12, r13 = 8.0, 15.0   # reach 9.6 cells
+    wmin = torch.empty(hermes.workspace_size(hermes.OP_TRIPLET, n, torch.float32, 6, 0), dtype=torch.uint8,
+                       device="cuda")
+    cases = [({"centres": torch.from_numpy(c).cuda(), "weights": torch.from_numpy(w).cuda()},
+              {"centres": c, "weights": w}),
+             ({"n_box": 500, "f1": t2}, {"n_box": 500, "f1": f2}),
+             ({"n_box": 500, "f1": t1}, {"n_box": 500, "f1": f1}),
+             ({"n_box": 333}, {"n_box": 333})]
+    for kw, okw in cases:
+        blocks, st = _stages(hermes, lambda: hermes.triplet_mc(t2, t2, L, r12, r13, 6, 5, 41, **kw))
+        assert "bucket" in st, st
+        direct, st = _stages(hermes, lambda: hermes.triplet_mc(t2, t2, L, r12, r13, 6, 5, 41, work=wmin, **kw))
+        assert "bucket" not in st, st
+        ref = O.triplet_mc(f2, f2, L, r12, r13, 6, 5, 41, **okw)
+        for q in range(4):
+            assert normwise(blocks[:, q], ref[:, q]) < 1e-5, q
+            assert normwise(blocks[:, q], direct[:, q]) < 1e-12, q
+
+
+def test_triplet_block_local_crowded_bucket_and_determinism(hermes):
+    """4000 centres inside one block plus 1000 spread ones: the stable sort
+    keeps each bucket's centres in index order, so repeated calls agree bit
+    for bit; the sums match the direct path on the same samples."""
+    n, L = 64, 100.0
+    _, _, f2, _ = _fields(n, L, 8500)
+    t2 = torch.from_numpy(f2.astype(np.float32)).cuda()
+    rng = np.random.default_rng(85)
+    c = np.concatenate([rng.uniform(10.0, 11.0, (4000, 3)), rng.uniform(0.0, L, (1000, 3))]).astype(np.float32)
+    rng.shuffle(c)
+    tc = torch.from_numpy(c).cuda()
+    a = hermes.triplet_mc(t2, t2, L, 7.0, 12.0, 9, 6, 3, centres=tc)
+    b = hermes.triplet_mc(t2, t2, L, 7.0, 12.0, 9, 6, 3, centres=tc)
+    assert torch.equal(a, b)
+    wmin = torch.empty(hermes.workspace_size(hermes.OP_TRIPLET, n, torch.float32, 9, 0), dtype=torch.uint8,
+                       device="cuda")
+    d = hermes.triplet_mc(t2, t2, L, 7.0, 12.0, 9, 6, 3, centres=tc, work=wmin).cpu().numpy()
+    got = a.cpu().numpy()
+    assert np.all(got[:, 0] == 6.0 * c.shape[0])
+    for q in (1, 2, 3):
+        assert normwise(got[:, q], d[:, q]) < 1e-12, q
+    box1 = hermes.triplet_mc(t2, t2, L, 7.0, 12.0, 9, 6, 3, n_box=30000, f1=t2)
+    box2 = hermes.triplet_mc(t2, t2, L, 7.0, 12.0, 9, 6, 3, n_box=30000, f1=t2)
+    assert torch.equal(box1, box2)
