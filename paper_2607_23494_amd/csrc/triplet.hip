@@ -60,10 +60,34 @@ __device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t 
 // The top 53 bits of a word plus one half, scaled to (0, 1).
 __device__ __forceinline__ double uniform53(uint64_t w) { return (double(w >> 11) + 0.5) * 0x1p-53; }
 
+// One DPP step on a double: the value of the lane CTRL selects, in the rows
+// ROWS enables (0 in the others).
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(b)), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(unsigned(hi)) << 32) |
+                                                       unsigned(lo)));
+}
+
+// Sum over the wavefront's 64 lanes (all active), the same in every lane, in
+// a fixed order: within rows of 16 by quad permutes and mirrors (every lane
+// of a row then holds the row's sum), then the row broadcasts 15 and 31
+// carry rows 0 and 2 into rows 1 and 3 and rows 0 + 1 into row 3, whose lane
+// 63 holds the total.  DPP moves stay in the vector unit: no LDS round trip
+// per step.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-    return v;
+    v += dpp_f64<0xB1>(v);          // quad_perm(1, 0, 3, 2)
+    v += dpp_f64<0x4E>(v);          // quad_perm(2, 3, 0, 1)
+    v += dpp_f64<0x141>(v);         // row_half_mirror
+    v += dpp_f64<0x140>(v);         // row_mirror
+    v += dpp_f64<0x142, 0xA>(v);    // row_bcast:15 into rows 1, 3
+    v += dpp_f64<0x143, 0xC>(v);    // row_bcast:31 into rows 2, 3
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(b)), 63));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(b >> 32)), 63));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
 // Primary vertex c: a uniform point of the box from the generator, or
@@ -318,8 +342,9 @@ __global__ void k_triplet_final(const double* __restrict__ part, int n_blocks, i
 // sample of the block's centres from it: the 1 + n_theta reads of a sample
 // become LDS reads instead of gathers of 128-byte lines from L2.  Usable when
 // the triangles' reach fits the region: E + 2 M + NT - 1 <= kTriReg with the
-// margin M = floor(max(r12, r13) N / L) + 2 cells.  Workgroups take the
-// buckets in a fixed round-robin order, so the sums keep a fixed order.
+// margin M = floor(max(r12, r13) N / L) + 2 cells.  Workgroup g takes the
+// contiguous run of buckets that holds centres g n_c / G .. (g + 1) n_c / G
+// (about equal sample counts), so the sums keep a fixed order.
 constexpr int kTriReg = 32;             // region edge (nodes)
 constexpr int kTriThreads = 1024;       // one workgroup per CU (the region's LDS)
 constexpr int kTriWaves = kTriThreads / 64;
@@ -471,8 +496,23 @@ __global__ __launch_bounds__(kTriThreads) void k_triplet_blocks(
         cs[2 * j + 1] = sin(th);
     }
     const double scale = double(N) / box_L;
+    // this workgroup's buckets: those whose first centre falls in
+    // [g n_c / G, (g + 1) n_c / G), a contiguous range of buckets holding
+    // about n_c / G centres (off is non-decreasing)
+    const int64_t n_c = off[K];
+    auto first_at = [&](int64_t t) {   // smallest b in [0, K] with off[b] >= t
+        int64_t lo_b = 0, hi_b = K;
+        while (lo_b < hi_b) {
+            const int64_t mid = (lo_b + hi_b) / 2;
+            if (int64_t(off[mid]) < t) lo_b = mid + 1;
+            else hi_b = mid;
+        }
+        return lo_b;
+    };
+    const int64_t b_begin = first_at(n_c * blockIdx.x / gridDim.x);
+    const int64_t b_end = first_at(n_c * (int64_t(blockIdx.x) + 1) / gridDim.x);
     double s0 = 0.0, s1 = 0.0;
-    for (int64_t b = blockIdx.x; b < K; b += gridDim.x) {
+    for (int64_t b = b_begin; b < b_end; ++b) {
         const uint32_t lo = off[b], hi = off[b + 1];
         if (lo == hi) continue;   // uniform over the workgroup
         const int o[3] = {int(b / (NB * NB)) * E, int((b / NB) % NB) * E, int(b % NB) * E};
