@@ -266,15 +266,17 @@ __global__ __launch_bounds__(kThreads) void k_readout_tiles(const T* __restrict_
     }
 }
 
-// moments[f][m] = (sum over workgroups in index order) / n.
-__global__ void k_readout_moments(const double* __restrict__ part, int blocks, int fc, int nf, double inv_n,
-                                  double* __restrict__ moments) {
-    const int e = threadIdx.x;
-    if (e >= nf * 3) return;
-    const int f = e / 3, m = e % 3;
+// moments[f][m] = (sum over the workgroups' partials) / n: one workgroup per
+// output, thread t summing partials t, t + kThreads, ..., then the block's
+// tree sum (a fixed order).
+__global__ __launch_bounds__(kThreads) void k_readout_moments(const double* __restrict__ part, int blocks, int fc,
+                                                              double inv_n, double* __restrict__ moments) {
+    __shared__ double red[kThreads];
+    const int f = blockIdx.x / 3, m = blockIdx.x % 3;
     double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += part[(int64_t(b) * fc + f) * 3 + m];
-    moments[e] = s * inv_n;
+    for (int b = threadIdx.x; b < blocks; b += kThreads) s += part[(int64_t(b) * fc + f) * 3 + m];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) moments[blockIdx.x] = s * inv_n;
 }
 
 __global__ void k_scale3(double* __restrict__ mom, double s) {
@@ -344,7 +346,7 @@ static hermes_status readout_n(hermes_ctx ctx, const void* fields, int n_fields,
                 }
                 if (moments) {
                     LaunchScope ls(ctx, stream, "reduce");
-                    hipLaunchKernelGGL(k_readout_moments, dim3(1), dim3(kThreads), 0, stream, part, grid, fc, nf,
+                    hipLaunchKernelGGL(k_readout_moments, dim3(3 * nf), dim3(kThreads), 0, stream, part, grid, fc,
                                        1.0 / double(n_pts), moments + 3 * f0);
                 }
             }
