@@ -54,11 +54,14 @@ size_t xi_workspace(int n, int n_ells, int n_bins) {
 
 // One thread per representative (|kx|, |ky|, kz), kx, ky in [0, N/2]; the
 // modes (+-kx, +-ky, kz) share q and |mu| and are summed before the atomic.
+// With swap (line of sight z, or only l = 0), (|ky|, |kx|, kz) shares them
+// too (phi^ is the same function per axis): the thread with |kx| <= |ky|
+// adds both, the other one does nothing, and half the atomics remain.
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_xi_hist(const typename cplx_of<T>::type* __restrict__ dk,
                                                       EllSet ells, int los, const double* __restrict__ phi1d,
                                                       const double* __restrict__ b7dft, double* __restrict__ H,
-                                                      double* __restrict__ Hs, int64_t nq) {
+                                                      double* __restrict__ Hs, int64_t nq, bool swap) {
     constexpr int M = N / 2, P = M + 1;
     const int64_t total = int64_t(P) * P * P;
     const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
@@ -66,15 +69,21 @@ __global__ __launch_bounds__(kThreads) void k_xi_hist(const typename cplx_of<T>:
     const int kz = int(t % P);
     const int iy = int((t / P) % P);
     const int ix = int(t / (int64_t(P) * P));
+    if (swap && ix > iy) return;   // added by the thread of (iy, ix)
     const int xs[2] = {ix, (N - ix) & (N - 1)};
     const int ys[2] = {iy, (N - iy) & (N - 1)};
     const int nx = (ix == 0 || ix == M) ? 1 : 2;
     const int ny = (iy == 0 || iy == M) ? 1 : 2;
+    const int pairs = swap && ix != iy ? 2 : 1;   // (ix, iy) and, swapped, (iy, ix)
     double p = 0.0;
     for (int a = 0; a < nx; ++a)
         for (int b = 0; b < ny; ++b) {
             const auto v = dk[(int64_t(xs[a]) * N + ys[b]) * P + kz];
             p += double(v.x) * v.x + double(v.y) * v.y;
+            if (pairs == 2) {
+                const auto w = dk[(int64_t(ys[b]) * N + xs[a]) * P + kz];
+                p += double(w.x) * w.x + double(w.y) * w.y;
+            }
         }
     const int64_t q = int64_t(ix) * ix + int64_t(iy) * iy + int64_t(kz) * kz;
     const double herm = (kz == 0 || kz == M) ? 1.0 : 2.0;
@@ -83,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_xi_hist(const typename cplx_of<T>:
     const double mu = q == 0 ? 0.0 : double(comp) / sqrt(double(q));
     if (Hs) {
         // B~ is even in every component: the nx ny sign-related modes share it
-        const double ps = double(nx * ny) * ph * b7dft[N + ix] * b7dft[N + iy] * b7dft[N + kz];
+        const double ps = double(nx * ny * pairs) * ph * b7dft[N + ix] * b7dft[N + iy] * b7dft[N + kz];
         for (int i = 0; i < ells.n; ++i) unsafeAtomicAdd(Hs + int64_t(i) * nq + q, ps * legendre(ells.l[i], mu));
     }
     if (q == 0) return;
@@ -158,8 +167,14 @@ static hermes_status xi_n(hermes_ctx ctx, const void* delta_k, double box_L, con
     const int64_t reps = int64_t(P) * P * P;
     {
         LaunchScope ls(ctx, stream, "xi_hist");
+        bool swap = los == 2;   // mu = kz / |k| does not change under kx <-> ky
+        if (!swap) {
+            swap = true;        // nor does P_0(mu) = 1
+            for (int i = 0; i < ells.n; ++i) swap = swap && ells.l[i] == 0;
+        }
         hipLaunchKernelGGL((k_xi_hist<T, N>), dim3((reps + kThreads - 1) / kThreads), dim3(kThreads), 0, stream,
-                           static_cast<const C*>(delta_k), ells, los, basis_phi1d(ctx), basis_selfdft(ctx), H, Hs, nq);
+                           static_cast<const C*>(delta_k), ells, los, basis_phi1d(ctx), basis_selfdft(ctx), H, Hs, nq,
+                           swap);
     }
     {
         LaunchScope ls(ctx, stream, "xi_sum");
