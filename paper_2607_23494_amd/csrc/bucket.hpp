@@ -1,9 +1,8 @@
-// Bucketing of points by tiles of E^3 cells (E = 16 unless given): per-tile
-// counts, their exclusive prefix sum, and the point indices scattered into
-// per-tile lists.
-// Shared by the assignment (one workgroup accumulates a tile's points in
-// LDS) and the readout (points are read tile by tile, so that neighbouring
-// threads gather from one region of the field).
+// Bucketing of points by tiles of E^3 cells (E = 16 unless given): the tile
+// of a point, the exclusive prefix sum of per-tile counts, and the point
+// indices scattered into per-tile lists.  Used by the assignment (one
+// workgroup accumulates a tile's points in LDS); the readout takes the tile
+// of a point, and the radix sort and the triangle sums the prefix sum.
 #pragma once
 
 #include "common.hpp"
@@ -43,14 +42,6 @@ __device__ __forceinline__ int tile_of_point(const float* __restrict__ pos, int6
     const int cy = cell_of<N>(pos[3 * i + 1], scale, f);
     const int cz = cell_of<N>(pos[3 * i + 2], scale, f);
     return ((cx / G::TS) * G::NT + cy / G::TS) * G::NT + cz / G::TS;
-}
-
-template <int N, int E = kBucketTile>
-__global__ __launch_bounds__(kThreads) void k_bucket_count(const float* __restrict__ pos, int64_t n_pts, double scale,
-                                                           uint32_t* __restrict__ count) {
-    const int64_t stride = int64_t(gridDim.x) * kThreads;
-    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride)
-        atomicAdd(count + tile_of_point<N, E>(pos, i, scale), 1u);
 }
 
 // Exclusive prefix sum of cnt[0 .. n) in blocks of kScanBlock: the block's

@@ -6,8 +6,9 @@
 // The value at a point is the node sum v = sum_l f_l prod_a phi(x_a/h - l_a)
 // (64 nodes with B3, 27 with the D4 function), the transpose of the
 // assignment's scatter: one thread per point gathers its rows of nodes.
-// Large calls first bucket the points by tiles of 8^3 cells (16^3 at 1024^3;
-// the positions are copied in bucket order beside the point indices).  Where
+// Large calls first bucket the points by tiles of 8^3 cells (16^3 at 1024^3)
+// with a stable radix sort of their tile keys (a tile's points stay in index
+// order; the positions are copied in list order beside the point indices).  Where
 // the tiles hold enough points, a workgroup stages the nodes around a tile
 // (up to four fields at once) in LDS and reads the tile's points from there;
 // sparser calls read the bucketed points by per-lane gathers.  Either way the
@@ -24,6 +25,7 @@
 #include "common.hpp"
 #include "interp.hpp"
 #include "kernels.hpp"
+#include "sort.hpp"
 
 namespace hermes {
 
@@ -55,51 +57,70 @@ constexpr int kRdTileFields = 4;
 constexpr int kRdTileBlocks = 2048;
 constexpr size_t kRdLdsBudget = 65536;   // bytes of staged nodes per workgroup
 
-// Workspace layout (bytes, each part 256-aligned): tile counts, offsets,
-// cursors, scan block sums, the point list and the positions in list order.
+// Workspace layout (bytes, each part 256-aligned): the points' tile keys,
+// the keys in sorted order, the tile offsets, the point list (indices in
+// tile order), the positions in list order, the per-workgroup moment sums,
+// and the sort's buffers.
 struct RdLayout {
-    size_t count, off, cursor, blocksum, list, spos, part, total;
+    size_t key, skey, off, list, spos, part, sort, total;
 };
 
 static RdLayout rd_layout(int n, int64_t n_pts) {
     const int ts = n < rd_edge(n) ? n : rd_edge(n);
     const int64_t tiles = int64_t(n / ts) * (n / ts) * (n / ts);
-    const int64_t nblk = (tiles + kScanBlock - 1) / kScanBlock;
     RdLayout l{};
     size_t at = 0;
-    l.count = at;
-    at += align256(size_t(tiles) * 4);
+    l.key = at;
+    at += align256(size_t(n_pts) * 4);
+    l.skey = at;
+    at += align256(size_t(n_pts) * 4);
     l.off = at;
     at += align256(size_t(tiles + 1) * 4);
-    l.cursor = at;
-    at += align256(size_t(tiles) * 4);
-    l.blocksum = at;
-    at += align256(size_t(nblk) * 4);
     l.list = at;
     at += align256(size_t(n_pts) * 4);
     l.spos = at;
     at += align256(size_t(n_pts) * 12);
     l.part = at;
     at += align256(size_t(kRdTileBlocks) * kRdTileFields * 3 * sizeof(double));
+    l.sort = at;
+    at += sort_layout(n_pts).total;
     l.total = at;
     return l;
 }
 
-// The bucket scatter of the readout: point i goes to slot off[t] + cursor of
-// its tile t, which receives its index and its position.
+// Tile of every point (the cell of its wrapped position, divided by E).
 template <int N, int E>
-__global__ __launch_bounds__(kThreads) void k_readout_scatter(const float* __restrict__ pos, int64_t n_pts,
-                                                              double scale, const uint32_t* __restrict__ off,
-                                                              uint32_t* __restrict__ cursor,
-                                                              uint32_t* __restrict__ list, float* __restrict__ spos) {
+__global__ __launch_bounds__(kThreads) void k_readout_keys(const float* __restrict__ pos, int64_t n_pts,
+                                                           double scale, uint32_t* __restrict__ key) {
     const int64_t stride = int64_t(gridDim.x) * kThreads;
-    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride) {
-        const int t = tile_of_point<N, E>(pos, i, scale);
-        const uint32_t k = off[t] + atomicAdd(cursor + t, 1u);
-        list[k] = uint32_t(i);
-        spos[3 * size_t(k)] = pos[3 * i];
-        spos[3 * size_t(k) + 1] = pos[3 * i + 1];
-        spos[3 * size_t(k) + 2] = pos[3 * i + 2];
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride)
+        key[i] = uint32_t(tile_of_point<N, E>(pos, i, scale));
+}
+
+// off[t] = the first list slot of tile t (off[tiles] = n): every slot whose
+// key differs from the previous slot's opens the tiles in between.
+__global__ __launch_bounds__(kThreads) void k_readout_offsets(const uint32_t* __restrict__ skey, int64_t n_pts,
+                                                              int64_t tiles, uint32_t* __restrict__ off) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n_pts; j += stride) {
+        const int64_t k = skey[j];
+        const int64_t prev = j > 0 ? int64_t(skey[j - 1]) : -1;
+        for (int64_t t = prev + 1; t <= k; ++t) off[t] = uint32_t(j);
+        if (j == n_pts - 1)
+            for (int64_t t = k + 1; t <= tiles; ++t) off[t] = uint32_t(n_pts);
+    }
+}
+
+// Positions in list order.
+__global__ __launch_bounds__(kThreads) void k_readout_gather_pos(const float* __restrict__ pos, int64_t n_pts,
+                                                                 const uint32_t* __restrict__ list,
+                                                                 float* __restrict__ spos) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n_pts; j += stride) {
+        const int64_t i = list[j];
+        spos[3 * j] = pos[3 * i];
+        spos[3 * j + 1] = pos[3 * i + 1];
+        spos[3 * j + 2] = pos[3 * i + 2];
     }
 }
 
@@ -303,20 +324,17 @@ static hermes_status readout_n(hermes_ctx ctx, const void* fields, int n_fields,
             using G = tile_grid<N, E>;
             const RdLayout l = rd_layout(N, n_pts);
             char* w = static_cast<char*>(work);
-            uint32_t* count = reinterpret_cast<uint32_t*>(w + l.count);
+            uint32_t* key = reinterpret_cast<uint32_t*>(w + l.key);
+            uint32_t* skey = reinterpret_cast<uint32_t*>(w + l.skey);
             uint32_t* off = reinterpret_cast<uint32_t*>(w + l.off);
-            uint32_t* cursor = reinterpret_cast<uint32_t*>(w + l.cursor);
-            uint32_t* blocksum = reinterpret_cast<uint32_t*>(w + l.blocksum);
             uint32_t* lst = reinterpret_cast<uint32_t*>(w + l.list);
             float* spos = reinterpret_cast<float*>(w + l.spos);
             LaunchScope ls(ctx, stream, "bucket");
-            launch_fill<uint32_t>(count, G::TILES, 0u, stream);
-            launch_fill<uint32_t>(cursor, G::TILES, 0u, stream);
-            hipLaunchKernelGGL((k_bucket_count<N, E>), dim3(blocks), dim3(kThreads), 0, stream, pos, n_pts, scale,
-                               count);
-            launch_tile_scan(count, int64_t(G::TILES), off, blocksum, stream);
-            hipLaunchKernelGGL((k_readout_scatter<N, E>), dim3(blocks), dim3(kThreads), 0, stream, pos, n_pts, scale,
-                               off, cursor, lst, spos);
+            hipLaunchKernelGGL((k_readout_keys<N, E>), dim3(blocks), dim3(kThreads), 0, stream, pos, n_pts, scale, key);
+            radix_sort_indices(key, n_pts, uint32_t(G::TILES - 1), lst, w + l.sort, stream, skey);
+            hipLaunchKernelGGL(k_readout_offsets, dim3(blocks), dim3(kThreads), 0, stream, skey, n_pts,
+                               int64_t(G::TILES), off);
+            hipLaunchKernelGGL(k_readout_gather_pos, dim3(blocks), dim3(kThreads), 0, stream, pos, n_pts, lst, spos);
             list = lst;
             rpos = spos;
         }

@@ -18,6 +18,7 @@ namespace hermes {
 constexpr int kSortBits = 7;
 constexpr int kSortDigits = 1 << kSortBits;
 constexpr int kSortWaves = kThreads / 64;   // tiles per workgroup (one per wavefront)
+constexpr int kSortBatch = 8;               // 64-element steps whose loads are issued together
 
 // Elements per tile: a multiple of 64, large enough that the digit-count
 // matrix stays within the scan's reach (kScanBlock^2 entries).
@@ -97,41 +98,54 @@ static __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const uint64_t below = (uint64_t(1) << lane) - 1;
     const int64_t end = std::min(n, (t + 1) * tile);
-    for (int64_t base = t * tile; base < end; base += 64) {   // uniform over the wavefront
-        const int64_t i = base + lane;
-        const bool valid = i < end;
-        const uint32_t k = valid ? key_in[i] : 0u;
-        const uint32_t v = valid ? (val_in ? val_in[i] : uint32_t(i)) : 0u;
-        const int d = int((k >> shift) & (kSortDigits - 1));
-        uint64_t m = __ballot(valid);
+    // kSortBatch steps' keys and values are loaded together (their latencies
+    // overlap), then ranked step by step in index order
+    for (int64_t base0 = t * tile; base0 < end; base0 += 64 * kSortBatch) {   // uniform over the wavefront
+        uint32_t kb[kSortBatch], vb[kSortBatch];
 #pragma unroll
-        for (int b = 0; b < kSortBits; ++b) {
-            const bool bit = (d >> b) & 1;
-            const uint64_t bb = __ballot(valid && bit);
-            m &= bit ? bb : ~bb;
+        for (int u = 0; u < kSortBatch; ++u) {
+            const int64_t i = base0 + 64 * u + lane;
+            kb[u] = i < end ? key_in[i] : 0u;
+            vb[u] = i < end ? (val_in ? val_in[i] : uint32_t(i)) : 0u;
         }
-        // every lane of digit d reads the same running offset, then the
-        // lowest of them advances it by the group's size
-        const uint32_t start = cnt[wv][d];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (valid && (m & below) == 0) cnt[wv][d] = start + uint32_t(__popcll(m));
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (valid) {
-            const uint32_t dst = start + uint32_t(__popcll(m & below));
-            if (key_out) key_out[dst] = k;
-            val_out[dst] = v;
+#pragma unroll
+        for (int u = 0; u < kSortBatch; ++u) {
+            const int64_t base = base0 + 64 * u;
+            if (base >= end) break;   // uniform
+            const bool valid = base + lane < end;
+            const uint32_t k = kb[u], v = vb[u];
+            const int d = int((k >> shift) & (kSortDigits - 1));
+            uint64_t m = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < kSortBits; ++b) {
+                const bool bit = (d >> b) & 1;
+                const uint64_t bb = __ballot(valid && bit);
+                m &= bit ? bb : ~bb;
+            }
+            // every lane of digit d reads the same running offset, then the
+            // lowest of them advances it by the group's size
+            const uint32_t start = cnt[wv][d];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (valid && (m & below) == 0) cnt[wv][d] = start + uint32_t(__popcll(m));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (valid) {
+                const uint32_t dst = start + uint32_t(__popcll(m & below));
+                if (key_out) key_out[dst] = k;
+                val_out[dst] = v;
+            }
         }
     }
 }
 
 // Sort key[0 .. n) (keys <= max_key) with values 0 .. n-1; the values in key
-// order end in val_out.  key is overwritten.  n < 2^32.
+// order end in val_out, and the sorted keys in key_sorted when it is given.
+// key is overwritten.  n < 2^32.
 inline void radix_sort_indices(uint32_t* key, int64_t n, uint32_t max_key, uint32_t* val_out, char* work,
-                               hipStream_t stream) {
+                               hipStream_t stream, uint32_t* key_sorted = nullptr) {
     if (n <= 0) return;
     const SortLayout l = sort_layout(n);
     uint32_t* key2 = reinterpret_cast<uint32_t*>(work + l.key2);
@@ -147,7 +161,7 @@ inline void radix_sort_indices(uint32_t* key, int64_t n, uint32_t max_key, uint3
     const uint32_t* vin = nullptr;
     for (int p = 0; p < passes; ++p) {
         const bool last = p == passes - 1;
-        uint32_t* kout = last ? nullptr : (kin == key ? key2 : key);
+        uint32_t* kout = last ? key_sorted : (kin == key ? key2 : key);
         uint32_t* vout = last ? val_out : ((passes - 1 - p) % 2 == 1 ? val2 : val_out);
         const int shift = p * kSortBits;
         hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(kThreads), 0, stream, kin, n, tile, ntiles, shift, hist);
