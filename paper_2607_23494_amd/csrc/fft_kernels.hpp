@@ -198,13 +198,15 @@ __global__ __launch_bounds__(kColThreads) void k_c2c_cols(typename cplx_of<T>::t
 }
 
 // Tiles of 8-byte columns: more, smaller workgroups per CU keep more loads in
-// flight than 16-byte tiles, which these strided column passes need.
-template <typename T> constexpr int c2c_vec() { return 1; }
+// flight than 16-byte tiles, which these strided column passes need; at
+// N = 1024 that tile is only four float columns (32-byte row segments), so
+// there a thread takes two.
+template <typename T, int N> constexpr int c2c_vec() { return sizeof(T) == 4 && N >= 1024 ? 2 : 1; }
 
 template <typename T, int N, bool INV, bool VECLD>
 inline void launch_c2c_cols(typename cplx_of<T>::type* data, int n_planes, int64_t plane_stride, int ncols,
                             int64_t stride, bool zero_dc, const typename cplx_of<T>::type* tw, hipStream_t stream) {
-    constexpr int VEC = c2c_vec<T>();
+    constexpr int VEC = c2c_vec<T, N>();
     constexpr int TC = col_cfg<T, N, VEC>::TC;
     const int tiles = (ncols + TC - 1) / TC;
     hipLaunchKernelGGL((k_c2c_cols<T, N, INV, VECLD, VEC>), dim3(tiles, n_planes), dim3(kColThreads), 0, stream, data,
