@@ -447,17 +447,21 @@ typedef struct hermes_mark {
  *   mark    host hermes_mark or NULL (NULL or kind NONE: out_i = w_i v_i)
  *   out     device [n_pts] of dtype, or NULL: out_i = w_i m(v_i)
  *   moments device double[3], or NULL: the means over the points of v^2, v^3,
- *           v^4 (unweighted, unmarked), accumulated in float64 (the order of
- *           the float64 additions across workgroups is not fixed); zeros for
- *           n_pts = 0
+ *           v^4 (unweighted, unmarked), accumulated in float64; with the
+ *           tile-staged read (below) in a fixed order, the same on every run,
+ *           otherwise by float64 atomics across workgroups (order not fixed);
+ *           zeros for n_pts = 0
  *   work    device workspace of >= hermes_workspace_size(READOUT, n_batch =
  *           n_pts) bytes, or NULL.  With it, calls of 2^16 to 2^31 - 1 points
- *           first bucket the points by 16^3-cell tiles (counts, offsets, a
- *           4-byte index and a copy of the position per point, 16 bytes) and
- *           read them tile by tile, which keeps
- *           the gathers of neighbouring threads in one region of the field;
- *           the size is 0 outside that range.  NULL reads the points in the
- *           given order.  Values land at their points' indices either way.
+ *           first bucket the points by tiles of 8^3 cells (16^3 at N = 1024)
+ *           with a stable radix sort of their tile keys (keys, sorted keys,
+ *           a 4-byte index and a copy of the position per point, and the
+ *           sort's buffers: about 36 bytes per point) and read them tile by
+ *           tile; when the tiles hold at least 8 points on average, a
+ *           workgroup stages the nodes around a tile in LDS and reads the
+ *           tile's points from there.  The size is 0 outside that range.
+ *           NULL reads the points in the given order.  Values are the same
+ *           bit for bit either way and land at their points' indices.
  * ERR_ARG for NULL buffers, out and moments both NULL, n_pts < 0, box_L <= 0,
  * a bad N or dtype, a non-zero reserved field, an unknown mark kind, a
  * non-finite exponent, offset < 0, or offset = 0 where rho = 0 would divide by
