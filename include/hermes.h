@@ -456,7 +456,7 @@ typedef struct hermes_mark {
  *           first bucket the points by tiles of 8^3 cells (16^3 at N = 1024)
  *           with a stable radix sort of their tile keys (keys, sorted keys,
  *           a 4-byte index and a copy of the position per point, and the
- *           sort's buffers: about 36 bytes per point) and read them tile by
+ *           sort's buffers: about 32 bytes per point) and read them tile by
  *           tile; when the tiles hold at least 8 points on average, a
  *           workgroup stages the nodes around a tile in LDS and reads the
  *           tile's points from there.  The size is 0 outside that range.
