@@ -364,8 +364,8 @@ hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, i
  *               each); a tile holds, for a pair of x planes, the 4 x 4 (y, z)
  *               block of nodes that points in a cell reach (D4 uses 3 x 3 of
  *               it).  Sized with n_ells = n_centres (< 2^31), it also holds
- *               the bucket lists of the block-local path (about 20 bytes per
- *               centre plus 12 bytes per bucket), which is taken when the
+ *               the bucket lists of the block-local path (about 16 bytes per
+ *               centre plus 8 bytes per bucket), which is taken when the
  *               fields are float32, f2 == f3 (one array) and the reach fits
  *               the staged region: E + 2 (floor(max(r12, r13) N / L) + 2) +
  *               NT - 1 <= 32, with E = 4 cells per bucket edge for N <= 256
