@@ -208,6 +208,36 @@ def test_db2_triplet(hermes, dtype):
         assert normwise(got[:, q], ref[:, q]) < tol, q
 
 
+def test_db2_triplet_block_local(hermes):
+    """float32, f2 = f3 and a reach within the staged region: the
+    block-local path with the D4 taps (3 per axis, two cells below the
+    point's cell), against the oracle and against the direct path (minimum
+    workspace) on the same samples; box points read f1 from the staged
+    region when it is the same array."""
+    L, n = 100.0, 32
+    pos = synth.neyman_scott(60, 30, 2.0, L, 8102)
+    eps, sw = O.assign(pos, None, L, n, basis=B)
+    dh = O.dft3(O.contrast(eps, sw))
+    f2 = O.filtered_field(dh, L, O.cic_window("sphere", 4.0), basis=B).astype(np.float32)
+    t2 = torch.from_numpy(f2).cuda()
+    c, w = pos[:201], synth.lognormal_marks(201, 4)
+    wmin = torch.empty(hermes.workspace_size(hermes.OP_TRIPLET, n, torch.float32, 7, 0), dtype=torch.uint8,
+                       device="cuda")
+    for kw, okw in [({"centres": torch.from_numpy(c).cuda(), "weights": torch.from_numpy(w).cuda()},
+                     {"centres": c, "weights": w}),
+                    ({"n_box": 333, "f1": t2}, {"n_box": 333, "f1": f2})]:
+        hermes.profile_enable(True)
+        hermes.profile_reset()
+        got = hermes.triplet_mc(t2, t2, L, 12.0, 20.0, 7, 9, 2607, **kw).cpu().numpy()
+        assert "bucket" in hermes.profile_read()
+        hermes.profile_enable(False)
+        direct = hermes.triplet_mc(t2, t2, L, 12.0, 20.0, 7, 9, 2607, work=wmin, **kw).cpu().numpy()
+        ref = O.triplet_mc(f2, f2, L, 12.0, 20.0, 7, 9, 2607, basis=B, **okw)
+        for q in range(4):
+            assert normwise(got[:, q], ref[:, q]) < 1e-5, q
+            assert normwise(got[:, q], direct[:, q]) < 1e-12, q
+
+
 def _gamma_oracle(e, fields):
     nb = len(fields)
     ref = np.zeros((nb, nb))
