@@ -453,6 +453,9 @@ def main() -> int:
     ap.add_argument("--no-configs", action="store_true", help="skip the 64^3, 256^3 and 1024^3 workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--configs-only", action="store_true",
+                    help="run only the other workloads, 64^3 to 1024^3 (for hardware counters of their "
+                         "kernels); prints their timings, not the benchmark line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise kernel that reads and writes 1 GiB, as the reference "
                          "for hardware byte counters")
@@ -498,6 +501,12 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
         log("copy calibration: 1 GiB read + 1 GiB write done")
+
+    if args.configs_only:
+        del pos, w, eps, sw, dk, delta, xi_out, zeta_out, xi_work, z_work, a_work
+        torch.cuda.empty_cache()
+        print(json.dumps({"configs": other_configs(1, max(1, min(args.steps, 5)))}), flush=True)
+        return 0
 
     def step_at(precision):
         def step():
