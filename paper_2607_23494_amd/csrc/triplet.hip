@@ -16,13 +16,17 @@
 // (centre, 0, 1, 0) for a box point, key (seed, 0): every sample can be drawn
 // by any thread, and the oracle draws the same numbers.
 //
-// Fields are read through tile-packed copies (each tile holds, for a pair of
-// x planes, the 4 x 4 (y, z) block of nodes a point in its cell reaches, so
-// a read is two or three 128-byte loads) up to 512^3 in float32 and 256^3 in
-// float64.  One thread per sample (grid-stride); per opening angle the
-// wavefront's 64 samples are summed by a butterfly over lanes and lane 0 adds
-// them to the wavefront's LDS accumulators, so every sum is formed in a fixed
-// order and the result does not depend on timing.
+// Two paths draw the same samples.  The block-local path (float32 fields,
+// f2 and f3 one array, the reach within a staged region; see below) buckets
+// the centres and reads the fields from the nodes around each bucket staged
+// in LDS.  The direct path reads them through tile-packed copies (each tile
+// holds, for a pair of x planes, the 4 x 4 (y, z) block of nodes a point in
+// its cell reaches, so a read is two or three 128-byte loads) up to 512^3 in
+// float32 and 256^3 in float64, larger grids directly, one thread per sample
+// (grid-stride).  Either way, per opening angle the wavefront's 64 samples
+// are summed in a fixed order (DPP steps) and added to the wavefront's LDS
+// accumulators, so every sum is formed in a fixed order and the result does
+// not depend on timing.
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
