@@ -237,3 +237,32 @@ def test_readout_fields_equals_single_reads(hermes, dtype):
     assert normwise(vals[1].cpu().numpy(), ref) < TOL[dtype]
     with pytest.raises(HermesError):
         hermes.readout_fields(torch.zeros((65, 8, 8, 8), device="cuda"), L, pos[:10].contiguous())
+
+
+@pytest.mark.parametrize("basis", ["b3", "db2"])
+def test_readout_fields_1024_tile_passes(hermes, basis):
+    """1024^3: tiles of 16^3 cells, and the staged nodes of only two float32
+    fields fit the LDS budget, so three fields take two passes; 3e6 points
+    (above 8 per tile): every row equals the unbucketed single-field read
+    (no workspace) bit for bit, and the moments agree to rounding."""
+    import ctypes
+    from paper_2607_23494_amd.hermes import _lib, context
+    n, L = 1024, 500.0
+    g = torch.Generator(device="cuda").manual_seed(1024)
+    f = torch.randn((3, n, n, n), device="cuda", generator=g)
+    pos = (torch.rand((3_000_000, 3), device="cuda", generator=g) * 1.5 * L - 0.25 * L).contiguous()
+    with hermes.basis(basis):
+        vals, mom = hermes.readout_fields(f, L, pos, moments=True)
+        for k in range(3):
+            direct = torch.empty(pos.shape[0], dtype=torch.float32, device="cuda")
+            dmom = torch.empty(3, dtype=torch.float64, device="cuda")
+            st = _lib.hermes_readout(context(0), ctypes.c_void_p(f[k].data_ptr()), n, 0, L,
+                                     ctypes.c_void_p(pos.data_ptr()), None, pos.shape[0], None,
+                                     ctypes.c_void_p(direct.data_ptr()), ctypes.c_void_p(dmom.data_ptr()), None, 0,
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            assert st == 0
+            torch.cuda.synchronize()
+            assert torch.equal(vals[k], direct), k
+            assert torch.allclose(mom[k], dmom, rtol=1e-12, atol=0), k
+    del f
+    torch.cuda.empty_cache()
