@@ -4,15 +4,16 @@
 //
 // The taps of every point are accumulated per tile of TS^3 cells in LDS and
 // in 64-bit fixed point:
-//   1. prep     count the points of every tile (by the cell of the point),
-//               and the per-block sums of w and |w|
+//   1. prep     the tile of every point (by the cell of the point), and the
+//               per-block sums of w and |w|
 //   2. scale    sum_w (the output) and the fixed-point scale 2^k, chosen from
 //               sum |w| so that no cell's sum can overflow: every cell is a
 //               sum of contributions of magnitude <= |w_i| M (M = 1 for B3,
 //               max |phi|^3 < 4 for D4, whose phi reaches (1 + sqrt3)/2), so
 //               |cell| <= sum |w| M 2^k <= 2^61
-//   3. scan     exclusive prefix of the tile counts: each tile's list offset
-//   4. scatter  the point indices into per-tile lists
+//   3. sort     a stable radix sort of the points by tile (a tile's points
+//               in index order), and each tile's list offset from the sorted
+//               keys
 //   5. tiles    one workgroup per tile: a wavefront loads 64 points, then
 //               for each of them lane t adds tap t (64 distinct cells; D4:
 //               27 taps per half-wavefront, two points at a time) to an LDS
@@ -30,6 +31,7 @@
 #include "common.hpp"
 #include "interp.hpp"
 #include "kernels.hpp"
+#include "sort.hpp"
 
 namespace hermes {
 
@@ -52,33 +54,35 @@ inline int asg_prep_blocks(int64_t n_pts) {
     return int(want < kAsgPrepBlocks ? (want > 0 ? want : 1) : kAsgPrepBlocks);
 }
 
-// Workspace layout (bytes, each part 256-aligned).
+// Workspace layout (bytes, each part 256-aligned): the accumulator, the
+// points' tile keys and the keys in sorted order, the tile offsets, the point
+// list in tile order, the prep partials, the scale, the sort's buffers.
 struct AsgLayout {
-    size_t acc, count, off, cursor, blocksum, list, partial, scale, total;
+    size_t acc, key, skey, off, list, partial, scale, sort, total;
 };
 
 inline AsgLayout asg_layout(int n, int64_t n_pts) {
     const int ts = n < kBucketTile ? n : kBucketTile;
     const int64_t tiles = int64_t(n / ts) * (n / ts) * (n / ts);
-    const int64_t nblk = (tiles + kScanBlock - 1) / kScanBlock;
+    const int64_t np = n_pts > 0 ? n_pts : 1;
     AsgLayout l{};
     size_t at = 0;
     l.acc = at;
     at += align256(size_t(n) * n * n * sizeof(int64_t));
-    l.count = at;
-    at += align256(size_t(tiles) * 4);
+    l.key = at;
+    at += align256(size_t(np) * 4);
+    l.skey = at;
+    at += align256(size_t(np) * 4);
     l.off = at;
     at += align256(size_t(tiles + 1) * 4);
-    l.cursor = at;
-    at += align256(size_t(tiles) * 4);
-    l.blocksum = at;
-    at += align256(size_t(nblk) * 4);
     l.list = at;
-    at += align256(size_t(n_pts > 0 ? n_pts : 1) * 4);
+    at += align256(size_t(np) * 4);
     l.partial = at;
     at += align256(size_t(asg_prep_blocks(n_pts)) * 2 * sizeof(double));
     l.scale = at;
     at += align256(sizeof(AsgScale));
+    l.sort = at;
+    at += sort_layout(np).total;
     l.total = at;
     return l;
 }
@@ -109,7 +113,7 @@ __device__ __forceinline__ double bcast(double v, int j) {
 
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_asg_prep(const float* __restrict__ pos, const float* __restrict__ weight,
-                                                       int64_t n_pts, double scale, uint32_t* __restrict__ count,
+                                                       int64_t n_pts, double scale, uint32_t* __restrict__ key,
                                                        double* __restrict__ partial) {
     __shared__ double red[kThreads];
     double s = 0.0, sa = 0.0;
@@ -118,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void k_asg_prep(const float* __restrict__
         const double w = weight ? double(weight[i]) : 1.0;
         s += w;
         sa += fabs(w);
-        atomicAdd(count + tile_of_point<N>(pos, i, scale), 1u);
+        key[i] = uint32_t(tile_of_point<N>(pos, i, scale));
     }
     s = block_sum(s, red);
     sa = block_sum(sa, red);
@@ -257,10 +261,9 @@ static hermes_status assign_n(hermes_ctx ctx, const float* pos, const float* wei
     const AsgLayout l = asg_layout(N, n_pts);
     char* w = static_cast<char*>(work);
     long long* acc = reinterpret_cast<long long*>(w + l.acc);
-    uint32_t* count = reinterpret_cast<uint32_t*>(w + l.count);
+    uint32_t* key = reinterpret_cast<uint32_t*>(w + l.key);
+    uint32_t* skey = reinterpret_cast<uint32_t*>(w + l.skey);
     uint32_t* off = reinterpret_cast<uint32_t*>(w + l.off);
-    uint32_t* cursor = reinterpret_cast<uint32_t*>(w + l.cursor);
-    uint32_t* blocksum = reinterpret_cast<uint32_t*>(w + l.blocksum);
     uint32_t* list = reinterpret_cast<uint32_t*>(w + l.list);
     double* partial = reinterpret_cast<double*>(w + l.partial);
     AsgScale* sc = reinterpret_cast<AsgScale*>(w + l.scale);
@@ -269,21 +272,19 @@ static hermes_status assign_n(hermes_ctx ctx, const float* pos, const float* wei
     {
         LaunchScope ls(ctx, stream, "fill");
         launch_fill<long long>(acc, cells, 0ll, stream);
-        launch_fill<uint32_t>(count, G::TILES, 0u, stream);
-        launch_fill<uint32_t>(cursor, G::TILES, 0u, stream);
         launch_fill<double>(partial, 2 * int64_t(pblocks), 0.0, stream);
     }
     {
         LaunchScope ls(ctx, stream, "assign");
         if (n_pts > 0)
             hipLaunchKernelGGL((k_asg_prep<N>), dim3(pblocks), dim3(kThreads), 0, stream, pos, weight, n_pts, scale,
-                               count, partial);
+                               key, partial);
         const int head = ctx->basis == HERMES_BASIS_DB2 ? 2 : 0;
         hipLaunchKernelGGL(k_asg_scale, dim3(1), dim3(64), 0, stream, partial, pblocks, head, sum_w, sc);
-        launch_tile_scan(count, int64_t(G::TILES), off, blocksum, stream);
         if (n_pts > 0) {
-            hipLaunchKernelGGL((k_bucket_scatter<N>), dim3(pblocks), dim3(kThreads), 0, stream, pos, n_pts, scale,
-                               off, cursor, list);
+            radix_sort_indices(key, n_pts, uint32_t(G::TILES - 1), list, w + l.sort, stream, skey);
+            hipLaunchKernelGGL(k_sorted_offsets, dim3(pblocks), dim3(kThreads), 0, stream, skey, n_pts,
+                               int64_t(G::TILES), off);
             if (ctx->basis == HERMES_BASIS_DB2)
                 hipLaunchKernelGGL((k_asg_tiles<T, N, HERMES_BASIS_DB2>), dim3(G::TILES), dim3(kTileThreads), 0, stream,
                                    pos, weight, scale, off, list, sc, ctx->t.db2tab,

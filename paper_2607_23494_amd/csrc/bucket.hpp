@@ -1,8 +1,7 @@
 // Bucketing of points by tiles of E^3 cells (E = 16 unless given): the tile
-// of a point, the exclusive prefix sum of per-tile counts, and the point
-// indices scattered into per-tile lists.  Used by the assignment (one
-// workgroup accumulates a tile's points in LDS); the readout takes the tile
-// of a point, and the radix sort and the triangle sums the prefix sum.
+// of a point and the exclusive prefix sum of per-tile counts, used by the
+// assignment and the readout (which sort their points by tile) and by the
+// radix sort and the triangle sums (prefix sums).
 #pragma once
 
 #include "common.hpp"
@@ -95,18 +94,6 @@ inline void launch_tile_scan(const uint32_t* count, int64_t tiles, uint32_t* off
     hipLaunchKernelGGL(k_scan_block, dim3(nblk), dim3(kScanBlock), 0, stream, count, tiles, off, blocksum);
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, stream, blocksum, nblk, off, tiles);
     hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kScanBlock), 0, stream, off, tiles, blocksum);
-}
-
-template <int N>
-__global__ __launch_bounds__(kThreads) void k_bucket_scatter(const float* __restrict__ pos, int64_t n_pts,
-                                                             double scale, const uint32_t* __restrict__ off,
-                                                             uint32_t* __restrict__ cursor,
-                                                             uint32_t* __restrict__ list) {
-    const int64_t stride = int64_t(gridDim.x) * kThreads;
-    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n_pts; i += stride) {
-        const int t = tile_of_point<N>(pos, i, scale);
-        list[off[t] + atomicAdd(cursor + t, 1u)] = uint32_t(i);
-    }
 }
 
 }  // namespace hermes

@@ -97,20 +97,6 @@ __global__ __launch_bounds__(kThreads) void k_readout_keys(const float* __restri
         key[i] = uint32_t(tile_of_point<N, E>(pos, i, scale));
 }
 
-// off[t] = the first list slot of tile t (off[tiles] = n): every slot whose
-// key differs from the previous slot's opens the tiles in between.
-__global__ __launch_bounds__(kThreads) void k_readout_offsets(const uint32_t* __restrict__ skey, int64_t n_pts,
-                                                              int64_t tiles, uint32_t* __restrict__ off) {
-    const int64_t stride = int64_t(gridDim.x) * kThreads;
-    for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n_pts; j += stride) {
-        const int64_t k = skey[j];
-        const int64_t prev = j > 0 ? int64_t(skey[j - 1]) : -1;
-        for (int64_t t = prev + 1; t <= k; ++t) off[t] = uint32_t(j);
-        if (j == n_pts - 1)
-            for (int64_t t = k + 1; t <= tiles; ++t) off[t] = uint32_t(n_pts);
-    }
-}
-
 // Positions in list order.
 __global__ __launch_bounds__(kThreads) void k_readout_gather_pos(const float* __restrict__ pos, int64_t n_pts,
                                                                  const uint32_t* __restrict__ list,
@@ -332,7 +318,7 @@ static hermes_status readout_n(hermes_ctx ctx, const void* fields, int n_fields,
             LaunchScope ls(ctx, stream, "bucket");
             hipLaunchKernelGGL((k_readout_keys<N, E>), dim3(blocks), dim3(kThreads), 0, stream, pos, n_pts, scale, key);
             radix_sort_indices(key, n_pts, uint32_t(G::TILES - 1), lst, w + l.sort, stream, skey);
-            hipLaunchKernelGGL(k_readout_offsets, dim3(blocks), dim3(kThreads), 0, stream, skey, n_pts,
+            hipLaunchKernelGGL(k_sorted_offsets, dim3(blocks), dim3(kThreads), 0, stream, skey, n_pts,
                                int64_t(G::TILES), off);
             hipLaunchKernelGGL(k_readout_gather_pos, dim3(blocks), dim3(kThreads), 0, stream, pos, n_pts, lst, spos);
             list = lst;

@@ -141,6 +141,21 @@ static __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t
     }
 }
 
+// off[t] = the first slot of key t in the sorted keys skey[0 .. n), for
+// t = 0 .. n_keys (off[n_keys] = n): every slot whose key differs from the
+// previous slot's opens the keys in between.
+static __global__ __launch_bounds__(kThreads) void k_sorted_offsets(const uint32_t* __restrict__ skey, int64_t n,
+                                                                    int64_t n_keys, uint32_t* __restrict__ off) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n; j += stride) {
+        const int64_t k = skey[j];
+        const int64_t prev = j > 0 ? int64_t(skey[j - 1]) : -1;
+        for (int64_t t = prev + 1; t <= k; ++t) off[t] = uint32_t(j);
+        if (j == n - 1)
+            for (int64_t t = k + 1; t <= n_keys; ++t) off[t] = uint32_t(n);
+    }
+}
+
 // Sort key[0 .. n) (keys <= max_key) with values 0 .. n-1; the values in key
 // order end in val_out, and the sorted keys in key_sorted when it is given.
 // key is overwritten.  n < 2^32.
