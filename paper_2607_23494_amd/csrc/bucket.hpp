@@ -96,4 +96,31 @@ inline void launch_tile_scan(const uint32_t* count, int64_t tiles, uint32_t* off
     hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kScanBlock), 0, stream, off, tiles, blocksum);
 }
 
+static __global__ void k_scan_set_total(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src) {
+    if (threadIdx.x == 0) dst[0] = src[0];
+}
+
+// uint32 entries of scratch that launch_scan needs for n counts.
+inline int64_t scan_tmp_entries(int64_t n) {
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    return nb <= kScanBlock ? nb : 2 * nb + 1 + scan_tmp_entries(nb);
+}
+
+// off[0 .. n] = exclusive prefix of cnt (off[n] = total) for any n < 2^32
+// whose total fits 32 bits: blocks of kScanBlock, then the block totals
+// scanned the same way (recursively) and added back.
+inline void launch_scan(const uint32_t* cnt, int64_t n, uint32_t* off, uint32_t* tmp, hipStream_t stream) {
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb <= kScanBlock) {
+        launch_tile_scan(cnt, n, off, tmp, stream);
+        return;
+    }
+    uint32_t* bs = tmp;            // nb block totals
+    uint32_t* boff = tmp + nb;     // their exclusive prefix, nb + 1 entries
+    hipLaunchKernelGGL(k_scan_block, dim3(unsigned(nb)), dim3(kScanBlock), 0, stream, cnt, n, off, bs);
+    launch_scan(bs, nb, boff, tmp + 2 * nb + 1, stream);
+    hipLaunchKernelGGL(k_scan_add, dim3(unsigned(nb)), dim3(kScanBlock), 0, stream, off, n, boff);
+    hipLaunchKernelGGL(k_scan_set_total, dim3(1), dim3(64), 0, stream, off + n, boff + nb);
+}
+
 }  // namespace hermes
