@@ -407,18 +407,23 @@ def other_configs(warmup: int, steps: int) -> dict:
     awork = torch.empty(hermes.workspace_size(hermes.OP_ASSIGN, n, torch.float32, int(pos.shape[0]), 1),
                         dtype=torch.uint8, device="cuda")
 
+    xi_m = torch.empty((1, e.size - 1), dtype=torch.float64, device="cuda")
+    xi_n = torch.empty_like(xi_m)
+    mr = torch.empty_like(xi_m)
+
     def step1024():
         hermes.assign(pos, w, L, n, eps=eps, sum_w=sw, work=awork)
         hermes.fft(eps, sw, want_delta=False, delta_k=dk)
-        hermes.xi(dk, L, e, work=xwork)
+        hermes.xi(dk, L, e, out=xi_m, work=xwork)
         hermes.assign(pos, None, L, n, eps=eps, sum_w=sw, work=awork)
         hermes.fft(eps, sw, want_delta=False, delta_k=dk)
-        hermes.xi(dk, L, e, work=xwork)
+        hermes.xi(dk, L, e, out=xi_n, work=xwork)
+        hermes.mark_ratio(xi_m, xi_n, out=mr)
         hermes.filter_bins(dk, L, wins, store_fields=False, moments=True, work=fwork)
     record("ns1024_cic", step1024, n ** 3 * (2 * (e.size - 1) + len(wins)),
            "1e8 marked Neyman-Scott points, 1024^3, float32: assign and FFT of the mark-weighted and number "
-           "fields, 40-bin 2PCF of each, counts-in-cells moments (p = 2, 3, 4) of the number field for the "
-           "sphere and Gaussian at 8 radii (16 windows)")
+           "fields, 40-bin 2PCF of each and their ratio M(r) = (1 + xi_m) / (1 + xi), counts-in-cells moments "
+           "(p = 2, 3, 4) of the number field for the sphere and Gaussian at 8 radii (16 windows)")
     del pos, w, eps, dk, fwork, xwork, awork
     torch.cuda.empty_cache()
     return out

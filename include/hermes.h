@@ -330,6 +330,17 @@ hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, i
                               int los_axis, double* xi, void* work, size_t work_bytes,
                               hipStream_t stream);
 
+/* Mark ratio of the density-marked 2PCF (Sec. 3.3.1 Eqs. power-law-mark,
+ * inverse-density-mark; Sec. 4.3.2): the marked correlation function is the
+ * 2PCF of the mark-weighted catalogue normalised by the unmarked pair counts,
+ *   out[b] = (1 + xi_marked[b]) / (1 + xi[b]),  b < n,
+ * with xi_marked and xi from hermes_xi on the mark-weighted and the plain
+ * catalogue over the same bins.  xi_marked, xi and out are device double
+ * [n] (out may alias either input); computed in float64 on the stream.
+ * ERR_ARG for NULL pointers or n < 0. */
+hermes_status hermes_mark_ratio(const double* xi_marked, const double* xi, int n, double* out,
+                                hipStream_t stream);
+
 /* Monte-Carlo triangle sums (Sec. 3.4 particle-based summation, Eq.
  * particle-based-sum; Sec. 4.3.3 dual-/triplet-sphere 3PCF).  Primary
  * vertices: the n_centres catalogue points `centres` (dual sphere; primary

@@ -467,6 +467,13 @@ hermes_status hermes_xi_aniso(hermes_ctx ctx, const void* delta_k, int n_grid, i
     return xi_aniso_impl(ctx, delta_k, n_grid, dtype, box_L, win, n_win, los_axis, xi, work, stream);
 }
 
+hermes_status hermes_mark_ratio(const double* xi_marked, const double* xi, int n, double* out,
+                                hipStream_t stream) {
+    if (!xi_marked || !xi || !out) return fail(HERMES_ERR_ARG, "hermes_mark_ratio: NULL argument");
+    if (n < 0) return fail(HERMES_ERR_ARG, "hermes_mark_ratio: n < 0");
+    return mark_ratio_impl(xi_marked, xi, n, out, stream);
+}
+
 hermes_status hermes_triplet_mc(hermes_ctx ctx, const void* f1, const void* f2, const void* f3, int n_grid,
                                 int dtype, double box_L, const float* centres, const float* weights,
                                 int64_t n_centres, double r12, double r13, int n_theta, int n_rot, uint64_t seed,

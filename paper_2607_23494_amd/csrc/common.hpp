@@ -148,6 +148,7 @@ hermes_status triplet_impl(hermes_ctx ctx, const void* f1, const void* f2, const
                            double r13, int n_theta, int n_rot, uint64_t seed, double* out, void* work,
                            size_t work_bytes, hipStream_t stream);
 size_t triplet_workspace(int n, int dtype, int n_theta, int64_t n_centres);
+hermes_status mark_ratio_impl(const double* xim, const double* xi, int n, double* out, hipStream_t stream);
 hermes_status gamma_impl(hermes_ctx ctx, const void* eps, const void* fields, int n_fields, int n, int dtype,
                          double* out, void* work, hipStream_t stream);
 size_t gamma_workspace();

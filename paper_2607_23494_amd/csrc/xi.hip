@@ -146,6 +146,19 @@ __global__ void k_xi_final(const double* __restrict__ part, const double* __rest
     }
 }
 
+// out[b] = (1 + xi_m[b]) / (1 + xi[b]): the marked correlation function
+// normalised by the unmarked pair counts (Sec. 4.3.2).
+__global__ void k_mark_ratio(const double* __restrict__ xim, const double* __restrict__ xi, int n,
+                             double* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n) out[b] = (1.0 + xim[b]) / (1.0 + xi[b]);
+}
+
+hermes_status mark_ratio_impl(const double* xim, const double* xi, int n, double* out, hipStream_t stream) {
+    if (n > 0) hipLaunchKernelGGL(k_mark_ratio, dim3((n + 255) / 256), dim3(256), 0, stream, xim, xi, n, out);
+    return check_launch("hermes_mark_ratio");
+}
+
 template <typename T, int N>
 static hermes_status xi_n(hermes_ctx ctx, const void* delta_k, double box_L, const Edges& edges, const EllSet& ells,
                           int los, double* xi, double* shot, void* work, hipStream_t stream) {

@@ -77,6 +77,7 @@ def _load() -> ctypes.CDLL:
     lib.hermes_readout.argtypes = [vp, vp, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp, vp, sz, vp]
     lib.hermes_readout_fields.argtypes = [vp, vp, i32, i32, i32, f64, vp, vp, i64, ctypes.POINTER(_Mark), vp, vp,
                                           vp, sz, vp]
+    lib.hermes_mark_ratio.argtypes = [vp, vp, i32, vp, vp]
     lib.hermes_set_basis.argtypes = [vp, i32]
     lib.hermes_get_basis.argtypes = [vp]
     lib.hermes_get_basis.restype = ctypes.c_int
@@ -85,7 +86,7 @@ def _load() -> ctypes.CDLL:
     lib.hermes_profile_read.argtypes = [vp, i32, ctypes.c_char_p, sz, ctypes.POINTER(i64), ctypes.POINTER(f64)]
     for name in ("hermes_create", "hermes_workspace_size", "hermes_assign", "hermes_fft", "hermes_xi", "hermes_xi_static", "hermes_xi_aniso", "hermes_triplet_mc", "hermes_ddd_gamma",
                  "hermes_filter_bins", "hermes_zeta_l", "hermes_readout", "hermes_profile_enable", "hermes_profile_reset",
-                 "hermes_profile_read", "hermes_set_basis", "hermes_readout_fields"):
+                 "hermes_profile_read", "hermes_set_basis", "hermes_readout_fields", "hermes_mark_ratio"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -283,6 +284,22 @@ def xi_aniso(delta_k: torch.Tensor, box_L: float, windows, los_axis: int = 2, ou
             out = torch.empty((nw,), dtype=torch.float64, device=delta_k.device)
         _check(_lib.hermes_xi_aniso(context(dev), _ptr(delta_k), n, _dtype_code(delta_k.dtype), float(box_L), arr, nw,
                                     los_axis, _ptr(out), _ptr(w), wbytes, _stream(dev, stream)))
+    return out
+
+
+def mark_ratio(xi_marked: torch.Tensor, xi_plain: torch.Tensor, out: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    """M(r) = (1 + xi_marked) / (1 + xi) per bin: the marked 2PCF normalised
+    by the unmarked pair counts.  Device float64 tensors of one shape."""
+    dev = _dev(xi_marked)
+    if (xi_marked.dtype != torch.float64 or xi_plain.dtype != torch.float64 or xi_marked.shape != xi_plain.shape
+            or not xi_marked.is_contiguous() or not xi_plain.is_contiguous()):
+        raise ValueError("xi_marked and xi must be contiguous float64 tensors of one shape")
+    with _on(stream):
+        if out is None:
+            out = torch.empty_like(xi_marked)
+        _check(_lib.hermes_mark_ratio(_ptr(xi_marked), _ptr(xi_plain), int(xi_marked.numel()), _ptr(out),
+                                      _stream(dev, stream)))
     return out
 
 

@@ -72,6 +72,23 @@ def test_readout_moments_and_empty(hermes, dtype):
     assert none is None and torch.count_nonzero(mom0).item() == 0
 
 
+def test_mark_ratio_values_and_errors(hermes):
+    """hermes_mark_ratio: (1 + a) / (1 + b) per bin, in place too; errors."""
+    from paper_2607_23494_amd.hermes import HermesError
+    a = torch.tensor([0.5, -0.25, 3.0, 0.0], dtype=torch.float64, device="cuda")
+    b = torch.tensor([1.0, 0.5, -0.5, 0.0], dtype=torch.float64, device="cuda")
+    got = hermes.mark_ratio(a, b).cpu().numpy()
+    assert np.array_equal(got, np.array([0.75, 0.5, 8.0, 1.0]))
+    hermes.mark_ratio(a, b, out=a)
+    assert np.array_equal(a.cpu().numpy(), np.array([0.75, 0.5, 8.0, 1.0]))
+    with pytest.raises(ValueError):
+        hermes.mark_ratio(a, b.float())
+    from paper_2607_23494_amd.hermes import _lib, _stream
+    import ctypes
+    assert _lib.hermes_mark_ratio(None, ctypes.c_void_p(b.data_ptr()), 4, ctypes.c_void_p(b.data_ptr()),
+                                  _stream(0)) != 0
+
+
 def test_readout_errors(hermes):
     from paper_2607_23494_amd.hermes import HermesError
     f = torch.zeros((16, 16, 16), dtype=torch.float32, device="cuda")
@@ -100,11 +117,13 @@ def test_marked_2pcf_workflow(hermes):
         marks, _ = hermes.readout(fields[0], L, tp, mark=(kind, ex, off, st))
         eps_m, sw_m = hermes.assign(tp, marks, L, n)
         dk_m, _ = hermes.fft(eps_m, sw_m, want_delta=False)
-        xm = hermes.xi(dk_m, L, edges).cpu().numpy()[0]
+        xm_t = hermes.xi(dk_m, L, edges)
+        xm = xm_t.cpu().numpy()[0]
+        M = hermes.mark_ratio(xm_t, hermes.xi(dk, L, edges)).cpu().numpy()[0]
         rxm, rxi, rM = O.marked_xi(pos, None, L, n, edges, R, kind, ex, off, st)
         assert normwise(xi, rxi) < 1e-5
         assert normwise(xm, rxm) < 1e-5, kind
-        assert normwise((1 + xm) / (1 + xi), rM) < 1e-5
+        assert normwise(M, rM) < 1e-5, kind
 
 
 # --------------------------------------------------------------------------
