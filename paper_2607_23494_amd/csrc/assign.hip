@@ -133,16 +133,20 @@ __global__ __launch_bounds__(kThreads) void k_asg_prep(const float* __restrict__
 }
 
 // sum_w and the fixed-point scale 2^k, k = 61 - head - ceil(log2(sum |w|)),
-// from the per-block partials in block order (2^head bounds a point's
-// largest tap weight).
-__global__ void k_asg_scale(const double* __restrict__ partial, int nblocks, int head, double* __restrict__ sum_w,
-                            AsgScale* __restrict__ sc) {
-    if (threadIdx.x != 0) return;
+// from the per-block partials (2^head bounds a point's largest tap weight).
+// One workgroup: thread t adds the partials t, t + kThreads, ... in order,
+// then the fixed tree of block_sum, so the sums repeat bit for bit.
+__global__ __launch_bounds__(kThreads) void k_asg_scale(const double* __restrict__ partial, int nblocks, int head,
+                                                        double* __restrict__ sum_w, AsgScale* __restrict__ sc) {
+    __shared__ double red[kThreads];
     double s = 0.0, sa = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = threadIdx.x; b < nblocks; b += kThreads) {
         s += partial[2 * b];
         sa += partial[2 * b + 1];
     }
+    s = block_sum(s, red);
+    sa = block_sum(sa, red);
+    if (threadIdx.x != 0) return;
     sum_w[0] = s;
     int e = 0;
     if (sa > 0.0) {
@@ -160,7 +164,12 @@ __global__ void k_asg_scale(const double* __restrict__ partial, int nblocks, int
 // t % 3) of point j and lanes 32-58 those of point j + 1.  The cell
 // i0 - LO + o of a tap sits at local index i0 - tile origin + o in
 // [0, TS + 2] per axis of the region, whose origin is LO cells below the
-// tile; the taps of one point hit distinct cells.
+// tile; the taps of one point hit distinct cells.  In float32 with B3 each
+// lane first evaluates the twelve axis weights of its own point into the
+// wavefront's LDS rows (row a 4 + o holds b3_tap(frac_a, o) of the 64
+// points, rows 65 apart so that the four rows a tap instruction reads sit
+// on different banks), and the tap of point j multiplies three of them: the
+// same products in the same order as evaluating them per tap.
 template <typename T, int N, int B>
 __global__ __launch_bounds__(kTileThreads) void k_asg_tiles(const float* __restrict__ pos, const float* __restrict__ weight,
                                                         double scale, const uint32_t* __restrict__ off,
@@ -173,6 +182,9 @@ __global__ __launch_bounds__(kTileThreads) void k_asg_tiles(const float* __restr
     constexpr int LO = BasisTaps<B>::LO;
     constexpr int NW = kTileThreads / 64;
     __shared__ unsigned long long reg[RCELLS];
+    constexpr bool STAGE = B == HERMES_BASIS_B3 && sizeof(T) == 4;   // axis weights staged in LDS
+    constexpr int WROW = 65;
+    __shared__ float wax[STAGE ? NW * 12 * WROW : 1];
     const int tile = blockIdx.x;
     const uint32_t p0 = off[tile], p1 = off[tile + 1];
     if (p0 == p1) return;   // uniform: an empty tile adds nothing
@@ -181,7 +193,7 @@ __global__ __launch_bounds__(kTileThreads) void k_asg_tiles(const float* __restr
     for (int c = threadIdx.x; c < RCELLS; c += kTileThreads) reg[c] = 0ull;
     __syncthreads();
     const double fxp = sc->scale;
-    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
     // this lane's tap (and, for D4, which of the two points it serves)
     const int half = B == HERMES_BASIS_DB2 ? lane >> 5 : 0;
     const int sub = B == HERMES_BASIS_DB2 ? lane & 31 : lane;
@@ -224,6 +236,23 @@ __global__ __launch_bounds__(kTileThreads) void k_asg_tiles(const float* __restr
                     atomicAdd(&reg[lj + tap], (unsigned long long)q);
                 }
             }
+        } else if constexpr (STAGE) {
+            float* wrow = wax + wv * 12 * WROW;
+            const T fr[3] = {fx, fy, fz};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int o = 0; o < 4; ++o) wrow[(4 * a + o) * WROW + lane] = b3_tap<T>(fr[a], o);
+            wave_sync();
+            const float* rx = wrow + ox * WROW;
+            const float* ry = wrow + (4 + oy) * WROW;
+            const float* rz = wrow + (8 + oz) * WROW;
+            for (int j = 0; j < cnt; ++j) {
+                const T wt = rx[j] * ry[j] * rz[j];
+                const long long q = llrint(bcast(wq, j) * double(wt));
+                atomicAdd(&reg[bcast(loc, j) + tap], (unsigned long long)q);
+            }
+            wave_sync();   // every lane's reads of this batch precede the next batch's writes
         } else {
             for (int j = 0; j < cnt; ++j) {
                 const T wt = b3_tap<T>(bcast(fx, j), ox) * b3_tap<T>(bcast(fy, j), oy) * b3_tap<T>(bcast(fz, j), oz);
@@ -280,7 +309,7 @@ static hermes_status assign_n(hermes_ctx ctx, const float* pos, const float* wei
             hipLaunchKernelGGL((k_asg_prep<N>), dim3(pblocks), dim3(kThreads), 0, stream, pos, weight, n_pts, scale,
                                key, partial);
         const int head = ctx->basis == HERMES_BASIS_DB2 ? 2 : 0;
-        hipLaunchKernelGGL(k_asg_scale, dim3(1), dim3(64), 0, stream, partial, pblocks, head, sum_w, sc);
+        hipLaunchKernelGGL(k_asg_scale, dim3(1), dim3(kThreads), 0, stream, partial, pblocks, head, sum_w, sc);
         if (n_pts > 0) {
             radix_sort_indices(key, n_pts, uint32_t(G::TILES - 1), list, w + l.sort, stream, skey);
             hipLaunchKernelGGL(k_sorted_offsets, dim3(pblocks), dim3(kThreads), 0, stream, skey, n_pts,

@@ -326,14 +326,19 @@ __global__ __launch_bounds__(kGammaThreads) void k_ddd_gamma(const T* __restrict
     }
 }
 
-__global__ void k_gamma_final(const double* __restrict__ part, int n_blocks, int nf, double scale,
-                              double* __restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nf * nf) return;
+// out[b1 nf + b2] = scale sum_b part[b][b1][b2]; one workgroup per entry,
+// thread t adds the blocks t, t + kThreads, ... in order, then the fixed tree
+// of block_sum, so the result repeats bit for bit.
+__global__ __launch_bounds__(kThreads) void k_gamma_final(const double* __restrict__ part, int n_blocks, int nf,
+                                                          double scale, double* __restrict__ out) {
+    __shared__ double red[kThreads];
+    const int i = blockIdx.x;
     const int b1 = i / nf, b2 = i % nf;
     double s = 0.0;
-    for (int b = 0; b < n_blocks; ++b) s += part[int64_t(b) * kGammaMaxFields * kGammaMaxFields + b1 * kGammaMaxFields + b2];
-    out[i] = s * scale;
+    for (int b = threadIdx.x; b < n_blocks; b += kThreads)
+        s += part[int64_t(b) * kGammaMaxFields * kGammaMaxFields + b1 * kGammaMaxFields + b2];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[i] = s * scale;
 }
 
 template <typename T, int N, int NT>
@@ -358,7 +363,7 @@ static hermes_status gamma_nb(hermes_ctx ctx, const void* eps, const void* field
     {
         LaunchScope ls(ctx, stream, "reduce");
         const double nc = double(N) * N * N;
-        hipLaunchKernelGGL(k_gamma_final, dim3((nf * nf + 127) / 128), dim3(128), 0, stream, part, blocks,
+        hipLaunchKernelGGL(k_gamma_final, dim3(nf * nf), dim3(kThreads), 0, stream, part, blocks,
                            nf, 1.0 / nc, out);
     }
     return check_launch("hermes_ddd_gamma");

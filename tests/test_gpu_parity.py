@@ -78,6 +78,29 @@ def test_assign_bitwise_reproducible_and_order_free(hermes, dtype):
         torch.cuda.empty_cache()
 
 
+def test_assign_heavy_point_batches(hermes):
+    """Two points carrying 2 % of sum |w| each: their taps reach 2^54
+    fixed-point units (the scale leaves 2^61 for sum |w|).  Compared with the
+    oracle over the whole grid and over the cells the heavy points do not reach
+    (normalised by their own largest value, so the heavy taps do not hide the
+    light ones)."""
+    L, n = 100.0, 64
+    pos, _ = _cat(400, 50, 2.0, L, 1700)
+    w = np.random.default_rng(17).uniform(0.5, 1.5, pos.shape[0]).astype(np.float32)
+    heavy = [123, 9000]
+    w[heavy] = np.float32(0.02 * w.sum())
+    eps, _ = hermes.assign(torch.from_numpy(pos).cuda(), torch.from_numpy(w).cuda(), L, n, dtype=torch.float32)
+    got = eps.cpu().numpy()
+    oe, _ = O.assign(pos, w, L, n)
+    assert normwise(got, oe) < TOL[torch.float32]
+    far = np.ones((n, n, n), dtype=bool)
+    for h in heavy:
+        c = np.floor(pos[h].astype(np.float64) * n / L).astype(int)
+        idx = [np.arange(c[a] - 2, c[a] + 3) % n for a in range(3)]
+        far[np.ix_(*idx)] = False
+    assert normwise(got[far], oe[far]) < TOL[torch.float32]
+
+
 def test_assign_wraps_and_empty(hermes):
     L, n = 50.0, 16
     rng = np.random.default_rng(4)
