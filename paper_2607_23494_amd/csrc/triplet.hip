@@ -342,14 +342,22 @@ __global__ void k_triplet_final(const double* __restrict__ part, int n_blocks, i
 // ---------------------------------------------------------------- block-local path
 // For float32 fields with f2 and f3 the same array, the centres are
 // bucketed by blocks of E^3 cells and a workgroup stages the nodes around
-// its block (a kTriReg^3 region, 128 KB of LDS) once, then draws every
+// its block (a kTriReg^3 region, 133 KB of LDS) once, then draws every
 // sample of the block's centres from it: the 1 + n_theta reads of a sample
 // become LDS reads instead of gathers of 128-byte lines from L2.  Usable when
 // the triangles' reach fits the region: E + 2 M + NT - 1 <= kTriReg with the
 // margin M = floor(max(r12, r13) N / L) + 2 cells.  Workgroup g takes the
 // contiguous run of buckets that holds centres g n_c / G .. (g + 1) n_c / G
-// (about equal sample counts), so the sums keep a fixed order.
+// (about equal sample counts), so the sums keep a fixed order.  Node
+// (i, j, k) of the region sits at i kTriPS + j kTriRS + k: with rows of 32
+// floats the bank of a read would be its z node alone, and a wavefront's 64
+// samples around one centre span only about 2 M + 4 z nodes, so several
+// lanes would share each bank; the padded strides spread them as random
+// addresses would (about five lanes on the busiest of 32 banks instead of
+// seven to nine, by a model of the sample geometry).
 constexpr int kTriReg = 32;             // region edge (nodes)
+constexpr int kTriRS = kTriReg + 1;     // row stride (floats)
+constexpr int kTriPS = kTriReg * kTriRS + 8;   // plane stride (floats)
 constexpr int kTriThreads = 1024;       // one workgroup per CU (the region's LDS)
 constexpr int kTriWaves = kTriThreads / 64;
 
@@ -443,7 +451,7 @@ __device__ __forceinline__ double region_value(const float* __restrict__ reg, co
         rel[a] = int(f) - o[a] + marg;
         P::weights(u[a] - f, tab, tap[a]);
     }
-    const float* p = reg + (rel[0] * kTriReg + rel[1]) * kTriReg + rel[2];
+    const float* p = reg + rel[0] * kTriPS + rel[1] * kTriRS + rel[2];
     double val = 0.0;
 #pragma unroll
     for (int ox = 0; ox < NT; ++ox) {
@@ -452,7 +460,7 @@ __device__ __forceinline__ double region_value(const float* __restrict__ reg, co
         for (int oy = 0; oy < NT; ++oy) {
             double vy = 0.0;
 #pragma unroll
-            for (int oz = 0; oz < NT; ++oz) vy += tap[2][oz] * double(p[(ox * kTriReg + oy) * kTriReg + oz]);
+            for (int oz = 0; oz < NT; ++oz) vy += tap[2][oz] * double(p[ox * kTriPS + oy * kTriRS + oz]);
             vx += tap[1][oy] * vy;
         }
         val += tap[0][ox] * vx;
@@ -472,8 +480,9 @@ __device__ __forceinline__ double block_sum_tri(double v, double* scratch) {
     return r;
 }
 
+// 161,792 bytes at n_theta = HERMES_MAX_THETA, within the 160 KiB of a CU.
 inline size_t tri_lds_bytes(int n_theta) {
-    return size_t(kTriReg) * kTriReg * kTriReg * sizeof(float) + size_t(kTriWaves) * n_theta * 2 * sizeof(double) +
+    return size_t(kTriReg) * kTriPS * sizeof(float) + size_t(kTriWaves) * n_theta * 2 * sizeof(double) +
            size_t(n_theta) * 2 * sizeof(double) + size_t(kTriThreads) * sizeof(double);
 }
 
@@ -486,10 +495,11 @@ __global__ __launch_bounds__(kTriThreads) void k_triplet_blocks(
     const uint32_t* __restrict__ list, double* __restrict__ part) {
     constexpr int E = tri_blk(N), NB = N / E, LO = BasisTaps<B>::LO;
     constexpr int64_t K = int64_t(NB) * NB * NB;
-    constexpr int RV = kTriReg * kTriReg * kTriReg;
+    constexpr int RV = kTriReg * kTriReg * kTriReg;   // region nodes
+    static_assert(kTriReg * kTriPS % 2 == 0, "the float64 arrays follow the region");
     extern __shared__ double lds_raw[];
     float* reg = reinterpret_cast<float*>(lds_raw);
-    double* acc = lds_raw + RV / 2;                 // [wave][j][2]: sum a f3, sum a f2 f3
+    double* acc = lds_raw + kTriReg * kTriPS / 2;   // [wave][j][2]: sum a f3, sum a f2 f3
     double* cs = acc + kTriWaves * n_theta * 2;     // [j][2]: cos, sin of the opening angles
     double* red = cs + n_theta * 2;                 // [kTriThreads]
     const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -525,7 +535,7 @@ __global__ __launch_bounds__(kTriThreads) void k_triplet_blocks(
             const int i = e / (kTriReg * kTriReg), j = (e / kTriReg) % kTriReg, k = e % kTriReg;
             const int gx = (o[0] - marg - LO + i) & (N - 1), gy = (o[1] - marg - LO + j) & (N - 1),
                       gz = (o[2] - marg - LO + k) & (N - 1);
-            reg[e] = f23[(int64_t(gx) * N + gy) * N + gz];
+            reg[i * kTriPS + j * kTriRS + k] = f23[(int64_t(gx) * N + gy) * N + gz];
         }
         __syncthreads();
         const int64_t tot = int64_t(hi - lo) * n_rot;
@@ -670,7 +680,7 @@ static hermes_status triplet_nb(hermes_ctx ctx, const void* f1, const void* f2, 
         const double reach = std::max(r12, r13) * double(N) / box_L;
         const int marg = int(std::floor(reach)) + 2;
         if (f2 == f3 && n_centres >= 1 && n_centres <= INT32_MAX &&
-            tri_blk(N) + 2 * marg + BasisTaps<B>::NT - 1 <= kTriReg &&
+            tri_blk(N) + 2 * marg + BasisTaps<B>::NT - 1 <= kTriReg && tri_lds_bytes(n_theta) <= size_t(160) * 1024 &&
             work_bytes >= triplet_workspace(N, HERMES_F32, n_theta, n_centres))
             return triplet_blocks<N, B>(ctx, static_cast<const float*>(f1), static_cast<const float*>(f2), box_L,
                                         centres, weights, n_centres, r12, r13, n_theta, n_rot, seed, marg, out, work,
