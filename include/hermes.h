@@ -64,7 +64,7 @@ typedef enum hermes_status {
     HERMES_ERR_ARG = 1,         /* bad pointer, size, bin edges, multipole, ... */
     HERMES_ERR_OOM = 2,         /* workspace smaller than hermes_workspace_size() */
     HERMES_ERR_HIP = 3,         /* HIP runtime error */
-    HERMES_ERR_UNSUPPORTED = 4  /* valid request outside what this build supports */
+    HERMES_ERR_UNSUPPORTED = 4  /* valid request outside what the library supports */
 } hermes_status;
 
 typedef enum hermes_dtype { HERMES_F32 = 0, HERMES_F64 = 1 } hermes_dtype;
