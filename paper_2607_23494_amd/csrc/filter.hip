@@ -417,7 +417,7 @@ __global__ __launch_bounds__((ypack_cfg<T, N>::NT)) void k_inv_y_pack(typename c
     const int lpos = pos == M + 1 ? M : pos;
     C x[8][1];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) x[i][0] = pos <= M + 1 ? base[int64_t(j + i * PER) * PP + lpos] : C{T(0), T(0)};
+    for (int i = 0; i < 8; ++i) x[i][0] = pos <= M + 1 ? ld_stream(base + int64_t(j + i * PER) * PP + lpos) : C{T(0), T(0)};
     // Z[kz] from own X[kz] and partner X[M-kz]: (X + X'*) + i e^{+2 pi i kz/N} (X - X'*),
     // e^{+2 pi i kz/N} = conj(tw[N + kz])
     auto pack = [&](C own, C oth, C w) {
@@ -439,7 +439,7 @@ __global__ __launch_bounds__((ypack_cfg<T, N>::NT)) void k_inv_y_pack(typename c
                 if (r < R) {
                     const C oth{__shfl_xor(v[r].x, 1), __shfl_xor(v[r].y, 1)};
                     const C z = pack(v[r], oth, w);
-                    if (store) base[int64_t(jj + r * NS) * PP + p] = z;
+                    if (store) st_stream(base + int64_t(jj + r * NS) * PP + p, z);
                 }
             }
         };
