@@ -416,8 +416,13 @@ __global__ __launch_bounds__((ypack_cfg<T, N>::NT)) void k_inv_y_pack(typename c
     const int pos = c0 + c;
     const int lpos = pos == M + 1 ? M : pos;
     C x[8][1];
+    // streaming (non-temporal) accesses where a tile row fills whole 128-byte
+    // lines (measured faster at 512^3); with 64-byte row segments (float at
+    // 1024^3) they were much slower than plain ones
+    constexpr bool STREAM = TC * int(sizeof(C)) >= 128;
+    auto ld = [&](const C* q) { return STREAM ? ld_stream(q) : *q; };
 #pragma unroll
-    for (int i = 0; i < 8; ++i) x[i][0] = pos <= M + 1 ? ld_stream(base + int64_t(j + i * PER) * PP + lpos) : C{T(0), T(0)};
+    for (int i = 0; i < 8; ++i) x[i][0] = pos <= M + 1 ? ld(base + int64_t(j + i * PER) * PP + lpos) : C{T(0), T(0)};
     // Z[kz] from own X[kz] and partner X[M-kz]: (X + X'*) + i e^{+2 pi i kz/N} (X - X'*),
     // e^{+2 pi i kz/N} = conj(tw[N + kz])
     auto pack = [&](C own, C oth, C w) {
@@ -439,7 +444,12 @@ __global__ __launch_bounds__((ypack_cfg<T, N>::NT)) void k_inv_y_pack(typename c
                 if (r < R) {
                     const C oth{__shfl_xor(v[r].x, 1), __shfl_xor(v[r].y, 1)};
                     const C z = pack(v[r], oth, w);
-                    if (store) st_stream(base + int64_t(jj + r * NS) * PP + p, z);
+                    if (store) {
+                        if constexpr (STREAM)
+                            st_stream(base + int64_t(jj + r * NS) * PP + p, z);
+                        else
+                            base[int64_t(jj + r * NS) * PP + p] = z;
+                    }
                 }
             }
         };
